@@ -1,0 +1,243 @@
+"""Seeded synthetic workloads shared by the GPU path and the FP64 oracle.
+
+This module only draws random numbers and lays out initial states, boundary
+descriptors and time-step parameters.  It contains none of the method's
+arithmetic (no operator, flux, rate or solver code), so both the HIP library
+and the oracle can consume its arrays without sharing any numerical code.
+
+Workloads (all SI units unless stated):
+
+* ``cfg1``: 32^3 cube of 1 cm, three species (e, Ar+, Ar*) over a background
+  of Ar at 1 atm / 300 K; Gaussian blob (peak 1e17 m^-3, sigma 2 mm) at the
+  centre on a 1e13 m^-3 background with 1 % seeded uniform noise; Te = 2 eV
+  fixed; phi = 1 kV at x = 0 and 0 at x = L, Neumann elsewhere; dt = 1e-12 s.
+* ``cfg3``: 160^3 cube of 12.5 mm, 15-species Ar-H2 (95/5 by volume at
+  101325 Pa, 300 K); electron/Ar+ Gaussian seed (peak 1e19 m^-3, sigma
+  0.5 mm) centred 1 mm from the x = 0 electrode at 15 kV; background 1e13
+  m^-3 with 1 % noise; Te from the reduced-field table; dt = 1e-12 s.
+* ``cfg4``: 64 independent Helmholtz problems of uneven size (edges drawn
+  from {32, 48, ..., 160}), log-uniform beta with a sheath-like slab jump,
+  random Dirichlet/Neumann faces, N(0,1) right-hand sides.
+* Random small Helmholtz / Poisson problems and the manufactured-solution
+  fields used by the tests.
+
+The electron temperature table used in local-field mode is a stand-in for
+the Boltzmann-solver output the paper uses (Sec. 2.3 and the streamer
+benchmark in Sec. 5.4): Te[eV] = 0.02585 + 5.47 (E/N / 300 Td)^0.6, sampled on
+256 log-spaced points between 1e-2 and 1e3 Td.  Only its shape (about 5.5 eV
+at 300 Td, the pairing the paper reports at 3D streamer heads in Sec. 6.1)
+is taken from the paper.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Boundary kinds, per domain face in the order x-, x+, y-, y+, z-, z+.
+BC_DIRICHLET, BC_NEUMANN, BC_WALLFLUX, BC_PERIODIC = 0, 1, 2, 3
+
+# Electron-temperature modes of the time step.
+TE_FIXED, TE_LFA, TE_ENERGY = 0, 1, 2
+
+# Mechanism identifiers.
+MECH_NONE, MECH_DECAY, MECH_AR3, MECH_ARH2_15 = 0, 1, 2, 3
+
+# Unit-conversion and gas-state constants used to *describe* the inputs.
+EV_IN_K = 11604.518
+ATM = 101325.0
+KB = 1.380649e-23
+N_1ATM_300K = ATM / (KB * 300.0)          # 2.4463e25 m^-3
+
+LFA_NPTS = 256
+LFA_EN_MIN_TD = 1e-2
+LFA_EN_MAX_TD = 1e3
+
+
+def rng(seed: int) -> np.random.Generator:
+    """numpy PCG64 generator; every workload names its own seed."""
+    return np.random.default_rng(seed)
+
+
+def lfa_table() -> dict:
+    """Stand-in Te(E/N) table (K) on log-spaced reduced fields (Td)."""
+    ln_en = np.linspace(np.log(LFA_EN_MIN_TD), np.log(LFA_EN_MAX_TD), LFA_NPTS)
+    en = np.exp(ln_en)
+    te_ev = 0.02585 + 5.47 * (en / 300.0) ** 0.6
+    return {
+        "te_K": np.ascontiguousarray(te_ev * EV_IN_K, dtype=np.float64),
+        "ln_en_min": float(ln_en[0]),
+        "ln_en_max": float(ln_en[-1]),
+        "npts": LFA_NPTS,
+    }
+
+
+def bc(kinds, values=(0.0,) * 6) -> dict:
+    return {"kind": [int(k) for k in kinds], "value": [float(v) for v in values]}
+
+
+def cell_centres(nx, ny, nz, dx, dy, dz):
+    """Cell-centre coordinates, each array shaped [nz][ny][nx]."""
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    z = (np.arange(nz) + 0.5) * dz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def _blob(X, Y, Z, c, sigma):
+    r2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+    return np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def cfg1(seed: int = 1, n: int = 32) -> dict:
+    """Three-species argon step on an n^3 grid over a 1 cm cube."""
+    L = 0.01
+    h = L / n
+    g = rng(seed)
+    X, Y, Z = cell_centres(n, n, n, h, h, h)
+    shape = _blob(X, Y, Z, (L / 2, L / 2, L / 2), 2e-3)
+    base = 1e13 + 1e17 * shape
+    S = 3
+    dens = np.empty((S, n, n, n))
+    dens[0] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))   # e
+    dens[1] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))   # Ar+
+    dens[2] = 1e13 * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))   # Ar*
+    te = np.full((n, n, n), 2.0 * EV_IN_K)
+    wall = [BC_WALLFLUX, BC_WALLFLUX, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN]
+    return {
+        "name": "cfg1-ar3-%d" % n,
+        "grid": (n, n, n, h, h, h),
+        "mech": MECH_AR3,
+        "n": dens,
+        "phi": np.zeros((n, n, n)),
+        "Te": te,
+        "te_mode": TE_FIXED,
+        "phi_bc": bc([BC_DIRICHLET, BC_DIRICHLET] + [BC_NEUMANN] * 4, [1000.0, 0, 0, 0, 0, 0]),
+        "species_bc": [bc(wall)] * S,
+        "energy_bc": bc(wall),
+        "dt": 1e-12,
+        "n_t": 1,
+        "Tg": 300.0,
+        "N_gas": N_1ATM_300K,
+        "bg": [N_1ATM_300K],
+        # Constant electron mobility 0.03 m^2/Vs with Einstein diffusion at
+        # 2 eV: D = mu * (kB Te / e) = 0.03 * 2 V.
+        "electron_const": (-0.03, 0.06),
+    }
+
+
+def cfg3(seed: int = 3, n: int = 160, L: float = 0.0125, voltage: float = 15e3,
+         seed_centre=None) -> dict:
+    """15-species Ar-H2 streamer-shaped state on an n^3 grid."""
+    h = L / n
+    g = rng(seed)
+    X, Y, Z = cell_centres(n, n, n, h, h, h)
+    c = seed_centre if seed_centre is not None else (1.0e-3, L / 2, L / 2)
+    shape = _blob(X, Y, Z, c, 0.5e-3)
+    base = 1e13 + 1e19 * shape
+    S = 15
+    N = N_1ATM_300K
+    dens = np.zeros((S, n, n, n))
+    dens[0] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))    # e
+    dens[1] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))    # Ar+
+    dens[13] = 0.95 * N                                               # Ar
+    dens[14] = 0.05 * N                                               # H2
+    wall = [BC_WALLFLUX, BC_WALLFLUX, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN]
+    return {
+        "name": "cfg3-arh2-%d" % n,
+        "grid": (n, n, n, h, h, h),
+        "mech": MECH_ARH2_15,
+        "n": dens,
+        "phi": np.zeros((n, n, n)),
+        "Te": np.full((n, n, n), 300.0),
+        "te_mode": TE_LFA,
+        "phi_bc": bc([BC_DIRICHLET, BC_DIRICHLET] + [BC_NEUMANN] * 4, [voltage, 0, 0, 0, 0, 0]),
+        "species_bc": [bc(wall)] * S,
+        "energy_bc": bc(wall),
+        "dt": 1e-12,
+        "n_t": 1,
+        "Tg": 300.0,
+        "N_gas": N,
+        "bg": [],
+        "lfa": lfa_table(),
+    }
+
+
+def random_helmholtz(seed: int, shape, *, alpha_kind="array", beta_kind="array",
+                     kinds=None, mask_holes=0, beta_jump=False, h=None) -> dict:
+    """A random (alpha - div beta grad) x = b problem for solver tests.
+
+    shape = (nx, ny, nz).  alpha_kind / beta_kind in {"array", "const",
+    "zero" (alpha only)}.  kinds: six boundary kinds (random if None).
+    mask_holes: number of covered boxes cut into the mask.
+    """
+    g = rng(seed)
+    nx, ny, nz = shape
+    if h is None:
+        h = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    if kinds is None:
+        kinds = []
+        for d in range(3):
+            if g.uniform() < 0.2:
+                kinds += [BC_PERIODIC, BC_PERIODIC]
+            else:
+                kinds += [int(g.choice([BC_DIRICHLET, BC_NEUMANN])) for _ in range(2)]
+        if BC_DIRICHLET not in kinds:
+            kinds[0] = BC_DIRICHLET
+    values = g.uniform(-1, 1, 6)
+    prob = {"grid": (nx, ny, nz) + tuple(h), "bc": bc(kinds, values)}
+    if alpha_kind == "array":
+        prob["alpha"], prob["alpha_c"] = g.uniform(0.5, 2.0, (nz, ny, nx)), 0.0
+    elif alpha_kind == "const":
+        prob["alpha"], prob["alpha_c"] = None, float(g.uniform(0.5, 2.0))
+    else:
+        prob["alpha"], prob["alpha_c"] = None, 0.0
+    if beta_kind == "array":
+        beta = np.exp(g.uniform(np.log(1e-3), 0.0, (nz, ny, nx)))
+        if beta_jump:
+            beta = np.full((nz, ny, nx), np.exp(g.uniform(np.log(1e-3), 0.0)))
+            w = int(g.integers(2, 7))
+            beta[:, :, :w] = np.exp(g.uniform(np.log(1e-3), 0.0))
+        prob["beta"], prob["beta_c"] = beta, 0.0
+    else:
+        prob["beta"], prob["beta_c"] = None, float(np.exp(g.uniform(np.log(1e-3), 0.0)))
+    mask = None
+    if mask_holes:
+        mask = np.ones((nz, ny, nx), dtype=np.uint8)
+        for _ in range(mask_holes):
+            lo = [int(g.integers(0, s - 1)) for s in (nz, ny, nx)]
+            ext = [int(g.integers(1, max(2, s // 3))) for s in (nz, ny, nx)]
+            mask[lo[0]:lo[0] + ext[0], lo[1]:lo[1] + ext[1], lo[2]:lo[2] + ext[2]] = 0
+    prob["mask"] = mask
+    prob["rhs"] = g.standard_normal((nz, ny, nx))
+    prob["x0"] = g.standard_normal((nz, ny, nx))
+    return prob
+
+
+def cfg4(seed: int = 4, count: int = 64, sizes=tuple(range(32, 161, 16))) -> list:
+    """64 uneven Helmholtz problems with a sheath-like beta jump each."""
+    g = rng(seed)
+    probs = []
+    for p in range(count):
+        n = int(g.choice(sizes))
+        h = 1.0 / n
+        kinds = [int(g.choice([BC_DIRICHLET, BC_NEUMANN])) for _ in range(6)]
+        values = g.uniform(-1, 1, 6)
+        bulk = np.exp(g.uniform(np.log(1e-3), 0.0))
+        sheath = np.exp(g.uniform(np.log(1e-3), 0.0))
+        width = int(g.integers(2, 7))
+        face = int(g.integers(0, 6))
+        beta = np.full((n, n, n), bulk)
+        axis, side = 2 - face // 2, face % 2
+        sl = [slice(None)] * 3
+        sl[axis] = slice(0, width) if side == 0 else slice(n - width, n)
+        beta[tuple(sl)] = sheath
+        probs.append({
+            "grid": (n, n, n, h, h, h),
+            "bc": bc(kinds, values),
+            "alpha": None, "alpha_c": 1.0,
+            "beta": beta, "beta_c": 0.0,
+            "mask": None,
+            "rhs": g.standard_normal((n, n, n)),
+            "x0": np.zeros((n, n, n)),
+        })
+    return probs
