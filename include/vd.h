@@ -1,0 +1,262 @@
+/*
+ * vd.h -- C ABI of libvd, an MI355X (gfx950) implementation of the hot path
+ * of one semi-implicit non-equilibrium plasma-fluid time step on a uniform
+ * 3D Cartesian grid (Vidyut3d, arXiv 2507.08200).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments documented "device" are device pointers owned by the
+ *     caller (allocated in HBM, e.g. by PyTorch); the library never frees
+ *     them.  Arrays documented "host" are ordinary host memory.
+ *   - Cell arrays are contiguous [nz][ny][nx] (x fastest); multi-field
+ *     arrays are [S][nz][ny][nx].  FP64 unless noted.  SI units; electron
+ *     temperature in kelvin.
+ *   - Boundary faces are indexed x-, x+, y-, y+, z-, z+.
+ *   - Work is enqueued on the context's stream in order.  A function that
+ *     fills a host info struct synchronises that stream before returning.
+ *   - Errors are status codes; no exception crosses the ABI.  The message of
+ *     the last failure is available from vd_last_error().  Arguments are
+ *     validated on the host before anything is launched; on VD_EINVAL no
+ *     device memory has been touched.
+ *   - One context per host thread.  Calls on one context must not overlap.
+ */
+#ifndef VD_H
+#define VD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vd_ctx vd_ctx;
+
+typedef enum {
+    VD_OK = 0,
+    VD_EINVAL = -1,      /* bad argument (shape, kind, pointer, option) */
+    VD_ENOMEM = -2,      /* device allocation failed */
+    VD_EHIP = -3,        /* HIP runtime error */
+    VD_ENOCONV = -4,     /* solver did not reach the tolerance, or produced a non-finite residual */
+    VD_ESINGULAR = -5    /* operator is singular (alpha = 0, no Dirichlet face, no mask) */
+} vd_status;
+
+/* Boundary kinds (per domain face).  DIRICHLET imposes a face value
+ * (ghost 2g - x_c); NEUMANN a zero normal gradient; WALLFLUX (species and
+ * electron energy) a zero diffusive flux in the implicit operator with the
+ * wall flux of Sec. 2.2 entering through the drift divergence; PERIODIC
+ * wraps (both faces of a direction or neither). */
+enum { VD_BC_DIRICHLET = 0, VD_BC_NEUMANN = 1, VD_BC_WALLFLUX = 2, VD_BC_PERIODIC = 3 };
+
+enum { VD_FP64 = 0, VD_FP32_IR = 1 };                               /* vd_mg_opts.precision */
+enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2 }; /* vd_mg_opts.guess */
+enum { VD_TE_FIXED = 0, VD_TE_LFA = 1, VD_TE_ENERGY = 2 };          /* electron temperature */
+enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3 };
+/* mobility models (Table A.4 with the Einstein relation):
+ *   CONST:        mu = mu_const (signed), D = D_const
+ *   ELECTRON_FIT: |mu| = exp(0.05481 - 2.911 tanh(0.289 ln(E/N) + 0.543)) 1.1296e25/N,
+ *                 mu = sign(Z)|mu|, D = |mu| kB Te / e
+ *   ION_N0:       |mu| = mob_coef N0/N, mu = sign(Z)|mu|, D = |mu| kB Tg / e
+ *   NEUTRAL_N0:   mu = 0, D = mob_coef (N0/N) kB Tg / e (the ionic counterpart's) */
+enum { VD_MOB_CONST = 0, VD_MOB_ELECTRON_FIT = 1, VD_MOB_ION_N0 = 2, VD_MOB_NEUTRAL_N0 = 3 };
+/* wall-flux models at WALLFLUX faces (Sec. 2.2, Eqs. (13)-(15)):
+ *   ELECTRON: n/4 sqrt(8 kB Te/(pi m_e)); ION: max(mu n E.n, 0);
+ *   NEUTRAL: n/4 sqrt(8 kB Tg/(pi m)); NONE: no flux (background gas). */
+enum { VD_WALL_NONE = 0, VD_WALL_ELECTRON = 1, VD_WALL_ION = 2, VD_WALL_NEUTRAL = 3 };
+
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } vd_grid;
+typedef struct { int32_t kind[6]; double value[6]; } vd_bc;
+
+/* Multigrid options.  Cycles: V(nu_pre, nu_post) with red-black Gauss-Seidel,
+ * mean-of-8 restriction, piecewise-constant prolongation, FP64
+ * Jacobi-preconditioned CG on the coarsest level (to 1e-14 or 500
+ * iterations).  Levels: n_levels if > 0 (each coarsening needs every
+ * dimension even), otherwise coarsen while every dimension is even and
+ * larger than 4.  With one level a cycle is nu_pre + nu_post sweeps.
+ * Stopping: before each cycle ||b - A x||_2 / ||b||_2 over valid cells (b
+ * including the Dirichlet lifting) is compared with rtol; fixed_cycles > 0
+ * runs exactly that many cycles instead.  precision = VD_FP32_IR runs the
+ * cycles in FP32 on the FP64 residual and adds the FP32 correction to the
+ * FP64 iterate (iterative refinement; ir_inner cycles per outer step; the
+ * outer residual, face coefficients and bottom solve stay FP64). */
+typedef struct {
+    double rtol;
+    int32_t max_cycles;
+    int32_t fixed_cycles;
+    int32_t nu_pre, nu_post;
+    int32_t n_levels;
+    int32_t precision;
+    int32_t guess;
+    int32_t ir_inner;
+} vd_mg_opts;
+
+/* cycles: V-cycles run (FP32 cycles in IR mode); outer_iters: FP64
+ * residual evaluations in IR mode; rel_res0 / rel_res: relative residual
+ * before the first and after the last cycle; bnorm = ||b||_2; status as the
+ * return code for this problem; fallback = 1 if a learned guess was
+ * rejected. */
+typedef struct {
+    int32_t cycles, outer_iters, fallback, levels, status, pad;
+    double rel_res, rel_res0, bnorm;
+} vd_solve_info;
+
+/* One Helmholtz problem (alpha - div(beta grad)) x = rhs (Sec. 3, the
+ * Helmholtz casting of each implicit equation; Sec. 4).  Cell-centred
+ * alpha and beta; face coefficients are harmonic means of the two cells
+ * (the boundary cell's value on a domain face).  NULL alpha / beta mean
+ * uniform alpha_c / beta_c.  mask (uint8, nullable): 1 valid, 0 covered;
+ * covered cells hold 0 and act as a homogeneous Dirichlet face for their
+ * valid neighbours (cell masking of Sec. 3).  rhs, x: device cell arrays; x
+ * holds the initial guess on entry and the solution on exit. */
+typedef struct {
+    vd_grid grid;
+    vd_bc bc;
+    const uint8_t *mask;
+    const double *alpha;
+    double alpha_c;
+    const double *beta;
+    double beta_c;
+    const double *rhs;
+    double *x;
+} vd_problem;
+
+typedef struct {
+    double Z;               /* charge number */
+    double mass_kg;
+    int32_t transported;    /* 0: density held fixed in the step */
+    int32_t mob_kind;       /* VD_MOB_* */
+    int32_t wall_kind;      /* VD_WALL_* */
+    int32_t pad;
+    double mob_coef, mu_const, D_const;
+} vd_species;
+
+typedef struct { double qe, eps0, kB, me; } vd_consts;
+
+/* ------------------------------------------------------------------ */
+vd_status vd_ctx_create(vd_ctx **out, void *hip_stream /* hipStream_t, NULL = default stream */);
+void vd_ctx_destroy(vd_ctx *ctx);
+vd_status vd_ctx_set_stream(vd_ctx *ctx, void *hip_stream);
+const char *vd_last_error(const vd_ctx *ctx);
+const char *vd_version(void);
+
+/* Electrostatic Poisson (Sec. 2.1, Eqs. (3)-(4)) in Helmholtz form:
+ *   -div(beta grad phi) = rho,  beta = eps (beta_cell, NULL = beta_c everywhere),
+ *   rho = e sum_k Z_k n_k (C/m^3; device cell array).
+ * phi: device cell array, initial guess in (ignored for VD_GUESS_ZERO),
+ * solution out.  Electrodes are Dirichlet faces of phi_bc.
+ * VD_ESINGULAR when no face is Dirichlet and no mask is given. */
+vd_status vd_poisson_solve(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const uint8_t *mask,
+                           const double *beta_cell, double beta_c, const double *rho, double *phi,
+                           const vd_mg_opts *opts, vd_solve_info *info /* host, nullable */);
+
+/* nprob independent Helmholtz problems of possibly different sizes solved
+ * together (Sec. 7: several components per multigrid solve): one launch per
+ * smoother colour covers every problem's level, coarse levels of all
+ * problems run in one fused launch, and per-problem convergence flags live
+ * on the device.  probs, infos: host arrays [nprob]. */
+vd_status vd_helmholtz_solve_batched(vd_ctx *ctx, int32_t nprob, const vd_problem *probs,
+                                     const vd_mg_opts *opts, vd_solve_info *infos /* host, nullable */);
+
+/* Divergence of the drift flux mu_k n_k E of every species (Sec. 2.1,
+ * Eq. (2); WENO5 upwind reconstruction of Sec. 3): face velocity
+ * v = mu_f E_f with E_f = -(phi_R - phi_L)/h (Dirichlet faces of phi_bc:
+ * over half a cell; Neumann: 0) and mu_f the mean of the two cells' signed
+ * mobilities; flux = v times the upwind WENO5 value (ghosts: mirror at
+ * Neumann/wall faces, odd reflection at Dirichlet faces, wrap at periodic).
+ * WALLFLUX faces of species_bc[k] carry the wall flux of species[k].wall_kind
+ * at the boundary cell instead.
+ *   n, mu: device [S][cells]; phi, Te_K: device cells; Tg: gas temperature.
+ *   div_drift: device [S][cells] output. */
+vd_status vd_species_flux(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const vd_bc *species_bc /* host[S] */,
+                          int32_t S, const vd_species *species /* host[S] */, const double *n, const double *phi,
+                          const double *mu, const double *Te_K, double Tg, const vd_consts *consts,
+                          double *div_drift);
+
+/* Chemical production rates G_k = sum_i nu_ik r_i, r_i = k_i(Te) prod n
+ * (#/m^3/s) and electron inelastic loss sum_i dE_i e r_i (J/m^3/s) of the
+ * mechanism of Appendix A (Tables A.1-A.3).  mech VD_MECH_ARH2_15: S = 15
+ * in the order e, Ar+, Ar2+, H+, H2+, H3+, ArH+, Ar*, Ar2*, H2(v1), H2(v2),
+ * H2(v3), H, Ar, H2.  VD_MECH_AR3: S = 3 (e, Ar+, Ar*) with background Ar
+ * density bg[0] and reactions R1-R5, R12, R13.  VD_MECH_DECAY: G = -k n for
+ * every species (k = bg[0]).  n: device [S][ncells]; Te_K: device cells;
+ * G: device [S][ncells]; S_inel: device cells or NULL. */
+vd_status vd_reaction_source(vd_ctx *ctx, int32_t mech, int64_t ncells, int32_t S, const double *n,
+                             const double *Te_K, const double *bg /* host[4] */, double qe, double *G,
+                             double *S_inel);
+
+/* Parameters of one semi-implicit step (Sec. 3). */
+typedef struct {
+    vd_grid grid;
+    double dt;
+    int32_t n_t;            /* mid-point corrector iterations, Eqs. (17)-(18) (1 = Backward Euler) */
+    int32_t mech;           /* VD_MECH_* */
+    int32_t S;              /* species count, 1..32 */
+    int32_t te_mode;        /* VD_TE_* */
+    int32_t electron;       /* index of the electron species, -1 if none */
+    int32_t pad0;
+    double Tg;              /* gas temperature, K */
+    double N_gas;           /* gas number density for E/N and ion mobilities, m^-3 */
+    double m_bg;            /* background neutral mass for the elastic loss, kg */
+    double k_decay;         /* VD_MECH_DECAY rate */
+    double bg[4];           /* background densities used by the mechanism */
+    vd_consts consts;
+    vd_bc phi_bc;
+    vd_bc energy_bc;
+    const vd_bc *species_bc;        /* host [S] */
+    const vd_species *species;      /* host [S] */
+    const double *lfa_te;           /* device [lfa_n], Te (K) on uniform ln(E/N[Td]) nodes */
+    double lfa_ln_min, lfa_ln_max;
+    int32_t lfa_n, pad1;
+    const double *extra_source;     /* device [S][cells] or NULL */
+    const double *extra_energy;     /* device cells or NULL */
+    const double *eps_cell;         /* device cells or NULL (eps0) */
+    vd_mg_opts poisson, species_mg, energy_mg;
+} vd_step_params;
+
+/* State updated in place (device arrays). */
+typedef struct {
+    double *n;      /* [S][cells] */
+    double *phi;    /* [cells]; in: guess, out: potential at the last corrector's u* */
+    double *Te;     /* [cells], K; input in VD_TE_FIXED, output otherwise */
+    double *Ee;     /* [cells], electron energy density (J/m^3); VD_TE_ENERGY only */
+} vd_state;
+
+typedef struct {
+    int32_t poisson_cycles, species_cycles, energy_cycles, status;
+    double poisson_rel, dt_used;
+    double ms_poisson, ms_transport, ms_energy, ms_species, ms_total;
+} vd_step_info;
+
+/* One step of the segregated semi-implicit scheme (Sec. 3):
+ *   for m = 0..n_t-1:  u* = (u^n + u^m)/2;  Poisson at u*;  E, E/N, Te,
+ *   mobilities at u*;  [electron energy: (1/dt - div(5/3 D_e grad)) Ee^{m+1} =
+ *   Ee^n/dt - div(5/3 mu_e Ee* E) + Joule - elastic - inelastic];  species:
+ *   (1/dt - div(D_k grad)) n_k^{m+1} = n_k^n/dt - div(mu_k n*_k E) + G_k(u*)
+ *   (+ extra_source);  u^{n+1} = u^{n_t}.
+ * The species solves of each corrector go through one batched multigrid
+ * solve.  No host copies happen inside the step besides the per-solve
+ * convergence words. */
+vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
+                  vd_step_info *info /* host, nullable */);
+
+/* ---- inspection entry points (tests and tuning) ---- */
+
+/* Per-cell flags of multigrid level `level` of a problem: bit 0 colour
+ * (i+j+k)&1, bit 1 valid (a coarse cell is valid iff its 8 children are),
+ * bit 2+f face f does not couple to a valid neighbour.  out: device uint8
+ * cells of that level. */
+vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, int32_t level, uint8_t *out);
+
+/* ncolour Gauss-Seidel half-sweeps (red first) on the finest level of one
+ * problem, with the Dirichlet lifting; x updated in place. */
+vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour);
+
+/* Kernel timing: bracket every launch of the named kernel family with HIP
+ * events on the context stream ("gsrb", "resid_restrict", "weno", ...; NULL
+ * turns timing off) and read back count and total milliseconds. */
+vd_status vd_timing_select(vd_ctx *ctx, const char *kernel);
+vd_status vd_timing_read(vd_ctx *ctx, int64_t *launches, double *total_ms, double *units);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VD_H */

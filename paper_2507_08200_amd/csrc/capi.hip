@@ -1,0 +1,165 @@
+// extern "C" entry points of libvd: argument checks, error capture and
+// dispatch to the internal engines.  No exception crosses this boundary.
+#include "physics.hpp"
+
+namespace vd {
+vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step_info *info);
+vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const vd_bc *sp_bc, int S, const vd_species *sp,
+                       const double *n, const double *phi, const double *mu, const double *Te, double Tg, const vd_consts *c,
+                       double *div);
+vd_status reaction_source(vd_ctx *ctx, int mech, long ncell, int S, const double *n, const double *Te, const double *bg,
+                          double qe, double *G, double *S_inel);
+
+bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *ev1) {
+    Timing &T = ctx->timing;
+    if (T.family.empty() || T.family != family) return false;
+    if (T.pool.size() < 2) {
+        for (int q = 0; q < 64; q++) {
+            hipEvent_t e;
+            VD_HIP(hipEventCreate(&e));
+            T.pool.push_back(e);
+        }
+    }
+    *ev0 = T.pool.back(); T.pool.pop_back();
+    *ev1 = T.pool.back(); T.pool.pop_back();
+    return true;
+}
+
+void timing_end(vd_ctx *ctx, hipEvent_t ev0, hipEvent_t ev1, double units) {
+    Timing &T = ctx->timing;
+    T.pending.push_back({ev0, ev1});
+    T.units += units;
+    T.launches += 1;
+    if (T.pending.size() >= 256) timing_flush(ctx);
+}
+
+void timing_flush(vd_ctx *ctx) {
+    Timing &T = ctx->timing;
+    for (auto &pr : T.pending) {
+        VD_HIP(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        VD_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        T.total_ms += ms;
+        T.pool.push_back(pr.first);
+        T.pool.push_back(pr.second);
+    }
+    T.pending.clear();
+}
+
+}  // namespace vd
+
+template <typename F>
+static vd_status guarded(vd_ctx *ctx, F &&fn) {
+    if (!ctx) return VD_EINVAL;
+    try {
+        vd_status s = fn();
+        if (s == VD_OK) ctx->last_error.clear();
+        return s;
+    } catch (const vd::Error &e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        ctx->last_error = e.what();
+        return VD_EHIP;
+    }
+}
+
+extern "C" {
+
+const char *vd_version(void) { return "libvd 0.1 gfx950"; }
+
+vd_status vd_ctx_create(vd_ctx **out, void *stream) {
+    if (!out) return VD_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return VD_EHIP;
+    vd_ctx *c = new (std::nothrow) vd_ctx();
+    if (!c) return VD_ENOMEM;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return VD_OK;
+}
+
+void vd_ctx_destroy(vd_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    try { vd::timing_flush(ctx); } catch (...) {}
+    for (auto &e : ctx->timing.pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+vd_status vd_ctx_set_stream(vd_ctx *ctx, void *stream) {
+    return guarded(ctx, [&] {
+        VD_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->stream = (hipStream_t)stream;
+        return VD_OK;
+    });
+}
+
+const char *vd_last_error(const vd_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+vd_status vd_poisson_solve(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const uint8_t *mask, const double *beta_cell,
+                           double beta_c, const double *rho, double *phi, const vd_mg_opts *opts, vd_solve_info *info) {
+    return guarded(ctx, [&] {
+        VD_CHECK(grid && phi_bc && rho && phi && opts, "null argument");
+        VD_CHECK(beta_cell || beta_c > 0.0, "permittivity must be positive");
+        vd_problem p;
+        memset(&p, 0, sizeof(p));
+        p.grid = *grid; p.bc = *phi_bc; p.mask = mask; p.beta = beta_cell; p.beta_c = beta_c;
+        p.rhs = rho; p.x = phi;
+        return vd::mg_solve_batch(ctx, 1, &p, opts, info, "poisson:");
+    });
+}
+
+vd_status vd_helmholtz_solve_batched(vd_ctx *ctx, int32_t nprob, const vd_problem *probs, const vd_mg_opts *opts,
+                                     vd_solve_info *infos) {
+    return guarded(ctx, [&] { return vd::mg_solve_batch(ctx, nprob, probs, opts, infos, "batch:"); });
+}
+
+vd_status vd_species_flux(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const vd_bc *species_bc, int32_t S,
+                          const vd_species *species, const double *n, const double *phi, const double *mu, const double *Te_K,
+                          double Tg, const vd_consts *consts, double *div_drift) {
+    return guarded(ctx, [&] {
+        return vd::species_flux(ctx, grid, phi_bc, species_bc, S, species, n, phi, mu, Te_K, Tg, consts, div_drift);
+    });
+}
+
+vd_status vd_reaction_source(vd_ctx *ctx, int32_t mech, int64_t ncells, int32_t S, const double *n, const double *Te_K,
+                             const double *bg, double qe, double *G, double *S_inel) {
+    return guarded(ctx, [&] { return vd::reaction_source(ctx, mech, (long)ncells, S, n, Te_K, bg, qe, G, S_inel); });
+}
+
+vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state, vd_step_info *info) {
+    return guarded(ctx, [&] { return vd::step(ctx, params, state, info); });
+}
+
+vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, int32_t level, uint8_t *out) {
+    return guarded(ctx, [&] { return vd::mg_cell_flags(ctx, prob, n_levels, level, out); });
+}
+
+vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour) {
+    return guarded(ctx, [&] { return vd::mg_smooth(ctx, prob, ncolour); });
+}
+
+vd_status vd_timing_select(vd_ctx *ctx, const char *kernel) {
+    return guarded(ctx, [&] {
+        vd::timing_flush(ctx);
+        ctx->timing.family = kernel ? kernel : "";
+        ctx->timing.launches = 0;
+        ctx->timing.total_ms = 0.0;
+        ctx->timing.units = 0.0;
+        return VD_OK;
+    });
+}
+
+vd_status vd_timing_read(vd_ctx *ctx, int64_t *launches, double *total_ms, double *units) {
+    return guarded(ctx, [&] {
+        vd::timing_flush(ctx);
+        if (launches) *launches = ctx->timing.launches;
+        if (total_ms) *total_ms = ctx->timing.total_ms;
+        if (units) *units = ctx->timing.units;
+        return VD_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,1014 @@
+// Geometric multigrid for batches of Helmholtz problems (alpha - div beta grad) x = b
+// on uniform Cartesian grids, FP64 or FP32 inside FP64 iterative refinement.
+//
+// Each implicit equation of the scheme is cast in Helmholtz form and solved
+// by multigrid (Sec. 4 of the paper); several right-hand sides go through
+// one solve (Sec. 7).  The cycle itself is this library's design: V(nu1,nu2)
+// with red-black Gauss-Seidel, mean-of-8 restriction, piecewise-constant
+// prolongation, coarse operators rediscretised from averaged coefficients
+// and FP64 Jacobi-PCG on the coarsest level.
+//
+// Launch structure on gfx950:
+//   * fine levels: one launch per colour / transfer covers that level of
+//     every problem in the batch (block -> (problem, tile) via a prefix
+//     table; blocks are spread so each XCD gets a contiguous tile range);
+//   * coarse levels (<= kCoarseMax cells) and the bottom solve of every
+//     problem run in ONE fused launch, one workgroup per problem;
+//   * residual norms are deterministic two-stage reductions, and the
+//     convergence decisions are taken on the device (per-problem active
+//     flags), so the host reads back one small state array per chunk.
+#include "vd_internal.hpp"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace vd {
+
+constexpr int kCoarseMax = 4096;     // levels at or below this size run in the fused kernel
+constexpr int kFusedThreads = 1024;
+constexpr int kBottomMaxIt = 500;
+constexpr double kBottomTol = 1e-14;
+
+// ------------------------------------------------------------ cell bodies
+template <typename T>
+__device__ __forceinline__ T load_b(const LevDesc &L, int c, int i, int j, int k) {
+    T b = ((const T *)L.b)[c];
+    if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
+    return b;
+}
+
+template <typename T>
+__device__ __forceinline__ void gs_update(const LevDesc &L, int c, int i, int j, int k) {
+    if (L.has_mask && !L.mask[c]) return;
+    T *x = (T *)L.x;
+    T dg, of;
+    row_terms<T, T>(L, x, i, j, k, c, dg, of);
+    T b = load_b<T>(L, c, i, j, k);
+    x[c] = (b + of) / dg;
+}
+
+template <typename T>
+__device__ __forceinline__ T residual_at(const LevDesc &L, int c, int i, int j, int k) {
+    if (L.has_mask && !L.mask[c]) return (T)0;
+    const T *x = (const T *)L.x;
+    T dg, of;
+    row_terms<T, T>(L, x, i, j, k, c, dg, of);
+    T b = load_b<T>(L, c, i, j, k);
+    return b - (dg * x[c] - of);
+}
+
+// coarse cell (I,J,K): mean of the 8 children's residuals (k, j, i order)
+template <typename T>
+__device__ __forceinline__ void restrict_cell(const LevDesc &F, const LevDesc &C, int cc, int I, int J, int K) {
+    T s = 0;
+    for (int kk = 0; kk < 2; kk++)
+        for (int jj = 0; jj < 2; jj++)
+            for (int ii = 0; ii < 2; ii++) {
+                int i = 2 * I + ii, j = 2 * J + jj, k = 2 * K + kk;
+                int c = i + F.nx * j + F.nxy * k;
+                s += residual_at<T>(F, c, i, j, k);
+            }
+    T v = (C.has_mask && !C.mask[cc]) ? (T)0 : (T)0.125 * s;
+    ((T *)C.b)[cc] = v;
+    ((T *)C.x)[cc] = (T)0;
+}
+
+template <typename T>
+__device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C, int c, int i, int j, int k) {
+    if (F.has_mask && !F.mask[c]) return;
+    int cc = (i >> 1) + C.nx * (j >> 1) + C.nxy * (k >> 1);
+    ((T *)F.x)[c] += ((const T *)C.x)[cc];
+}
+
+// ------------------------------------------------------------ grid kernels
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gsrb(const LevDesc *__restrict__ descs, Plan pl, int colour,
+                                                 const ProbState *__restrict__ st) {
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    const LevDesc &L = descs[pl.ids[d]];
+    if (!st[L.prob].active) return;
+    int lt = t - pl.prefix[d];
+    if ((L.nx & 1) == 0) {
+        // one thread per pair (2m, 2m+1) of a row; exactly one has the colour
+        int q = lt * kBlock + threadIdx.x;
+        int c0 = 2 * q;
+        if (c0 >= L.ncell) return;
+        int i, j, k;
+        cell_ijk(L, c0, i, j, k);
+        int off = ((i + j + k) & 1) != colour;
+        gs_update<T>(L, c0 + off, i + off, j, k);
+    } else {
+        int c = lt * kBlock + threadIdx.x;
+        if (c >= L.ncell) return;
+        int i, j, k;
+        cell_ijk(L, c, i, j, k);
+        if (((i + j + k) & 1) != colour) return;
+        gs_update<T>(L, c, i, j, k);
+    }
+}
+
+// plan over COARSE descriptors; fine = descs[id - 1]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__ descs, Plan pl,
+                                                     const ProbState *__restrict__ st) {
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    int id = pl.ids[d];
+    const LevDesc &C = descs[id];
+    if (!st[C.prob].active) return;
+    const LevDesc &F = descs[id - 1];
+    int cc = (t - pl.prefix[d]) * kBlock + threadIdx.x;
+    if (cc >= C.ncell) return;
+    int I, J, K;
+    cell_ijk(C, cc, I, J, K);
+    restrict_cell<T>(F, C, cc, I, J, K);
+}
+
+// plan over FINE descriptors; coarse = descs[id + 1]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong(const LevDesc *__restrict__ descs, Plan pl,
+                                                    const ProbState *__restrict__ st) {
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    int id = pl.ids[d];
+    const LevDesc &F = descs[id];
+    if (!st[F.prob].active) return;
+    const LevDesc &C = descs[id + 1];
+    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
+    if (c >= F.ncell) return;
+    int i, j, k;
+    cell_ijk(F, c, i, j, k);
+    prolong_cell<T>(F, C, c, i, j, k);
+}
+
+// Sum of squares of the lifted right-hand side (mode 0) or of the FP64
+// residual (mode 1) per tile of the finest level; mode 2 additionally
+// stores the residual rounded to FP32 into the FP32 hierarchy's finest
+// right-hand side and clears its unknown (iterative refinement).
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64, const LevDesc *__restrict__ d32,
+                                                 Plan pl, double *__restrict__ partials,
+                                                 const ProbState *__restrict__ st, int check_active) {
+    __shared__ double lds[kBlock / 64];
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    int id = pl.ids[d];
+    const LevDesc &L = d64[id];
+    if (check_active && !st[L.prob].active) return;
+    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (c < L.ncell) {
+        int i, j, k;
+        cell_ijk(L, c, i, j, k);
+        bool valid = !(L.has_mask && !L.mask[c]);
+        double r;
+        if (MODE == 0) r = valid ? load_b<double>(L, c, i, j, k) : 0.0;
+        else r = residual_at<double>(L, c, i, j, k);
+        v = r * r;
+        if (MODE == 2) {
+            const LevDesc &E = d32[id];
+            ((float *)E.b)[c] = (float)r;
+            ((float *)E.x)[c] = 0.0f;
+        }
+    }
+    double s = block_sum(v, lds);
+    if (threadIdx.x == 0) partials[t] = s;
+}
+
+// x = 0 on covered cells, on problems whose right-hand side vanishes, and
+// everywhere for a zero initial guess.
+__global__ void __launch_bounds__(kBlock) k_prep(const LevDesc *__restrict__ d64, Plan pl,
+                                                 const ProbState *__restrict__ st, int zero_guess) {
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    const LevDesc &L = d64[pl.ids[d]];
+    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
+    if (c >= L.ncell) return;
+    bool covered = L.has_mask && !L.mask[c];
+    if (zero_guess || covered || st[L.prob].bnorm == 0.0) ((double *)L.x)[c] = 0.0;
+}
+
+// x64 += e32 after the inner FP32 cycles of an outer refinement step.
+__global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict__ d64, const LevDesc *__restrict__ d32,
+                                                      Plan pl, const ProbState *__restrict__ st) {
+    int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    int d = plan_find(pl, t);
+    int id = pl.ids[d];
+    const LevDesc &L = d64[id];
+    if (!st[L.prob].active) return;
+    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
+    if (c >= L.ncell) return;
+    ((double *)L.x)[c] += (double)((const float *)d32[id].x)[c];
+}
+
+__global__ void k_state_init(ProbState *st, int n) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    ProbState s;
+    s.active = 1; s.cycles = 0; s.outer = 0; s.status = VD_OK;
+    s.bnorm = 0.0; s.rel0 = 0.0; s.rel = 0.0;
+    st[p] = s;
+}
+
+// One workgroup per problem: sum its partials in a fixed order and take the
+// stopping decision.  mode 0: ||b||; mode 1: residual check before a cycle.
+__global__ void __launch_bounds__(kBlock) k_finalize(Plan pl, const int *__restrict__ prob_of, const double *__restrict__ partials,
+                                                     ProbState *__restrict__ st, int mode, double rtol, int max_cycles,
+                                                     int fixed, int inner) {
+    __shared__ double lds[kBlock / 64];
+    int d = blockIdx.x;
+    int p = prob_of[d];
+    ProbState s = st[p];
+    if (mode == 1 && !s.active) return;
+    double v = 0.0;
+    for (int q = pl.prefix[d] + threadIdx.x; q < pl.prefix[d + 1]; q += blockDim.x) v += partials[q];
+    double tot = block_sum(v, lds);
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        s.bnorm = sqrt(tot);
+        if (s.bnorm == 0.0) { s.active = 0; s.rel = 0.0; }
+        st[p] = s;
+        return;
+    }
+    double rel = sqrt(tot) / s.bnorm;
+    if (s.outer == 0) s.rel0 = rel;
+    s.rel = rel;
+    s.outer += 1;
+    int done_iters = s.outer - 1;   // cycles (FP64) or outer steps (IR) already run
+    if (!isfinite(rel)) { s.status = VD_ENOCONV; s.active = 0; }
+    else if (fixed > 0) { if (done_iters == fixed) s.active = 0; }
+    else if (rel <= rtol) s.active = 0;
+    else if (done_iters == max_cycles) { s.status = VD_ENOCONV; s.active = 0; }
+    if (s.active) s.cycles += inner;
+    st[p] = s;
+}
+
+// ---------------------------------------------------- fused coarse kernel
+struct FusedDesc {
+    int prob, lc, L, base;     // base = index of level 0 in the descriptor arrays
+    double *pcg;               // FP64 scratch: 6 * bottom cells
+};
+
+template <typename T>
+__device__ void block_sweep(const LevDesc &L, int colour) {
+    for (int c = threadIdx.x; c < L.ncell; c += blockDim.x) {
+        int i, j, k;
+        cell_ijk(L, c, i, j, k);
+        if (((i + j + k) & 1) == colour) gs_update<T>(L, c, i, j, k);
+    }
+    __syncthreads();
+}
+
+// Jacobi-preconditioned CG in FP64 on the coarsest level, from a zero guess.
+template <typename T>
+__device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *scr, double *lds) {
+    const int n = A64.ncell;
+    double *r = scr, *z = scr + n, *p = scr + 2 * n, *q = scr + 3 * n, *dg = scr + 4 * n, *xb = scr + 5 * n;
+    const T *bT = (const T *)AT.b;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int i, j, k;
+        cell_ijk(A64, c, i, j, k);
+        double d, of;
+        row_terms<double, double>(A64, xb, i, j, k, c, d, of);   // xb unused by diag
+        dg[c] = d;
+        bool valid = !(A64.has_mask && !A64.mask[c]);
+        r[c] = valid ? (double)bT[c] : 0.0;
+        xb[c] = 0.0;
+    }
+    __syncthreads();
+    double v = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) v += r[c] * r[c];
+    double bn = sqrt(block_sum(v, lds));
+    v = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        bool valid = !(A64.has_mask && !A64.mask[c]);
+        double zz = valid ? r[c] / dg[c] : 0.0;
+        z[c] = zz;
+        p[c] = zz;
+        v += r[c] * zz;
+    }
+    double rz = block_sum(v, lds);
+    for (int it = 0; it < kBottomMaxIt; it++) {
+        v = 0.0;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) v += r[c] * r[c];
+        double rn = sqrt(block_sum(v, lds));
+        if (!(rn > kBottomTol * bn)) break;
+        v = 0.0;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            double qq = 0.0;
+            if (!(A64.has_mask && !A64.mask[c])) {
+                int i, j, k;
+                cell_ijk(A64, c, i, j, k);
+                double d, of;
+                row_terms<double, double>(A64, p, i, j, k, c, d, of);
+                qq = d * p[c] - of;
+            }
+            q[c] = qq;
+            v += p[c] * qq;
+        }
+        double pq = block_sum(v, lds);
+        if (pq == 0.0) break;
+        double a = rz / pq;
+        v = 0.0;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            xb[c] += a * p[c];
+            r[c] -= a * q[c];
+            bool valid = !(A64.has_mask && !A64.mask[c]);
+            double zz = valid ? r[c] / dg[c] : 0.0;
+            z[c] = zz;
+            v += r[c] * zz;
+        }
+        double rz_new = block_sum(v, lds);
+        double bcoef = rz_new / rz;
+        rz = rz_new;
+        for (int c = threadIdx.x; c < n; c += blockDim.x) p[c] = z[c] + bcoef * p[c];
+        __syncthreads();
+    }
+    T *xT = (T *)AT.x;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) xT[c] = (T)xb[c];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
+                                                          const FusedDesc *__restrict__ fd, const ProbState *__restrict__ st,
+                                                          int nu_pre, int nu_post) {
+    __shared__ double lds[kFusedThreads / 64];
+    const FusedDesc f = fd[blockIdx.x];
+    if (!st[f.prob].active) return;
+    const int base = f.base, lc = f.lc, L = f.L;
+    if (L == 1) {
+        const LevDesc &A = dT[base];
+        for (int s = 0; s < nu_pre + nu_post; s++) { block_sweep<T>(A, 0); block_sweep<T>(A, 1); }
+        return;
+    }
+    for (int l = lc; l < L - 1; l++) {
+        const LevDesc &A = dT[base + l];
+        for (int s = 0; s < nu_pre; s++) { block_sweep<T>(A, 0); block_sweep<T>(A, 1); }
+        const LevDesc &C = dT[base + l + 1];
+        for (int cc = threadIdx.x; cc < C.ncell; cc += blockDim.x) {
+            int I, J, K;
+            cell_ijk(C, cc, I, J, K);
+            restrict_cell<T>(A, C, cc, I, J, K);
+        }
+        __syncthreads();
+    }
+    block_pcg<T>(d64[base + L - 1], dT[base + L - 1], f.pcg, lds);
+    for (int l = L - 2; l >= lc; l--) {
+        const LevDesc &A = dT[base + l];
+        const LevDesc &C = dT[base + l + 1];
+        for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) {
+            int i, j, k;
+            cell_ijk(A, c, i, j, k);
+            prolong_cell<T>(A, C, c, i, j, k);
+        }
+        __syncthreads();
+        for (int s = 0; s < nu_post; s++) { block_sweep<T>(A, 0); block_sweep<T>(A, 1); }
+    }
+}
+
+// -------------------------------------------------------- setup kernels
+__device__ __forceinline__ double harmonic(double a, double b) { return (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b); }
+
+// finest-level face coefficients from the cell coefficient (harmonic mean;
+// a non-periodic domain face takes the boundary cell's value)
+__global__ void __launch_bounds__(kBlock) k_faces0(const double *__restrict__ beta, int nx, int ny, int nz, int perx,
+                                                   int pery, int perz, double *bx, double *by, double *bz, float *bx32,
+                                                   float *by32, float *bz32) {
+    long nfx = (long)(nx + 1) * ny * nz, nfy = (long)nx * (ny + 1) * nz, nfz = (long)nx * ny * (nz + 1);
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long nxy = (long)nx * ny;
+    if (q < nfx) {
+        int i = (int)(q % (nx + 1));
+        long r = q / (nx + 1);
+        int j = (int)(r % ny), k = (int)(r / ny);
+        long row = nx * (j + (long)ny * k);
+        double v;
+        if (i > 0 && i < nx) v = harmonic(beta[row + i - 1], beta[row + i]);
+        else if (perx) v = harmonic(beta[row + nx - 1], beta[row]);
+        else v = beta[row + (i == 0 ? 0 : nx - 1)];
+        bx[q] = v;
+        if (bx32) bx32[q] = (float)v;
+        return;
+    }
+    q -= nfx;
+    if (q < nfy) {
+        int i = (int)(q % nx);
+        long r = q / nx;
+        int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
+        long pl = nxy * k + i;
+        double v;
+        if (j > 0 && j < ny) v = harmonic(beta[pl + (long)nx * (j - 1)], beta[pl + (long)nx * j]);
+        else if (pery) v = harmonic(beta[pl + (long)nx * (ny - 1)], beta[pl]);
+        else v = beta[pl + (long)nx * (j == 0 ? 0 : ny - 1)];
+        by[q] = v;
+        if (by32) by32[q] = (float)v;
+        return;
+    }
+    q -= nfy;
+    if (q < nfz) {
+        long col = q % nxy;
+        int k = (int)(q / nxy);
+        double v;
+        if (k > 0 && k < nz) v = harmonic(beta[col + nxy * (k - 1)], beta[col + nxy * k]);
+        else if (perz) v = harmonic(beta[col + nxy * (nz - 1)], beta[col]);
+        else v = beta[col + nxy * (k == 0 ? 0 : nz - 1)];
+        bz[q] = v;
+        if (bz32) bz32[q] = (float)v;
+    }
+}
+
+// coarse faces (mean of 4 coincident fine faces), alpha (mean of 8 children),
+// mask (valid iff all 8 children are); FP64 plus optional FP32 copies
+__global__ void __launch_bounds__(kBlock) k_coarsen(LevDesc F, LevDesc C, double *bx, double *by, double *bz, double *al,
+                                                    uint8_t *mk, float *bx32, float *by32, float *bz32, float *al32) {
+    const int nx = C.nx, ny = C.ny, nz = C.nz, fx = F.nx, fy = F.ny;
+    long nfx = C.var_beta ? (long)(nx + 1) * ny * nz : 0;
+    long nfy = C.var_beta ? (long)nx * (ny + 1) * nz : 0;
+    long nfz = C.var_beta ? (long)nx * ny * (nz + 1) : 0;
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nfx) {
+        int i = (int)(q % (nx + 1));
+        long r = q / (nx + 1);
+        int j = (int)(r % ny), k = (int)(r / ny);
+        double s = 0.0;
+        for (int kk = 0; kk < 2; kk++)
+            for (int jj = 0; jj < 2; jj++) s += F.bx[(long)(2 * i) + (long)(fx + 1) * ((2 * j + jj) + (long)fy * (2 * k + kk))];
+        bx[q] = 0.25 * s;
+        if (bx32) bx32[q] = (float)(0.25 * s);
+        return;
+    }
+    q -= nfx;
+    if (q < nfy) {
+        int i = (int)(q % nx);
+        long r = q / nx;
+        int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
+        double s = 0.0;
+        for (int kk = 0; kk < 2; kk++)
+            for (int ii = 0; ii < 2; ii++) s += F.by[(long)(2 * i + ii) + (long)fx * ((2 * j) + (long)(fy + 1) * (2 * k + kk))];
+        by[q] = 0.25 * s;
+        if (by32) by32[q] = (float)(0.25 * s);
+        return;
+    }
+    q -= nfy;
+    if (q < nfz) {
+        int i = (int)(q % nx);
+        long r = q / nx;
+        int j = (int)(r % ny), k = (int)(r / ny);
+        double s = 0.0;
+        for (int jj = 0; jj < 2; jj++)
+            for (int ii = 0; ii < 2; ii++) s += F.bz[(long)(2 * i + ii) + (long)fx * ((2 * j + jj) + (long)fy * (2 * k))];
+        bz[q] = 0.25 * s;
+        if (bz32) bz32[q] = (float)(0.25 * s);
+        return;
+    }
+    q -= nfz;
+    if (q < (long)C.ncell) {
+        int c = (int)q;
+        int i, j, k;
+        cell_ijk(C, c, i, j, k);
+        double s = 0.0;
+        int valid = 1;
+        for (int kk = 0; kk < 2; kk++)
+            for (int jj = 0; jj < 2; jj++)
+                for (int ii = 0; ii < 2; ii++) {
+                    long f = (long)(2 * i + ii) + (long)fx * ((2 * j + jj) + (long)fy * (2 * k + kk));
+                    if (C.var_alpha) s += F.alpha[f];
+                    if (C.has_mask) valid = valid && F.mask[f];
+                }
+        if (C.var_alpha) { al[c] = 0.125 * s; if (al32) al32[c] = (float)(0.125 * s); }
+        if (C.has_mask) mk[c] = (uint8_t)valid;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_f32(const double *__restrict__ a, float *__restrict__ b, long n) {
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = (float)a[q];
+}
+
+// ---------------------------------------------------------- host engine
+struct HLevel {
+    int nx, ny, nz;
+    DevBuf<double> bx, by, bz, alpha, x, b;
+    DevBuf<float> bx32, by32, bz32, alpha32, x32, b32;
+    DevBuf<uint8_t> mask;
+};
+
+struct HProblem {
+    int L = 1, lc = 0;
+    bool var_beta = false, var_alpha = false, has_mask = false;
+    std::vector<HLevel> lv;
+    DevBuf<double> pcg;
+};
+
+struct HPlan {
+    DevBuf<int> ids, prefix;
+    int nd = 0, ntiles = 0;
+    std::vector<int> h_ids, h_prefix;
+    Plan dev() const { return Plan{ids.p, prefix.p, nd, ntiles}; }
+};
+
+struct Solver {
+    int nprob = 0, Lmax = 0, prec = VD_FP64;
+    std::vector<HProblem> probs;
+    DevBuf<LevDesc> d64, d32;
+    std::vector<LevDesc> h64, h32;
+    LevDesc *pin64 = nullptr, *pin32 = nullptr;   // pinned staging of the descriptors
+    DevBuf<ProbState> st;
+    ProbState *pin_st = nullptr;
+    DevBuf<double> partials;
+    DevBuf<FusedDesc> fused;
+    int nfused = 0;
+    DevBuf<int> prob_of;
+    HPlan all0;                                  // finest level, every problem
+    std::vector<HPlan> pre, restr, prolong;      // per level
+    std::vector<char> key;                       // problem bytes the descriptors were built from
+    ~Solver() {
+        if (pin64) (void)hipHostFree(pin64);
+        if (pin32) (void)hipHostFree(pin32);
+        if (pin_st) (void)hipHostFree(pin_st);
+    }
+};
+
+static void upload_plan(HPlan &pl, hipStream_t s) {
+    pl.nd = (int)pl.h_ids.size();
+    pl.ntiles = pl.h_prefix.empty() ? 0 : pl.h_prefix.back();
+    if (pl.nd == 0) return;
+    pl.ids.alloc(pl.nd);
+    pl.prefix.alloc(pl.nd + 1);
+    VD_HIP(hipMemcpyAsync(pl.ids.p, pl.h_ids.data(), sizeof(int) * pl.nd, hipMemcpyHostToDevice, s));
+    VD_HIP(hipMemcpyAsync(pl.prefix.p, pl.h_prefix.data(), sizeof(int) * (pl.nd + 1), hipMemcpyHostToDevice, s));
+    VD_HIP(hipStreamSynchronize(s));
+}
+
+static void plan_add(HPlan &pl, int id, long units, int per_tile) {
+    if (pl.h_prefix.empty()) pl.h_prefix.push_back(0);
+    pl.h_ids.push_back(id);
+    pl.h_prefix.push_back(pl.h_prefix.back() + ceil_div(units, per_tile));
+}
+
+static int count_levels(const vd_grid &g, int requested) {
+    if (requested > 0) {
+        int nx = g.nx, ny = g.ny, nz = g.nz;
+        for (int l = 1; l < requested; l++) {
+            if (nx % 2 || ny % 2 || nz % 2) return -1;
+            nx /= 2; ny /= 2; nz /= 2;
+        }
+        return requested;
+    }
+    int nl = 1, nx = g.nx, ny = g.ny, nz = g.nz;
+    while (nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx > 4 && ny > 4 && nz > 4) {
+        nx /= 2; ny /= 2; nz /= 2; nl++;
+    }
+    return nl;
+}
+
+static void validate(int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    VD_CHECK(nprob >= 1, "nprob must be >= 1");
+    VD_CHECK(probs != nullptr && o != nullptr, "null problems or options");
+    VD_CHECK(o->precision == VD_FP64 || o->precision == VD_FP32_IR, "unknown precision");
+    VD_CHECK(o->nu_pre >= 0 && o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1, "need at least one smoothing sweep");
+    VD_CHECK(o->max_cycles >= 0 && o->fixed_cycles >= 0, "negative cycle counts");
+    VD_CHECK(o->guess == VD_GUESS_GIVEN || o->guess == VD_GUESS_ZERO, "guess must be GIVEN or ZERO here");
+    VD_CHECK(o->precision == VD_FP64 || o->ir_inner >= 1, "ir_inner must be >= 1");
+    for (int p = 0; p < nprob; p++) {
+        const vd_problem &P = probs[p];
+        const vd_grid &g = P.grid;
+        VD_CHECK(g.nx >= 1 && g.ny >= 1 && g.nz >= 1, "grid dimensions must be positive");
+        VD_CHECK((long)g.nx * g.ny * g.nz < (1L << 31) / 2, "grid too large");
+        VD_CHECK(g.dx > 0 && g.dy > 0 && g.dz > 0, "mesh spacing must be positive");
+        for (int d = 0; d < 3; d++) {
+            int a = P.bc.kind[2 * d], b = P.bc.kind[2 * d + 1];
+            VD_CHECK(a >= 0 && a <= 3 && b >= 0 && b <= 3, "unknown boundary kind");
+            VD_CHECK((a == VD_BC_PERIODIC) == (b == VD_BC_PERIODIC), "periodic must be set on both faces of a direction");
+        }
+        VD_CHECK(P.rhs != nullptr && P.x != nullptr, "rhs and x are required");
+        VD_CHECK(count_levels(g, o->n_levels) >= 1, "n_levels not compatible with the grid (dimensions must stay even)");
+        bool dir = false;
+        for (int f = 0; f < 6; f++) dir = dir || P.bc.kind[f] == VD_BC_DIRICHLET;
+        if (!P.alpha && P.alpha_c == 0.0 && !P.mask && !dir)
+            throw Error{VD_ESINGULAR, "singular operator: alpha = 0, no Dirichlet face and no mask (problem " +
+                                          std::to_string(p) + ")"};
+    }
+}
+
+static std::vector<char> problem_key(int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    std::vector<char> k(sizeof(vd_problem) * nprob + sizeof(int) * 3);
+    memcpy(k.data(), probs, sizeof(vd_problem) * nprob);
+    int extra[3] = {o->precision, o->n_levels, nprob};
+    memcpy(k.data() + sizeof(vd_problem) * nprob, extra, sizeof(extra));
+    return k;
+}
+
+static std::string shape_key(int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    std::string s = "mg:" + std::to_string(o->precision) + ":" + std::to_string(o->n_levels) + ":";
+    for (int p = 0; p < nprob; p++) {
+        const vd_problem &P = probs[p];
+        char buf[160];
+        snprintf(buf, sizeof buf, "%d,%d,%d,%d%d%d;", P.grid.nx, P.grid.ny, P.grid.nz, P.beta != nullptr,
+                 P.alpha != nullptr, P.mask != nullptr);
+        s += buf;
+        for (int f = 0; f < 6; f++) s += std::to_string(P.bc.kind[f]);
+    }
+    return s;
+}
+
+static LevDesc make_desc(const HProblem &H, const vd_problem &P, int l, int prob, bool fp32) {
+    const HLevel &V = H.lv[l];
+    LevDesc D;
+    memset(&D, 0, sizeof(D));
+    D.nx = V.nx; D.ny = V.ny; D.nz = V.nz;
+    D.nxy = V.nx * V.ny;
+    D.ncell = V.nx * V.ny * V.nz;
+    for (int f = 0; f < 6; f++) { D.kind[f] = P.bc.kind[f]; D.gval[f] = P.bc.value[f]; }
+    D.var_beta = H.var_beta; D.var_alpha = H.var_alpha; D.has_mask = H.has_mask;
+    D.lift = (l == 0 && !fp32) ? 1 : 0;
+    D.prob = prob;
+    // spacing from the problem of this call (a cached hierarchy is shared by
+    // every problem of the same shape, whatever its mesh spacing)
+    const double dx = P.grid.dx * (double)(1 << l), dy = P.grid.dy * (double)(1 << l), dz = P.grid.dz * (double)(1 << l);
+    D.idx2 = 1.0 / (dx * dx); D.idy2 = 1.0 / (dy * dy); D.idz2 = 1.0 / (dz * dz);
+    D.beta_c = P.beta_c; D.alpha_c = P.alpha_c;
+    D.bx = V.bx.p; D.by = V.by.p; D.bz = V.bz.p;
+    D.alpha = (l == 0) ? P.alpha : V.alpha.p;
+    D.bx32 = V.bx32.p; D.by32 = V.by32.p; D.bz32 = V.bz32.p; D.alpha32 = V.alpha32.p;
+    D.mask = (l == 0) ? P.mask : V.mask.p;
+    if (fp32) { D.x = V.x32.p; D.b = V.b32.p; }
+    else if (l == 0) { D.x = P.x; D.b = P.rhs; }
+    else { D.x = V.x.p; D.b = V.b.p; }
+    return D;
+}
+
+static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    auto S = std::make_shared<Solver>();
+    S->nprob = nprob;
+    S->prec = o->precision;
+    bool ir = o->precision == VD_FP32_IR;
+    S->probs.resize(nprob);
+    for (int p = 0; p < nprob; p++) {
+        HProblem &H = S->probs[p];
+        const vd_problem &P = probs[p];
+        H.L = count_levels(P.grid, o->n_levels);
+        H.var_beta = P.beta != nullptr;
+        H.var_alpha = P.alpha != nullptr;
+        H.has_mask = P.mask != nullptr;
+        H.lv.resize(H.L);
+        for (int l = 0; l < H.L; l++) {
+            HLevel &V = H.lv[l];
+            V.nx = P.grid.nx >> l; V.ny = P.grid.ny >> l; V.nz = P.grid.nz >> l;
+            long n = (long)V.nx * V.ny * V.nz;
+            if (H.var_beta) {
+                V.bx.alloc((size_t)(V.nx + 1) * V.ny * V.nz);
+                V.by.alloc((size_t)V.nx * (V.ny + 1) * V.nz);
+                V.bz.alloc((size_t)V.nx * V.ny * (V.nz + 1));
+                if (ir) { V.bx32.alloc(V.bx.n); V.by32.alloc(V.by.n); V.bz32.alloc(V.bz.n); }
+            }
+            if (H.var_alpha) {
+                if (l > 0) V.alpha.alloc(n);
+                if (ir) V.alpha32.alloc(n);
+            }
+            if (H.has_mask && l > 0) V.mask.alloc(n);
+            if (l > 0) { V.x.alloc(n); V.b.alloc(n); }
+            if (ir) { V.x32.alloc(n); V.b32.alloc(n); }
+        }
+        H.lc = H.L == 1 ? (((long)H.lv[0].nx * H.lv[0].ny * H.lv[0].nz <= kCoarseMax) ? 0 : 1) : H.L - 1;
+        for (int l = 0; l < H.L - 1; l++)
+            if ((long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz <= kCoarseMax) { H.lc = l; break; }
+        if (H.L >= 2) {
+            const HLevel &B = H.lv[H.L - 1];
+            H.pcg.alloc((size_t)6 * B.nx * B.ny * B.nz);
+        }
+        S->Lmax = std::max(S->Lmax, H.L);
+    }
+    int Lmax = S->Lmax;
+    S->h64.assign((size_t)nprob * Lmax, LevDesc{});
+    S->h32.assign((size_t)nprob * Lmax, LevDesc{});
+    S->d64.alloc(S->h64.size());
+    if (ir) S->d32.alloc(S->h32.size());
+    VD_HIP(hipHostMalloc((void **)&S->pin64, sizeof(LevDesc) * S->h64.size(), hipHostMallocDefault));
+    if (ir) VD_HIP(hipHostMalloc((void **)&S->pin32, sizeof(LevDesc) * S->h32.size(), hipHostMallocDefault));
+    S->st.alloc(nprob);
+    VD_HIP(hipHostMalloc((void **)&S->pin_st, sizeof(ProbState) * nprob, hipHostMallocDefault));
+    // plans
+    S->pre.resize(Lmax);
+    S->restr.resize(Lmax);
+    S->prolong.resize(Lmax);
+    std::vector<FusedDesc> fds;
+    std::vector<int> prob_of;
+    for (int p = 0; p < nprob; p++) {
+        HProblem &H = S->probs[p];
+        int base = p * Lmax;
+        long n0 = (long)H.lv[0].nx * H.lv[0].ny * H.lv[0].nz;
+        plan_add(S->all0, base, n0, kBlock);
+        prob_of.push_back(p);
+        for (int l = 0; l < H.lc; l++) {
+            long n = (long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz;
+            plan_add(S->pre[l], base + l, (H.lv[l].nx % 2 == 0) ? (n + 1) / 2 : n, kBlock);
+            if (H.L >= 2) {
+                long nc = (long)H.lv[l + 1].nx * H.lv[l + 1].ny * H.lv[l + 1].nz;
+                plan_add(S->restr[l], base + l + 1, nc, kBlock);
+                plan_add(S->prolong[l], base + l, n, kBlock);
+            }
+        }
+        if (H.lc < H.L) fds.push_back(FusedDesc{p, H.lc, H.L, base, H.pcg.p});
+    }
+    upload_plan(S->all0, ctx->stream);
+    for (int l = 0; l < Lmax; l++) {
+        upload_plan(S->pre[l], ctx->stream);
+        upload_plan(S->restr[l], ctx->stream);
+        upload_plan(S->prolong[l], ctx->stream);
+    }
+    S->partials.alloc(std::max(1, S->all0.ntiles));
+    S->nfused = (int)fds.size();
+    if (S->nfused) {
+        S->fused.alloc(fds.size());
+        VD_HIP(hipMemcpyAsync(S->fused.p, fds.data(), sizeof(FusedDesc) * fds.size(), hipMemcpyHostToDevice, ctx->stream));
+    }
+    S->prob_of.alloc(nprob);
+    VD_HIP(hipMemcpyAsync(S->prob_of.p, prob_of.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, ctx->stream));
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    return S;
+}
+
+static void refresh_descs(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    auto key = problem_key(nprob, probs, o);
+    if (key == S.key) return;
+    bool ir = S.prec == VD_FP32_IR;
+    for (int p = 0; p < nprob; p++)
+        for (int l = 0; l < S.probs[p].L; l++) {
+            S.h64[(size_t)p * S.Lmax + l] = make_desc(S.probs[p], probs[p], l, p, false);
+            if (ir) S.h32[(size_t)p * S.Lmax + l] = make_desc(S.probs[p], probs[p], l, p, true);
+        }
+    // the stream may still read the pinned staging of a previous call
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    memcpy(S.pin64, S.h64.data(), sizeof(LevDesc) * S.h64.size());
+    VD_HIP(hipMemcpyAsync(S.d64.p, S.pin64, sizeof(LevDesc) * S.h64.size(), hipMemcpyHostToDevice, ctx->stream));
+    if (ir) {
+        memcpy(S.pin32, S.h32.data(), sizeof(LevDesc) * S.h32.size());
+        VD_HIP(hipMemcpyAsync(S.d32.p, S.pin32, sizeof(LevDesc) * S.h32.size(), hipMemcpyHostToDevice, ctx->stream));
+    }
+    S.key = std::move(key);
+}
+
+// Coefficients of every level from the user's arrays (values may change
+// between calls with the same pointers, so this runs on every solve).
+static void setup_coefficients(vd_ctx *ctx, Solver &S, const vd_problem *probs) {
+    bool ir = S.prec == VD_FP32_IR;
+    hipStream_t s = ctx->stream;
+    for (int p = 0; p < S.nprob; p++) {
+        HProblem &H = S.probs[p];
+        const vd_problem &P = probs[p];
+        HLevel &V0 = H.lv[0];
+        long n0 = (long)V0.nx * V0.ny * V0.nz;
+        if (H.var_beta) {
+            long nf = (long)(V0.nx + 1) * V0.ny * V0.nz + (long)V0.nx * (V0.ny + 1) * V0.nz + (long)V0.nx * V0.ny * (V0.nz + 1);
+            timed(ctx, "setup", 0.0, [&] {
+                k_faces0<<<ceil_div(nf, kBlock), kBlock, 0, s>>>(P.beta, V0.nx, V0.ny, V0.nz, P.bc.kind[0] == VD_BC_PERIODIC,
+                                                                  P.bc.kind[2] == VD_BC_PERIODIC, P.bc.kind[4] == VD_BC_PERIODIC,
+                                                                  V0.bx.p, V0.by.p, V0.bz.p, V0.bx32.p, V0.by32.p, V0.bz32.p);
+            });
+        }
+        if (H.var_alpha && ir)
+            timed(ctx, "setup", 0.0, [&] { k_to_f32<<<ceil_div(n0, kBlock), kBlock, 0, s>>>(P.alpha, V0.alpha32.p, n0); });
+        if (!(H.var_beta || H.var_alpha || H.has_mask)) continue;
+        for (int l = 1; l < H.L; l++) {
+            HLevel &V = H.lv[l];
+            const LevDesc &F = S.h64[(size_t)p * S.Lmax + l - 1];
+            const LevDesc &C = S.h64[(size_t)p * S.Lmax + l];
+            long nf = H.var_beta ? ((long)(V.nx + 1) * V.ny * V.nz + (long)V.nx * (V.ny + 1) * V.nz + (long)V.nx * V.ny * (V.nz + 1)) : 0;
+            long tot = nf + (long)V.nx * V.ny * V.nz;
+            timed(ctx, "setup", 0.0, [&] {
+                k_coarsen<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(F, C, V.bx.p, V.by.p, V.bz.p, V.alpha.p, V.mask.p, V.bx32.p,
+                                                                    V.by32.p, V.bz32.p, V.alpha32.p);
+            });
+        }
+    }
+}
+
+template <typename T>
+static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o) {
+    hipStream_t s = ctx->stream;
+    const ProbState *st = S.st.p;
+    for (int l = 0; l < S.Lmax; l++) {
+        const HPlan &pp = S.pre[l];
+        if (pp.nd) {
+            for (int q = 0; q < o->nu_pre; q++)
+                for (int col = 0; col < 2; col++)
+                    timed(ctx, "gsrb", (double)pp.ntiles, [&] {
+                        k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, st);
+                    });
+        }
+        const HPlan &pr = S.restr[l];
+        if (pr.nd)
+            timed(ctx, "resid_restrict", (double)pr.ntiles, [&] {
+                k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st);
+            });
+    }
+    if (S.nfused)
+        timed(ctx, "coarse", 0.0, [&] {
+            k_coarse<T><<<S.nfused, kFusedThreads, 0, s>>>(dT, S.d64.p, S.fused.p, st, o->nu_pre, o->nu_post);
+        });
+    for (int l = S.Lmax - 1; l >= 0; l--) {
+        const HPlan &pp = S.prolong[l];
+        if (pp.nd)
+            timed(ctx, "prolong", (double)pp.ntiles, [&] {
+                k_prolong<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), st);
+            });
+        const HPlan &ps = S.pre[l];
+        if (ps.nd) {
+            for (int q = 0; q < o->nu_post; q++)
+                for (int col = 0; col < 2; col++)
+                    timed(ctx, "gsrb", (double)ps.ntiles, [&] {
+                        k_gsrb<T><<<xcd_grid(ps.ntiles), kBlock, 0, s>>>(dT, ps.dev(), col, st);
+                    });
+        }
+    }
+}
+
+static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
+    const HPlan &pl = S.all0;
+    hipStream_t s = ctx->stream;
+    timed(ctx, "norm", (double)pl.ntiles, [&] {
+        if (mode == 0)
+            k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+        else if (mode == 1)
+            k_norm<1><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+        else
+            k_norm<2><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+    });
+}
+
+static void launch_finalize(vd_ctx *ctx, Solver &S, int mode, const vd_mg_opts *o, int inner) {
+    timed(ctx, "finalize", 0.0, [&] {
+        k_finalize<<<S.nprob, kBlock, 0, ctx->stream>>>(S.all0.dev(), S.prob_of.p, S.partials.p, S.st.p, mode, o->rtol,
+                                                        o->max_cycles, o->fixed_cycles, inner);
+    });
+}
+
+static int read_active(vd_ctx *ctx, Solver &S) {
+    VD_HIP(hipMemcpyAsync(S.pin_st, S.st.p, sizeof(ProbState) * S.nprob, hipMemcpyDeviceToHost, ctx->stream));
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    int n = 0;
+    for (int p = 0; p < S.nprob; p++) n += S.pin_st[p].active;
+    return n;
+}
+
+// Full solve of a batch (the engine behind vd_poisson_solve,
+// vd_helmholtz_solve_batched and the implicit solves of vd_step).
+vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                         const char *cache_tag) {
+    validate(nprob, probs, o);
+    std::string key = std::string(cache_tag ? cache_tag : "") + shape_key(nprob, probs, o);
+    std::shared_ptr<Solver> S;
+    auto it = ctx->cache.find(key);
+    if (it != ctx->cache.end()) S = std::static_pointer_cast<Solver>(it->second);
+    else {
+        S = build_solver(ctx, nprob, probs, o);
+        ctx->cache[key] = S;
+    }
+    refresh_descs(ctx, *S, nprob, probs, o);
+    setup_coefficients(ctx, *S, probs);
+    hipStream_t s = ctx->stream;
+    k_state_init<<<ceil_div(nprob, 64), 64, 0, s>>>(S->st.p, nprob);
+    VD_HIP(hipGetLastError());
+    launch_norm(ctx, *S, 0, 0);
+    launch_finalize(ctx, *S, 0, o, 0);
+    timed(ctx, "prep", 0.0, [&] {
+        k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO);
+    });
+    const bool ir = S->prec == VD_FP32_IR;
+    const bool async_fixed = o->fixed_cycles > 0 && infos == nullptr;
+    int iters = 0;
+    const int chunk = async_fixed ? (o->fixed_cycles + 1) : 2;
+    while (true) {
+        for (int c = 0; c < chunk; c++) {
+            if (!ir) {
+                launch_norm(ctx, *S, 1, 1);
+                launch_finalize(ctx, *S, 1, o, 1);
+                if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
+                vcycle<double>(ctx, *S, S->d64.p, o);
+            } else {
+                launch_norm(ctx, *S, 2, 1);
+                launch_finalize(ctx, *S, 1, o, o->ir_inner);
+                if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
+                for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, *S, S->d32.p, o);
+                timed(ctx, "ir_update", 0.0, [&] {
+                    k_ir_update<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->d32.p, S->all0.dev(), S->st.p);
+                });
+            }
+            iters++;
+        }
+        if (async_fixed) break;
+        if (read_active(ctx, *S) == 0) break;
+        if (iters > 4 * (o->max_cycles + 2) + 8) throw Error{VD_ENOCONV, "internal: convergence loop did not terminate"};
+    }
+    vd_status worst = VD_OK;
+    if (infos) {
+        for (int p = 0; p < nprob; p++) {
+            const ProbState &q = S->pin_st[p];
+            vd_solve_info &I = infos[p];
+            memset(&I, 0, sizeof(I));
+            I.cycles = q.cycles;
+            I.outer_iters = q.outer;
+            I.levels = S->probs[p].L;
+            I.status = q.status;
+            I.rel_res = q.rel;
+            I.rel_res0 = q.rel0;
+            I.bnorm = q.bnorm;
+            if (q.status != VD_OK) worst = (vd_status)q.status;
+        }
+    } else if (!async_fixed) {
+        for (int p = 0; p < nprob; p++)
+            if (S->pin_st[p].status != VD_OK) worst = (vd_status)S->pin_st[p].status;
+    }
+    if (worst != VD_OK) throw Error{worst, "multigrid did not converge (non-finite residual or max_cycles reached)"};
+    return VD_OK;
+}
+
+// ------------------------------------------------ inspection entry points
+__global__ void __launch_bounds__(kBlock) k_flags(const LevDesc *__restrict__ descs, int id, uint8_t *out) {
+    const LevDesc &L = descs[id];
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.ncell) return;
+    int i, j, k;
+    cell_ijk(L, c, i, j, k);
+    uint8_t fl = (uint8_t)((i + j + k) & 1);
+    if (!(L.has_mask && !L.mask[c])) {
+        fl |= 2;
+        const int nx = L.nx, ny = L.ny, nz = L.nz;
+        int pos[6] = {i, i, j, j, k, k};
+        int lim[6] = {0, nx - 1, 0, ny - 1, 0, nz - 1};
+        int step[6] = {-1, 1, -nx, nx, -L.nxy, L.nxy};
+        int wrap[6] = {nx - 1, -(nx - 1), nx * (ny - 1), -nx * (ny - 1), L.nxy * (nz - 1), -L.nxy * (nz - 1)};
+        for (int f = 0; f < 6; f++) {
+            bool inside = pos[f] != lim[f];
+            bool closed;
+            if (inside || L.kind[f] == VD_BC_PERIODIC) {
+                int nb = c + (inside ? step[f] : wrap[f]);
+                closed = L.has_mask && !L.mask[nb];
+            } else {
+                closed = true;
+            }
+            if (closed) fl |= (uint8_t)(1 << (2 + f));
+        }
+    }
+    out[c] = fl;
+}
+
+__global__ void __launch_bounds__(kBlock) k_smooth_colour(const LevDesc *__restrict__ descs, int id, int colour) {
+    const LevDesc &L = descs[id];
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.ncell) return;
+    int i, j, k;
+    cell_ijk(L, c, i, j, k);
+    if (((i + j + k) & 1) != colour) return;
+    gs_update<double>(L, c, i, j, k);
+}
+
+vd_status mg_cell_flags(vd_ctx *ctx, const vd_problem *prob, int n_levels, int level, uint8_t *out) {
+    VD_CHECK(prob && out, "null argument");
+    vd_mg_opts o{};
+    o.rtol = 1e-10; o.max_cycles = 1; o.nu_pre = 1; o.n_levels = n_levels; o.precision = VD_FP64;
+    vd_problem P = *prob;
+    double dummy_ptr = 0;  // rhs/x are not touched by the flag kernel
+    if (!P.rhs) P.rhs = &dummy_ptr;
+    if (!P.x) P.x = &dummy_ptr;
+    validate(1, &P, &o);
+    int L = count_levels(P.grid, n_levels);
+    VD_CHECK(level >= 0 && level < L, "level out of range");
+    std::string key = "flags" + shape_key(1, &P, &o);
+    auto S = build_solver(ctx, 1, &P, &o);
+    refresh_descs(ctx, *S, 1, &P, &o);
+    setup_coefficients(ctx, *S, &P);
+    const LevDesc &D = S->h64[level];
+    k_flags<<<ceil_div(D.ncell, kBlock), kBlock, 0, ctx->stream>>>(S->d64.p, level, out);
+    VD_HIP(hipGetLastError());
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    return VD_OK;
+}
+
+vd_status mg_smooth(vd_ctx *ctx, const vd_problem *prob, int ncolour) {
+    VD_CHECK(prob && ncolour >= 0, "bad argument");
+    vd_mg_opts o{};
+    o.rtol = 1e-10; o.max_cycles = 1; o.nu_pre = 1; o.n_levels = 1; o.precision = VD_FP64;
+    validate(1, prob, &o);
+    auto S = build_solver(ctx, 1, prob, &o);
+    refresh_descs(ctx, *S, 1, prob, &o);
+    setup_coefficients(ctx, *S, prob);
+    const LevDesc &D = S->h64[0];
+    for (int q = 0; q < ncolour; q++) {
+        k_smooth_colour<<<ceil_div(D.ncell, kBlock), kBlock, 0, ctx->stream>>>(S->d64.p, 0, q & 1);
+        VD_HIP(hipGetLastError());
+    }
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    return VD_OK;
+}
+
+}  // namespace vd

@@ -1,0 +1,528 @@
+// Explicit terms of the semi-implicit step: electric field and transport,
+// WENO5 drift-flux divergence with wall fluxes, chemical sources, Poisson
+// charge density.  FP64 throughout (the rate polynomials cancel
+// catastrophically in lower precision).
+#include "vd_internal.hpp"
+#include "physics.hpp"
+
+namespace vd {
+
+// ----------------------------------------------------- electric field
+// E along direction d at the face between row positions p-1 and p (face
+// index p in 0..n): interior -(phi_R - phi_L)/h; Dirichlet face with value
+// g: one-sided over half a cell; Neumann/wall: 0; periodic: wrapped.
+__device__ __forceinline__ double e_face(const GridDev &G, const double *__restrict__ phi, int d, int c, int pos, int fidx) {
+    const int n = G.n[d];
+    const long st = G.stride[d];
+    const double ih = G.ih[d];
+    const long c0 = c - (long)pos * st;     // index of row position 0
+    if (fidx > 0 && fidx < n) return -(phi[c0 + fidx * st] - phi[c0 + (fidx - 1) * st]) * ih;
+    const int f = 2 * d + (fidx == 0 ? 0 : 1);
+    const int kind = G.phi_kind[f];
+    if (kind == VD_BC_PERIODIC) return -(phi[c0] - phi[c0 + (n - 1) * st]) * ih;
+    if (kind == VD_BC_DIRICHLET) {
+        const double g = G.phi_val[f];
+        if (fidx == 0) return -(phi[c0] - g) * (2.0 * ih);
+        return -(g - phi[c0 + (n - 1) * st]) * (2.0 * ih);
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ void e_cell(const GridDev &G, const double *__restrict__ phi, int c, const int pos[3], double E[3]) {
+    for (int d = 0; d < 3; d++) E[d] = 0.5 * (e_face(G, phi, d, c, pos[d], pos[d]) + e_face(G, phi, d, c, pos[d], pos[d] + 1));
+}
+
+constexpr double kTd = 1e-21;
+constexpr double kENFloor = 1e-3;     // reduced-field floor before the log
+
+__device__ __forceinline__ double mu_electron(double en_td, double N) {
+    double en = en_td < kENFloor ? kENFloor : en_td;
+    return exp(0.05481 - 2.911 * tanh(0.289 * log(en) + 0.543)) * (1.1296e25 / N);
+}
+
+__device__ __forceinline__ double te_lfa(const double *__restrict__ tab, int npts, double ln_min, double ln_max, double en_td) {
+    double en = en_td < kENFloor ? kENFloor : en_td;
+    double x = log(en);
+    if (x <= ln_min) return tab[0];
+    if (x >= ln_max) return tab[npts - 1];
+    double t = (x - ln_min) / ((ln_max - ln_min) / (double)(npts - 1));
+    int i0 = (int)floor(t);
+    i0 = i0 > npts - 2 ? npts - 2 : (i0 < 0 ? 0 : i0);
+    double w = t - (double)i0;
+    return (1.0 - w) * tab[i0] + w * tab[i0 + 1];
+}
+
+// Per cell: E/N, Te (fixed / table / from the electron energy) and, for the
+// species with a field-dependent mobility, signed mu and D.
+__global__ void __launch_bounds__(kBlock) k_transport(TransportArgs a) {
+    const GridDev &G = a.g;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell) return;
+    int pos[3];
+    pos[2] = c / G.nxy;
+    int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    double E[3];
+    e_cell(G, a.phi, c, pos, E);
+    double en = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]) / a.N_gas / kTd;
+    double Te;
+    if (a.te_mode == VD_TE_LFA) {
+        Te = te_lfa(a.lfa, a.lfa_n, a.lfa_ln_min, a.lfa_ln_max, en);
+        a.Te[c] = Te;
+    } else if (a.te_mode == VD_TE_ENERGY) {
+        double ne = a.ne[c];
+        double t = ne > 0.0 ? a.Ee[c] / (1.5 * ne * a.kB) : a.Tg;
+        Te = ne > 0.0 ? (t < a.Tg ? a.Tg : (t > a.Te_max ? a.Te_max : t)) : a.Tg;
+        a.Te[c] = Te;
+    } else {
+        Te = a.Te[c];
+    }
+    for (int v = 0; v < a.nvar; v++) {
+        double m = mu_electron(en, a.N_gas);
+        a.mu[(long)v * G.ncell + c] = a.var_sign[v] * m;
+        double D = m * a.kB * Te / a.qe;
+        a.D[(long)v * G.ncell + c] = D;
+        if (a.beta_e && v == a.e_var) a.beta_e[c] = 5.0 / 3.0 * D;
+    }
+}
+
+// ------------------------------------------------------------- WENO5
+// Jiang-Shu WENO5 value at the right face of the middle cell of
+// (a, b, c, d, e), epsilon 1e-6, power 2.  The normalised weights
+// alpha_k / sum(alpha) are evaluated with a single division by clearing the
+// three denominators (algebraically identical).
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+    const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+    const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, u1 = b - d;
+    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+    const double s0 = 1e-6 + (13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0;
+    const double s1 = 1e-6 + (13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1;
+    const double s2 = 1e-6 + (13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2;
+    const double p0 = s0 * s0, p1 = s1 * s1, p2 = s2 * s2;
+    const double w0 = 0.1 * (p1 * p2), w1 = 0.6 * (p0 * p2), w2 = 0.3 * (p0 * p1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// value of field u at row position p along d (may be up to 3 outside):
+// mirror at Neumann/wall faces, odd reflection about g at Dirichlet faces,
+// wrap at periodic faces
+__device__ __forceinline__ double u_at(const GridDev &G, const int *kind, const double *gval, const double *__restrict__ u,
+                                       int d, long c0, int p) {
+    const int n = G.n[d];
+    const long st = G.stride[d];
+    if (p >= 0 && p < n) return u[c0 + p * st];
+    const int f = 2 * d + (p < 0 ? 0 : 1);
+    const int kd = kind[f];
+    if (kd == VD_BC_PERIODIC) return u[c0 + (p < 0 ? p + n : p - n) * st];
+    const int q = p < 0 ? -1 - p : 2 * n - 1 - p;
+    const double v = u[c0 + q * st];
+    return kd == VD_BC_DIRICHLET ? 2.0 * gval[f] - v : v;
+}
+
+__device__ __forceinline__ double wall_flux(int wk, double uc, double mu, double e_n, double Te, double Tg, double mass,
+                                            double kB, double me) {
+    switch (wk) {
+    case VD_WALL_ELECTRON: return uc * 0.25 * sqrt(8.0 * kB * Te / (M_PI * me));
+    case VD_WALL_ION: { double f = mu * uc * e_n; return f > 0.0 ? f : 0.0; }
+    case VD_WALL_NEUTRAL: return uc * 0.25 * sqrt(8.0 * kB * Tg / (M_PI * mass));
+    default: return 0.0;
+    }
+}
+
+// Drift flux along +d at a non-wall face fidx of the row through c: face
+// velocity mu_f E_f (mu_f the mean of the two cells, the boundary cell's on
+// a domain face) times the upwind WENO5 value.
+__device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &F, const double *__restrict__ phi, int d, int c,
+                                             int pos, int fidx) {
+    const int n = G.n[d];
+    const long st = G.stride[d];
+    const long c0 = c - (long)pos * st;
+    const bool boundary = (fidx == 0 || fidx == n);
+    const int kd = F.kind[2 * d + (fidx == 0 ? 0 : 1)];
+    const double *__restrict__ u = F.u;
+    const double Ef = e_face(G, phi, d, c, pos, fidx);
+    double muf;
+    if (F.mu) {
+        const int pl = fidx - 1, pr = fidx;
+        if (boundary && kd != VD_BC_PERIODIC) muf = fidx == 0 ? F.mu[c0] : F.mu[c0 + (n - 1) * st];
+        else {
+            const int ql = pl < 0 ? pl + n : pl, qr = pr >= n ? pr - n : pr;
+            muf = 0.5 * (F.mu[c0 + ql * st] + F.mu[c0 + qr * st]);
+        }
+    } else {
+        muf = F.mu_c;
+    }
+    const double v = muf * F.mu_scale * Ef;
+    if (v == 0.0) return 0.0;
+    double s0, s1, s2, s3, s4;
+    if (v > 0.0) {
+        const int b = fidx - 3;
+        s0 = u_at(G, F.kind, F.gval, u, d, c0, b);
+        s1 = u_at(G, F.kind, F.gval, u, d, c0, b + 1);
+        s2 = u_at(G, F.kind, F.gval, u, d, c0, b + 2);
+        s3 = u_at(G, F.kind, F.gval, u, d, c0, b + 3);
+        s4 = u_at(G, F.kind, F.gval, u, d, c0, b + 4);
+    } else {
+        const int b = fidx + 2;
+        s0 = u_at(G, F.kind, F.gval, u, d, c0, b);
+        s1 = u_at(G, F.kind, F.gval, u, d, c0, b - 1);
+        s2 = u_at(G, F.kind, F.gval, u, d, c0, b - 2);
+        s3 = u_at(G, F.kind, F.gval, u, d, c0, b - 3);
+        s4 = u_at(G, F.kind, F.gval, u, d, c0, b - 4);
+    }
+    return v * weno5(s0, s1, s2, s3, s4);
+}
+
+// Drift-flux divergence of one field at cell c (faces x-, x+, y-, y+, z-, z+).
+__device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const double *__restrict__ phi,
+                                 const double *__restrict__ Te, double Tg, double kB, double me, int c, const int pos[3]) {
+    double total = 0.0;
+    const double *__restrict__ u = F.u;
+    for (int d = 0; d < 3; d++) {
+        const int n = G.n[d];
+        double Fs[2];
+        for (int side = 0; side < 2; side++) {
+            const int fidx = pos[d] + side;
+            const bool boundary = (fidx == 0 || fidx == n);
+            const int kd = F.kind[2 * d + side];
+            if (boundary && kd == VD_BC_NEUMANN) { Fs[side] = 0.0; continue; }
+            const double Ef = e_face(G, phi, d, c, pos[d], fidx);
+            if (boundary && kd == VD_BC_WALLFLUX) {
+                const double e_n = fidx == 0 ? -Ef : Ef;
+                double fl;
+                if (F.ne_wall) {
+                    fl = 2.0 * kB * Te[c] * wall_flux(VD_WALL_ELECTRON, F.ne_wall[c], 0.0, e_n, Te[c], Tg, me, kB, me);
+                } else {
+                    const double muc = F.mu ? F.mu[c] : F.mu_c;
+                    fl = wall_flux(F.wall, u[c], muc, e_n, Te[c], Tg, F.mass, kB, me);
+                }
+                Fs[side] = fidx == 0 ? -fl : fl;
+                continue;
+            }
+            Fs[side] = face_drift(G, F, phi, d, c, pos[d], fidx);
+        }
+        total += (Fs[1] - Fs[0]) * G.ihl[d];
+    }
+    return total;
+}
+
+// blockIdx.y = field.  mode 0: out = div.  mode 1 (species / energy
+// right-hand side of the implicit solve): out = u0/dt - div + src + extra.
+__global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
+    const GridDev &G = a.g;
+    const FieldDesc &F = a.f[blockIdx.y];
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell) return;
+    int pos[3];
+    pos[2] = c / G.nxy;
+    int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    double div = drift_div_cell(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, c, pos);
+    if (a.mode == 0) {
+        F.out[c] = div;
+    } else {
+        double v = F.u0[c] * a.inv_dt - div;
+        if (F.src) v += F.src[c];
+        if (F.extra) v += F.extra[c];
+        F.out[c] = v;
+    }
+}
+
+// ------------------------------------------------------------ chemistry
+constexpr double kEvK = 11604.518;
+
+// Ar-H2 mechanism, Tables A.1-A.3 (species e, Ar+, Ar2+, H+, H2+, H3+, ArH+,
+// Ar*, Ar2*, H2(v1), H2(v2), H2(v3), H, Ar, H2).  R6 read as an ionization
+// (Ar2+ + 2e), R11 as 2 Ar2* -> Ar2+ + 2 Ar + e, R24-R26 with Te in eV.
+enum { SE = 0, SARP, SAR2P, SHP, SH2P, SH3P, SARHP, SARS, SAR2S, SH2V1, SH2V2, SH2V3, SH, SAR, SH2 };
+
+__device__ __forceinline__ double vib(double L, double c0, double c1, double c2, double c3, double c4, double c5,
+                                      double c6, double c7, double c8) {
+    return exp(c0 + L * (c1 + L * (c2 + L * (c3 + L * (c4 + L * (c5 + L * (c6 + L * (c7 + L * c8))))))));
+}
+
+// rates of the 33 reactions at Te (K); units m^3/s, m^6/s, 1/s
+__device__ void rates_arh2(double T, double k[33]) {
+    const double Tev = T / kEvK, eps = 1.5 * Tev;
+    const double ie = 1.0 / eps, it = 1.0 / T, iv = 1.0 / Tev;
+    const double lT = log(T), lv = log(Tev);
+    k[0] = exp(-37.44 + 1.407 * log(eps) + ie * (50.34 + ie * (-348.6 - 230.5 * ie)));
+    k[1] = exp(14.37 - 8.641 * log(eps) + ie * (-622.9 + ie * (5341.0 - 0.1862e5 * ie)));
+    k[2] = exp(-29.7 + it * (1.39e5 + it * (-3.34e10 + it * (3.38e15 + it * (-1.85e20 + it * (5.08e24 - 5.5e28 * it))))));
+    k[3] = 5.0e-16;
+    k[4] = exp(-4.82e4 * it - 32.46);
+    k[5] = 1.29e-16 * exp(0.7 * lT - 0.4245e5 * it);
+    k[6] = 1e-13;
+    k[7] = 1.14e-44;
+    k[8] = 2.5e-43;
+    k[9] = 6e7;
+    k[10] = 5e-16;
+    k[11] = 43e-18 * exp(-0.5 * lT);
+    k[12] = 9.75e-21 * exp(-4.5 * lT);
+    k[13] = 25.9e-12 * exp(-0.66 * lT);
+    k[14] = 8.4e-14 * exp(-0.45 * lv - 11.18 * iv);
+    k[15] = 1.1e-14 * exp(0.29 * lv - 15.28 * iv);
+    k[16] = 2.3e-14 * exp(0.19 * lv - 17.87 * iv);
+    k[17] = 9.4e-16 * exp(0.45 * lv - 29.94 * iv);
+    k[18] = 1.5e-13 * exp(-1.97 * iv);
+    k[19] = 2.8e-15 * exp(0.48 * lv);
+    k[20] = 1.6e-15 * exp(0.48 * lv);
+    k[21] = 1.4e-15 * exp(0.43 * lv);
+    k[22] = 20e-16;
+    k[23] = 3.086e-15 * vib(lv, -0.714, 1.389, -0.897, 0.206, -0.00126, -0.0175, 0.000166, 0.00200, -0.000311);
+    k[24] = 2.66e-16 * vib(lv, -1.379, 2.630, -1.838, 0.549, -0.107, 0.0966, -0.0731, 0.0210, -0.00203);
+    k[25] = 2.5e-17 * vib(lv, -1.396, 2.937, -2.573, 1.206, -0.263, -0.0185, 0.0101, 0.00147, -0.00043);
+    k[26] = 1e-15;
+    k[27] = 6.3e-16;
+    k[28] = 21.0e-16;
+    k[29] = 2.0e-16;
+    k[30] = 3.7e-16;
+    k[31] = 8.7e-16;
+    k[32] = 0.2e-16;
+}
+
+// Net production per species for the full mechanism (rates of progress r_i
+// accumulated into the 15 species) and the inelastic electron loss.
+__device__ void source_arh2(const double n[15], double T, double qe, double G[15], double *loss) {
+    double k[33];
+    rates_arh2(T, k);
+    const double e = n[SE];
+    double r[33];
+    r[0] = k[0] * e * n[SAR];
+    r[1] = k[1] * e * n[SAR];
+    r[2] = k[2] * e * n[SARS];
+    r[3] = k[3] * n[SARS] * n[SARS];
+    r[4] = k[4] * n[SARS] * e;
+    r[5] = k[5] * n[SAR2S] * e;
+    r[6] = k[6] * n[SAR2S] * e;
+    r[7] = k[7] * n[SARS] * n[SAR] * n[SAR];
+    r[8] = k[8] * n[SARP] * n[SAR] * n[SAR];
+    r[9] = k[9] * n[SAR2S];
+    r[10] = k[10] * n[SAR2S] * n[SAR2S];
+    r[11] = k[11] * n[SARP] * e;
+    r[12] = k[12] * n[SARP] * e * e;
+    r[13] = k[13] * n[SAR2P] * e;
+    r[14] = k[14] * e * n[SH2];
+    r[15] = k[15] * e * n[SH];
+    r[16] = k[16] * e * n[SH2];
+    r[17] = k[17] * n[SH2] * e;
+    r[18] = k[18] * n[SH2P] * e;
+    r[19] = k[19] * n[SH3P] * e;
+    r[20] = k[20] * n[SH3P] * e;
+    r[21] = k[21] * n[SH2P] * e;
+    r[22] = k[22] * n[SH2P] * n[SH2];
+    r[23] = k[23] * e * n[SH2];
+    r[24] = k[24] * e * n[SH2];
+    r[25] = k[25] * e * n[SH2];
+    r[26] = k[26] * e * n[SARHP];
+    r[27] = k[27] * n[SARHP] * n[SH2];
+    r[28] = k[28] * n[SH2P] * n[SAR];
+    r[29] = k[29] * n[SH2P] * n[SAR];
+    r[30] = k[30] * n[SH3P] * n[SAR];
+    r[31] = k[31] * n[SARP] * n[SH2];
+    r[32] = k[32] * n[SARP] * n[SH2];
+    // net production, written species by species
+    G[SE] = r[1] + r[2] + r[3] + r[5] + r[10] - r[11] - r[12] - r[13] + r[15] + r[16] + r[17] - r[19] - r[20] - r[21] - r[26];
+    G[SARP] = r[1] + r[2] + r[3] - r[8] - r[11] - r[12] + r[29] - r[31] - r[32];
+    G[SAR2P] = r[5] + r[8] + r[10] - r[13];
+    G[SHP] = r[15] + r[17] + r[18];
+    G[SH2P] = r[16] - r[18] - r[21] - r[22] - r[28] - r[29] + r[32];
+    G[SH3P] = -r[19] - r[20] + r[22] + r[27] - r[30];
+    G[SARHP] = -r[26] - r[27] + r[28] + r[30] + r[31];
+    G[SARS] = r[0] - r[2] - 2.0 * r[3] - r[4] - r[7] + r[11] + r[12] + r[13];
+    G[SAR2S] = -r[5] - r[6] + r[7] - r[9] - 2.0 * r[10];
+    G[SH2V1] = r[23];
+    G[SH2V2] = r[24];
+    G[SH2V3] = r[25];
+    G[SH] = 2.0 * r[14] - r[15] + r[17] + r[18] + 3.0 * r[19] + r[20] + 2.0 * r[21] + r[22] + r[26] + r[28] + r[31];
+    G[SAR] = -r[0] - r[1] + r[3] + r[4] + 2.0 * r[6] - r[7] - r[8] + 2.0 * r[9] + 2.0 * r[10] + r[13] + r[26] + r[27] - r[28]
+             - r[29] - r[30] + r[32];
+    G[SH2] = -r[14] - r[16] - r[17] + r[20] - r[22] - r[23] - r[24] - r[25] - r[27] + r[29] + r[30] - r[31] - r[32];
+    *loss = qe * (11.6 * r[0] + 15.759 * r[1] + 4.159 * r[2] + 4.2 * r[5] + 14.68 * r[14] + 13.6 * r[15] + 15.4 * r[16] +
+                  28.08 * r[17] + 12.68 * r[18]);
+}
+
+// Argon subset on (e, Ar+, Ar*) with background Ar: R1-R5, R12, R13.
+__device__ void source_ar3(const double n[3], double T, double nAr, double qe, double G[3], double *loss) {
+    const double Tev = T / kEvK, eps = 1.5 * Tev, ie = 1.0 / eps, it = 1.0 / T, lT = log(T);
+    const double e = n[0], ip = n[1], ms = n[2];
+    const double k1 = exp(-37.44 + 1.407 * log(eps) + ie * (50.34 + ie * (-348.6 - 230.5 * ie)));
+    const double k2 = exp(14.37 - 8.641 * log(eps) + ie * (-622.9 + ie * (5341.0 - 0.1862e5 * ie)));
+    const double k3 = exp(-29.7 + it * (1.39e5 + it * (-3.34e10 + it * (3.38e15 + it * (-1.85e20 + it * (5.08e24 - 5.5e28 * it))))));
+    const double k5 = exp(-4.82e4 * it - 32.46);
+    const double k12 = 43e-18 * exp(-0.5 * lT), k13 = 9.75e-21 * exp(-4.5 * lT);
+    const double r1 = k1 * e * nAr, r2 = k2 * e * nAr, r3 = k3 * e * ms, r4 = 5.0e-16 * ms * ms, r5 = k5 * ms * e;
+    const double r12 = k12 * ip * e, r13 = k13 * ip * e * e;
+    G[0] = r2 + r3 + r4 - r12 - r13;
+    G[1] = r2 + r3 + r4 - r12 - r13;
+    G[2] = r1 - r3 - 2.0 * r4 - r5 + r12 + r13;
+    *loss = qe * (11.6 * r1 + 15.759 * r2 + 4.159 * r3);
+}
+
+__global__ void __launch_bounds__(kBlock) k_react(ReactArgs a) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    const long N = a.ncell;
+    double loss = 0.0;
+    if (a.mech == VD_MECH_ARH2_15) {
+        double n[15], G[15];
+        for (int s = 0; s < 15; s++) n[s] = a.n[s * N + c];
+        source_arh2(n, a.Te[c], a.qe, G, &loss);
+        for (int s = 0; s < 15; s++) a.G[s * N + c] = G[s];
+    } else if (a.mech == VD_MECH_AR3) {
+        double n[3], G[3];
+        for (int s = 0; s < 3; s++) n[s] = a.n[s * N + c];
+        source_ar3(n, a.Te[c], a.bg0, a.qe, G, &loss);
+        for (int s = 0; s < 3; s++) a.G[s * N + c] = G[s];
+    } else if (a.mech == VD_MECH_DECAY) {
+        for (int s = 0; s < a.S; s++) a.G[s * N + c] = -a.bg0 * a.n[s * N + c];
+    } else {
+        for (int s = 0; s < a.S; s++) a.G[s * N + c] = 0.0;
+    }
+    if (a.S_inel) a.S_inel[c] = loss;
+}
+
+// rho = e sum_k Z_k n_k (optionally at the mid-point (n0 + n)/2)
+__global__ void __launch_bounds__(kBlock) k_rho(RhoArgs a) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    double s = 0.0;
+    for (int k = 0; k < a.S; k++) s += a.Z[k] * a.n[k * a.ncell + c];
+    a.rho[c] = a.qe * s;
+}
+
+// u* = (u0 + u)/2 (mid-point of the corrector iteration)
+__global__ void __launch_bounds__(kBlock) k_mid(const double *__restrict__ u0, const double *__restrict__ u, double *__restrict__ out, long n) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = 0.5 * (u0[c] + u[c]);
+}
+
+// ------------------------------------------------------ electron energy
+// Central diffusive flux along +d at face fidx: -beta_f (u_R - u_L)/h with
+// the harmonic-mean face coefficient; Dirichlet face: one-sided over half a
+// cell with the boundary cell's coefficient; Neumann and wall: 0.
+__device__ __forceinline__ double diff_face(const GridDev &G, const int *kind, const double *gval, const double *__restrict__ u,
+                                            const double *__restrict__ D, double D_c, int d, int c, int pos, int fidx) {
+    const int n = G.n[d];
+    const long st = G.stride[d];
+    const double ih = G.ih[d];
+    const long c0 = c - (long)pos * st;
+#define DV(q) (D ? D[c0 + (long)(q) * st] : D_c)
+    if (fidx > 0 && fidx < n) {
+        const double a = DV(fidx - 1), b = DV(fidx);
+        const double hm = (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b);
+        return -hm * (u[c0 + fidx * st] - u[c0 + (fidx - 1) * st]) * ih;
+    }
+    const int f = 2 * d + (fidx == 0 ? 0 : 1);
+    const int kd = kind[f];
+    if (kd == VD_BC_PERIODIC) {
+        const double a = DV(n - 1), b = DV(0);
+        const double hm = (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b);
+        return -hm * (u[c0] - u[c0 + (n - 1) * st]) * ih;
+    }
+    if (kd == VD_BC_DIRICHLET) {
+        const double g = gval[f];
+        if (fidx == 0) return -DV(0) * (u[c0] - g) * (2.0 * ih);
+        return -DV(n - 1) * (g - u[c0 + (n - 1) * st]) * (2.0 * ih);
+    }
+    return 0.0;
+#undef DV
+}
+
+// Electron-energy right-hand side (Eqs. (5)-(8)) at u*:
+//   Ee0/dt - div(5/3 mu_e Ee* E)_WENO + Joule - elastic - inelastic + extra,
+// Joule = -e Gamma_e . E at the cell with Gamma_e per direction the mean of
+// the two face fluxes (WENO drift + central diffusion, wall faces carrying
+// the electron wall flux); elastic = 1.5 ne kB (Te - Tg)(2 me/mb) e/(me|mu_e|).
+__global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
+    const GridDev &G = a.g;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell) return;
+    int pos[3];
+    pos[2] = c / G.nxy;
+    int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    const double divE = drift_div_cell(G, a.fE, a.phi, a.Te, a.Tg, a.kB, a.me, c, pos);
+    const FieldDesc &Fe = a.fe;
+    double gam[3];
+    for (int d = 0; d < 3; d++) {
+        const int n = G.n[d];
+        double Fs[2];
+        for (int side = 0; side < 2; side++) {
+            const int fidx = pos[d] + side;
+            const bool boundary = (fidx == 0 || fidx == n);
+            const int kd = Fe.kind[2 * d + side];
+            if (boundary && kd == VD_BC_NEUMANN) { Fs[side] = 0.0; continue; }
+            if (boundary && kd == VD_BC_WALLFLUX) {
+                const double fl = wall_flux(VD_WALL_ELECTRON, Fe.u[c], 0.0, 0.0, a.Te[c], a.Tg, a.me, a.kB, a.me);
+                Fs[side] = fidx == 0 ? -fl : fl;
+                continue;
+            }
+            Fs[side] = face_drift(G, Fe, a.phi, d, c, pos[d], fidx) +
+                       diff_face(G, Fe.kind, Fe.gval, Fe.u, a.De, a.De_c, d, c, pos[d], fidx);
+        }
+        gam[d] = 0.5 * (Fs[0] + Fs[1]);
+    }
+    double E[3];
+    e_cell(G, a.phi, c, pos, E);
+    const double joule = -a.qe * (gam[0] * E[0] + gam[1] * E[1] + gam[2] * E[2]);
+    const double mue = Fe.mu ? Fe.mu[c] : Fe.mu_c;
+    const double nu = a.qe / (a.me * fabs(mue));
+    const double ne = Fe.u[c];
+    const double elastic = 1.5 * ne * a.kB * (a.Te[c] - a.Tg) * (2.0 * a.me / a.m_bg) * nu;
+    double src = joule - elastic - a.S_inel[c];
+    if (a.extra) src += a.extra[c];
+    a.out[c] = a.Ee0[c] * a.inv_dt - divE + src;
+}
+
+// ----------------------------------------------------- host launchers
+void launch_transport(vd_ctx *ctx, const TransportArgs &a) {
+    timed(ctx, "transport", (double)a.g.ncell, [&] {
+        k_transport<<<ceil_div(a.g.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
+    });
+}
+
+void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields, const char *tag) {
+    if (nfields == 0) return;
+    VD_CHECK(nfields <= kMaxFields, "too many fields");
+    a.f = (const FieldDesc *)upload_blob(ctx, std::string("fields:") + tag, fields, sizeof(FieldDesc) * nfields);
+    dim3 grid(ceil_div(a.g.ncell, kBlock), nfields);
+    timed(ctx, "weno", (double)a.g.ncell * nfields, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_react(vd_ctx *ctx, const ReactArgs &a) {
+    timed(ctx, "react", (double)a.ncell, [&] { k_react<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_rho(vd_ctx *ctx, const RhoArgs &a) {
+    timed(ctx, "rho", (double)a.ncell, [&] { k_rho<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
+    timed(ctx, "energy", (double)a.g.ncell, [&] { k_energy_rhs<<<ceil_div(a.g.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n) {
+    timed(ctx, "mid", (double)n, [&] { k_mid<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(u0, u, out, n); });
+}
+
+GridDev make_grid(const vd_grid &g, const vd_bc &phi_bc) {
+    GridDev G;
+    memset(&G, 0, sizeof(G));
+    G.n[0] = g.nx; G.n[1] = g.ny; G.n[2] = g.nz;
+    G.nxy = g.nx * g.ny;
+    G.ncell = g.nx * g.ny * g.nz;
+    G.stride[0] = 1; G.stride[1] = g.nx; G.stride[2] = (long)g.nx * g.ny;
+    G.ih[0] = 1.0 / g.dx; G.ih[1] = 1.0 / g.dy; G.ih[2] = 1.0 / g.dz;
+    G.ihl[0] = 1.0 / g.dx; G.ihl[1] = 1.0 / g.dy; G.ihl[2] = 1.0 / g.dz;
+    for (int f = 0; f < 6; f++) { G.phi_kind[f] = phi_bc.kind[f]; G.phi_val[f] = phi_bc.value[f]; }
+    return G;
+}
+
+}  // namespace vd

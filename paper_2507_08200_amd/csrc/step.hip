@@ -1,0 +1,328 @@
+// One semi-implicit step of the plasma-fluid model (Sec. 3 of the paper):
+// segregated Poisson -> electron energy -> species, explicit WENO5 drift and
+// chemistry at the mid-point state u*, implicit central diffusion, with the
+// mid-point corrector iteration of Eqs. (17)-(18).
+#include "physics.hpp"
+
+#include <chrono>
+
+namespace vd {
+
+struct StepBuffers {
+    long ncell = 0;
+    int S = 0;
+    DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
+};
+
+static void validate_step(const vd_step_params *P, const vd_state *st) {
+    VD_CHECK(P && st, "null params or state");
+    const vd_grid &g = P->grid;
+    VD_CHECK(g.nx >= 3 && g.ny >= 3 && g.nz >= 3 && g.dx > 0 && g.dy > 0 && g.dz > 0,
+             "bad grid (WENO5 ghosts need at least 3 cells per direction)");
+    VD_CHECK(P->S >= 1 && P->S <= 32, "S must be in 1..32");
+    VD_CHECK(P->dt > 0 && P->n_t >= 1, "dt must be positive and n_t >= 1");
+    VD_CHECK(P->species && P->species_bc, "species and species_bc are required");
+    VD_CHECK(st->n && st->phi && st->Te, "state n, phi and Te are required");
+    VD_CHECK(P->te_mode >= VD_TE_FIXED && P->te_mode <= VD_TE_ENERGY, "unknown te_mode");
+    if (P->te_mode == VD_TE_LFA) VD_CHECK(P->lfa_te && P->lfa_n >= 2 && P->lfa_ln_max > P->lfa_ln_min, "LFA table required");
+    if (P->te_mode == VD_TE_ENERGY) {
+        VD_CHECK(st->Ee, "Ee required in energy mode");
+        VD_CHECK(P->electron >= 0 && P->electron < P->S, "electron index required in energy mode");
+        VD_CHECK(P->m_bg > 0, "background mass required in energy mode");
+    }
+    if (P->mech == VD_MECH_ARH2_15) VD_CHECK(P->S == 15, "Ar-H2 mechanism needs S = 15");
+    if (P->mech == VD_MECH_AR3) VD_CHECK(P->S == 3, "argon subset needs S = 3");
+    VD_CHECK(P->mech >= VD_MECH_NONE && P->mech <= VD_MECH_ARH2_15, "unknown mechanism");
+    int nvar = 0;
+    for (int k = 0; k < P->S; k++) {
+        const vd_species &s = P->species[k];
+        VD_CHECK(s.mob_kind >= 0 && s.mob_kind <= 3 && s.wall_kind >= 0 && s.wall_kind <= 3, "bad species model");
+        if (s.mob_kind == VD_MOB_ELECTRON_FIT) nvar++;
+        VD_CHECK(s.mob_kind == VD_MOB_CONST || P->N_gas > 0, "N_gas required for fitted mobilities");
+        for (int d = 0; d < 3; d++) {
+            int a = P->species_bc[k].kind[2 * d], b = P->species_bc[k].kind[2 * d + 1];
+            VD_CHECK(a >= 0 && a <= 3 && b >= 0 && b <= 3 && ((a == 3) == (b == 3)), "bad species boundary kinds");
+        }
+    }
+    VD_CHECK(nvar <= 4, "at most 4 species with field-dependent mobility");
+}
+
+static inline double sgn(double z) { return z > 0.0 ? 1.0 : (z < 0.0 ? -1.0 : 0.0); }
+
+// constant (cell-independent) mobility and diffusion of a species
+static void const_transport(const vd_species &s, const vd_step_params *P, double *mu, double *D) {
+    const double N0 = 2.68e25;
+    const vd_consts &c = P->consts;
+    if (s.mob_kind == VD_MOB_ION_N0) {
+        double m = s.mob_coef * N0 / P->N_gas;
+        *mu = sgn(s.Z) * m;
+        *D = m * c.kB * P->Tg / c.qe;
+    } else if (s.mob_kind == VD_MOB_NEUTRAL_N0) {
+        *mu = 0.0;
+        *D = s.mob_coef * N0 / P->N_gas * c.kB * P->Tg / c.qe;
+    } else {
+        *mu = s.mu_const;
+        *D = s.D_const;
+    }
+}
+
+static vd_bc implicit_bc(const vd_bc &b) {
+    vd_bc o = b;
+    for (int f = 0; f < 6; f++)
+        if (o.kind[f] == VD_BC_WALLFLUX) o.kind[f] = VD_BC_NEUMANN;
+    return o;
+}
+
+vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step_info *info) {
+    validate_step(P, st);
+    const vd_grid &g = P->grid;
+    const long N = (long)g.nx * g.ny * g.nz;
+    const int S = P->S;
+    const bool energy = P->te_mode == VD_TE_ENERGY;
+    const bool corr = P->n_t > 1;
+    hipStream_t s = ctx->stream;
+    auto t_start = std::chrono::steady_clock::now();
+
+    // buffers cached on the context for this shape
+    std::string key = "step:" + std::to_string(g.nx) + "," + std::to_string(g.ny) + "," + std::to_string(g.nz) + ":" +
+                      std::to_string(S);
+    std::shared_ptr<StepBuffers> B;
+    auto it = ctx->cache.find(key);
+    if (it != ctx->cache.end()) B = std::static_pointer_cast<StepBuffers>(it->second);
+    else { B = std::make_shared<StepBuffers>(); ctx->cache[key] = B; }
+    int var_idx[32];
+    int nvar = 0;
+    for (int k = 0; k < S; k++) var_idx[k] = (P->species[k].mob_kind == VD_MOB_ELECTRON_FIT) ? nvar++ : -1;
+    B->rho.alloc(N);
+    B->G.alloc(N * S);
+    B->b.alloc(N * S);
+    B->S_inel.alloc(N);
+    if (nvar) { B->mu.alloc(N * nvar); B->D.alloc(N * nvar); }
+    if (corr) { B->n0.alloc(N * S); B->nstar.alloc(N * S); }
+    if (energy) {
+        B->Erhs.alloc(N);
+        B->beta_e.alloc(N);
+        if (corr) { B->Ee0.alloc(N); B->Eestar.alloc(N); }
+    }
+    if (corr) {
+        VD_HIP(hipMemcpyAsync(B->n0.p, st->n, sizeof(double) * N * S, hipMemcpyDeviceToDevice, s));
+        if (energy) VD_HIP(hipMemcpyAsync(B->Ee0.p, st->Ee, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    }
+    const double *n_old = corr ? B->n0.p : st->n;          // u^n
+    const double *Ee_old = energy ? (corr ? B->Ee0.p : st->Ee) : nullptr;
+
+    // constant transport per species, on the host
+    double mu_c[32], D_c[32];
+    for (int k = 0; k < S; k++) const_transport(P->species[k], P, &mu_c[k], &D_c[k]);
+
+    GridDev G = make_grid(g, P->phi_bc);
+    vd_step_info I;
+    memset(&I, 0, sizeof(I));
+    I.dt_used = P->dt;
+    const bool want_info = info != nullptr;
+    hipEvent_t ev[6];
+    if (want_info) for (auto &e : ev) VD_HIP(hipEventCreate(&e));
+    double ms_poisson = 0, ms_transport = 0, ms_energy = 0, ms_species = 0;
+
+    for (int m = 0; m < P->n_t; m++) {
+        // ---- u* = (u^n + u^m)/2
+        const double *nst = st->n;
+        const double *Est = energy ? st->Ee : nullptr;
+        if (corr && m > 0) {
+            launch_mid(ctx, n_old, st->n, B->nstar.p, N * S);
+            nst = B->nstar.p;
+            if (energy) { launch_mid(ctx, Ee_old, st->Ee, B->Eestar.p, N); Est = B->Eestar.p; }
+        }
+        if (want_info) VD_HIP(hipEventRecord(ev[0], s));
+        // ---- Poisson at u*: -div(eps grad phi) = e sum Z n*
+        RhoArgs ra;
+        memset(&ra, 0, sizeof(ra));
+        ra.ncell = N; ra.S = S; ra.qe = P->consts.qe; ra.n = nst; ra.rho = B->rho.p;
+        for (int k = 0; k < S; k++) ra.Z[k] = P->species[k].Z;
+        launch_rho(ctx, ra);
+        vd_problem pp;
+        memset(&pp, 0, sizeof(pp));
+        pp.grid = g; pp.bc = P->phi_bc; pp.beta = P->eps_cell; pp.beta_c = P->consts.eps0;
+        pp.rhs = B->rho.p; pp.x = st->phi;
+        vd_solve_info pinfo;
+        mg_solve_batch(ctx, 1, &pp, &P->poisson, &pinfo, "poisson:");
+        I.poisson_cycles += pinfo.cycles;
+        I.poisson_rel = pinfo.rel_res;
+        if (want_info) VD_HIP(hipEventRecord(ev[1], s));
+
+        // ---- E/N, Te, field-dependent mobilities at u*
+        TransportArgs ta;
+        memset(&ta, 0, sizeof(ta));
+        ta.g = G; ta.phi = st->phi; ta.Te = st->Te; ta.te_mode = P->te_mode;
+        ta.ne = energy ? nst + (long)P->electron * N : nullptr;
+        ta.Ee = Est;
+        ta.lfa = P->lfa_te; ta.lfa_ln_min = P->lfa_ln_min; ta.lfa_ln_max = P->lfa_ln_max; ta.lfa_n = P->lfa_n;
+        ta.N_gas = P->N_gas > 0 ? P->N_gas : 1.0; ta.Tg = P->Tg; ta.kB = P->consts.kB; ta.qe = P->consts.qe;
+        ta.Te_max = 1e6;
+        ta.nvar = nvar; ta.mu = B->mu.p; ta.D = B->D.p;
+        for (int k = 0; k < S; k++) if (var_idx[k] >= 0) ta.var_sign[var_idx[k]] = sgn(P->species[k].Z);
+        ta.beta_e = nullptr; ta.e_var = -1;
+        if (energy && var_idx[P->electron] >= 0) { ta.beta_e = B->beta_e.p; ta.e_var = var_idx[P->electron]; }
+        launch_transport(ctx, ta);
+
+        // ---- chemistry at u*
+        ReactArgs rc;
+        memset(&rc, 0, sizeof(rc));
+        rc.ncell = N; rc.mech = P->mech; rc.S = S; rc.n = nst; rc.Te = st->Te;
+        rc.bg0 = P->mech == VD_MECH_DECAY ? P->k_decay : P->bg[0];
+        rc.qe = P->consts.qe; rc.G = B->G.p; rc.S_inel = B->S_inel.p;
+        launch_react(ctx, rc);
+        if (want_info) VD_HIP(hipEventRecord(ev[2], s));
+
+        // ---- electron energy
+        if (energy) {
+            const int e = P->electron;
+            EnergyArgs ea;
+            memset(&ea, 0, sizeof(ea));
+            ea.g = G; ea.phi = st->phi; ea.Te = st->Te; ea.Tg = P->Tg; ea.kB = P->consts.kB; ea.me = P->consts.me;
+            ea.qe = P->consts.qe; ea.m_bg = P->m_bg; ea.inv_dt = 1.0 / P->dt;
+            FieldDesc fe;
+            memset(&fe, 0, sizeof(fe));
+            fe.u = nst + (long)e * N;
+            fe.mu = var_idx[e] >= 0 ? B->mu.p + (long)var_idx[e] * N : nullptr;
+            fe.mu_c = mu_c[e];
+            fe.mu_scale = 1.0;
+            for (int f = 0; f < 6; f++) { fe.kind[f] = P->species_bc[e].kind[f]; fe.gval[f] = P->species_bc[e].value[f]; }
+            fe.wall = VD_WALL_ELECTRON; fe.mass = P->consts.me;
+            FieldDesc fE = fe;
+            fE.u = Est;
+            fE.mu_scale = 5.0 / 3.0;
+            for (int f = 0; f < 6; f++) { fE.kind[f] = P->energy_bc.kind[f]; fE.gval[f] = P->energy_bc.value[f]; }
+            fE.ne_wall = nst + (long)e * N;
+            ea.fE = fE; ea.fe = fe;
+            ea.De = var_idx[e] >= 0 ? B->D.p + (long)var_idx[e] * N : nullptr;
+            ea.De_c = D_c[e];
+            ea.S_inel = B->S_inel.p; ea.extra = P->extra_energy; ea.Ee0 = Ee_old; ea.out = B->Erhs.p;
+            launch_energy(ctx, ea);
+            vd_problem ep;
+            memset(&ep, 0, sizeof(ep));
+            ep.grid = g; ep.bc = implicit_bc(P->energy_bc); ep.alpha_c = 1.0 / P->dt;
+            ep.beta = var_idx[e] >= 0 ? B->beta_e.p : nullptr;
+            ep.beta_c = 5.0 / 3.0 * D_c[e];
+            ep.rhs = B->Erhs.p; ep.x = st->Ee;
+            vd_solve_info einfo;
+            mg_solve_batch(ctx, 1, &ep, &P->energy_mg, &einfo, "energy:");
+            I.energy_cycles = std::max(I.energy_cycles, einfo.cycles);
+        }
+        if (want_info) VD_HIP(hipEventRecord(ev[3], s));
+
+        // ---- species right-hand sides: n^n/dt - div(mu n* E)_WENO + G(u*) + extra
+        DriftArgs da;
+        memset(&da, 0, sizeof(da));
+        da.g = G; da.phi = st->phi; da.Te = st->Te; da.Tg = P->Tg; da.kB = P->consts.kB; da.me = P->consts.me;
+        da.inv_dt = 1.0 / P->dt; da.mode = 1;
+        vd_problem sp[32];
+        FieldDesc fds[32];
+        memset(fds, 0, sizeof(fds));
+        int nf = 0;
+        for (int k = 0; k < S; k++) {
+            if (!P->species[k].transported) continue;
+            FieldDesc &F = fds[nf];
+            F.u = nst + (long)k * N;
+            F.mu = var_idx[k] >= 0 ? B->mu.p + (long)var_idx[k] * N : nullptr;
+            F.mu_c = mu_c[k];
+            F.mu_scale = 1.0;
+            for (int f = 0; f < 6; f++) { F.kind[f] = P->species_bc[k].kind[f]; F.gval[f] = P->species_bc[k].value[f]; }
+            F.wall = P->species[k].wall_kind;
+            F.mass = P->species[k].mass_kg;
+            F.ne_wall = nullptr;
+            F.out = B->b.p + (long)k * N;
+            F.u0 = n_old + (long)k * N;
+            F.src = B->G.p + (long)k * N;
+            F.extra = P->extra_source ? P->extra_source + (long)k * N : nullptr;
+            vd_problem &q = sp[nf];
+            memset(&q, 0, sizeof(q));
+            q.grid = g; q.bc = implicit_bc(P->species_bc[k]); q.alpha_c = 1.0 / P->dt;
+            q.beta = var_idx[k] >= 0 ? B->D.p + (long)var_idx[k] * N : nullptr;
+            q.beta_c = D_c[k];
+            q.rhs = F.out; q.x = st->n + (long)k * N;
+            nf++;
+        }
+        launch_drift(ctx, da, fds, nf, "step");
+        if (want_info) VD_HIP(hipEventRecord(ev[4], s));
+        if (nf) {
+            vd_solve_info sinfo[32];
+            mg_solve_batch(ctx, nf, sp, &P->species_mg, want_info ? sinfo : nullptr, "species:");
+            if (want_info)
+                for (int q = 0; q < nf; q++) I.species_cycles = std::max(I.species_cycles, sinfo[q].cycles);
+        }
+        if (want_info) {
+            VD_HIP(hipEventRecord(ev[5], s));
+            VD_HIP(hipEventSynchronize(ev[5]));
+            float a;
+            VD_HIP(hipEventElapsedTime(&a, ev[0], ev[1])); ms_poisson += a;
+            VD_HIP(hipEventElapsedTime(&a, ev[1], ev[2])); ms_transport += a;
+            VD_HIP(hipEventElapsedTime(&a, ev[2], ev[3])); ms_energy += a;
+            VD_HIP(hipEventElapsedTime(&a, ev[3], ev[5])); ms_species += a;
+        }
+    }
+    if (energy) {
+        // Te from the new electron energy and density
+        TransportArgs ta;
+        memset(&ta, 0, sizeof(ta));
+        ta.g = G; ta.phi = st->phi; ta.Te = st->Te; ta.te_mode = VD_TE_ENERGY;
+        ta.ne = st->n + (long)P->electron * N; ta.Ee = st->Ee;
+        ta.N_gas = P->N_gas > 0 ? P->N_gas : 1.0; ta.Tg = P->Tg; ta.kB = P->consts.kB; ta.qe = P->consts.qe;
+        ta.Te_max = 1e6; ta.nvar = 0;
+        launch_transport(ctx, ta);
+    }
+    if (want_info) {
+        VD_HIP(hipStreamSynchronize(s));
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        I.ms_poisson = ms_poisson; I.ms_transport = ms_transport; I.ms_energy = ms_energy; I.ms_species = ms_species;
+        I.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        I.status = VD_OK;
+        *info = I;
+    }
+    return VD_OK;
+}
+
+// Standalone drift divergence (vd_species_flux).
+vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const vd_bc *sp_bc, int S, const vd_species *sp,
+                       const double *n, const double *phi, const double *mu, const double *Te, double Tg, const vd_consts *c,
+                       double *div) {
+    VD_CHECK(g && phi_bc && sp_bc && sp && n && phi && mu && Te && c && div, "null argument");
+    VD_CHECK(S >= 1 && S <= kMaxFields, "S out of range");
+    VD_CHECK(g->nx >= 3 && g->ny >= 3 && g->nz >= 3, "WENO5 ghosts need at least 3 cells per direction");
+    const long N = (long)g->nx * g->ny * g->nz;
+    DriftArgs da;
+    memset(&da, 0, sizeof(da));
+    da.g = make_grid(*g, *phi_bc);
+    da.phi = phi; da.Te = Te; da.Tg = Tg; da.kB = c->kB; da.me = c->me; da.mode = 0;
+    FieldDesc fds[kMaxFields];
+    memset(fds, 0, sizeof(fds));
+    for (int k = 0; k < S; k++) {
+        FieldDesc &F = fds[k];
+        F.u = n + (long)k * N;
+        F.mu = mu + (long)k * N;
+        F.mu_scale = 1.0;
+        for (int f = 0; f < 6; f++) { F.kind[f] = sp_bc[k].kind[f]; F.gval[f] = sp_bc[k].value[f]; }
+        F.wall = sp[k].wall_kind;
+        F.mass = sp[k].mass_kg;
+        F.out = div + (long)k * N;
+    }
+    launch_drift(ctx, da, fds, S, "flux");
+    return VD_OK;
+}
+
+vd_status reaction_source(vd_ctx *ctx, int mech, long ncell, int S, const double *n, const double *Te, const double *bg,
+                          double qe, double *G, double *S_inel) {
+    VD_CHECK(n && Te && G && ncell > 0, "null argument");
+    VD_CHECK(mech >= VD_MECH_NONE && mech <= VD_MECH_ARH2_15, "unknown mechanism");
+    VD_CHECK(mech != VD_MECH_ARH2_15 || S == 15, "Ar-H2 mechanism needs S = 15");
+    VD_CHECK(mech != VD_MECH_AR3 || S == 3, "argon subset needs S = 3");
+    VD_CHECK(S >= 1 && S <= 32, "S out of range");
+    ReactArgs rc;
+    memset(&rc, 0, sizeof(rc));
+    rc.ncell = ncell; rc.mech = mech; rc.S = S; rc.n = n; rc.Te = Te;
+    rc.bg0 = bg ? bg[0] : 0.0; rc.qe = qe; rc.G = G; rc.S_inel = S_inel;
+    launch_react(ctx, rc);
+    return VD_OK;
+}
+
+}  // namespace vd

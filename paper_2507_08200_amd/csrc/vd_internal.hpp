@@ -1,0 +1,295 @@
+// Internal declarations of libvd (HIP, gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/vd.h"
+
+namespace vd {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    vd_status code;
+    std::string msg;
+};
+
+#define VD_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::vd::Error{VD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define VD_CHECK(cond, msg)                                           \
+    do {                                                              \
+        if (!(cond)) throw ::vd::Error{VD_EINVAL, std::string(msg)}; \
+    } while (0)
+
+// ------------------------------------------------------- device buffers
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{VD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+        }
+        n = count;
+    }
+};
+
+// ---------------------------------------------------- level descriptor
+// One multigrid level of one problem, as the kernels see it.  Coefficient
+// pointers are null for uniform coefficients (beta_c / alpha_c used).
+struct LevDesc {
+    int nx, ny, nz, ncell;
+    int kind[6];
+    int var_beta, var_alpha, has_mask, lift;
+    int prob, nxy;
+    double idx2, idy2, idz2;     // 1/h^2 per direction
+    double beta_c, alpha_c;
+    double gval[6];              // Dirichlet face values (used when lift)
+    const double *bx, *by, *bz, *alpha;
+    const float *bx32, *by32, *bz32, *alpha32;
+    const uint8_t *mask;
+    void *x;                     // unknown (double or float by hierarchy)
+    const void *b;               // right-hand side
+};
+
+// Per-problem convergence state, device resident.
+struct ProbState {
+    int active;      // 1 while more cycles are needed
+    int cycles;      // V-cycles run (inner cycles in IR mode)
+    int outer;       // FP64 residual checks
+    int status;
+    double bnorm, rel0, rel;
+};
+
+// A launch plan: a list of level descriptors and the prefix sum of their
+// tile counts; block -> (descriptor, tile) by search.
+struct Plan {
+    const int *ids;
+    const int *prefix;
+    int nd;
+    int ntiles;
+};
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------- kernel timing
+struct Timing {
+    std::string family;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+    double units = 0.0;
+};
+
+}  // namespace vd
+
+struct vd_ctx {
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    vd::Timing timing;
+    std::map<std::string, std::shared_ptr<void>> cache;   // solver hierarchies by key
+    vd::DevBuf<double> scratch64;
+    vd::DevBuf<char> scratch_bytes;
+};
+
+namespace vd {
+
+// Small host blobs (kernel descriptor tables) mirrored in device memory.
+// The device copy is refreshed only when the bytes change, so repeated calls
+// with the same arguments enqueue no host-to-device copy.
+struct DevBlob {
+    DevBuf<char> d;
+    std::vector<char> last;
+    char *pinned = nullptr;
+    size_t cap = 0;
+    ~DevBlob() { if (pinned) (void)hipHostFree(pinned); }
+};
+
+inline const void *upload_blob(vd_ctx *ctx, const std::string &key, const void *data, size_t bytes) {
+    std::shared_ptr<DevBlob> B;
+    auto it = ctx->cache.find("blob:" + key);
+    if (it != ctx->cache.end()) B = std::static_pointer_cast<DevBlob>(it->second);
+    else { B = std::make_shared<DevBlob>(); ctx->cache["blob:" + key] = B; }
+    if (B->last.size() == bytes && memcmp(B->last.data(), data, bytes) == 0) return B->d.p;
+    VD_HIP(hipStreamSynchronize(ctx->stream));   // the previous staging may still be in flight
+    if (B->cap < bytes) {
+        if (B->pinned) (void)hipHostFree(B->pinned);
+        B->pinned = nullptr;
+        VD_HIP(hipHostMalloc((void **)&B->pinned, bytes, hipHostMallocDefault));
+        B->cap = bytes;
+    }
+    B->d.alloc(bytes);
+    memcpy(B->pinned, data, bytes);
+    VD_HIP(hipMemcpyAsync(B->d.p, B->pinned, bytes, hipMemcpyHostToDevice, ctx->stream));
+    B->last.assign((const char *)data, (const char *)data + bytes);
+    return B->d.p;
+}
+
+// Kernel timing hooks (host).  begin() returns true when the family matches.
+bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *ev1);
+void timing_end(vd_ctx *ctx, hipEvent_t ev0, hipEvent_t ev1, double units);
+void timing_flush(vd_ctx *ctx);
+
+template <typename F>
+inline void timed(vd_ctx *ctx, const char *family, double units, F &&launch) {
+    hipEvent_t a, b;
+    bool on = timing_begin(ctx, family, &a, &b);
+    if (on) VD_HIP(hipEventRecord(a, ctx->stream));
+    launch();
+    VD_HIP(hipGetLastError());
+    if (on) {
+        VD_HIP(hipEventRecord(b, ctx->stream));
+        timing_end(ctx, a, b, units);
+    }
+}
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Grid of 8*ceil(n/8) blocks; the kernel maps block -> tile so that each
+// of the 8 XCDs (blocks are dealt round-robin) gets a contiguous range of
+// tiles, keeping stencil neighbours in the same L2.
+inline int xcd_grid(int ntiles) { return 8 * ceil_div(ntiles, 8); }
+
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+    int chunk = (ntiles + 7) >> 3;
+    int b = blockIdx.x;
+    return (b & 7) * chunk + (b >> 3);
+}
+
+__device__ __forceinline__ int plan_find(const Plan &pl, int tile) {
+    int lo = 0, hi = pl.nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pl.prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------ the 7-point operator
+template <typename T> struct Coef;
+template <> struct Coef<double> {
+    static __device__ __forceinline__ const double *bx(const LevDesc &L) { return L.bx; }
+    static __device__ __forceinline__ const double *by(const LevDesc &L) { return L.by; }
+    static __device__ __forceinline__ const double *bz(const LevDesc &L) { return L.bz; }
+    static __device__ __forceinline__ const double *al(const LevDesc &L) { return L.alpha; }
+};
+template <> struct Coef<float> {
+    static __device__ __forceinline__ const float *bx(const LevDesc &L) { return L.bx32; }
+    static __device__ __forceinline__ const float *by(const LevDesc &L) { return L.by32; }
+    static __device__ __forceinline__ const float *bz(const LevDesc &L) { return L.bz32; }
+    static __device__ __forceinline__ const float *al(const LevDesc &L) { return L.alpha32; }
+};
+
+// diag and off-diagonal sum of row c = (i,j,k): (A x)_c = diag x_c - off.
+// Faces in the order x-, x+, y-, y+, z-, z+.  A Dirichlet domain face or a
+// covered neighbour adds twice the face coefficient to the diagonal;
+// Neumann and wall faces add nothing; periodic faces wrap.
+template <typename T, typename XT>
+__device__ __forceinline__ void row_terms(const LevDesc &L, const XT *__restrict__ x, int i, int j, int k, int c,
+                                          T &diag, T &off) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    T dg = L.var_alpha ? Coef<T>::al(L)[c] : (T)L.alpha_c;
+    T of = 0;
+    const T bc = (T)L.beta_c;
+#define VD_FACE(NBCOND, NBIDX, BETA, IH2, FACE)                        \
+    {                                                                  \
+        T cf = (L.var_beta ? (T)(BETA) : bc) * (T)(IH2);               \
+        int nb;                                                        \
+        bool inside = (NBCOND);                                        \
+        int kd = L.kind[FACE];                                         \
+        if (inside || kd == VD_BC_PERIODIC) {                          \
+            nb = (NBIDX);                                              \
+            if (L.has_mask && !L.mask[nb]) dg += (T)2 * cf;            \
+            else { dg += cf; of += cf * (T)x[nb]; }                    \
+        } else if (kd == VD_BC_DIRICHLET) {                            \
+            dg += (T)2 * cf;                                           \
+        }                                                              \
+    }
+    const long fxrow = (long)(nx + 1) * (j + (long)ny * k);
+    const long fyrow = (long)nx * (j + (long)(ny + 1) * k);
+    const long fzpl = (long)nx * j;
+    VD_FACE(i > 0, (i > 0 ? c - 1 : c + nx - 1), Coef<T>::bx(L)[fxrow + i], L.idx2, 0)
+    VD_FACE(i < nx - 1, (i < nx - 1 ? c + 1 : c - (nx - 1)), Coef<T>::bx(L)[fxrow + i + 1], L.idx2, 1)
+    VD_FACE(j > 0, (j > 0 ? c - nx : c + nx * (ny - 1)), Coef<T>::by(L)[fyrow + i], L.idy2, 2)
+    VD_FACE(j < ny - 1, (j < ny - 1 ? c + nx : c - nx * (ny - 1)), Coef<T>::by(L)[fyrow + i + nx], L.idy2, 3)
+    VD_FACE(k > 0, (k > 0 ? c - L.nxy : c + L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * k], L.idz2, 4)
+    VD_FACE(k < nz - 1, (k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * (k + 1)], L.idz2, 5)
+#undef VD_FACE
+    diag = dg;
+    off = of;
+}
+
+// Dirichlet lifting of the finest level: 2 beta_f g / h^2 per Dirichlet
+// face of a boundary cell, added to the right-hand side.
+__device__ __forceinline__ double lift_term(const LevDesc &L, int i, int j, int k) {
+    double v = 0.0;
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    if (i == 0 && L.kind[0] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.bx[(long)(nx + 1) * (j + (long)ny * k)] : L.beta_c) * L.gval[0] * L.idx2;
+    if (i == nx - 1 && L.kind[1] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.bx[(long)(nx + 1) * (j + (long)ny * k) + nx] : L.beta_c) * L.gval[1] * L.idx2;
+    if (j == 0 && L.kind[2] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.by[i + (long)nx * ((long)(ny + 1) * k)] : L.beta_c) * L.gval[2] * L.idy2;
+    if (j == ny - 1 && L.kind[3] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.by[i + (long)nx * (ny + (long)(ny + 1) * k)] : L.beta_c) * L.gval[3] * L.idy2;
+    if (k == 0 && L.kind[4] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.bz[i + (long)nx * j] : L.beta_c) * L.gval[4] * L.idz2;
+    if (k == nz - 1 && L.kind[5] == VD_BC_DIRICHLET)
+        v += 2.0 * (L.var_beta ? L.bz[i + (long)nx * (j + (long)ny * nz)] : L.beta_c) * L.gval[5] * L.idz2;
+    return v;
+}
+
+__device__ __forceinline__ void cell_ijk(const LevDesc &L, int c, int &i, int &j, int &k) {
+    k = c / L.nxy;
+    int r = c - k * L.nxy;
+    j = r / L.nx;
+    i = r - j * L.nx;
+}
+
+// Deterministic block sum (fixed shuffle tree, then fixed LDS order).
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; q++) s += lds[q];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace vd
