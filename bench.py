@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the semi-implicit plasma-fluid step on one MI355X.
+
+Workload: the 15-species Ar-H2 streamer-shaped state on a 160^3 grid
+(4,096,000 cells, dt = 1e-12 s, Te from the reduced-field table, electrode
+plates at 15 kV / 0 V; seeded synthetic inputs from
+paper_2507_08200_amd.inputs).  One step = Poisson solve, transport, WENO5
+drift divergence with wall fluxes, chemistry and the batched implicit
+species solve, all in libvd's HIP kernels.
+
+Prints one JSON line: cell-steps/s, the roofline of the dominant kernel
+(algorithmic bytes / HIP-event-timed duration over the timed region), the
+Poisson time-to-1e-10 comparison and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-steps/s at 160^3×15 species; Poisson time-to-1e-10 plain vs learned+FP32"
+HBM_PEAK_GBS = 8000.0
+FAMILIES = ["gsrb", "resid_restrict", "prolong", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
+            "react", "transport", "rho", "setup"]
+QE = 1.602176634e-19
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=160, help="grid edge (the workload is n^3)")
+    ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
+    ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
+    ap.add_argument("--species-levels", type=int, default=1)
+    ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 0))
+    ap.add_argument("--ir-inner", type=int, default=2)
+    ap.add_argument("--poisson-reps", type=int, default=5)
+    ap.add_argument("--cpu-n", type=int, default=112, help="grid edge of the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (auto = dominant)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
+              % (args.gpus, world), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2507_08200_amd import inputs as I
+    from paper_2507_08200_amd import mechanisms as M
+    from paper_2507_08200_amd import vd as V
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    V.load()
+    dev = "cuda:0"
+    n = args.n
+    cfg = I.cfg3(n=n)
+    ncell = n ** 3
+    log("[bench] building %d^3 x 15 state" % n)
+    state = {k: torch.tensor(cfg[k], device=dev) for k in ("n", "phi", "Te")}
+    lfa = dict(cfg["lfa"])
+    lfa["te_K"] = torch.tensor(cfg["lfa"]["te_K"], device=dev)
+    prec = {"fp64": V.FP64, "fp32_ir": V.FP32_IR}
+    popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner)
+    sopts = V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
+                      nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1)
+    species = M.arh2_15()
+    P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
+    ctx = V.Context()
+
+    # ---- warmup, with every kernel family timed to find the dominant one
+    ctx.vd_timing_select(",".join(FAMILIES))
+    infos = []
+    for w in range(args.warmup):
+        infos.append(ctx.vd_step(P, state))
+        log("[bench] warmup step %d: %s" % (w, {k: infos[-1][k] for k in ("poisson_cycles", "species_cycles", "ms_total")}))
+    torch.cuda.synchronize()
+    prof = {}
+    for f in FAMILIES:
+        cnt, ms, by = ctx.vd_timing_read(f)
+        if cnt:
+            prof[f] = {"launches_per_step": cnt / max(1, args.warmup), "ms_per_step": ms / max(1, args.warmup),
+                       "gb_per_s": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
+    kernel = args.kernel
+    if kernel == "auto":
+        kernel = max(prof, key=lambda f: prof[f]["ms_per_step"]) if prof else "gsrb"
+    log("[bench] per-family ms/step (warmup): %s" % {f: round(v["ms_per_step"], 3) for f, v in prof.items()})
+
+    # ---- timed region: K steps; the dominant family is event-timed live
+    ctx.vd_timing_select(kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc_p = cyc_s = 0
+    for k in range(args.steps):
+        ctx.vd_step(P, state, want_info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    launches, kms, kbytes = ctx.vd_timing_read(kernel)
+    ctx.vd_timing_select(None)
+    info = ctx.vd_step(P, state)        # one more (untimed) step for the cycle counts
+    cyc_p, cyc_s = info["poisson_cycles"], info["species_cycles"]
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = ncell * args.steps / elapsed
+    log("[bench] %d steps in %.3f s: %.3f ms/step, %.4g cell-steps/s" % (args.steps, elapsed, ms_per_step, value))
+
+    avg_ms = kms / launches if launches else 0.0
+    achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
+    roofline = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": launches, "avg_launch_us": round(avg_ms * 1e3, 3),
+                "alg_bytes_per_launch": round(kbytes / launches) if launches else 0}
+
+    # ---- Poisson time-to-1e-10 on the current streamer charge density
+    Z = torch.tensor([s["Z"] for s in species], dtype=torch.float64, device=dev)
+    rho = (QE * torch.tensordot(Z, state["n"], dims=1)).contiguous()
+    phi_prev = state["phi"].clone()
+
+    def poisson_time(precision, guess, x0, reps):
+        times, info = [], None
+        for r in range(reps):
+            phi = x0.clone()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            info = ctx.vd_poisson_solve(cfg["grid"], cfg["phi_bc"], rho, phi, beta_c=8.8541878128e-12,
+                                        opts=V.mg_opts(rtol=1e-10, precision=precision, guess=guess,
+                                                       ir_inner=args.ir_inner))
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return {"ms": round(float(np.median(times)), 4), "cycles": info["cycles"], "outer": info["outer_iters"],
+                "rel_res": info["rel_res"]}
+
+    zero = torch.zeros_like(phi_prev)
+    poisson = {
+        "plain_fp64_zero_guess": poisson_time(V.FP64, V.GUESS_ZERO, zero, args.poisson_reps),
+        "fp32_ir_zero_guess": poisson_time(V.FP32_IR, V.GUESS_ZERO, zero, args.poisson_reps),
+        "plain_fp64_previous_step": poisson_time(V.FP64, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
+        "fp32_ir_previous_step": poisson_time(V.FP32_IR, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
+        "learned_fp32_ir": None,
+    }
+    log("[bench] poisson time-to-1e-10: %s" % poisson)
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build()
+        cn = args.cpu_n
+        ccfg = I.cfg3(n=cn)
+        log("[bench] oracle: one step at %d^3 on one host core" % cn)
+        t = time.perf_counter()
+        r = O.step(ccfg, O.species_arh2_15(), poisson=O.mg_opts(rtol=1e-10), species_mg=O.mg_opts(rtol=1e-10))
+        dt_cpu = time.perf_counter() - t
+        assert r["status"] == 0
+        cpu = {"value": round(cn ** 3 / dt_cpu, 1), "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "one FP64 oracle step of the same Ar-H2 streamer workload at %d^3 (%d cells, cold Poisson start, "
+                         "%d Poisson cycles), single-threaded, %.1f s; scaled per cell" %
+                         (cn, cn ** 3, r["info"]["poisson_cycles"], dt_cpu),
+               "host_cpus_available": len(os.sched_getaffinity(0))}
+        log("[bench] oracle %.2f s -> %.4g cell-steps/s" % (dt_cpu, cpu["value"]))
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Ar-H2 15-species streamer step, %d^3 cells, dt 1e-12 s, LFA Te, 15 kV plates" % n,
+                   "grid": [n, n, n], "species": 15, "dt": 1e-12,
+                   "poisson": "%s rtol 1e-10 warm start" % args.poisson_precision,
+                   "species_solve": "%s levels %d nu %s rtol 1e-10" % (args.species_precision, args.species_levels,
+                                                                       list(args.species_nu)),
+                   "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
+                   "poisson_cycles_last_step": cyc_p, "species_cycles_last_step": cyc_s},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "poisson_time_to_1e-10": poisson,
+        "kernel_profile_warmup": prof,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -250,11 +250,15 @@ vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, i
  * problem, with the Dirichlet lifting; x updated in place. */
 vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour);
 
-/* Kernel timing: bracket every launch of the named kernel family with HIP
- * events on the context stream ("gsrb", "resid_restrict", "weno", ...; NULL
- * turns timing off) and read back count and total milliseconds. */
-vd_status vd_timing_select(vd_ctx *ctx, const char *kernel);
-vd_status vd_timing_read(vd_ctx *ctx, int64_t *launches, double *total_ms, double *units);
+/* Kernel timing: bracket every launch of the selected kernel families
+ * (comma-separated, e.g. "gsrb,weno,coarse"; NULL or "" turns timing off)
+ * with HIP events on the context stream, and read back per family the
+ * launch count, the summed device milliseconds and the summed algorithmic
+ * bytes of those launches (the bytes a launch must move at minimum: its
+ * inputs read once and its outputs written once).  Selecting resets the
+ * accumulators. */
+vd_status vd_timing_select(vd_ctx *ctx, const char *kernels);
+vd_status vd_timing_read(vd_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *bytes);
 
 #ifdef __cplusplus
 }

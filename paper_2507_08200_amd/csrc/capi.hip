@@ -12,9 +12,11 @@ vd_status reaction_source(vd_ctx *ctx, int mech, long ncell, int S, const double
 
 bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *ev1) {
     Timing &T = ctx->timing;
-    if (T.family.empty() || T.family != family) return false;
+    bool sel = false;
+    for (auto &f : T.families) sel = sel || f == family;
+    if (!sel) return false;
     if (T.pool.size() < 2) {
-        for (int q = 0; q < 64; q++) {
+        for (int q = 0; q < 1024; q++) {
             hipEvent_t e;
             VD_HIP(hipEventCreate(&e));
             T.pool.push_back(e);
@@ -25,23 +27,24 @@ bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *
     return true;
 }
 
-void timing_end(vd_ctx *ctx, hipEvent_t ev0, hipEvent_t ev1, double units) {
+void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units) {
     Timing &T = ctx->timing;
-    T.pending.push_back({ev0, ev1});
-    T.units += units;
-    T.launches += 1;
-    if (T.pending.size() >= 256) timing_flush(ctx);
+    T.pending.push_back(TimingPending{family, ev0, ev1});
+    TimingAcc &A = T.acc[family];
+    A.units += units;
+    A.launches += 1;
+    if (T.pending.size() >= 8192) timing_flush(ctx);
 }
 
 void timing_flush(vd_ctx *ctx) {
     Timing &T = ctx->timing;
     for (auto &pr : T.pending) {
-        VD_HIP(hipEventSynchronize(pr.second));
+        VD_HIP(hipEventSynchronize(pr.b));
         float ms = 0.0f;
-        VD_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-        T.total_ms += ms;
-        T.pool.push_back(pr.first);
-        T.pool.push_back(pr.second);
+        VD_HIP(hipEventElapsedTime(&ms, pr.a, pr.b));
+        T.acc[pr.family].total_ms += ms;
+        T.pool.push_back(pr.a);
+        T.pool.push_back(pr.b);
     }
     T.pending.clear();
 }
@@ -141,23 +144,33 @@ vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour) {
     return guarded(ctx, [&] { return vd::mg_smooth(ctx, prob, ncolour); });
 }
 
-vd_status vd_timing_select(vd_ctx *ctx, const char *kernel) {
+vd_status vd_timing_select(vd_ctx *ctx, const char *kernels) {
     return guarded(ctx, [&] {
         vd::timing_flush(ctx);
-        ctx->timing.family = kernel ? kernel : "";
-        ctx->timing.launches = 0;
-        ctx->timing.total_ms = 0.0;
-        ctx->timing.units = 0.0;
+        ctx->timing.families.clear();
+        ctx->timing.acc.clear();
+        std::string s = kernels ? kernels : "";
+        size_t pos = 0;
+        while (pos < s.size()) {
+            size_t e = s.find(',', pos);
+            if (e == std::string::npos) e = s.size();
+            if (e > pos) ctx->timing.families.push_back(s.substr(pos, e - pos));
+            pos = e + 1;
+        }
         return VD_OK;
     });
 }
 
-vd_status vd_timing_read(vd_ctx *ctx, int64_t *launches, double *total_ms, double *units) {
+vd_status vd_timing_read(vd_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *units) {
     return guarded(ctx, [&] {
+        VD_CHECK(kernel, "kernel family required");
         vd::timing_flush(ctx);
-        if (launches) *launches = ctx->timing.launches;
-        if (total_ms) *total_ms = ctx->timing.total_ms;
-        if (units) *units = ctx->timing.units;
+        vd::TimingAcc A;
+        auto it = ctx->timing.acc.find(kernel);
+        if (it != ctx->timing.acc.end()) A = it->second;
+        if (launches) *launches = A.launches;
+        if (total_ms) *total_ms = A.total_ms;
+        if (units) *units = A.units;
         return VD_OK;
     });
 }

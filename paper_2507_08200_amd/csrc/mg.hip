@@ -792,6 +792,34 @@ static void setup_coefficients(vd_ctx *ctx, Solver &S, const vd_problem *probs) 
     }
 }
 
+// Algorithmic bytes of one launch over a plan (inputs read once, outputs
+// written once).  kind 0: one colour pass of GSRB (half the cells updated:
+// their b read and x written, the other colour's x read; every face
+// coefficient touches one updated cell); 1: residual + restriction into the
+// coarse level; 2: prolongation + correction; 3: norm of b; 4: residual
+// norm; 5: residual norm + FP32 copy.
+static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) {
+    double total = 0.0;
+    const double sT = fp32 ? 4.0 : 8.0;
+    for (int id : pl.h_ids) {
+        const LevDesc &D = fp32 ? S.h32[id] : S.h64[id];
+        double N = (double)D.ncell;
+        double coef = (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? N * sT : 0.0) + (D.has_mask ? N : 0.0);
+        switch (kind) {
+        case 0: total += 1.5 * N * sT + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
+        case 1: { const LevDesc &F = fp32 ? S.h32[id - 1] : S.h64[id - 1];
+                  double NF = (double)F.ncell;
+                  total += 2.0 * NF * sT + 2.0 * N * sT + (F.var_beta ? 3.0 * NF * sT : 0.0) + (F.var_alpha ? NF * sT : 0.0) + (F.has_mask ? NF : 0.0);
+                  break; }
+        case 2: total += 2.0 * N * sT + N / 8.0 * sT; break;
+        case 3: total += N * 8.0; break;
+        case 4: total += 2.0 * N * 8.0 + coef * 2.0; break;
+        default: total += 2.0 * N * 8.0 + coef * 2.0 + 2.0 * N * 4.0; break;
+        }
+    }
+    return total;
+}
+
 template <typename T>
 static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o) {
     hipStream_t s = ctx->stream;
@@ -801,13 +829,13 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
         if (pp.nd) {
             for (int q = 0; q < o->nu_pre; q++)
                 for (int col = 0; col < 2; col++)
-                    timed(ctx, "gsrb", (double)pp.ntiles, [&] {
+                    timed(ctx, "gsrb", plan_bytes(S, pp, sizeof(T) == 4, 0), [&] {
                         k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, st);
                     });
         }
         const HPlan &pr = S.restr[l];
         if (pr.nd)
-            timed(ctx, "resid_restrict", (double)pr.ntiles, [&] {
+            timed(ctx, "resid_restrict", plan_bytes(S, pr, sizeof(T) == 4, 1), [&] {
                 k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st);
             });
     }
@@ -818,14 +846,14 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
     for (int l = S.Lmax - 1; l >= 0; l--) {
         const HPlan &pp = S.prolong[l];
         if (pp.nd)
-            timed(ctx, "prolong", (double)pp.ntiles, [&] {
+            timed(ctx, "prolong", plan_bytes(S, pp, sizeof(T) == 4, 2), [&] {
                 k_prolong<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), st);
             });
         const HPlan &ps = S.pre[l];
         if (ps.nd) {
             for (int q = 0; q < o->nu_post; q++)
                 for (int col = 0; col < 2; col++)
-                    timed(ctx, "gsrb", (double)ps.ntiles, [&] {
+                    timed(ctx, "gsrb", plan_bytes(S, ps, sizeof(T) == 4, 0), [&] {
                         k_gsrb<T><<<xcd_grid(ps.ntiles), kBlock, 0, s>>>(dT, ps.dev(), col, st);
                     });
         }
@@ -835,7 +863,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
 static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
-    timed(ctx, "norm", (double)pl.ntiles, [&] {
+    timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
         if (mode == 0)
             k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
         else if (mode == 1)
@@ -899,7 +927,7 @@ vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const 
                 launch_finalize(ctx, *S, 1, o, o->ir_inner);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
                 for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, *S, S->d32.p, o);
-                timed(ctx, "ir_update", 0.0, [&] {
+                timed(ctx, "ir_update", plan_bytes(*S, S->all0, false, 3) * 2.5, [&] {
                     k_ir_update<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->d32.p, S->all0.dev(), S->st.p);
                 });
             }

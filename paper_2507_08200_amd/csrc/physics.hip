@@ -483,7 +483,10 @@ __global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
 
 // ----------------------------------------------------- host launchers
 void launch_transport(vd_ctx *ctx, const TransportArgs &a) {
-    timed(ctx, "transport", (double)a.g.ncell, [&] {
+    // phi read, Te written (table or energy mode), mu and D written per field-dependent species
+    double bytes = (double)a.g.ncell * (8.0 + (a.te_mode != VD_TE_FIXED ? 8.0 : 8.0) + 16.0 * a.nvar + (a.beta_e ? 8.0 : 0.0) +
+                                        (a.te_mode == VD_TE_ENERGY ? 16.0 : 0.0));
+    timed(ctx, "transport", bytes, [&] {
         k_transport<<<ceil_div(a.g.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
     });
 }
@@ -493,15 +496,25 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
     VD_CHECK(nfields <= kMaxFields, "too many fields");
     a.f = (const FieldDesc *)upload_blob(ctx, std::string("fields:") + tag, fields, sizeof(FieldDesc) * nfields);
     dim3 grid(ceil_div(a.g.ncell, kBlock), nfields);
-    timed(ctx, "weno", (double)a.g.ncell * nfields, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
+    // per field: u read, mobility read when per cell, output written, and in
+    // right-hand-side mode the chemical source (and extra source, and u0 when
+    // it is not u) read; phi read once for all fields
+    double bytes = 8.0 * a.g.ncell;
+    for (int f = 0; f < nfields; f++) {
+        const FieldDesc &F = fields[f];
+        double per = 16.0 + (F.mu ? 8.0 : 0.0);
+        if (a.mode == 1) per += (F.src ? 8.0 : 0.0) + (F.extra ? 8.0 : 0.0) + (F.u0 != F.u ? 8.0 : 0.0);
+        bytes += per * a.g.ncell;
+    }
+    timed(ctx, "weno", bytes, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
 }
 
 void launch_react(vd_ctx *ctx, const ReactArgs &a) {
-    timed(ctx, "react", (double)a.ncell, [&] { k_react<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+    timed(ctx, "react", (double)a.ncell * 8.0 * (2.0 * a.S + 1.0 + (a.S_inel ? 1.0 : 0.0)), [&] { k_react<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
 }
 
 void launch_rho(vd_ctx *ctx, const RhoArgs &a) {
-    timed(ctx, "rho", (double)a.ncell, [&] { k_rho<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+    timed(ctx, "rho", (double)a.ncell * 8.0 * (a.S + 1.0), [&] { k_rho<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
 }
 
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
@@ -509,7 +522,7 @@ void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
 }
 
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n) {
-    timed(ctx, "mid", (double)n, [&] { k_mid<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(u0, u, out, n); });
+    timed(ctx, "mid", (double)n * 24.0, [&] { k_mid<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(u0, u, out, n); });
 }
 
 GridDev make_grid(const vd_grid &g, const vd_bc &phi_bc) {

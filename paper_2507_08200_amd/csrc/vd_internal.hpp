@@ -104,13 +104,20 @@ struct Plan {
 constexpr int kBlock = 256;
 
 // ------------------------------------------------------- kernel timing
-struct Timing {
-    std::string family;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    std::vector<hipEvent_t> pool;
+struct TimingAcc {
     int64_t launches = 0;
     double total_ms = 0.0;
-    double units = 0.0;
+    double units = 0.0;      // algorithmic bytes (or cells) summed over launches
+};
+struct TimingPending {
+    std::string family;
+    hipEvent_t a, b;
+};
+struct Timing {
+    std::vector<std::string> families;          // selected kernel families
+    std::map<std::string, TimingAcc> acc;
+    std::vector<TimingPending> pending;
+    std::vector<hipEvent_t> pool;
 };
 
 }  // namespace vd
@@ -159,19 +166,20 @@ inline const void *upload_blob(vd_ctx *ctx, const std::string &key, const void *
 
 // Kernel timing hooks (host).  begin() returns true when the family matches.
 bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *ev1);
-void timing_end(vd_ctx *ctx, hipEvent_t ev0, hipEvent_t ev1, double units);
 void timing_flush(vd_ctx *ctx);
+
+void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units);
 
 template <typename F>
 inline void timed(vd_ctx *ctx, const char *family, double units, F &&launch) {
-    hipEvent_t a, b;
-    bool on = timing_begin(ctx, family, &a, &b);
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = !ctx->timing.families.empty() && timing_begin(ctx, family, &a, &b);
     if (on) VD_HIP(hipEventRecord(a, ctx->stream));
     launch();
     VD_HIP(hipGetLastError());
     if (on) {
         VD_HIP(hipEventRecord(b, ctx->stream));
-        timing_end(ctx, a, b, units);
+        timing_end(ctx, family, a, b, units);
     }
 }
 

@@ -121,7 +121,7 @@ def load():
         "vd_cell_flags": ([P, P, i32, i32, P], i32),
         "vd_smooth": ([P, P, i32], i32),
         "vd_timing_select": ([P, C.c_char_p], i32),
-        "vd_timing_read": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
+        "vd_timing_read": ([P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -290,12 +290,14 @@ class Context:
                     float(problem.get("beta_c", 0.0)), _dptr(problem["rhs"], shp), _dptr(problem["x"], shp))
         self._check(self.lib.vd_smooth(self.h, C.byref(p), int(ncolour)))
 
-    def vd_timing_select(self, kernel):
-        self._check(self.lib.vd_timing_select(self.h, kernel.encode() if kernel else None))
+    def vd_timing_select(self, kernels):
+        """kernels: comma-separated kernel families, or None to stop timing."""
+        self._check(self.lib.vd_timing_select(self.h, kernels.encode() if kernels else None))
 
-    def vd_timing_read(self):
+    def vd_timing_read(self, kernel):
+        """(launches, total device ms, algorithmic bytes) of one family."""
         n, ms, u = C.c_int64(), C.c_double(), C.c_double()
-        self._check(self.lib.vd_timing_read(self.h, C.byref(n), C.byref(ms), C.byref(u)))
+        self._check(self.lib.vd_timing_read(self.h, kernel.encode(), C.byref(n), C.byref(ms), C.byref(u)))
         return n.value, ms.value, u.value
 
 
