@@ -25,7 +25,6 @@
 namespace vd {
 
 constexpr int kCoarseMax = 4096;     // levels at or below this size run in the fused kernel
-constexpr int kFusedThreads = 1024;
 constexpr int kBottomMaxIt = 500;
 constexpr double kBottomTol = 1e-14;
 
@@ -81,68 +80,76 @@ __device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C,
 }
 
 // ------------------------------------------------------------ grid kernels
+// Cells (or row pairs) per thread in each tile of the persistent loops.
+constexpr int kGsrbU = 1;       // GSRB: 256 row pairs (512 cells) per tile
+constexpr int kRestrictU = 1;   // restriction: 256 coarse cells per tile
+constexpr int kProlongU = 2;    // prolongation: 512 fine cells per tile
+constexpr int kNormU = 4;       // norms, prep, refinement update: 1024 cells per tile
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gsrb(const LevDesc *__restrict__ descs, Plan pl, int colour,
                                                  const ProbState *__restrict__ st) {
-    int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    const LevDesc &L = descs[pl.ids[d]];
-    if (!st[L.prob].active) return;
-    int lt = t - pl.prefix[d];
-    if ((L.nx & 1) == 0) {
-        // one thread per pair (2m, 2m+1) of a row; exactly one has the colour
-        int q = lt * kBlock + threadIdx.x;
-        int c0 = 2 * q;
-        if (c0 >= L.ncell) return;
-        int i, j, k;
-        cell_ijk(L, c0, i, j, k);
-        int off = ((i + j + k) & 1) != colour;
-        gs_update<T>(L, c0 + off, i + off, j, k);
-    } else {
-        int c = lt * kBlock + threadIdx.x;
-        if (c >= L.ncell) return;
-        int i, j, k;
-        cell_ijk(L, c, i, j, k);
-        if (((i + j + k) & 1) != colour) return;
-        gs_update<T>(L, c, i, j, k);
-    }
+    for_tiles(pl, [&](int d, int lt, int) {
+        const LevDesc &L = descs[pl.ids[d]];
+        if (!st[L.prob].active) return;
+        if ((L.nx & 1) == 0) {
+            // one thread per pair (2m, 2m+1) of a row; exactly one has the colour
+            for (int u = 0; u < kGsrbU; u++) {
+                int c0 = 2 * ((lt * kGsrbU + u) * kBlock + (int)threadIdx.x);
+                if (c0 >= L.ncell) break;
+                int i, j, k;
+                cell_ijk(L, c0, i, j, k);
+                int off = ((i + j + k) & 1) != colour;
+                gs_update<T>(L, c0 + off, i + off, j, k);
+            }
+        } else {
+            for (int u = 0; u < kGsrbU; u++) {
+                int c = (lt * kGsrbU + u) * kBlock + threadIdx.x;
+                if (c >= L.ncell) break;
+                int i, j, k;
+                cell_ijk(L, c, i, j, k);
+                if (((i + j + k) & 1) == colour) gs_update<T>(L, c, i, j, k);
+            }
+        }
+    });
 }
 
 // plan over COARSE descriptors; fine = descs[id - 1]
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__ descs, Plan pl,
                                                      const ProbState *__restrict__ st) {
-    int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    int id = pl.ids[d];
-    const LevDesc &C = descs[id];
-    if (!st[C.prob].active) return;
-    const LevDesc &F = descs[id - 1];
-    int cc = (t - pl.prefix[d]) * kBlock + threadIdx.x;
-    if (cc >= C.ncell) return;
-    int I, J, K;
-    cell_ijk(C, cc, I, J, K);
-    restrict_cell<T>(F, C, cc, I, J, K);
+    for_tiles(pl, [&](int d, int lt, int) {
+        int id = pl.ids[d];
+        const LevDesc &C = descs[id];
+        if (!st[C.prob].active) return;
+        const LevDesc &F = descs[id - 1];
+        for (int u = 0; u < kRestrictU; u++) {
+            int cc = (lt * kRestrictU + u) * kBlock + threadIdx.x;
+            if (cc >= C.ncell) break;
+            int I, J, K;
+            cell_ijk(C, cc, I, J, K);
+            restrict_cell<T>(F, C, cc, I, J, K);
+        }
+    });
 }
 
 // plan over FINE descriptors; coarse = descs[id + 1]
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const LevDesc *__restrict__ descs, Plan pl,
                                                     const ProbState *__restrict__ st) {
-    int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    int id = pl.ids[d];
-    const LevDesc &F = descs[id];
-    if (!st[F.prob].active) return;
-    const LevDesc &C = descs[id + 1];
-    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
-    if (c >= F.ncell) return;
-    int i, j, k;
-    cell_ijk(F, c, i, j, k);
-    prolong_cell<T>(F, C, c, i, j, k);
+    for_tiles(pl, [&](int d, int lt, int) {
+        int id = pl.ids[d];
+        const LevDesc &F = descs[id];
+        if (!st[F.prob].active) return;
+        const LevDesc &C = descs[id + 1];
+        for (int u = 0; u < kProlongU; u++) {
+            int c = (lt * kProlongU + u) * kBlock + threadIdx.x;
+            if (c >= F.ncell) break;
+            int i, j, k;
+            cell_ijk(F, c, i, j, k);
+            prolong_cell<T>(F, C, c, i, j, k);
+        }
+    });
 }
 
 // Sum of squares of the lifted right-hand side (mode 0) or of the FP64
@@ -154,58 +161,234 @@ __global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64
                                                  Plan pl, double *__restrict__ partials,
                                                  const ProbState *__restrict__ st, int check_active) {
     __shared__ double lds[kBlock / 64];
-    int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    int id = pl.ids[d];
-    const LevDesc &L = d64[id];
-    if (check_active && !st[L.prob].active) return;
-    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
-    double v = 0.0;
-    if (c < L.ncell) {
-        int i, j, k;
-        cell_ijk(L, c, i, j, k);
-        bool valid = !(L.has_mask && !L.mask[c]);
-        double r;
-        if (MODE == 0) r = valid ? load_b<double>(L, c, i, j, k) : 0.0;
-        else r = residual_at<double>(L, c, i, j, k);
-        v = r * r;
-        if (MODE == 2) {
-            const LevDesc &E = d32[id];
-            ((float *)E.b)[c] = (float)r;
-            ((float *)E.x)[c] = 0.0f;
+    for_tiles(pl, [&](int d, int lt, int t) {
+        int id = pl.ids[d];
+        const LevDesc &L = d64[id];
+        if (check_active && !st[L.prob].active) return;
+        double v = 0.0;
+        for (int u = 0; u < kNormU; u++) {
+            int c = (lt * kNormU + u) * kBlock + threadIdx.x;
+            if (c >= L.ncell) break;
+            int i, j, k;
+            cell_ijk(L, c, i, j, k);
+            bool valid = !(L.has_mask && !L.mask[c]);
+            double r;
+            if (MODE == 0) r = valid ? load_b<double>(L, c, i, j, k) : 0.0;
+            else r = residual_at<double>(L, c, i, j, k);
+            v += r * r;
+            if (MODE == 2) {
+                const LevDesc &E = d32[id];
+                ((float *)E.b)[c] = (float)r;
+                ((float *)E.x)[c] = 0.0f;
+            }
         }
-    }
-    double s = block_sum(v, lds);
-    if (threadIdx.x == 0) partials[t] = s;
+        double s = block_sum(v, lds);
+        if (threadIdx.x == 0) partials[t] = s;
+    });
 }
 
 // x = 0 on covered cells, on problems whose right-hand side vanishes, and
 // everywhere for a zero initial guess.
 __global__ void __launch_bounds__(kBlock) k_prep(const LevDesc *__restrict__ d64, Plan pl,
                                                  const ProbState *__restrict__ st, int zero_guess) {
-    int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    const LevDesc &L = d64[pl.ids[d]];
-    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
-    if (c >= L.ncell) return;
-    bool covered = L.has_mask && !L.mask[c];
-    if (zero_guess || covered || st[L.prob].bnorm == 0.0) ((double *)L.x)[c] = 0.0;
+    for_tiles(pl, [&](int d, int lt, int) {
+        const LevDesc &L = d64[pl.ids[d]];
+        const bool all = zero_guess || st[L.prob].bnorm == 0.0;
+        if (!all && !L.has_mask) return;
+        for (int u = 0; u < kNormU; u++) {
+            int c = (lt * kNormU + u) * kBlock + threadIdx.x;
+            if (c >= L.ncell) break;
+            if (all || !L.mask[c]) ((double *)L.x)[c] = 0.0;
+        }
+    });
 }
 
 // x64 += e32 after the inner FP32 cycles of an outer refinement step.
 __global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict__ d64, const LevDesc *__restrict__ d32,
                                                       Plan pl, const ProbState *__restrict__ st) {
-    int t = xcd_tile(pl.ntiles);
+    for_tiles(pl, [&](int d, int lt, int) {
+        int id = pl.ids[d];
+        const LevDesc &L = d64[id];
+        if (!st[L.prob].active) return;
+        const float *e = (const float *)d32[id].x;
+        double *x = (double *)L.x;
+        for (int u = 0; u < kNormU; u++) {
+            int c = (lt * kNormU + u) * kBlock + threadIdx.x;
+            if (c >= L.ncell) break;
+            x[c] += (double)e[c];
+        }
+    });
+}
+
+// ------------------------------------------------ 2.5D LDS-tiled stencils
+// A workgroup owns a 32 x 16 tile of x-y planes and marches kz planes in z.
+// Each thread holds one row pair (i, i+1) in registers for planes k-1, k,
+// k+1 (wide loads); the x-y neighbours of plane k come from an LDS copy of
+// the tile with a one-cell halo.  Every element is fetched from memory once
+// per pass (plus the halo).  Needs an even nx (row pairs).
+constexpr int kT25X = 32, kT25Y = 16, kT25W = kT25X + 2;
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { using V = double2; };
+template <> struct Pair<float> { using V = float2; };
+
+// value at (i, j, k) with periodic wrap; 0 across a non-periodic face
+template <typename T>
+__device__ __forceinline__ T ld_wrap(const LevDesc &L, const T *__restrict__ X, int i, int j, int k) {
+    if (i < 0 || i >= L.nx) { if (L.kind[0] != VD_BC_PERIODIC) return (T)0; i = i < 0 ? i + L.nx : i - L.nx; }
+    if (j < 0 || j >= L.ny) { if (L.kind[2] != VD_BC_PERIODIC) return (T)0; j = j < 0 ? j + L.ny : j - L.ny; }
+    if (k < 0 || k >= L.nz) { if (L.kind[4] != VD_BC_PERIODIC) return (T)0; k = k < 0 ? k + L.nz : k - L.nz; }
+    return X[i + (long)L.nx * j + (long)L.nxy * k];
+}
+
+// the two values of row pair (ia, ia+1) of row j in plane k: a wide load
+// for pairs inside the domain, wrapped (or zero) values otherwise
+template <typename T>
+__device__ __forceinline__ void ld_slot(const LevDesc &L, const T *__restrict__ X, int ia, int j, int k, bool own, T &a,
+                                        T &b) {
+    if (!own) {
+        a = ld_wrap<T>(L, X, ia, j, k);
+        b = ld_wrap<T>(L, X, ia + 1, j, k);
+        return;
+    }
+    if (k < 0 || k >= L.nz) {
+        if (L.kind[4] != VD_BC_PERIODIC) { a = b = (T)0; return; }
+        k = k < 0 ? k + L.nz : k - L.nz;
+    }
+    typename Pair<T>::V v = *(const typename Pair<T>::V *)(X + ia + (long)L.nx * j + (long)L.nxy * k);
+    a = v.x;
+    b = v.y;
+}
+
+// halo value of plane k loaded by thread tid (< 96): x-halo columns for
+// tid < 32, y-halo rows otherwise
+template <typename T>
+__device__ __forceinline__ T ld_halo(const LevDesc &L, const T *__restrict__ X, int tid, int i0, int j0, int k) {
+    if (tid < 2 * kT25Y) {
+        const int rr = tid & (kT25Y - 1), side = tid / kT25Y;
+        return ld_wrap<T>(L, X, side ? i0 + kT25X : i0 - 1, j0 + rr, k);
+    }
+    const int q = tid - 2 * kT25Y, cc = q & (kT25X - 1), side = q / kT25X;
+    return ld_wrap<T>(L, X, i0 + cc, side ? j0 + kT25Y : j0 - 1, k);
+}
+
+template <typename T>
+__device__ __forceinline__ int halo_slot(int tid) {
+    if (tid < 2 * kT25Y) {
+        const int rr = tid & (kT25Y - 1), side = tid / kT25Y;
+        return (rr + 1) * kT25W + (side ? kT25X + 1 : 0);
+    }
+    const int q = tid - 2 * kT25Y, cc = q & (kT25X - 1), side = q / kT25X;
+    return (side ? kT25Y + 1 : 0) * kT25W + cc + 1;
+}
+
+// MODE 0: one Gauss-Seidel colour pass (in place); MODE 1: FP64 residual
+// norm partials; MODE 2: same, also storing the FP32 residual and clearing
+// the FP32 unknown (iterative refinement).  Software-pipelined: while plane
+// k is computed, plane k+2's pair, plane k+1's halo and plane k+1's b are in
+// flight; the LDS tile is double-buffered so one barrier per plane suffices.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
+                                                 int kz, int colour, double *__restrict__ partials,
+                                                 const ProbState *__restrict__ st, int check_active) {
+    __shared__ T xs[2][(kT25Y + 2) * kT25W];
+    __shared__ double red[kBlock / 64];
+    const int t = xcd_tile(pl.ntiles);
     if (t >= pl.ntiles) return;
-    int d = plan_find(pl, t);
-    int id = pl.ids[d];
-    const LevDesc &L = d64[id];
-    if (!st[L.prob].active) return;
-    int c = (t - pl.prefix[d]) * kBlock + threadIdx.x;
-    if (c >= L.ncell) return;
-    ((double *)L.x)[c] += (double)((const float *)d32[id].x)[c];
+    const int d = plan_find(pl, t);
+    const int id = pl.ids[d];
+    const LevDesc &L = descs[id];
+    if ((MODE == 0 || check_active) && !st[L.prob].active) return;
+    int lt = t - pl.prefix[d];
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int ntx = (nx + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
+    const int tx = lt % ntx;
+    lt /= ntx;
+    const int ty = lt % nty;
+    const int zc = lt / nty;
+    const int i0 = tx * kT25X, j0 = ty * kT25Y, k0 = zc * kz;
+    const int k1 = min(k0 + kz, nz);
+    const int tid = threadIdx.x;
+    const int tp = tid & 15, r = tid >> 4;
+    const int ia = i0 + 2 * tp, j = j0 + r;
+    const bool own = ia < nx && j < ny;
+    const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
+    const int hslot = halo_slot<T>(tid);
+    T *X = (T *)L.x;
+    const T *B = (const T *)L.b;
+    T xm0, xm1, xc0, xc1, xp0, xp1;
+    ld_slot<T>(L, X, ia, j, k0 - 1, own, xm0, xm1);
+    ld_slot<T>(L, X, ia, j, k0, own, xc0, xc1);
+    ld_slot<T>(L, X, ia, j, k0 + 1, own, xp0, xp1);
+    T hcur = halo_thread ? ld_halo<T>(L, X, tid, i0, j0, k0) : (T)0;
+    T bc0 = 0, bc1 = 0;
+    const long rowoff = (long)nx * j;
+    if (own) {
+        typename Pair<T>::V bv = *(const typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * k0);
+        bc0 = bv.x;
+        bc1 = bv.y;
+    }
+    double v = 0.0;
+    for (int k = k0; k < k1; k++) {
+        T *buf = xs[k & 1];
+        buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
+        buf[(r + 1) * kT25W + 2 * tp + 2] = xc1;
+        if (halo_thread) buf[hslot] = hcur;
+        // prefetch for the next plane
+        T xq0, xq1, hnext = (T)0, bn0 = (T)0, bn1 = (T)0;
+        ld_slot<T>(L, X, ia, j, k + 2, own, xq0, xq1);
+        if (k + 1 < k1) {
+            if (halo_thread) hnext = ld_halo<T>(L, X, tid, i0, j0, k + 1);
+            if (own) {
+                typename Pair<T>::V bv = *(const typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * (k + 1));
+                bn0 = bv.x;
+                bn1 = bv.y;
+            }
+        }
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const int i = ia + q;
+                if (MODE == 0 && ((i + j + k) & 1) != colour) continue;
+                const int c = i + nx * j + L.nxy * k;
+                const bool valid = !(L.has_mask && !L.mask[c]);
+                if (MODE == 0 && !valid) continue;
+                T nbv[6];
+                nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
+                nbv[1] = q == 0 ? xc1 : buf[(r + 1) * kT25W + 2 * tp + 3];
+                nbv[2] = buf[r * kT25W + 2 * tp + 1 + q];
+                nbv[3] = buf[(r + 2) * kT25W + 2 * tp + 1 + q];
+                nbv[4] = q == 0 ? xm0 : xm1;
+                nbv[5] = q == 0 ? xp0 : xp1;
+                T dg, of;
+                row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
+                T b = q == 0 ? bc0 : bc1;
+                if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
+                if (MODE == 0) {
+                    X[c] = (b + of) / dg;
+                } else {
+                    const T xv = q == 0 ? xc0 : xc1;
+                    const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
+                    v += rv * rv;
+                    if (MODE == 2) {
+                        const LevDesc &E = d32[id];
+                        ((float *)E.b)[c] = (float)rv;
+                        ((float *)E.x)[c] = 0.0f;
+                    }
+                }
+            }
+        }
+        xm0 = xc0; xm1 = xc1;
+        xc0 = xp0; xc1 = xp1;
+        xp0 = xq0; xp1 = xq1;
+        hcur = hnext;
+        bc0 = bn0; bc1 = bn1;
+    }
+    if (MODE != 0) {
+        const double sum = block_sum(v, red);
+        if (tid == 0) partials[t] = sum;
+    }
 }
 
 __global__ void k_state_init(ProbState *st, int n) {
@@ -253,8 +436,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Plan pl, const int *__restr
 // ---------------------------------------------------- fused coarse kernel
 struct FusedDesc {
     int prob, lc, L, base;     // base = index of level 0 in the descriptor arrays
-    double *pcg;               // FP64 scratch: 6 * bottom cells
+    double *pcg;               // FP64 scratch: 6 * bottom cells (used when not in LDS)
 };
+
+constexpr int kFusedThreads = 256;
+constexpr int kPcgLdsCells = 768;    // bottom levels up to this size keep the CG vectors in LDS
 
 template <typename T>
 __device__ void block_sweep(const LevDesc &L, int colour) {
@@ -266,41 +452,53 @@ __device__ void block_sweep(const LevDesc &L, int colour) {
     __syncthreads();
 }
 
-// Jacobi-preconditioned CG in FP64 on the coarsest level, from a zero guess.
+// two deterministic block sums with one pair of barriers
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds) {
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_xor(a, o, 64); b += __shfl_xor(b, o, 64); }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { lds[2 * w] = a; lds[2 * w + 1] = b; }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; q++) { sa += lds[2 * q]; sb += lds[2 * q + 1]; }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
+// Jacobi-preconditioned CG in FP64 on the coarsest level, from a zero guess,
+// to ||r|| <= 1e-14 ||b|| or 500 iterations.  vec: 6 n doubles (LDS or global).
 template <typename T>
-__device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *scr, double *lds) {
+__device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *vec, double *red) {
     const int n = A64.ncell;
-    double *r = scr, *z = scr + n, *p = scr + 2 * n, *q = scr + 3 * n, *dg = scr + 4 * n, *xb = scr + 5 * n;
+    double *r = vec, *z = vec + n, *p = vec + 2 * n, *q = vec + 3 * n, *dg = vec + 4 * n, *xb = vec + 5 * n;
     const T *bT = (const T *)AT.b;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        int i, j, k;
-        cell_ijk(A64, c, i, j, k);
-        double d, of;
-        row_terms<double, double>(A64, xb, i, j, k, c, d, of);   // xb unused by diag
-        dg[c] = d;
         bool valid = !(A64.has_mask && !A64.mask[c]);
         r[c] = valid ? (double)bT[c] : 0.0;
         xb[c] = 0.0;
     }
     __syncthreads();
-    double v = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) v += r[c] * r[c];
-    double bn = sqrt(block_sum(v, lds));
-    v = 0.0;
+    double rr = 0.0, rz = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int i, j, k;
+        cell_ijk(A64, c, i, j, k);
+        double d, of;
+        row_terms<double, double>(A64, xb, i, j, k, c, d, of);   // xb is zero: only the diagonal is used
+        dg[c] = d;
         bool valid = !(A64.has_mask && !A64.mask[c]);
-        double zz = valid ? r[c] / dg[c] : 0.0;
+        double zz = valid ? r[c] / d : 0.0;
         z[c] = zz;
         p[c] = zz;
-        v += r[c] * zz;
+        rr += r[c] * r[c];
+        rz += r[c] * zz;
     }
-    double rz = block_sum(v, lds);
+    block_sum2(rr, rz, red);
+    const double bn = sqrt(rr);
     for (int it = 0; it < kBottomMaxIt; it++) {
-        v = 0.0;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) v += r[c] * r[c];
-        double rn = sqrt(block_sum(v, lds));
-        if (!(rn > kBottomTol * bn)) break;
-        v = 0.0;
+        if (!(sqrt(rr) > kBottomTol * bn)) break;
+        double v = 0.0;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
             double qq = 0.0;
             if (!(A64.has_mask && !A64.mask[c])) {
@@ -313,21 +511,24 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *scr, do
             q[c] = qq;
             v += p[c] * qq;
         }
-        double pq = block_sum(v, lds);
+        double pq = block_sum(v, red);
         if (pq == 0.0) break;
-        double a = rz / pq;
-        v = 0.0;
+        const double a = rz / pq;
+        double rz_new = 0.0, rr_new = 0.0;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
             xb[c] += a * p[c];
-            r[c] -= a * q[c];
+            double rc = r[c] - a * q[c];
+            r[c] = rc;
             bool valid = !(A64.has_mask && !A64.mask[c]);
-            double zz = valid ? r[c] / dg[c] : 0.0;
+            double zz = valid ? rc / dg[c] : 0.0;
             z[c] = zz;
-            v += r[c] * zz;
+            rz_new += rc * zz;
+            rr_new += rc * rc;
         }
-        double rz_new = block_sum(v, lds);
-        double bcoef = rz_new / rz;
+        block_sum2(rz_new, rr_new, red);
+        const double bcoef = rz_new / rz;
         rz = rz_new;
+        rr = rr_new;
         for (int c = threadIdx.x; c < n; c += blockDim.x) p[c] = z[c] + bcoef * p[c];
         __syncthreads();
     }
@@ -339,8 +540,9 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *scr, do
 template <typename T>
 __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
                                                           const FusedDesc *__restrict__ fd, const ProbState *__restrict__ st,
-                                                          int nu_pre, int nu_post) {
-    __shared__ double lds[kFusedThreads / 64];
+                                                          int nu_pre, int nu_post, int pcg_in_lds) {
+    __shared__ double red[2 * (kFusedThreads / 64)];
+    extern __shared__ double pcg_lds[];
     const FusedDesc f = fd[blockIdx.x];
     if (!st[f.prob].active) return;
     const int base = f.base, lc = f.lc, L = f.L;
@@ -360,7 +562,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
         }
         __syncthreads();
     }
-    block_pcg<T>(d64[base + L - 1], dT[base + L - 1], f.pcg, lds);
+    block_pcg<T>(d64[base + L - 1], dT[base + L - 1], pcg_in_lds ? pcg_lds : f.pcg, red);
     for (int l = L - 2; l >= lc; l--) {
         const LevDesc &A = dT[base + l];
         const LevDesc &C = dT[base + l + 1];
@@ -511,6 +713,7 @@ struct HProblem {
 struct HPlan {
     DevBuf<int> ids, prefix;
     int nd = 0, ntiles = 0;
+    int kz = 0;                  // 2.5D tiled plans: planes per workgroup
     std::vector<int> h_ids, h_prefix;
     Plan dev() const { return Plan{ids.p, prefix.p, nd, ntiles}; }
 };
@@ -526,10 +729,14 @@ struct Solver {
     DevBuf<double> partials;
     DevBuf<FusedDesc> fused;
     int nfused = 0;
+    size_t pcg_lds_bytes = 0;     // dynamic LDS of the fused kernel (0: CG vectors in global memory)
     DevBuf<int> prob_of;
     HPlan all0;                                  // finest level, every problem
     std::vector<HPlan> pre, restr, prolong;      // per level
+    HPlan all0_25;                               // finest level as 2.5D tiles (residual norms), if usable
+    std::vector<HPlan> pre25;                    // smoother levels as 2.5D tiles, if usable
     std::vector<char> key;                       // problem bytes the descriptors were built from
+    bool aligned = true;                         // finest-level unknowns 16-byte aligned (row-pair loads)
     ~Solver() {
         if (pin64) (void)hipHostFree(pin64);
         if (pin32) (void)hipHostFree(pin32);
@@ -590,7 +797,16 @@ static void validate(int nprob, const vd_problem *probs, const vd_mg_opts *o) {
             VD_CHECK((a == VD_BC_PERIODIC) == (b == VD_BC_PERIODIC), "periodic must be set on both faces of a direction");
         }
         VD_CHECK(P.rhs != nullptr && P.x != nullptr, "rhs and x are required");
-        VD_CHECK(count_levels(g, o->n_levels) >= 1, "n_levels not compatible with the grid (dimensions must stay even)");
+        const int L = count_levels(g, o->n_levels);
+        VD_CHECK(L >= 1, "n_levels not compatible with the grid (dimensions must stay even)");
+        // red-black ordering is only a valid parallel colouring if a periodic
+        // direction has an even number of cells on every smoothed level
+        const int nd[3] = {g.nx, g.ny, g.nz};
+        for (int d = 0; d < 3; d++) {
+            if (P.bc.kind[2 * d] != VD_BC_PERIODIC) continue;
+            for (int l = 0; l <= std::max(L - 2, 0); l++)
+                VD_CHECK(((nd[d] >> l) % 2) == 0, "periodic direction needs an even cell count on every smoothed level");
+        }
         bool dir = false;
         for (int f = 0; f < 6; f++) dir = dir || P.bc.kind[f] == VD_BC_DIRICHLET;
         if (!P.alpha && P.alpha_c == 0.0 && !P.mask && !dir)
@@ -702,22 +918,56 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
     S->prolong.resize(Lmax);
     std::vector<FusedDesc> fds;
     std::vector<int> prob_of;
+    long max_bottom = 0;
     for (int p = 0; p < nprob; p++) {
         HProblem &H = S->probs[p];
         int base = p * Lmax;
         long n0 = (long)H.lv[0].nx * H.lv[0].ny * H.lv[0].nz;
-        plan_add(S->all0, base, n0, kBlock);
+        plan_add(S->all0, base, n0, kNormU * kBlock);
         prob_of.push_back(p);
         for (int l = 0; l < H.lc; l++) {
             long n = (long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz;
-            plan_add(S->pre[l], base + l, (H.lv[l].nx % 2 == 0) ? (n + 1) / 2 : n, kBlock);
+            plan_add(S->pre[l], base + l, (H.lv[l].nx % 2 == 0) ? (n + 1) / 2 : n, kGsrbU * kBlock);
             if (H.L >= 2) {
                 long nc = (long)H.lv[l + 1].nx * H.lv[l + 1].ny * H.lv[l + 1].nz;
-                plan_add(S->restr[l], base + l + 1, nc, kBlock);
-                plan_add(S->prolong[l], base + l, n, kBlock);
+                plan_add(S->restr[l], base + l + 1, nc, kRestrictU * kBlock);
+                plan_add(S->prolong[l], base + l, n, kProlongU * kBlock);
             }
         }
         if (H.lc < H.L) fds.push_back(FusedDesc{p, H.lc, H.L, base, H.pcg.p});
+        if (H.L >= 2) {
+            const HLevel &Bt = H.lv[H.L - 1];
+            max_bottom = std::max(max_bottom, (long)Bt.nx * Bt.ny * Bt.nz);
+        }
+    }
+    // 2.5D tiled plans: usable when every level in the plan has an even nx;
+    // planes per workgroup chosen so that a launch has >= 2048 workgroups
+    auto build25 = [&](HPlan &out, const std::vector<std::pair<int, const HLevel *>> &items) {
+        if (items.empty()) return;
+        for (auto &it : items) if (it.second->nx % 2) return;
+        int kz = 2;
+        for (int cand : {16, 8, 4, 2}) {
+            long tot = 0;
+            for (auto &it : items)
+                tot += (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
+            if (tot >= 2048 || cand == 2) { kz = cand; break; }
+        }
+        out.kz = kz;
+        for (auto &it : items)
+            plan_add(out, it.first, (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) *
+                                        ceil_div(it.second->nz, kz), 1);
+        upload_plan(out, ctx->stream);
+    };
+    {
+        std::vector<std::pair<int, const HLevel *>> items;
+        for (int p = 0; p < nprob; p++) items.push_back({p * Lmax, &S->probs[p].lv[0]});
+        build25(S->all0_25, items);
+    }
+    S->pre25.resize(Lmax);
+    for (int l = 0; l < Lmax; l++) {
+        std::vector<std::pair<int, const HLevel *>> items;
+        for (int id : S->pre[l].h_ids) items.push_back({id, &S->probs[id / Lmax].lv[id % Lmax]});
+        build25(S->pre25[l], items);
     }
     upload_plan(S->all0, ctx->stream);
     for (int l = 0; l < Lmax; l++) {
@@ -725,8 +975,9 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         upload_plan(S->restr[l], ctx->stream);
         upload_plan(S->prolong[l], ctx->stream);
     }
-    S->partials.alloc(std::max(1, S->all0.ntiles));
+    S->partials.alloc(std::max(1, std::max(S->all0.ntiles, S->all0_25.ntiles)));
     S->nfused = (int)fds.size();
+    S->pcg_lds_bytes = (max_bottom > 0 && max_bottom <= kPcgLdsCells) ? (size_t)6 * max_bottom * sizeof(double) : 0;
     if (S->nfused) {
         S->fused.alloc(fds.size());
         VD_HIP(hipMemcpyAsync(S->fused.p, fds.data(), sizeof(FusedDesc) * fds.size(), hipMemcpyHostToDevice, ctx->stream));
@@ -754,6 +1005,9 @@ static void refresh_descs(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *p
         memcpy(S.pin32, S.h32.data(), sizeof(LevDesc) * S.h32.size());
         VD_HIP(hipMemcpyAsync(S.d32.p, S.pin32, sizeof(LevDesc) * S.h32.size(), hipMemcpyHostToDevice, ctx->stream));
     }
+    S.aligned = true;
+    for (int p = 0; p < nprob; p++)
+        S.aligned = S.aligned && ((uintptr_t)probs[p].x % 16 == 0) && ((uintptr_t)probs[p].rhs % 16 == 0);
     S.key = std::move(key);
 }
 
@@ -820,6 +1074,20 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) 
     return total;
 }
 
+// one Gauss-Seidel colour pass over level l of every problem in the plan
+template <typename T>
+static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
+    const HPlan &pp = S.pre[l];
+    const HPlan &p25 = S.pre25[l];
+    hipStream_t s = ctx->stream;
+    timed(ctx, "gsrb", plan_bytes(S, pp, sizeof(T) == 4, 0), [&] {
+        if (p25.nd && S.aligned)
+            k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1);
+        else
+            k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
+    });
+}
+
 template <typename T>
 static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o) {
     hipStream_t s = ctx->stream;
@@ -828,10 +1096,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
         const HPlan &pp = S.pre[l];
         if (pp.nd) {
             for (int q = 0; q < o->nu_pre; q++)
-                for (int col = 0; col < 2; col++)
-                    timed(ctx, "gsrb", plan_bytes(S, pp, sizeof(T) == 4, 0), [&] {
-                        k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, st);
-                    });
+                for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
         }
         const HPlan &pr = S.restr[l];
         if (pr.nd)
@@ -841,7 +1106,8 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
     }
     if (S.nfused)
         timed(ctx, "coarse", 0.0, [&] {
-            k_coarse<T><<<S.nfused, kFusedThreads, 0, s>>>(dT, S.d64.p, S.fused.p, st, o->nu_pre, o->nu_post);
+            k_coarse<T><<<S.nfused, kFusedThreads, S.pcg_lds_bytes, s>>>(dT, S.d64.p, S.fused.p, st, o->nu_pre, o->nu_post,
+                                                                          S.pcg_lds_bytes > 0);
         });
     for (int l = S.Lmax - 1; l >= 0; l--) {
         const HPlan &pp = S.prolong[l];
@@ -852,17 +1118,30 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
         const HPlan &ps = S.pre[l];
         if (ps.nd) {
             for (int q = 0; q < o->nu_post; q++)
-                for (int col = 0; col < 2; col++)
-                    timed(ctx, "gsrb", plan_bytes(S, ps, sizeof(T) == 4, 0), [&] {
-                        k_gsrb<T><<<xcd_grid(ps.ntiles), kBlock, 0, s>>>(dT, ps.dev(), col, st);
-                    });
+                for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
         }
     }
+}
+
+static const HPlan &norm_plan(const Solver &S, int mode) {
+    return (mode != 0 && S.all0_25.nd && S.aligned) ? S.all0_25 : S.all0;
 }
 
 static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
+    if (mode != 0 && S.all0_25.nd && S.aligned) {
+        const HPlan &p25 = S.all0_25;
+        timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
+            if (mode == 1)
+                k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                                                                          S.partials.p, S.st.p, check_active);
+            else
+                k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                                                                          S.partials.p, S.st.p, check_active);
+        });
+        return;
+    }
     timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
         if (mode == 0)
             k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
@@ -874,8 +1153,9 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
 }
 
 static void launch_finalize(vd_ctx *ctx, Solver &S, int mode, const vd_mg_opts *o, int inner) {
+    const HPlan &pl = norm_plan(S, mode);
     timed(ctx, "finalize", 0.0, [&] {
-        k_finalize<<<S.nprob, kBlock, 0, ctx->stream>>>(S.all0.dev(), S.prob_of.p, S.partials.p, S.st.p, mode, o->rtol,
+        k_finalize<<<S.nprob, kBlock, 0, ctx->stream>>>(pl.dev(), S.prob_of.p, S.partials.p, S.st.p, mode, o->rtol,
                                                         o->max_cycles, o->fixed_cycles, inner);
     });
 }

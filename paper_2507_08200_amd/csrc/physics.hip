@@ -144,6 +144,7 @@ __device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &
     const bool boundary = (fidx == 0 || fidx == n);
     const int kd = F.kind[2 * d + (fidx == 0 ? 0 : 1)];
     const double *__restrict__ u = F.u;
+    if (!F.mu && F.mu_c == 0.0) return 0.0;
     const double Ef = e_face(G, phi, d, c, pos, fidx);
     double muf;
     if (F.mu) {
@@ -208,6 +209,84 @@ __device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const dou
         total += (Fs[1] - Fs[0]) * G.ihl[d];
     }
     return total;
+}
+
+// Complete flux along +d through face fidx of the row starting at c0:
+// Neumann faces carry nothing, wall faces the wall flux of the adjacent
+// boundary cell (sign of the outward normal folded in), other faces the
+// upwind WENO5 drift flux.
+__device__ __forceinline__ double face_flux(const GridDev &G, const FieldDesc &F, const double *__restrict__ phi,
+                                            const double *__restrict__ Te, double Tg, double kB, double me, int d,
+                                            long c0, int fidx) {
+    const int n = G.n[d];
+    if (fidx == 0 || fidx == n) {
+        const int kd = F.kind[2 * d + (fidx == 0 ? 0 : 1)];
+        if (kd == VD_BC_NEUMANN) return 0.0;
+        if (kd == VD_BC_WALLFLUX) {
+            const long cb = c0 + (fidx == 0 ? 0 : (long)(n - 1) * G.stride[d]);
+            const double Ef = e_face(G, phi, d, (int)c0, 0, fidx);
+            const double e_n = fidx == 0 ? -Ef : Ef;
+            double fl;
+            if (F.ne_wall) fl = 2.0 * kB * Te[cb] * wall_flux(VD_WALL_ELECTRON, F.ne_wall[cb], 0.0, e_n, Te[cb], Tg, me, kB, me);
+            else fl = wall_flux(F.wall, F.u[cb], F.mu ? F.mu[cb] : F.mu_c, e_n, Te[cb], Tg, F.mass, kB, me);
+            return fidx == 0 ? -fl : fl;
+        }
+    }
+    return face_drift(G, F, phi, d, (int)c0, 0, fidx);
+}
+
+// Tiled drift divergence: a workgroup owns a kTX x kTY tile of an x-y plane
+// and marches kKZ planes in z.  Every face flux is evaluated once: x and y
+// faces go through LDS (the tile-edge faces are remapped onto the first
+// wave), the z face is carried from one plane to the next in a register.
+constexpr int kTX = 32, kTY = 8;
+
+__global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
+    __shared__ double fx[kTY * (kTX + 1)];
+    __shared__ double fy[(kTY + 1) * kTX];
+    const GridDev &G = a.g;
+    const FieldDesc &F = a.f[blockIdx.y];
+    const int nx = G.n[0], ny = G.n[1];
+    const int tiles_x = nx / kTX, tiles_y = ny / kTY;
+    int b = blockIdx.x;
+    const int bx = b % tiles_x;
+    b /= tiles_x;
+    const int by = b % tiles_y;
+    const int bz = b / tiles_y;
+    const int tx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;
+    const int i0 = bx * kTX, j0 = by * kTY, k0 = bz * kz;
+    const int i = i0 + tx, j = j0 + ty;
+    const long nxy = G.nxy;
+    const long col = i + (long)nx * j;                  // (i, j, 0)
+    // x faces: face f of row r of the tile, f in 0..kTX (kTY*(kTX+1) faces)
+    const int nfx = kTY * (kTX + 1), nfy = (kTY + 1) * kTX;
+    double fz_lo = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k0);
+    for (int k = k0; k < k0 + kz; k++) {
+        const long pl = nxy * k;
+        for (int q = threadIdx.x; q < nfx; q += kBlock) {
+            const int r = q / (kTX + 1), f = q - r * (kTX + 1);
+            fx[q] = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 0, pl + (long)nx * (j0 + r), i0 + f);
+        }
+        for (int q = threadIdx.x; q < nfy; q += kBlock) {
+            const int r = q / kTX, f = q - r * kTX;
+            fy[q] = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 1, pl + i0 + f, j0 + r);
+        }
+        const double fz_hi = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k + 1);
+        __syncthreads();
+        const double div = (fx[ty * (kTX + 1) + tx + 1] - fx[ty * (kTX + 1) + tx]) * G.ihl[0] +
+                           (fy[(ty + 1) * kTX + tx] - fy[ty * kTX + tx]) * G.ihl[1] + (fz_hi - fz_lo) * G.ihl[2];
+        const long c = col + pl;
+        if (a.mode == 0) {
+            F.out[c] = div;
+        } else {
+            double v = F.u0[c] * a.inv_dt - div;
+            if (F.src) v += F.src[c];
+            if (F.extra) v += F.extra[c];
+            F.out[c] = v;
+        }
+        fz_lo = fz_hi;
+        __syncthreads();
+    }
 }
 
 // blockIdx.y = field.  mode 0: out = div.  mode 1 (species / energy
@@ -506,7 +585,14 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
         if (a.mode == 1) per += (F.src ? 8.0 : 0.0) + (F.extra ? 8.0 : 0.0) + (F.u0 != F.u ? 8.0 : 0.0);
         bytes += per * a.g.ncell;
     }
-    timed(ctx, "weno", bytes, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    const int kz = (nz % 16 == 0) ? 16 : ((nz % 8 == 0) ? 8 : 0);
+    if (nx % kTX == 0 && ny % kTY == 0 && kz > 0) {
+        dim3 tg((nx / kTX) * (ny / kTY) * (nz / kz), nfields);
+        timed(ctx, "weno", bytes, [&] { k_drift_tiled<<<tg, kBlock, 0, ctx->stream>>>(a, kz); });
+    } else {
+        timed(ctx, "weno", bytes, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
+    }
 }
 
 void launch_react(vd_ctx *ctx, const ReactArgs &a) {

@@ -205,6 +205,34 @@ __device__ __forceinline__ int plan_find(const Plan &pl, int tile) {
     return lo;
 }
 
+// Upper bound of resident workgroups for the persistent grid kernels
+// (256 CUs x 8 workgroups of 256 threads).
+constexpr int kMaxGrid = 2048;
+
+inline int persistent_grid(int ntiles) {
+    int g = 8 * ceil_div(ntiles, 8);
+    return g < kMaxGrid ? g : kMaxGrid;
+}
+
+// Persistent, XCD-aware tile loop: workgroups are dealt round-robin to the 8
+// XCDs, so XCD x (= blockIdx.x mod 8) takes the contiguous tile range
+// [x*chunk, (x+1)*chunk) and its workgroups stride through it.  Neighbouring
+// tiles of a stencil therefore share that XCD's L2.  fn(d, local_tile) is
+// called with the plan entry d and the tile index within that entry.
+template <typename F>
+__device__ __forceinline__ void for_tiles(const Plan &pl, F &&fn) {
+    const int chunk = (pl.ntiles + 7) >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = gridDim.x >> 3;
+    const int t0 = xcd * chunk;
+    const int t1 = min(t0 + chunk, pl.ntiles);
+    int d = -1, lo = 0, hi = 0;
+    for (int t = t0 + (int)(blockIdx.x >> 3); t < t1; t += per_xcd) {
+        if (t < lo || t >= hi) { d = plan_find(pl, t); lo = pl.prefix[d]; hi = pl.prefix[d + 1]; }
+        fn(d, t - lo, t);
+    }
+}
+
 // ------------------------------------------------ the 7-point operator
 template <typename T> struct Coef;
 template <> struct Coef<double> {
@@ -255,6 +283,47 @@ __device__ __forceinline__ void row_terms(const LevDesc &L, const XT *__restrict
     VD_FACE(k > 0, (k > 0 ? c - L.nxy : c + L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * k], L.idz2, 4)
     VD_FACE(k < nz - 1, (k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * (k + 1)], L.idz2, 5)
 #undef VD_FACE
+    diag = dg;
+    off = of;
+}
+
+// Same row as row_terms, with the six neighbour values already gathered
+// (order x-, x+, y-, y+, z-, z+; a value across a non-periodic domain face
+// is ignored).  Covered neighbours are still read from the mask.
+template <typename T>
+__device__ __forceinline__ void row_terms_nb(const LevDesc &L, int i, int j, int k, int c, const T nbv[6], T &diag,
+                                             T &off) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    T dg = L.var_alpha ? Coef<T>::al(L)[c] : (T)L.alpha_c;
+    T of = 0;
+    const T bc = (T)L.beta_c;
+    const long fxrow = (long)(nx + 1) * (j + (long)ny * k);
+    const long fyrow = (long)nx * (j + (long)(ny + 1) * k);
+    const long fzpl = (long)nx * j;
+    const bool inside[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+    const int nbi[6] = {i > 0 ? c - 1 : c + nx - 1, i < nx - 1 ? c + 1 : c - (nx - 1),
+                        j > 0 ? c - nx : c + nx * (ny - 1), j < ny - 1 ? c + nx : c - nx * (ny - 1),
+                        k > 0 ? c - L.nxy : c + L.nxy * (nz - 1), k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)};
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        T beta;
+        if (!L.var_beta) beta = bc;
+        else if (f == 0) beta = (T)Coef<T>::bx(L)[fxrow + i];
+        else if (f == 1) beta = (T)Coef<T>::bx(L)[fxrow + i + 1];
+        else if (f == 2) beta = (T)Coef<T>::by(L)[fyrow + i];
+        else if (f == 3) beta = (T)Coef<T>::by(L)[fyrow + i + nx];
+        else if (f == 4) beta = (T)Coef<T>::bz(L)[fzpl + i + (long)L.nxy * k];
+        else beta = (T)Coef<T>::bz(L)[fzpl + i + (long)L.nxy * (k + 1)];
+        const T ih2 = (T)(f < 2 ? L.idx2 : (f < 4 ? L.idy2 : L.idz2));
+        const T cf = beta * ih2;
+        const int kd = L.kind[f];
+        if (inside[f] || kd == VD_BC_PERIODIC) {
+            if (L.has_mask && !L.mask[nbi[f]]) dg += (T)2 * cf;
+            else { dg += cf; of += cf * nbv[f]; }
+        } else if (kd == VD_BC_DIRICHLET) {
+            dg += (T)2 * cf;
+        }
+    }
     diag = dg;
     off = of;
 }

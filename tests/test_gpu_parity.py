@@ -77,6 +77,8 @@ SOLVE_CASES = [
     (206, (64, 32, 32), "array", "array", [0, 0, 1, 1, 3, 3], 0, 3, None),
     (207, (96, 96, 96), "zero", "const", [0, 0, 1, 1, 1, 1], 0, 0, None),
     (208, (40, 40, 40), "const", "array", None, 0, 0, None),
+    (209, (40, 24, 20), "array", "array", [3, 3, 1, 0, 3, 3], 0, 0, None),
+    (210, (40, 24, 20), "array", "const", [3, 3, 3, 3, 0, 1], 2, 0, None),
 ]
 
 
@@ -169,6 +171,11 @@ def test_errors(ctx, V):
     with pytest.raises(V.VDError) as e:
         ctx.vd_helmholtz_solve_batched([gpu_problem(prob)], V.mg_opts())
     assert e.value.status == V.VD_EINVAL
+    # odd periodic direction: red-black colouring would couple same-colour cells
+    prob = I.random_helmholtz(505, (15, 8, 8), kinds=[3, 3, 0, 0, 1, 1])
+    with pytest.raises(V.VDError) as e:
+        ctx.vd_helmholtz_solve_batched([gpu_problem(prob)], V.mg_opts())
+    assert e.value.status == V.VD_EINVAL
     prob = I.random_helmholtz(503, (16, 16, 16))
     infos, st = ctx.vd_helmholtz_solve_batched([gpu_problem(prob)], V.mg_opts(rtol=1e-30, max_cycles=3),
                                                allow_fail=True)
@@ -183,10 +190,12 @@ def test_errors(ctx, V):
 PHYS = {"qe": 1.602176634e-19, "eps0": 8.8541878128e-12, "kB": 1.380649e-23, "me": 9.1093837015e-31}
 
 
+@pytest.mark.parametrize("shape", [(20, 18, 16), (64, 16, 16), (32, 24, 32)])
 @pytest.mark.parametrize("kinds", [[2, 2, 3, 3, 1, 1], [0, 0, 1, 1, 3, 3], [3, 3, 2, 2, 0, 1]])
-def test_species_flux(ctx, oracle, kinds):
+def test_species_flux(ctx, oracle, kinds, shape):
+    """Per-cell kernel (ragged shapes) and tiled kernel (32 x 8 x 16 tiles)."""
     rng = np.random.default_rng(601)
-    nx, ny, nz = 20, 18, 16
+    nx, ny, nz = shape
     h = 1e-4
     g = (nx, ny, nz, h, h, h)
     S = 4
