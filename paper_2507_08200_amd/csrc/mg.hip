@@ -25,35 +25,36 @@
 namespace vd {
 
 constexpr int kCoarseMax = 4096;     // levels at or below this size run in the fused kernel
+constexpr int kLdsMaxCells = 8192;   // largest level a single workgroup smooths from LDS
 constexpr int kBottomMaxIt = 500;
 constexpr double kBottomTol = 1e-14;
 
 // ------------------------------------------------------------ cell bodies
 template <typename T>
 __device__ __forceinline__ T load_b(const LevDesc &L, int c, int i, int j, int k) {
-    T b = ((const T *)L.b)[c];
+    T b = gld((const T *)L.b, c);
     if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
     return b;
 }
 
 template <typename T>
 __device__ __forceinline__ void gs_update(const LevDesc &L, int c, int i, int j, int k) {
-    if (L.has_mask && !L.mask[c]) return;
+    if (L.has_mask && !gld(L.mask, c)) return;
     T *x = (T *)L.x;
     T dg, of;
     row_terms<T, T>(L, x, i, j, k, c, dg, of);
     T b = load_b<T>(L, c, i, j, k);
-    x[c] = (b + of) / dg;
+    gst(x, c, (b + of) / dg);
 }
 
 template <typename T>
 __device__ __forceinline__ T residual_at(const LevDesc &L, int c, int i, int j, int k) {
-    if (L.has_mask && !L.mask[c]) return (T)0;
+    if (L.has_mask && !gld(L.mask, c)) return (T)0;
     const T *x = (const T *)L.x;
     T dg, of;
     row_terms<T, T>(L, x, i, j, k, c, dg, of);
     T b = load_b<T>(L, c, i, j, k);
-    return b - (dg * x[c] - of);
+    return b - (dg * gld(x, c) - of);
 }
 
 // coarse cell (I,J,K): mean of the 8 children's residuals (k, j, i order)
@@ -67,16 +68,16 @@ __device__ __forceinline__ void restrict_cell(const LevDesc &F, const LevDesc &C
                 int c = i + F.nx * j + F.nxy * k;
                 s += residual_at<T>(F, c, i, j, k);
             }
-    T v = (C.has_mask && !C.mask[cc]) ? (T)0 : (T)0.125 * s;
-    ((T *)C.b)[cc] = v;
-    ((T *)C.x)[cc] = (T)0;
+    T v = (C.has_mask && !gld(C.mask, cc)) ? (T)0 : (T)0.125 * s;
+    gst((T *)C.b, cc, v);
+    gst((T *)C.x, cc, (T)0);
 }
 
 template <typename T>
 __device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C, int c, int i, int j, int k) {
-    if (F.has_mask && !F.mask[c]) return;
+    if (F.has_mask && !gld(F.mask, c)) return;
     int cc = (i >> 1) + C.nx * (j >> 1) + C.nxy * (k >> 1);
-    ((T *)F.x)[c] += ((const T *)C.x)[cc];
+    gst((T *)F.x, c, gld((T *)F.x, c) + gld((const T *)C.x, cc));
 }
 
 // ------------------------------------------------------------ grid kernels
@@ -90,8 +91,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gsrb(const LevDesc *__restrict__ descs, Plan pl, int colour,
                                                  const ProbState *__restrict__ st) {
     for_tiles(pl, [&](int d, int lt, int) {
-        const LevDesc &L = descs[pl.ids[d]];
-        if (!st[L.prob].active) return;
+        const LevDesc L = descs[pl.ids[d]];
+        if (!gld(&st[L.prob].active, 0)) return;
         if ((L.nx & 1) == 0) {
             // one thread per pair (2m, 2m+1) of a row; exactly one has the colour
             for (int u = 0; u < kGsrbU; u++) {
@@ -120,9 +121,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__
                                                      const ProbState *__restrict__ st) {
     for_tiles(pl, [&](int d, int lt, int) {
         int id = pl.ids[d];
-        const LevDesc &C = descs[id];
-        if (!st[C.prob].active) return;
-        const LevDesc &F = descs[id - 1];
+        const LevDesc C = descs[id];
+        if (!gld(&st[C.prob].active, 0)) return;
+        const LevDesc F = descs[id - 1];
         for (int u = 0; u < kRestrictU; u++) {
             int cc = (lt * kRestrictU + u) * kBlock + threadIdx.x;
             if (cc >= C.ncell) break;
@@ -139,9 +140,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const LevDesc *__restrict__ 
                                                     const ProbState *__restrict__ st) {
     for_tiles(pl, [&](int d, int lt, int) {
         int id = pl.ids[d];
-        const LevDesc &F = descs[id];
-        if (!st[F.prob].active) return;
-        const LevDesc &C = descs[id + 1];
+        const LevDesc F = descs[id];
+        if (!gld(&st[F.prob].active, 0)) return;
+        const LevDesc C = descs[id + 1];
         for (int u = 0; u < kProlongU; u++) {
             int c = (lt * kProlongU + u) * kBlock + threadIdx.x;
             if (c >= F.ncell) break;
@@ -163,27 +164,27 @@ __global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64
     __shared__ double lds[kBlock / 64];
     for_tiles(pl, [&](int d, int lt, int t) {
         int id = pl.ids[d];
-        const LevDesc &L = d64[id];
-        if (check_active && !st[L.prob].active) return;
+        const LevDesc L = d64[id];
+        if (check_active && !gld(&st[L.prob].active, 0)) return;
         double v = 0.0;
         for (int u = 0; u < kNormU; u++) {
             int c = (lt * kNormU + u) * kBlock + threadIdx.x;
             if (c >= L.ncell) break;
             int i, j, k;
             cell_ijk(L, c, i, j, k);
-            bool valid = !(L.has_mask && !L.mask[c]);
+            bool valid = !(L.has_mask && !gld(L.mask, c));
             double r;
             if (MODE == 0) r = valid ? load_b<double>(L, c, i, j, k) : 0.0;
             else r = residual_at<double>(L, c, i, j, k);
             v += r * r;
             if (MODE == 2) {
                 const LevDesc &E = d32[id];
-                ((float *)E.b)[c] = (float)r;
-                ((float *)E.x)[c] = 0.0f;
+                gst((float *)E.b, c, (float)r);
+                gst((float *)E.x, c, 0.0f);
             }
         }
         double s = block_sum(v, lds);
-        if (threadIdx.x == 0) partials[t] = s;
+        if (threadIdx.x == 0) gst(partials, t, s);
     });
 }
 
@@ -193,12 +194,12 @@ __global__ void __launch_bounds__(kBlock) k_prep(const LevDesc *__restrict__ d64
                                                  const ProbState *__restrict__ st, int zero_guess) {
     for_tiles(pl, [&](int d, int lt, int) {
         const LevDesc &L = d64[pl.ids[d]];
-        const bool all = zero_guess || st[L.prob].bnorm == 0.0;
+        const bool all = zero_guess || gld(&st[L.prob].bnorm, 0) == 0.0;
         if (!all && !L.has_mask) return;
         for (int u = 0; u < kNormU; u++) {
             int c = (lt * kNormU + u) * kBlock + threadIdx.x;
             if (c >= L.ncell) break;
-            if (all || !L.mask[c]) ((double *)L.x)[c] = 0.0;
+            if (all || !gld(L.mask, c)) gst((double *)L.x, c, 0.0);
         }
     });
 }
@@ -209,13 +210,13 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict_
     for_tiles(pl, [&](int d, int lt, int) {
         int id = pl.ids[d];
         const LevDesc &L = d64[id];
-        if (!st[L.prob].active) return;
+        if (!gld(&st[L.prob].active, 0)) return;
         const float *e = (const float *)d32[id].x;
         double *x = (double *)L.x;
         for (int u = 0; u < kNormU; u++) {
             int c = (lt * kNormU + u) * kBlock + threadIdx.x;
             if (c >= L.ncell) break;
-            x[c] += (double)e[c];
+            gst(x, c, gld(x, c) + (double)gld(e, c));
         }
     });
 }
@@ -228,9 +229,11 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict_
 // per pass (plus the halo).  Needs an even nx (row pairs).
 constexpr int kT25X = 32, kT25Y = 16, kT25W = kT25X + 2;
 
+typedef double PairD __attribute__((ext_vector_type(2)));
+typedef float PairF __attribute__((ext_vector_type(2)));
 template <typename T> struct Pair;
-template <> struct Pair<double> { using V = double2; };
-template <> struct Pair<float> { using V = float2; };
+template <> struct Pair<double> { using V = PairD; };
+template <> struct Pair<float> { using V = PairF; };
 
 // value at (i, j, k) with periodic wrap; 0 across a non-periodic face
 template <typename T>
@@ -238,7 +241,7 @@ __device__ __forceinline__ T ld_wrap(const LevDesc &L, const T *__restrict__ X, 
     if (i < 0 || i >= L.nx) { if (L.kind[0] != VD_BC_PERIODIC) return (T)0; i = i < 0 ? i + L.nx : i - L.nx; }
     if (j < 0 || j >= L.ny) { if (L.kind[2] != VD_BC_PERIODIC) return (T)0; j = j < 0 ? j + L.ny : j - L.ny; }
     if (k < 0 || k >= L.nz) { if (L.kind[4] != VD_BC_PERIODIC) return (T)0; k = k < 0 ? k + L.nz : k - L.nz; }
-    return X[i + (long)L.nx * j + (long)L.nxy * k];
+    return gld(X, i + (long)L.nx * j + (long)L.nxy * k);
 }
 
 // the two values of row pair (ia, ia+1) of row j in plane k: a wide load
@@ -255,7 +258,7 @@ __device__ __forceinline__ void ld_slot(const LevDesc &L, const T *__restrict__ 
         if (L.kind[4] != VD_BC_PERIODIC) { a = b = (T)0; return; }
         k = k < 0 ? k + L.nz : k - L.nz;
     }
-    typename Pair<T>::V v = *(const typename Pair<T>::V *)(X + ia + (long)L.nx * j + (long)L.nxy * k);
+    typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(X + ia + (long)L.nx * j + (long)L.nxy * k);
     a = v.x;
     b = v.y;
 }
@@ -297,8 +300,8 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     if (t >= pl.ntiles) return;
     const int d = plan_find(pl, t);
     const int id = pl.ids[d];
-    const LevDesc &L = descs[id];
-    if ((MODE == 0 || check_active) && !st[L.prob].active) return;
+    const LevDesc L = descs[id];
+    if ((MODE == 0 || check_active) && !gld(&st[L.prob].active, 0)) return;
     int lt = t - pl.prefix[d];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int ntx = (nx + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
@@ -313,9 +316,11 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const int ia = i0 + 2 * tp, j = j0 + r;
     const bool own = ia < nx && j < ny;
     const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
+    float *__restrict__ Eb = MODE == 2 ? (float *)d32[id].b : nullptr;
+    float *__restrict__ Ex = MODE == 2 ? (float *)d32[id].x : nullptr;
     const int hslot = halo_slot<T>(tid);
-    T *X = (T *)L.x;
-    const T *B = (const T *)L.b;
+    T *__restrict__ X = (T *)L.x;
+    const T *__restrict__ B = (const T *)L.b;
     T xm0, xm1, xc0, xc1, xp0, xp1;
     ld_slot<T>(L, X, ia, j, k0 - 1, own, xm0, xm1);
     ld_slot<T>(L, X, ia, j, k0, own, xc0, xc1);
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     T bc0 = 0, bc1 = 0;
     const long rowoff = (long)nx * j;
     if (own) {
-        typename Pair<T>::V bv = *(const typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * k0);
+        typename Pair<T>::V bv = *(const VD_GAS typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * k0);
         bc0 = bv.x;
         bc1 = bv.y;
     }
@@ -340,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         if (k + 1 < k1) {
             if (halo_thread) hnext = ld_halo<T>(L, X, tid, i0, j0, k + 1);
             if (own) {
-                typename Pair<T>::V bv = *(const typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * (k + 1));
+                typename Pair<T>::V bv = *(const VD_GAS typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * (k + 1));
                 bn0 = bv.x;
                 bn1 = bv.y;
             }
@@ -352,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 const int i = ia + q;
                 if (MODE == 0 && ((i + j + k) & 1) != colour) continue;
                 const int c = i + nx * j + L.nxy * k;
-                const bool valid = !(L.has_mask && !L.mask[c]);
+                const bool valid = !(L.has_mask && !gld(L.mask, c));
                 if (MODE == 0 && !valid) continue;
                 T nbv[6];
                 nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
@@ -366,15 +371,14 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 T b = q == 0 ? bc0 : bc1;
                 if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
                 if (MODE == 0) {
-                    X[c] = (b + of) / dg;
+                    gst(X, c, (b + of) / dg);
                 } else {
                     const T xv = q == 0 ? xc0 : xc1;
                     const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
                     v += rv * rv;
                     if (MODE == 2) {
-                        const LevDesc &E = d32[id];
-                        ((float *)E.b)[c] = (float)rv;
-                        ((float *)E.x)[c] = 0.0f;
+                        gst(Eb, c, (float)rv);
+                        gst(Ex, c, 0.0f);
                     }
                 }
             }
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     }
     if (MODE != 0) {
         const double sum = block_sum(v, red);
-        if (tid == 0) partials[t] = sum;
+        if (tid == 0) gst(partials, t, sum);
     }
 }
 
@@ -411,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Plan pl, const int *__restr
     ProbState s = st[p];
     if (mode == 1 && !s.active) return;
     double v = 0.0;
-    for (int q = pl.prefix[d] + threadIdx.x; q < pl.prefix[d + 1]; q += blockDim.x) v += partials[q];
+    for (int q = pl.prefix[d] + threadIdx.x; q < pl.prefix[d + 1]; q += blockDim.x) v += gld(partials, q);
     double tot = block_sum(v, lds);
     if (threadIdx.x != 0) return;
     if (mode == 0) {
@@ -443,7 +447,7 @@ constexpr int kFusedThreads = 256;
 constexpr int kPcgLdsCells = 768;    // bottom levels up to this size keep the CG vectors in LDS
 
 template <typename T>
-__device__ void block_sweep(const LevDesc &L, int colour) {
+__device__ __forceinline__ void block_sweep(const LevDesc L, int colour) {
     for (int c = threadIdx.x; c < L.ncell; c += blockDim.x) {
         int i, j, k;
         cell_ijk(L, c, i, j, k);
@@ -475,9 +479,9 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *vec, do
     double *r = vec, *z = vec + n, *p = vec + 2 * n, *q = vec + 3 * n, *dg = vec + 4 * n, *xb = vec + 5 * n;
     const T *bT = (const T *)AT.b;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        bool valid = !(A64.has_mask && !A64.mask[c]);
-        r[c] = valid ? (double)bT[c] : 0.0;
-        xb[c] = 0.0;
+        bool valid = !(A64.has_mask && !gld(A64.mask, c));
+        gst(r, c, valid ? (double)gld(bT, c) : 0.0);
+        gst(xb, c, 0.0);
     }
     __syncthreads();
     double rr = 0.0, rz = 0.0;
@@ -486,13 +490,14 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *vec, do
         cell_ijk(A64, c, i, j, k);
         double d, of;
         row_terms<double, double>(A64, xb, i, j, k, c, d, of);   // xb is zero: only the diagonal is used
-        dg[c] = d;
-        bool valid = !(A64.has_mask && !A64.mask[c]);
-        double zz = valid ? r[c] / d : 0.0;
-        z[c] = zz;
-        p[c] = zz;
-        rr += r[c] * r[c];
-        rz += r[c] * zz;
+        gst(dg, c, d);
+        bool valid = !(A64.has_mask && !gld(A64.mask, c));
+        const double rc = gld(r, c);
+        double zz = valid ? rc / d : 0.0;
+        gst(z, c, zz);
+        gst(p, c, zz);
+        rr += rc * rc;
+        rz += rc * zz;
     }
     block_sum2(rr, rz, red);
     const double bn = sqrt(rr);
@@ -501,27 +506,29 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *vec, do
         double v = 0.0;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
             double qq = 0.0;
-            if (!(A64.has_mask && !A64.mask[c])) {
+            const double pc = gld(p, c);
+            if (!(A64.has_mask && !gld(A64.mask, c))) {
                 int i, j, k;
                 cell_ijk(A64, c, i, j, k);
                 double d, of;
                 row_terms<double, double>(A64, p, i, j, k, c, d, of);
-                qq = d * p[c] - of;
+                qq = d * pc - of;
             }
-            q[c] = qq;
-            v += p[c] * qq;
+            gst(q, c, qq);
+            v += pc * qq;
         }
         double pq = block_sum(v, red);
         if (pq == 0.0) break;
         const double a = rz / pq;
         double rz_new = 0.0, rr_new = 0.0;
         for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            xb[c] += a * p[c];
-            double rc = r[c] - a * q[c];
-            r[c] = rc;
-            bool valid = !(A64.has_mask && !A64.mask[c]);
-            double zz = valid ? rc / dg[c] : 0.0;
-            z[c] = zz;
+            const double pc = gld(p, c);
+            gst(xb, c, gld(xb, c) + a * pc);
+            double rc = gld(r, c) - a * gld(q, c);
+            gst(r, c, rc);
+            bool valid = !(A64.has_mask && !gld(A64.mask, c));
+            double zz = valid ? rc / gld(dg, c) : 0.0;
+            gst(z, c, zz);
             rz_new += rc * zz;
             rr_new += rc * rc;
         }
@@ -529,11 +536,99 @@ __device__ void block_pcg(const LevDesc &A64, const LevDesc &AT, double *vec, do
         const double bcoef = rz_new / rz;
         rz = rz_new;
         rr = rr_new;
-        for (int c = threadIdx.x; c < n; c += blockDim.x) p[c] = z[c] + bcoef * p[c];
+        for (int c = threadIdx.x; c < n; c += blockDim.x) gst(p, c, gld(z, c) + bcoef * gld(p, c));
         __syncthreads();
     }
     T *xT = (T *)AT.x;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) xT[c] = (T)xb[c];
+    for (int c = threadIdx.x; c < n; c += blockDim.x) gst(xT, c, (T)gld(xb, c));
+    __syncthreads();
+}
+
+// Same CG on a single wavefront (lanes 0..63, vectors in LDS): the
+// reductions are shuffle trees and the only synchronisation is the
+// wavefront's own, so a small bottom level costs no workgroup barriers.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, int BAS>
+__device__ void wave_pcg(const LevDesc &A64, const T *bT, T *xT, double *vec) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int n = A64.ncell;
+        double *r = vec, *z = vec + n, *p = vec + 2 * n, *q = vec + 3 * n, *dg = vec + 4 * n, *xb = vec + 5 * n;
+        for (int c = lane; c < n; c += 64) {
+            const bool valid = !(A64.has_mask && !gld(A64.mask, c));
+            lst(r, c, valid ? (double)mld<BAS>(bT, c) : 0.0);
+            lst(xb, c, 0.0);
+        }
+        wave_sync();
+        double rr = 0.0, rz = 0.0;
+        for (int c = lane; c < n; c += 64) {
+            int i, j, k;
+            cell_ijk(A64, c, i, j, k);
+            double d, of;
+            row_terms<double, double, 3>(A64, xb, i, j, k, c, d, of);   // xb is zero: only the diagonal is used
+            lst(dg, c, d);
+            const bool valid = !(A64.has_mask && !gld(A64.mask, c));
+            const double rc = lld(r, c);
+            const double zz = valid ? rc / d : 0.0;
+            lst(z, c, zz);
+            lst(p, c, zz);
+            rr += rc * rc;
+            rz += rc * zz;
+        }
+        rr = wave_sum(rr);
+        rz = wave_sum(rz);
+        wave_sync();
+        const double bn = sqrt(rr);
+        for (int it = 0; it < kBottomMaxIt; it++) {
+            if (!(sqrt(rr) > kBottomTol * bn)) break;
+            double v = 0.0;
+            for (int c = lane; c < n; c += 64) {
+                double qq = 0.0;
+                const double pc = lld(p, c);
+                if (!(A64.has_mask && !gld(A64.mask, c))) {
+                    int i, j, k;
+                    cell_ijk(A64, c, i, j, k);
+                    double d, of;
+                    row_terms<double, double, 3>(A64, p, i, j, k, c, d, of);
+                    qq = d * pc - of;
+                }
+                lst(q, c, qq);
+                v += pc * qq;
+            }
+            const double pq = wave_sum(v);
+            if (pq == 0.0) break;
+            const double a = rz / pq;
+            double rz_new = 0.0, rr_new = 0.0;
+            for (int c = lane; c < n; c += 64) {
+                const double pc = lld(p, c);
+                lst(xb, c, lld(xb, c) + a * pc);
+                const double rc = lld(r, c) - a * lld(q, c);
+                lst(r, c, rc);
+                const bool valid = !(A64.has_mask && !gld(A64.mask, c));
+                const double zz = valid ? rc / lld(dg, c) : 0.0;
+                lst(z, c, zz);
+                rz_new += rc * zz;
+                rr_new += rc * rc;
+            }
+            rz_new = wave_sum(rz_new);
+            rr_new = wave_sum(rr_new);
+            const double bcoef = rz_new / rz;
+            rz = rz_new;
+            rr = rr_new;
+            for (int c = lane; c < n; c += 64) lst(p, c, lld(z, c) + bcoef * lld(p, c));
+            wave_sync();
+        }
+        for (int c = lane; c < n; c += 64) mst<BAS>(xT, c, (T)lld(xb, c));
+    }
     __syncthreads();
 }
 
@@ -544,7 +639,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
     __shared__ double red[2 * (kFusedThreads / 64)];
     extern __shared__ double pcg_lds[];
     const FusedDesc f = fd[blockIdx.x];
-    if (!st[f.prob].active) return;
+    if (!gld(&st[f.prob].active, 0)) return;
     const int base = f.base, lc = f.lc, L = f.L;
     if (L == 1) {
         const LevDesc &A = dT[base];
@@ -562,7 +657,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
         }
         __syncthreads();
     }
-    block_pcg<T>(d64[base + L - 1], dT[base + L - 1], pcg_in_lds ? pcg_lds : f.pcg, red);
+    if (pcg_in_lds) wave_pcg<T, 1>(d64[base + L - 1], (const T *)dT[base + L - 1].b, (T *)dT[base + L - 1].x, pcg_lds);
+    else block_pcg<T>(d64[base + L - 1], dT[base + L - 1], f.pcg, red);
     for (int l = L - 2; l >= lc; l--) {
         const LevDesc &A = dT[base + l];
         const LevDesc &C = dT[base + l + 1];
@@ -573,6 +669,128 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
         }
         __syncthreads();
         for (int s = 0; s < nu_post; s++) { block_sweep<T>(A, 0); block_sweep<T>(A, 1); }
+    }
+}
+
+// ------------------------------------------- LDS-resident coarse V-cycle
+// One workgroup per problem runs every level from lc down to the bottom
+// with the unknowns and right-hand sides of those levels held in LDS (the
+// face coefficients stay in global memory, read-only), then writes level
+// lc's unknown back.  Dynamic LDS: 2 * sum(cells) * sizeof(T) for the levels
+// plus 6 * bottom cells doubles for the CG vectors.
+constexpr int kLdsThreads = 512;
+
+template <typename T>
+__device__ __forceinline__ void lds_sweep(const LevDesc &L, T *x, const T *b, int colour) {
+    for (int c = threadIdx.x; c < L.ncell; c += blockDim.x) {
+        int i, j, k;
+        cell_ijk(L, c, i, j, k);
+        if (((i + j + k) & 1) != colour) continue;
+        if (L.has_mask && !gld(L.mask, c)) continue;
+        T dg, of;
+        row_terms<T, T, 3>(L, x, i, j, k, c, dg, of);
+        T bv = lld(b, c);
+        if (L.lift) bv = (T)((double)bv + lift_term(L, i, j, k));
+        lst(x, c, (bv + of) / dg);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_residual(const LevDesc &L, const T *x, const T *b, int c, int i, int j, int k) {
+    if (L.has_mask && !gld(L.mask, c)) return (T)0;
+    T dg, of;
+    row_terms<T, T, 3>(L, x, i, j, k, c, dg, of);
+    T bv = lld(b, c);
+    if (L.lift) bv = (T)((double)bv + lift_term(L, i, j, k));
+    return bv - (dg * lld(x, c) - of);
+}
+
+// start of level l's unknown in the LDS carve-out (x_l then b_l per level,
+// from level lc down)
+template <typename T>
+__device__ __forceinline__ T *lds_level(char *raw, const LevDesc *dT, int base, int lc, int l) {
+    size_t off = 0;
+    for (int m = lc; m < l; m++) off += 2 * sizeof(T) * (size_t)dT[base + m].ncell;
+    return (T *)(raw + off);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
+                                                            const FusedDesc *__restrict__ fd, const ProbState *__restrict__ st,
+                                                            int nu_pre, int nu_post) {
+    extern __shared__ double lds_raw[];
+    char *raw = (char *)lds_raw;
+    const FusedDesc f = fd[blockIdx.x];
+    if (!gld(&st[f.prob].active, 0)) return;
+    const int base = f.base, lc = f.lc, L = f.L;
+    {
+        const LevDesc A = dT[base + lc];
+        T *x = lds_level<T>(raw, dT, base, lc, lc);
+        T *b = x + A.ncell;
+        const T *gx = (const T *)A.x, *gb = (const T *)A.b;
+        for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) { lst(x, c, gld(gx, c)); lst(b, c, gld(gb, c)); }
+        __syncthreads();
+    }
+    if (L == 1) {
+        const LevDesc A = dT[base];
+        T *x = lds_level<T>(raw, dT, base, 0, 0);
+        T *b = x + A.ncell;
+        for (int s = 0; s < nu_pre + nu_post; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
+    } else {
+        for (int l = lc; l < L - 1; l++) {
+            const LevDesc A = dT[base + l];
+            T *x = lds_level<T>(raw, dT, base, lc, l);
+            T *b = x + A.ncell;
+            for (int s = 0; s < nu_pre; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
+            const LevDesc C = dT[base + l + 1];
+            T *xc = b + A.ncell;
+            T *bc = xc + C.ncell;
+            for (int cc = threadIdx.x; cc < C.ncell; cc += blockDim.x) {
+                int I, J, K;
+                cell_ijk(C, cc, I, J, K);
+                T sum = 0;
+                for (int kk = 0; kk < 2; kk++)
+                    for (int jj = 0; jj < 2; jj++)
+                        for (int ii = 0; ii < 2; ii++) {
+                            const int i = 2 * I + ii, j = 2 * J + jj, k = 2 * K + kk;
+                            sum += lds_residual<T>(A, x, b, i + A.nx * j + A.nxy * k, i, j, k);
+                        }
+                lst(bc, cc, (C.has_mask && !gld(C.mask, cc)) ? (T)0 : (T)0.125 * sum);
+                lst(xc, cc, (T)0);
+            }
+            __syncthreads();
+        }
+        {
+            const LevDesc A = dT[base + L - 1];
+            const LevDesc A64 = d64[base + L - 1];
+            T *x = lds_level<T>(raw, dT, base, lc, L - 1);
+            size_t used = 0;
+            for (int m = lc; m < L; m++) used += 2 * sizeof(T) * (size_t)dT[base + m].ncell;
+            used = (used + 15) & ~(size_t)15;
+            wave_pcg<T, 3>(A64, x + A.ncell, x, (double *)(raw + used));
+        }
+        for (int l = L - 2; l >= lc; l--) {
+            const LevDesc A = dT[base + l];
+            const LevDesc C = dT[base + l + 1];
+            T *x = lds_level<T>(raw, dT, base, lc, l);
+            T *b = x + A.ncell;
+            const T *xc = b + A.ncell;
+            for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) {
+                if (A.has_mask && !gld(A.mask, c)) continue;
+                int i, j, k;
+                cell_ijk(A, c, i, j, k);
+                lst(x, c, lld(x, c) + lld(xc, (i >> 1) + C.nx * (j >> 1) + C.nxy * (k >> 1)));
+            }
+            __syncthreads();
+            for (int s = 0; s < nu_post; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
+        }
+    }
+    {
+        const LevDesc A = dT[base + lc];
+        const T *x = lds_level<T>(raw, dT, base, lc, lc);
+        T *gx = (T *)A.x;
+        for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) gst(gx, c, lld(x, c));
     }
 }
 
@@ -642,7 +860,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(LevDesc F, LevDesc C, double
         int j = (int)(r % ny), k = (int)(r / ny);
         double s = 0.0;
         for (int kk = 0; kk < 2; kk++)
-            for (int jj = 0; jj < 2; jj++) s += F.bx[(long)(2 * i) + (long)(fx + 1) * ((2 * j + jj) + (long)fy * (2 * k + kk))];
+            for (int jj = 0; jj < 2; jj++) s += gld(F.bx, (long)(2 * i) + (long)(fx + 1) * ((2 * j + jj) + (long)fy * (2 * k + kk)));
         bx[q] = 0.25 * s;
         if (bx32) bx32[q] = (float)(0.25 * s);
         return;
@@ -654,7 +872,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(LevDesc F, LevDesc C, double
         int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
         double s = 0.0;
         for (int kk = 0; kk < 2; kk++)
-            for (int ii = 0; ii < 2; ii++) s += F.by[(long)(2 * i + ii) + (long)fx * ((2 * j) + (long)(fy + 1) * (2 * k + kk))];
+            for (int ii = 0; ii < 2; ii++) s += gld(F.by, (long)(2 * i + ii) + (long)fx * ((2 * j) + (long)(fy + 1) * (2 * k + kk)));
         by[q] = 0.25 * s;
         if (by32) by32[q] = (float)(0.25 * s);
         return;
@@ -666,7 +884,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(LevDesc F, LevDesc C, double
         int j = (int)(r % ny), k = (int)(r / ny);
         double s = 0.0;
         for (int jj = 0; jj < 2; jj++)
-            for (int ii = 0; ii < 2; ii++) s += F.bz[(long)(2 * i + ii) + (long)fx * ((2 * j + jj) + (long)fy * (2 * k))];
+            for (int ii = 0; ii < 2; ii++) s += gld(F.bz, (long)(2 * i + ii) + (long)fx * ((2 * j + jj) + (long)fy * (2 * k)));
         bz[q] = 0.25 * s;
         if (bz32) bz32[q] = (float)(0.25 * s);
         return;
@@ -682,8 +900,8 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(LevDesc F, LevDesc C, double
             for (int jj = 0; jj < 2; jj++)
                 for (int ii = 0; ii < 2; ii++) {
                     long f = (long)(2 * i + ii) + (long)fx * ((2 * j + jj) + (long)fy * (2 * k + kk));
-                    if (C.var_alpha) s += F.alpha[f];
-                    if (C.has_mask) valid = valid && F.mask[f];
+                    if (C.var_alpha) s += gld(F.alpha, f);
+                    if (C.has_mask) valid = valid && gld(F.mask, f);
                 }
         if (C.var_alpha) { al[c] = 0.125 * s; if (al32) al32[c] = (float)(0.125 * s); }
         if (C.has_mask) mk[c] = (uint8_t)valid;
@@ -705,6 +923,8 @@ struct HLevel {
 
 struct HProblem {
     int L = 1, lc = 0;
+    int lds_lc = -1;            // first LDS-resident coarse level (-1: none fits)
+    size_t lds_bytes = 0;
     bool var_beta = false, var_alpha = false, has_mask = false;
     std::vector<HLevel> lv;
     DevBuf<double> pcg;
@@ -730,6 +950,8 @@ struct Solver {
     DevBuf<FusedDesc> fused;
     int nfused = 0;
     size_t pcg_lds_bytes = 0;     // dynamic LDS of the fused kernel (0: CG vectors in global memory)
+    bool lds_mode = false;        // coarse levels held in LDS (k_coarse_lds)
+    size_t lds_bytes = 0;         // its dynamic LDS
     DevBuf<int> prob_of;
     HPlan all0;                                  // finest level, every problem
     std::vector<HPlan> pre, restr, prolong;      // per level
@@ -743,6 +965,32 @@ struct Solver {
         if (pin_st) (void)hipHostFree(pin_st);
     }
 };
+
+template <typename T>
+__global__ void k_coarse_lds(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
+                             const struct FusedDesc *__restrict__ fd, const ProbState *__restrict__ st, int nu_pre, int nu_post);
+
+// LDS a workgroup may allocate on this device; the LDS-resident coarse
+// kernel is allowed to use all of it
+static size_t lds_limit_bytes() {
+    static size_t cached = 0;
+    if (cached) return cached;
+    int dev = 0, v = 0;
+    VD_HIP(hipGetDevice(&dev));
+    VD_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    size_t lim = v > 0 ? (size_t)v : 65536;
+    if (lim > 65536) {
+        if (hipFuncSetAttribute((const void *)k_coarse_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim - 1024) !=
+                hipSuccess ||
+            hipFuncSetAttribute((const void *)k_coarse_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim - 1024) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            lim = 65536;
+        }
+    }
+    cached = lim;
+    return cached;
+}
 
 static void upload_plan(HPlan &pl, hipStream_t s) {
     pl.nd = (int)pl.h_ids.size();
@@ -798,7 +1046,7 @@ static void validate(int nprob, const vd_problem *probs, const vd_mg_opts *o) {
         }
         VD_CHECK(P.rhs != nullptr && P.x != nullptr, "rhs and x are required");
         const int L = count_levels(g, o->n_levels);
-        VD_CHECK(L >= 1, "n_levels not compatible with the grid (dimensions must stay even)");
+        VD_CHECK(L >= 1 && L <= 16, "n_levels not compatible with the grid (dimensions must stay even, at most 16 levels)");
         // red-black ordering is only a valid parallel colouring if a periodic
         // direction has an even number of cells on every smoothed level
         const int nd[3] = {g.nx, g.ny, g.nz};
@@ -867,6 +1115,7 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
     S->nprob = nprob;
     S->prec = o->precision;
     bool ir = o->precision == VD_FP32_IR;
+    size_t lds_limit = lds_limit_bytes() - 1024;   // leave room for the static reduction buffer
     S->probs.resize(nprob);
     for (int p = 0; p < nprob; p++) {
         HProblem &H = S->probs[p];
@@ -897,11 +1146,45 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         H.lc = H.L == 1 ? (((long)H.lv[0].nx * H.lv[0].ny * H.lv[0].nz <= kCoarseMax) ? 0 : 1) : H.L - 1;
         for (int l = 0; l < H.L - 1; l++)
             if ((long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz <= kCoarseMax) { H.lc = l; break; }
+        // LDS-resident coarse levels: the largest set of coarse levels whose
+        // unknowns, right-hand sides and CG vectors fit in one workgroup's LDS
+        {
+            const size_t sT = ir ? sizeof(float) : sizeof(double);
+            const long nb = H.L >= 2 ? (long)H.lv[H.L - 1].nx * H.lv[H.L - 1].ny * H.lv[H.L - 1].nz : 0;
+            int best = -1;
+            size_t best_bytes = 0;
+            for (int l = H.L - 1; l >= 0; l--) {
+                const long nl = (long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz;
+                if (nl > kLdsMaxCells) break;
+                size_t need = 0;
+                for (int m = l; m < H.L; m++) need += 2 * sT * (size_t)H.lv[m].nx * H.lv[m].ny * H.lv[m].nz;
+                need = ((need + 15) & ~(size_t)15) + (H.L >= 2 ? 6 * sizeof(double) * (size_t)nb : 0);
+                if (need > lds_limit) break;
+                best = l;
+                best_bytes = need;
+            }
+            // a single large level is smoothed by the grid kernels, not fused
+            H.lds_lc = (H.L == 1 && best < 0) ? -2 : best;
+            H.lds_bytes = best_bytes;
+        }
         if (H.L >= 2) {
             const HLevel &B = H.lv[H.L - 1];
             H.pcg.alloc((size_t)6 * B.nx * B.ny * B.nz);
         }
         S->Lmax = std::max(S->Lmax, H.L);
+    }
+    // use the LDS-resident coarse kernel when every problem's bottom fits;
+    // its coarse boundary then replaces the global-memory one
+    {
+        bool all = true;
+        for (auto &H : S->probs) all = all && (H.lds_lc >= 0 || H.lds_lc == -2);
+        if (all) {
+            S->lds_mode = true;
+            for (auto &H : S->probs) {
+                H.lc = H.lds_lc >= 0 ? H.lds_lc : 1;
+                if (H.lds_lc >= 0) S->lds_bytes = std::max(S->lds_bytes, H.lds_bytes);
+            }
+        }
     }
     int Lmax = S->Lmax;
     S->h64.assign((size_t)nprob * Lmax, LevDesc{});
@@ -1104,7 +1387,11 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
                 k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st);
             });
     }
-    if (S.nfused)
+    if (S.nfused && S.lds_mode)
+        timed(ctx, "coarse", 0.0, [&] {
+            k_coarse_lds<T><<<S.nfused, kLdsThreads, S.lds_bytes, s>>>(dT, S.d64.p, S.fused.p, st, o->nu_pre, o->nu_post);
+        });
+    else if (S.nfused)
         timed(ctx, "coarse", 0.0, [&] {
             k_coarse<T><<<S.nfused, kFusedThreads, S.pcg_lds_bytes, s>>>(dT, S.d64.p, S.fused.p, st, o->nu_pre, o->nu_post,
                                                                           S.pcg_lds_bytes > 0);

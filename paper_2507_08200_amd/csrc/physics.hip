@@ -16,14 +16,14 @@ __device__ __forceinline__ double e_face(const GridDev &G, const double *__restr
     const long st = G.stride[d];
     const double ih = G.ih[d];
     const long c0 = c - (long)pos * st;     // index of row position 0
-    if (fidx > 0 && fidx < n) return -(phi[c0 + fidx * st] - phi[c0 + (fidx - 1) * st]) * ih;
+    if (fidx > 0 && fidx < n) return -(gld(phi, c0 + fidx * st) - gld(phi, c0 + (fidx - 1) * st)) * ih;
     const int f = 2 * d + (fidx == 0 ? 0 : 1);
     const int kind = G.phi_kind[f];
-    if (kind == VD_BC_PERIODIC) return -(phi[c0] - phi[c0 + (n - 1) * st]) * ih;
+    if (kind == VD_BC_PERIODIC) return -(gld(phi, c0) - gld(phi, c0 + (n - 1) * st)) * ih;
     if (kind == VD_BC_DIRICHLET) {
         const double g = G.phi_val[f];
-        if (fidx == 0) return -(phi[c0] - g) * (2.0 * ih);
-        return -(g - phi[c0 + (n - 1) * st]) * (2.0 * ih);
+        if (fidx == 0) return -(gld(phi, c0) - g) * (2.0 * ih);
+        return -(g - gld(phi, c0 + (n - 1) * st)) * (2.0 * ih);
     }
     return 0.0;
 }
@@ -43,13 +43,13 @@ __device__ __forceinline__ double mu_electron(double en_td, double N) {
 __device__ __forceinline__ double te_lfa(const double *__restrict__ tab, int npts, double ln_min, double ln_max, double en_td) {
     double en = en_td < kENFloor ? kENFloor : en_td;
     double x = log(en);
-    if (x <= ln_min) return tab[0];
-    if (x >= ln_max) return tab[npts - 1];
+    if (x <= ln_min) return gld(tab, 0);
+    if (x >= ln_max) return gld(tab, npts - 1);
     double t = (x - ln_min) / ((ln_max - ln_min) / (double)(npts - 1));
     int i0 = (int)floor(t);
     i0 = i0 > npts - 2 ? npts - 2 : (i0 < 0 ? 0 : i0);
     double w = t - (double)i0;
-    return (1.0 - w) * tab[i0] + w * tab[i0 + 1];
+    return (1.0 - w) * gld(tab, i0) + w * gld(tab, i0 + 1);
 }
 
 // Per cell: E/N, Te (fixed / table / from the electron energy) and, for the
@@ -69,21 +69,21 @@ __global__ void __launch_bounds__(kBlock) k_transport(TransportArgs a) {
     double Te;
     if (a.te_mode == VD_TE_LFA) {
         Te = te_lfa(a.lfa, a.lfa_n, a.lfa_ln_min, a.lfa_ln_max, en);
-        a.Te[c] = Te;
+        gst(a.Te, c, Te);
     } else if (a.te_mode == VD_TE_ENERGY) {
-        double ne = a.ne[c];
-        double t = ne > 0.0 ? a.Ee[c] / (1.5 * ne * a.kB) : a.Tg;
+        double ne = gld(a.ne, c);
+        double t = ne > 0.0 ? gld(a.Ee, c) / (1.5 * ne * a.kB) : a.Tg;
         Te = ne > 0.0 ? (t < a.Tg ? a.Tg : (t > a.Te_max ? a.Te_max : t)) : a.Tg;
-        a.Te[c] = Te;
+        gst(a.Te, c, Te);
     } else {
-        Te = a.Te[c];
+        Te = gld(a.Te, c);
     }
     for (int v = 0; v < a.nvar; v++) {
         double m = mu_electron(en, a.N_gas);
-        a.mu[(long)v * G.ncell + c] = a.var_sign[v] * m;
+        gst(a.mu, (long)v * G.ncell + c, a.var_sign[v] * m);
         double D = m * a.kB * Te / a.qe;
-        a.D[(long)v * G.ncell + c] = D;
-        if (a.beta_e && v == a.e_var) a.beta_e[c] = 5.0 / 3.0 * D;
+        gst(a.D, (long)v * G.ncell + c, D);
+        if (a.beta_e && v == a.e_var) gst(a.beta_e, c, 5.0 / 3.0 * D);
     }
 }
 
@@ -114,13 +114,14 @@ __device__ __forceinline__ double u_at(const GridDev &G, const int *kind, const 
                                        int d, long c0, int p) {
     const int n = G.n[d];
     const long st = G.stride[d];
-    if (p >= 0 && p < n) return u[c0 + p * st];
-    const int f = 2 * d + (p < 0 ? 0 : 1);
-    const int kd = kind[f];
-    if (kd == VD_BC_PERIODIC) return u[c0 + (p < 0 ? p + n : p - n) * st];
+    if (p >= 0 && p < n) return gld(u, c0 + p * st);
+    // constant-index selects (no dynamic indexing of the descriptor arrays)
+    const int kd = p < 0 ? (d == 0 ? kind[0] : d == 1 ? kind[2] : kind[4]) : (d == 0 ? kind[1] : d == 1 ? kind[3] : kind[5]);
+    if (kd == VD_BC_PERIODIC) return gld(u, c0 + (p < 0 ? p + n : p - n) * st);
     const int q = p < 0 ? -1 - p : 2 * n - 1 - p;
-    const double v = u[c0 + q * st];
-    return kd == VD_BC_DIRICHLET ? 2.0 * gval[f] - v : v;
+    const double v = gld(u, c0 + q * st);
+    const double g = p < 0 ? (d == 0 ? gval[0] : d == 1 ? gval[2] : gval[4]) : (d == 0 ? gval[1] : d == 1 ? gval[3] : gval[5]);
+    return kd == VD_BC_DIRICHLET ? 2.0 * g - v : v;
 }
 
 __device__ __forceinline__ double wall_flux(int wk, double uc, double mu, double e_n, double Te, double Tg, double mass,
@@ -142,17 +143,18 @@ __device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &
     const long st = G.stride[d];
     const long c0 = c - (long)pos * st;
     const bool boundary = (fidx == 0 || fidx == n);
-    const int kd = F.kind[2 * d + (fidx == 0 ? 0 : 1)];
+    const int kd = fidx == 0 ? (d == 0 ? F.kind[0] : d == 1 ? F.kind[2] : F.kind[4])
+                             : (d == 0 ? F.kind[1] : d == 1 ? F.kind[3] : F.kind[5]);
     const double *__restrict__ u = F.u;
     if (!F.mu && F.mu_c == 0.0) return 0.0;
     const double Ef = e_face(G, phi, d, c, pos, fidx);
     double muf;
     if (F.mu) {
         const int pl = fidx - 1, pr = fidx;
-        if (boundary && kd != VD_BC_PERIODIC) muf = fidx == 0 ? F.mu[c0] : F.mu[c0 + (n - 1) * st];
+        if (boundary && kd != VD_BC_PERIODIC) muf = fidx == 0 ? gld(F.mu, c0) : gld(F.mu, c0 + (n - 1) * st);
         else {
             const int ql = pl < 0 ? pl + n : pl, qr = pr >= n ? pr - n : pr;
-            muf = 0.5 * (F.mu[c0 + ql * st] + F.mu[c0 + qr * st]);
+            muf = 0.5 * (gld(F.mu, c0 + ql * st) + gld(F.mu, c0 + qr * st));
         }
     } else {
         muf = F.mu_c;
@@ -183,9 +185,11 @@ __device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const dou
                                  const double *__restrict__ Te, double Tg, double kB, double me, int c, const int pos[3]) {
     double total = 0.0;
     const double *__restrict__ u = F.u;
+#pragma unroll
     for (int d = 0; d < 3; d++) {
         const int n = G.n[d];
         double Fs[2];
+#pragma unroll
         for (int side = 0; side < 2; side++) {
             const int fidx = pos[d] + side;
             const bool boundary = (fidx == 0 || fidx == n);
@@ -196,10 +200,10 @@ __device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const dou
                 const double e_n = fidx == 0 ? -Ef : Ef;
                 double fl;
                 if (F.ne_wall) {
-                    fl = 2.0 * kB * Te[c] * wall_flux(VD_WALL_ELECTRON, F.ne_wall[c], 0.0, e_n, Te[c], Tg, me, kB, me);
+                    fl = 2.0 * kB * gld(Te, c) * wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, c), 0.0, e_n, gld(Te, c), Tg, me, kB, me);
                 } else {
-                    const double muc = F.mu ? F.mu[c] : F.mu_c;
-                    fl = wall_flux(F.wall, u[c], muc, e_n, Te[c], Tg, F.mass, kB, me);
+                    const double muc = F.mu ? gld(F.mu, c) : F.mu_c;
+                    fl = wall_flux(F.wall, gld(u, c), muc, e_n, gld(Te, c), Tg, F.mass, kB, me);
                 }
                 Fs[side] = fidx == 0 ? -fl : fl;
                 continue;
@@ -220,15 +224,16 @@ __device__ __forceinline__ double face_flux(const GridDev &G, const FieldDesc &F
                                             long c0, int fidx) {
     const int n = G.n[d];
     if (fidx == 0 || fidx == n) {
-        const int kd = F.kind[2 * d + (fidx == 0 ? 0 : 1)];
+        const int kd = fidx == 0 ? (d == 0 ? F.kind[0] : d == 1 ? F.kind[2] : F.kind[4])
+                                 : (d == 0 ? F.kind[1] : d == 1 ? F.kind[3] : F.kind[5]);
         if (kd == VD_BC_NEUMANN) return 0.0;
         if (kd == VD_BC_WALLFLUX) {
             const long cb = c0 + (fidx == 0 ? 0 : (long)(n - 1) * G.stride[d]);
             const double Ef = e_face(G, phi, d, (int)c0, 0, fidx);
             const double e_n = fidx == 0 ? -Ef : Ef;
             double fl;
-            if (F.ne_wall) fl = 2.0 * kB * Te[cb] * wall_flux(VD_WALL_ELECTRON, F.ne_wall[cb], 0.0, e_n, Te[cb], Tg, me, kB, me);
-            else fl = wall_flux(F.wall, F.u[cb], F.mu ? F.mu[cb] : F.mu_c, e_n, Te[cb], Tg, F.mass, kB, me);
+            if (F.ne_wall) fl = 2.0 * kB * gld(Te, cb) * wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, cb), 0.0, e_n, gld(Te, cb), Tg, me, kB, me);
+            else fl = wall_flux(F.wall, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(Te, cb), Tg, F.mass, kB, me);
             return fidx == 0 ? -fl : fl;
         }
     }
@@ -245,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
     __shared__ double fx[kTY * (kTX + 1)];
     __shared__ double fy[(kTY + 1) * kTX];
     const GridDev &G = a.g;
-    const FieldDesc &F = a.f[blockIdx.y];
+    const FieldDesc F = a.f[blockIdx.y];
     const int nx = G.n[0], ny = G.n[1];
     const int tiles_x = nx / kTX, tiles_y = ny / kTY;
     int b = blockIdx.x;
@@ -277,12 +282,12 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
                            (fy[(ty + 1) * kTX + tx] - fy[ty * kTX + tx]) * G.ihl[1] + (fz_hi - fz_lo) * G.ihl[2];
         const long c = col + pl;
         if (a.mode == 0) {
-            F.out[c] = div;
+            gst(F.out, c, div);
         } else {
-            double v = F.u0[c] * a.inv_dt - div;
-            if (F.src) v += F.src[c];
-            if (F.extra) v += F.extra[c];
-            F.out[c] = v;
+            double v = gld(F.u0, c) * a.inv_dt - div;
+            if (F.src) v += gld(F.src, c);
+            if (F.extra) v += gld(F.extra, c);
+            gst(F.out, c, v);
         }
         fz_lo = fz_hi;
         __syncthreads();
@@ -293,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
 // right-hand side of the implicit solve): out = u0/dt - div + src + extra.
 __global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
     const GridDev &G = a.g;
-    const FieldDesc &F = a.f[blockIdx.y];
+    const FieldDesc F = a.f[blockIdx.y];
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= G.ncell) return;
     int pos[3];
@@ -303,12 +308,12 @@ __global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
     pos[0] = r - pos[1] * G.n[0];
     double div = drift_div_cell(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, c, pos);
     if (a.mode == 0) {
-        F.out[c] = div;
+        gst(F.out, c, div);
     } else {
-        double v = F.u0[c] * a.inv_dt - div;
-        if (F.src) v += F.src[c];
-        if (F.extra) v += F.extra[c];
-        F.out[c] = v;
+        double v = gld(F.u0, c) * a.inv_dt - div;
+        if (F.src) v += gld(F.src, c);
+        if (F.extra) v += gld(F.extra, c);
+        gst(F.out, c, v);
     }
 }
 
@@ -450,20 +455,20 @@ __global__ void __launch_bounds__(kBlock) k_react(ReactArgs a) {
     double loss = 0.0;
     if (a.mech == VD_MECH_ARH2_15) {
         double n[15], G[15];
-        for (int s = 0; s < 15; s++) n[s] = a.n[s * N + c];
-        source_arh2(n, a.Te[c], a.qe, G, &loss);
-        for (int s = 0; s < 15; s++) a.G[s * N + c] = G[s];
+        for (int s = 0; s < 15; s++) n[s] = gld(a.n, s * N + c);
+        source_arh2(n, gld(a.Te, c), a.qe, G, &loss);
+        for (int s = 0; s < 15; s++) gst(a.G, s * N + c, G[s]);
     } else if (a.mech == VD_MECH_AR3) {
         double n[3], G[3];
-        for (int s = 0; s < 3; s++) n[s] = a.n[s * N + c];
-        source_ar3(n, a.Te[c], a.bg0, a.qe, G, &loss);
-        for (int s = 0; s < 3; s++) a.G[s * N + c] = G[s];
+        for (int s = 0; s < 3; s++) n[s] = gld(a.n, s * N + c);
+        source_ar3(n, gld(a.Te, c), a.bg0, a.qe, G, &loss);
+        for (int s = 0; s < 3; s++) gst(a.G, s * N + c, G[s]);
     } else if (a.mech == VD_MECH_DECAY) {
-        for (int s = 0; s < a.S; s++) a.G[s * N + c] = -a.bg0 * a.n[s * N + c];
+        for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, -a.bg0 * gld(a.n, s * N + c));
     } else {
-        for (int s = 0; s < a.S; s++) a.G[s * N + c] = 0.0;
+        for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, 0.0);
     }
-    if (a.S_inel) a.S_inel[c] = loss;
+    if (a.S_inel) gst(a.S_inel, c, loss);
 }
 
 // rho = e sum_k Z_k n_k (optionally at the mid-point (n0 + n)/2)
@@ -471,14 +476,14 @@ __global__ void __launch_bounds__(kBlock) k_rho(RhoArgs a) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     double s = 0.0;
-    for (int k = 0; k < a.S; k++) s += a.Z[k] * a.n[k * a.ncell + c];
-    a.rho[c] = a.qe * s;
+    for (int k = 0; k < a.S; k++) s += a.Z[k] * gld(a.n, k * a.ncell + c);
+    gst(a.rho, c, a.qe * s);
 }
 
 // u* = (u0 + u)/2 (mid-point of the corrector iteration)
 __global__ void __launch_bounds__(kBlock) k_mid(const double *__restrict__ u0, const double *__restrict__ u, double *__restrict__ out, long n) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) out[c] = 0.5 * (u0[c] + u[c]);
+    if (c < n) gst(out, c, 0.5 * (gld(u0, c) + gld(u, c)));
 }
 
 // ------------------------------------------------------ electron energy
@@ -491,23 +496,23 @@ __device__ __forceinline__ double diff_face(const GridDev &G, const int *kind, c
     const long st = G.stride[d];
     const double ih = G.ih[d];
     const long c0 = c - (long)pos * st;
-#define DV(q) (D ? D[c0 + (long)(q) * st] : D_c)
+#define DV(q) (D ? gld(D, c0 + (long)(q) * st) : D_c)
     if (fidx > 0 && fidx < n) {
         const double a = DV(fidx - 1), b = DV(fidx);
         const double hm = (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b);
-        return -hm * (u[c0 + fidx * st] - u[c0 + (fidx - 1) * st]) * ih;
+        return -hm * (gld(u, c0 + fidx * st) - gld(u, c0 + (fidx - 1) * st)) * ih;
     }
     const int f = 2 * d + (fidx == 0 ? 0 : 1);
     const int kd = kind[f];
     if (kd == VD_BC_PERIODIC) {
         const double a = DV(n - 1), b = DV(0);
         const double hm = (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b);
-        return -hm * (u[c0] - u[c0 + (n - 1) * st]) * ih;
+        return -hm * (gld(u, c0) - gld(u, c0 + (n - 1) * st)) * ih;
     }
     if (kd == VD_BC_DIRICHLET) {
         const double g = gval[f];
-        if (fidx == 0) return -DV(0) * (u[c0] - g) * (2.0 * ih);
-        return -DV(n - 1) * (g - u[c0 + (n - 1) * st]) * (2.0 * ih);
+        if (fidx == 0) return -DV(0) * (gld(u, c0) - g) * (2.0 * ih);
+        return -DV(n - 1) * (g - gld(u, c0 + (n - 1) * st)) * (2.0 * ih);
     }
     return 0.0;
 #undef DV
@@ -539,7 +544,7 @@ __global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
             const int kd = Fe.kind[2 * d + side];
             if (boundary && kd == VD_BC_NEUMANN) { Fs[side] = 0.0; continue; }
             if (boundary && kd == VD_BC_WALLFLUX) {
-                const double fl = wall_flux(VD_WALL_ELECTRON, Fe.u[c], 0.0, 0.0, a.Te[c], a.Tg, a.me, a.kB, a.me);
+                const double fl = wall_flux(VD_WALL_ELECTRON, gld(Fe.u, c), 0.0, 0.0, gld(a.Te, c), a.Tg, a.me, a.kB, a.me);
                 Fs[side] = fidx == 0 ? -fl : fl;
                 continue;
             }
@@ -551,13 +556,13 @@ __global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
     double E[3];
     e_cell(G, a.phi, c, pos, E);
     const double joule = -a.qe * (gam[0] * E[0] + gam[1] * E[1] + gam[2] * E[2]);
-    const double mue = Fe.mu ? Fe.mu[c] : Fe.mu_c;
+    const double mue = Fe.mu ? gld(Fe.mu, c) : Fe.mu_c;
     const double nu = a.qe / (a.me * fabs(mue));
-    const double ne = Fe.u[c];
-    const double elastic = 1.5 * ne * a.kB * (a.Te[c] - a.Tg) * (2.0 * a.me / a.m_bg) * nu;
-    double src = joule - elastic - a.S_inel[c];
-    if (a.extra) src += a.extra[c];
-    a.out[c] = a.Ee0[c] * a.inv_dt - divE + src;
+    const double ne = gld(Fe.u, c);
+    const double elastic = 1.5 * ne * a.kB * (gld(a.Te, c) - a.Tg) * (2.0 * a.me / a.m_bg) * nu;
+    double src = joule - elastic - gld(a.S_inel, c);
+    if (a.extra) src += gld(a.extra, c);
+    gst(a.out, c, gld(a.Ee0, c) * a.inv_dt - divE + src);
 }
 
 // ----------------------------------------------------- host launchers

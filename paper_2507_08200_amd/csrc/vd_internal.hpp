@@ -103,6 +103,35 @@ struct Plan {
 
 constexpr int kBlock = 256;
 
+// Address-space qualified access.  Pointers that reach a kernel through a
+// descriptor struct are generic to the compiler, which then emits FLAT
+// instructions; FLAT loads also count against the LDS counter, so every LDS
+// wait would wait for them as well.  Casting to the global (1) or LDS (3)
+// address space gives global_load / ds_read instead.
+#define VD_GAS __attribute__((address_space(1)))
+#define VD_LAS __attribute__((address_space(3)))
+
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, long i) { return ((const VD_GAS T *)p)[i]; }
+template <typename T>
+__device__ __forceinline__ void gst(T *p, long i, T v) { ((VD_GAS T *)p)[i] = v; }
+template <typename T>
+__device__ __forceinline__ T lld(const T *p, long i) { return ((const VD_LAS T *)p)[i]; }
+template <typename T>
+__device__ __forceinline__ void lst(T *p, long i, T v) { ((VD_LAS T *)p)[i] = v; }
+
+// memory-space tagged access: AS 1 = global, 3 = LDS
+template <int AS, typename T>
+__device__ __forceinline__ T mld(const T *p, long i) {
+    if constexpr (AS == 3) return lld(p, i);
+    else return gld(p, i);
+}
+template <int AS, typename T>
+__device__ __forceinline__ void mst(T *p, long i, T v) {
+    if constexpr (AS == 3) lst(p, i, v);
+    else gst(p, i, v);
+}
+
 // ------------------------------------------------------- kernel timing
 struct TimingAcc {
     int64_t launches = 0;
@@ -252,36 +281,36 @@ template <> struct Coef<float> {
 // Faces in the order x-, x+, y-, y+, z-, z+.  A Dirichlet domain face or a
 // covered neighbour adds twice the face coefficient to the diagonal;
 // Neumann and wall faces add nothing; periodic faces wrap.
-template <typename T, typename XT>
+template <typename T, typename XT, int AS = 1>
 __device__ __forceinline__ void row_terms(const LevDesc &L, const XT *__restrict__ x, int i, int j, int k, int c,
                                           T &diag, T &off) {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    T dg = L.var_alpha ? Coef<T>::al(L)[c] : (T)L.alpha_c;
+    T dg = L.var_alpha ? gld(Coef<T>::al(L), c) : (T)L.alpha_c;
     T of = 0;
     const T bc = (T)L.beta_c;
-#define VD_FACE(NBCOND, NBIDX, BETA, IH2, FACE)                        \
-    {                                                                  \
-        T cf = (L.var_beta ? (T)(BETA) : bc) * (T)(IH2);               \
-        int nb;                                                        \
-        bool inside = (NBCOND);                                        \
-        int kd = L.kind[FACE];                                         \
-        if (inside || kd == VD_BC_PERIODIC) {                          \
-            nb = (NBIDX);                                              \
-            if (L.has_mask && !L.mask[nb]) dg += (T)2 * cf;            \
-            else { dg += cf; of += cf * (T)x[nb]; }                    \
-        } else if (kd == VD_BC_DIRICHLET) {                            \
-            dg += (T)2 * cf;                                           \
-        }                                                              \
+#define VD_FACE(NBCOND, NBIDX, BETA_ARR, BETA_IDX, IH2, FACE)            \
+    {                                                                    \
+        T cf = (L.var_beta ? gld(BETA_ARR, BETA_IDX) : bc) * (T)(IH2);   \
+        int nb;                                                          \
+        bool inside = (NBCOND);                                          \
+        int kd = L.kind[FACE];                                           \
+        if (inside || kd == VD_BC_PERIODIC) {                            \
+            nb = (NBIDX);                                                \
+            if (L.has_mask && !gld(L.mask, nb)) dg += (T)2 * cf;         \
+            else { dg += cf; of += cf * (T)mld<AS>(x, nb); }             \
+        } else if (kd == VD_BC_DIRICHLET) {                              \
+            dg += (T)2 * cf;                                             \
+        }                                                                \
     }
     const long fxrow = (long)(nx + 1) * (j + (long)ny * k);
     const long fyrow = (long)nx * (j + (long)(ny + 1) * k);
     const long fzpl = (long)nx * j;
-    VD_FACE(i > 0, (i > 0 ? c - 1 : c + nx - 1), Coef<T>::bx(L)[fxrow + i], L.idx2, 0)
-    VD_FACE(i < nx - 1, (i < nx - 1 ? c + 1 : c - (nx - 1)), Coef<T>::bx(L)[fxrow + i + 1], L.idx2, 1)
-    VD_FACE(j > 0, (j > 0 ? c - nx : c + nx * (ny - 1)), Coef<T>::by(L)[fyrow + i], L.idy2, 2)
-    VD_FACE(j < ny - 1, (j < ny - 1 ? c + nx : c - nx * (ny - 1)), Coef<T>::by(L)[fyrow + i + nx], L.idy2, 3)
-    VD_FACE(k > 0, (k > 0 ? c - L.nxy : c + L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * k], L.idz2, 4)
-    VD_FACE(k < nz - 1, (k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)), Coef<T>::bz(L)[fzpl + i + (long)L.nxy * (k + 1)], L.idz2, 5)
+    VD_FACE(i > 0, (i > 0 ? c - 1 : c + nx - 1), Coef<T>::bx(L), fxrow + i, L.idx2, 0)
+    VD_FACE(i < nx - 1, (i < nx - 1 ? c + 1 : c - (nx - 1)), Coef<T>::bx(L), fxrow + i + 1, L.idx2, 1)
+    VD_FACE(j > 0, (j > 0 ? c - nx : c + nx * (ny - 1)), Coef<T>::by(L), fyrow + i, L.idy2, 2)
+    VD_FACE(j < ny - 1, (j < ny - 1 ? c + nx : c - nx * (ny - 1)), Coef<T>::by(L), fyrow + i + nx, L.idy2, 3)
+    VD_FACE(k > 0, (k > 0 ? c - L.nxy : c + L.nxy * (nz - 1)), Coef<T>::bz(L), fzpl + i + (long)L.nxy * k, L.idz2, 4)
+    VD_FACE(k < nz - 1, (k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)), Coef<T>::bz(L), fzpl + i + (long)L.nxy * (k + 1), L.idz2, 5)
 #undef VD_FACE
     diag = dg;
     off = of;
@@ -294,7 +323,7 @@ template <typename T>
 __device__ __forceinline__ void row_terms_nb(const LevDesc &L, int i, int j, int k, int c, const T nbv[6], T &diag,
                                              T &off) {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    T dg = L.var_alpha ? Coef<T>::al(L)[c] : (T)L.alpha_c;
+    T dg = L.var_alpha ? gld(Coef<T>::al(L), c) : (T)L.alpha_c;
     T of = 0;
     const T bc = (T)L.beta_c;
     const long fxrow = (long)(nx + 1) * (j + (long)ny * k);
@@ -308,17 +337,17 @@ __device__ __forceinline__ void row_terms_nb(const LevDesc &L, int i, int j, int
     for (int f = 0; f < 6; f++) {
         T beta;
         if (!L.var_beta) beta = bc;
-        else if (f == 0) beta = (T)Coef<T>::bx(L)[fxrow + i];
-        else if (f == 1) beta = (T)Coef<T>::bx(L)[fxrow + i + 1];
-        else if (f == 2) beta = (T)Coef<T>::by(L)[fyrow + i];
-        else if (f == 3) beta = (T)Coef<T>::by(L)[fyrow + i + nx];
-        else if (f == 4) beta = (T)Coef<T>::bz(L)[fzpl + i + (long)L.nxy * k];
-        else beta = (T)Coef<T>::bz(L)[fzpl + i + (long)L.nxy * (k + 1)];
+        else if (f == 0) beta = gld(Coef<T>::bx(L), fxrow + i);
+        else if (f == 1) beta = gld(Coef<T>::bx(L), fxrow + i + 1);
+        else if (f == 2) beta = gld(Coef<T>::by(L), fyrow + i);
+        else if (f == 3) beta = gld(Coef<T>::by(L), fyrow + i + nx);
+        else if (f == 4) beta = gld(Coef<T>::bz(L), fzpl + i + (long)L.nxy * k);
+        else beta = gld(Coef<T>::bz(L), fzpl + i + (long)L.nxy * (k + 1));
         const T ih2 = (T)(f < 2 ? L.idx2 : (f < 4 ? L.idy2 : L.idz2));
         const T cf = beta * ih2;
         const int kd = L.kind[f];
         if (inside[f] || kd == VD_BC_PERIODIC) {
-            if (L.has_mask && !L.mask[nbi[f]]) dg += (T)2 * cf;
+            if (L.has_mask && !gld(L.mask, nbi[f])) dg += (T)2 * cf;
             else { dg += cf; of += cf * nbv[f]; }
         } else if (kd == VD_BC_DIRICHLET) {
             dg += (T)2 * cf;
@@ -334,17 +363,17 @@ __device__ __forceinline__ double lift_term(const LevDesc &L, int i, int j, int 
     double v = 0.0;
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     if (i == 0 && L.kind[0] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.bx[(long)(nx + 1) * (j + (long)ny * k)] : L.beta_c) * L.gval[0] * L.idx2;
+        v += 2.0 * (L.var_beta ? gld(L.bx, (long)(nx + 1) * (j + (long)ny * k)) : L.beta_c) * L.gval[0] * L.idx2;
     if (i == nx - 1 && L.kind[1] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.bx[(long)(nx + 1) * (j + (long)ny * k) + nx] : L.beta_c) * L.gval[1] * L.idx2;
+        v += 2.0 * (L.var_beta ? gld(L.bx, (long)(nx + 1) * (j + (long)ny * k) + nx) : L.beta_c) * L.gval[1] * L.idx2;
     if (j == 0 && L.kind[2] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.by[i + (long)nx * ((long)(ny + 1) * k)] : L.beta_c) * L.gval[2] * L.idy2;
+        v += 2.0 * (L.var_beta ? gld(L.by, i + (long)nx * ((long)(ny + 1) * k)) : L.beta_c) * L.gval[2] * L.idy2;
     if (j == ny - 1 && L.kind[3] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.by[i + (long)nx * (ny + (long)(ny + 1) * k)] : L.beta_c) * L.gval[3] * L.idy2;
+        v += 2.0 * (L.var_beta ? gld(L.by, i + (long)nx * (ny + (long)(ny + 1) * k)) : L.beta_c) * L.gval[3] * L.idy2;
     if (k == 0 && L.kind[4] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.bz[i + (long)nx * j] : L.beta_c) * L.gval[4] * L.idz2;
+        v += 2.0 * (L.var_beta ? gld(L.bz, i + (long)nx * j) : L.beta_c) * L.gval[4] * L.idz2;
     if (k == nz - 1 && L.kind[5] == VD_BC_DIRICHLET)
-        v += 2.0 * (L.var_beta ? L.bz[i + (long)nx * (j + (long)ny * nz)] : L.beta_c) * L.gval[5] * L.idz2;
+        v += 2.0 * (L.var_beta ? gld(L.bz, i + (long)nx * (j + (long)ny * nz)) : L.beta_c) * L.gval[5] * L.idz2;
     return v;
 }
 
