@@ -49,6 +49,15 @@ enum { VD_BC_DIRICHLET = 0, VD_BC_NEUMANN = 1, VD_BC_WALLFLUX = 2, VD_BC_PERIODI
 
 enum { VD_FP64 = 0, VD_FP32_IR = 1 };                               /* vd_mg_opts.precision */
 enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2 }; /* vd_mg_opts.guess */
+/* vd_mg_opts.flags.  VD_MG_GRAPH: in tolerance mode each cycle (residual
+ * check + V-cycle, or the IR outer step) is replayed from a HIP graph
+ * captured on the first call for this problem shape and options, instead of
+ * being launched kernel by kernel (ignored while kernel timing is on).
+ * VD_MG_AUTOTUNE: on the first solve of a problem shape, time each level's
+ * smoother colour pass for the candidate tile depths and keep the fastest
+ * (the iterate is restored afterwards; the arithmetic of a colour pass does
+ * not depend on the tiling, so results are unchanged). */
+enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2 };
 enum { VD_TE_FIXED = 0, VD_TE_LFA = 1, VD_TE_ENERGY = 2 };          /* electron temperature */
 enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3 };
 /* mobility models (Table A.4 with the Einstein relation):
@@ -87,6 +96,7 @@ typedef struct {
     int32_t precision;
     int32_t guess;
     int32_t ir_inner;
+    int32_t flags;          /* VD_MG_* bits */
 } vd_mg_opts;
 
 /* cycles: V-cycles run (FP32 cycles in IR mode); outer_iters: FP64

@@ -88,6 +88,8 @@ void vd_ctx_destroy(vd_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     try { vd::timing_flush(ctx); } catch (...) {}
     for (auto &e : ctx->timing.pool) (void)hipEventDestroy(e);
+    ctx->cache.clear();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 

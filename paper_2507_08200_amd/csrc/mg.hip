@@ -25,7 +25,6 @@
 namespace vd {
 
 constexpr int kCoarseMax = 4096;     // levels at or below this size run in the fused kernel
-constexpr int kLdsMaxCells = 8192;   // largest level a single workgroup smooths from LDS
 constexpr int kBottomMaxIt = 500;
 constexpr double kBottomTol = 1e-14;
 
@@ -674,45 +673,189 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
 
 // ------------------------------------------- LDS-resident coarse V-cycle
 // One workgroup per problem runs every level from lc down to the bottom
-// with the unknowns and right-hand sides of those levels held in LDS (the
-// face coefficients stay in global memory, read-only), then writes level
-// lc's unknown back.  Dynamic LDS: 2 * sum(cells) * sizeof(T) for the levels
-// plus 6 * bottom cells doubles for the CG vectors.
+// entirely out of LDS, then writes level lc's unknown back.  Each resident
+// level holds x, b and its assembled seven-point row (diagonal and six
+// neighbour weights, zero where the neighbour is absent), so a sweep is
+// branch-free LDS arithmetic; neighbour indices always wrap, an absent
+// neighbour having weight 0.  The rows are assembled once per solve by
+// k_stencils from the same face logic as row_terms, in the hierarchy's
+// precision (the bottom CG also gets an FP64 copy in FP32 hierarchies).
 constexpr int kLdsThreads = 512;
 
+__host__ __device__ __forceinline__ size_t lds_al16(size_t b) { return (b + 15) & ~(size_t)15; }
+// bytes of one resident level: x, b, the row (diagonal then 6 weight
+// planes, contiguous as assembled), optional mask
+__host__ __device__ __forceinline__ size_t lds_level_bytes(long n, size_t sT, bool mask) {
+    return 2 * lds_al16((size_t)n * sT) + lds_al16((size_t)7 * n * sT) + (mask ? lds_al16((size_t)n) : 0);
+}
+// bytes of the bottom CG: r, z, p, q, x (+ FP64 row copy in FP32 hierarchies)
+__host__ __device__ __forceinline__ size_t lds_pcg_bytes(long nb, bool fp32) {
+    return 5 * lds_al16((size_t)nb * sizeof(double)) + (fp32 ? lds_al16((size_t)7 * nb * sizeof(double)) : 0);
+}
+
 template <typename T>
-__device__ __forceinline__ void lds_sweep(const LevDesc &L, T *x, const T *b, int colour) {
-    for (int c = threadIdx.x; c < L.ncell; c += blockDim.x) {
-        int i, j, k;
-        cell_ijk(L, c, i, j, k);
-        if (((i + j + k) & 1) != colour) continue;
-        if (L.has_mask && !gld(L.mask, c)) continue;
-        T dg, of;
-        row_terms<T, T, 3>(L, x, i, j, k, c, dg, of);
-        T bv = lld(b, c);
-        if (L.lift) bv = (T)((double)bv + lift_term(L, i, j, k));
-        lst(x, c, (bv + of) / dg);
+struct LLev {
+    T *x, *b, *dg, *w;        // w: 6 weight planes of n values
+    const uint8_t *m;         // covered-cell mask in LDS (null: all valid)
+    int nx, ny, nz, nxy, n;
+    float inx, inxy;
+};
+
+template <typename T>
+__device__ __forceinline__ LLev<T> lds_lev(char *raw, const LevDesc *dT, int base, int lc, int l) {
+    size_t off = 0;
+    for (int m = lc; m < l; m++) off += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask);
+    const LevDesc &D = dT[base + l];
+    LLev<T> v;
+    const size_t a = lds_al16((size_t)D.ncell * sizeof(T));
+    v.x = (T *)(raw + off);
+    v.b = (T *)(raw + off + a);
+    v.dg = (T *)(raw + off + 2 * a);
+    v.w = v.dg + D.ncell;
+    v.m = D.has_mask ? (const uint8_t *)(raw + off + 2 * a + lds_al16((size_t)7 * D.ncell * sizeof(T))) : nullptr;
+    v.nx = D.nx; v.ny = D.ny; v.nz = D.nz; v.nxy = D.nxy; v.n = D.ncell;
+    v.inx = 1.0f / (float)D.nx;
+    v.inxy = 1.0f / (float)D.nxy;
+    return v;
+}
+
+// (i, j, k) of cell c; (c + 0.5) / d rounded in FP32 stays within the
+// open unit interval of the true quotient for c < 2^22
+template <typename T>
+__device__ __forceinline__ void llev_ijk(const LLev<T> &v, int c, int &i, int &j, int &k) {
+    k = (int)(((float)c + 0.5f) * v.inxy);
+    const int r = c - k * v.nxy;
+    j = (int)(((float)r + 0.5f) * v.inx);
+    i = r - j * v.nx;
+}
+
+template <typename T>
+__device__ __forceinline__ T llev_off(const LLev<T> &v, const T *x, int c, int i, int j, int k) {
+    const int n = v.n;
+    const int xm = i > 0 ? c - 1 : c + v.nx - 1, xp = i < v.nx - 1 ? c + 1 : c - (v.nx - 1);
+    const int ym = j > 0 ? c - v.nx : c + v.nx * (v.ny - 1), yp = j < v.ny - 1 ? c + v.nx : c - v.nx * (v.ny - 1);
+    const int zm = k > 0 ? c - v.nxy : c + v.nxy * (v.nz - 1), zp = k < v.nz - 1 ? c + v.nxy : c - v.nxy * (v.nz - 1);
+    T of = 0;
+    of += lld(v.w, c) * lld(x, xm);
+    of += lld(v.w, n + c) * lld(x, xp);
+    of += lld(v.w, 2 * n + c) * lld(x, ym);
+    of += lld(v.w, 3 * n + c) * lld(x, yp);
+    of += lld(v.w, 4 * n + c) * lld(x, zm);
+    of += lld(v.w, 5 * n + c) * lld(x, zp);
+    return of;
+}
+
+template <typename T>
+__device__ __forceinline__ bool llev_valid(const LLev<T> &v, int c) {
+    return !v.m || lld(v.m, c) != 0;
+}
+
+// one colour pass; with an even nx the two cells of a pair are one of each
+// colour, so every thread updates a cell
+template <typename T>
+__device__ __forceinline__ void llev_sweep(const LLev<T> &v, int colour) {
+    if ((v.nx & 1) == 0) {
+        const int np = v.n >> 1;
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            int i, j, k;
+            llev_ijk(v, 2 * p, i, j, k);
+            const int s = (i + j + k + colour) & 1;
+            const int c = 2 * p + s;
+            i += s;
+            if (!llev_valid(v, c)) continue;
+            const T of = llev_off(v, v.x, c, i, j, k);
+            lst(v.x, c, (lld(v.b, c) + of) / lld(v.dg, c));
+        }
+    } else {
+        for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
+            int i, j, k;
+            llev_ijk(v, c, i, j, k);
+            if (((i + j + k) & 1) != colour || !llev_valid(v, c)) continue;
+            const T of = llev_off(v, v.x, c, i, j, k);
+            lst(v.x, c, (lld(v.b, c) + of) / lld(v.dg, c));
+        }
     }
     __syncthreads();
 }
 
 template <typename T>
-__device__ __forceinline__ T lds_residual(const LevDesc &L, const T *x, const T *b, int c, int i, int j, int k) {
-    if (L.has_mask && !gld(L.mask, c)) return (T)0;
-    T dg, of;
-    row_terms<T, T, 3>(L, x, i, j, k, c, dg, of);
-    T bv = lld(b, c);
-    if (L.lift) bv = (T)((double)bv + lift_term(L, i, j, k));
-    return bv - (dg * lld(x, c) - of);
+__device__ __forceinline__ T llev_resid(const LLev<T> &v, int c) {
+    if (!llev_valid(v, c)) return (T)0;
+    int i, j, k;
+    llev_ijk(v, c, i, j, k);
+    const T of = llev_off(v, v.x, c, i, j, k);
+    return lld(v.b, c) - (lld(v.dg, c) * lld(v.x, c) - of);
 }
 
-// start of level l's unknown in the LDS carve-out (x_l then b_l per level,
-// from level lc down)
+// Jacobi-preconditioned CG on the bottom level, one wavefront, FP64, the
+// row (dg, w) and the vectors in LDS; b and x are the level's LDS arrays
 template <typename T>
-__device__ __forceinline__ T *lds_level(char *raw, const LevDesc *dT, int base, int lc, int l) {
-    size_t off = 0;
-    for (int m = lc; m < l; m++) off += 2 * sizeof(T) * (size_t)dT[base + m].ncell;
-    return (T *)(raw + off);
+__device__ void llev_pcg(const LLev<T> &v, const double *dg, const double *w, double *vec) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x, n = v.n;
+        const size_t a = lds_al16((size_t)n * sizeof(double)) / sizeof(double);
+        double *r = vec, *z = vec + a, *p = vec + 2 * a, *q = vec + 3 * a, *xb = vec + 4 * a;
+        double rr = 0.0, rz = 0.0;
+        for (int c = lane; c < n; c += 64) {
+            const bool valid = llev_valid(v, c);
+            const double rc = valid ? (double)lld(v.b, c) : 0.0;
+            const double zz = valid ? rc / lld(dg, c) : 0.0;
+            lst(r, c, rc);
+            lst(z, c, zz);
+            lst(p, c, zz);
+            lst(xb, c, 0.0);
+            rr += rc * rc;
+            rz += rc * zz;
+        }
+        rr = wave_sum(rr);
+        rz = wave_sum(rz);
+        wave_sync();
+        const double bn = sqrt(rr);
+        const LLev<double> vd{nullptr, nullptr, const_cast<double *>(dg), const_cast<double *>(w), v.m,
+                              v.nx, v.ny, v.nz, v.nxy, v.n, v.inx, v.inxy};
+        for (int it = 0; it < kBottomMaxIt; it++) {
+            if (!(sqrt(rr) > kBottomTol * bn)) break;
+            double pq = 0.0;
+            for (int c = lane; c < n; c += 64) {
+                const double pc = lld(p, c);
+                double qq = 0.0;
+                if (llev_valid(v, c)) {
+                    int i, j, k;
+                    llev_ijk(vd, c, i, j, k);
+                    qq = lld(dg, c) * pc - llev_off(vd, (const double *)p, c, i, j, k);
+                }
+                lst(q, c, qq);
+                pq += pc * qq;
+            }
+            pq = wave_sum(pq);
+            if (pq == 0.0) break;
+            const double al = rz / pq;
+            double rz_new = 0.0, rr_new = 0.0;
+            for (int c = lane; c < n; c += 64) {
+                lst(xb, c, lld(xb, c) + al * lld(p, c));
+                const double rc = lld(r, c) - al * lld(q, c);
+                lst(r, c, rc);
+                const double zz = llev_valid(v, c) ? rc / lld(dg, c) : 0.0;
+                lst(z, c, zz);
+                rz_new += rc * zz;
+                rr_new += rc * rc;
+            }
+            rz_new = wave_sum(rz_new);
+            rr_new = wave_sum(rr_new);
+            const double bcoef = rz_new / rz;
+            rz = rz_new;
+            rr = rr_new;
+            for (int c = lane; c < n; c += 64) lst(p, c, lld(z, c) + bcoef * lld(p, c));
+            wave_sync();
+        }
+        for (int c = lane; c < n; c += 64) lst(v.x, c, (T)lld(xb, c));
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_copy_in(T *dst, const T *src, int n) {
+    for (int c = threadIdx.x; c < n; c += blockDim.x) lst(dst, c, gld(src, c));
 }
 
 template <typename T>
@@ -724,74 +867,137 @@ __global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__res
     const FusedDesc f = fd[blockIdx.x];
     if (!gld(&st[f.prob].active, 0)) return;
     const int base = f.base, lc = f.lc, L = f.L;
-    {
-        const LevDesc A = dT[base + lc];
-        T *x = lds_level<T>(raw, dT, base, lc, lc);
-        T *b = x + A.ncell;
-        const T *gx = (const T *)A.x, *gb = (const T *)A.b;
-        for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) { lst(x, c, gld(gx, c)); lst(b, c, gld(gb, c)); }
-        __syncthreads();
+    // load: level lc's x and b (b + Dirichlet lifting on a finest level), every
+    // resident level's row and mask
+    for (int l = lc; l < L; l++) {
+        const LevDesc &D = dT[base + l];
+        const LLev<T> v = lds_lev<T>(raw, dT, base, lc, l);
+        const T *sg = (const T *)D.sten;
+        lds_copy_in(v.dg, sg, 7 * v.n);   // dg and the weight planes are contiguous
+        if (v.m) for (int c = threadIdx.x; c < v.n; c += blockDim.x) lst(const_cast<uint8_t *>(v.m), c, gld(D.mask, c));
+        if (l == lc) {
+            lds_copy_in(v.x, (const T *)D.x, v.n);
+            for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
+                T bv = gld((const T *)D.b, c);
+                if (D.lift) {
+                    int i, j, k;
+                    cell_ijk(D, c, i, j, k);
+                    bv = (T)((double)bv + lift_term(D, i, j, k));
+                }
+                lst(v.b, c, bv);
+            }
+        }
     }
+    size_t used = 0;
+    for (int m = lc; m < L; m++) used += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask);
+    double *pcg = (double *)(raw + used);
+    const LevDesc &B64 = d64[base + L - 1];
+    const size_t ab = lds_al16((size_t)B64.ncell * sizeof(double)) / sizeof(double);
+    if constexpr (sizeof(T) == 4)
+        if (L >= 2) lds_copy_in(pcg + 5 * ab, (const double *)B64.sten, 7 * B64.ncell);
+    __syncthreads();
     if (L == 1) {
-        const LevDesc A = dT[base];
-        T *x = lds_level<T>(raw, dT, base, 0, 0);
-        T *b = x + A.ncell;
-        for (int s = 0; s < nu_pre + nu_post; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
+        const LLev<T> v = lds_lev<T>(raw, dT, base, 0, 0);
+        for (int s = 0; s < nu_pre + nu_post; s++) { llev_sweep(v, 0); llev_sweep(v, 1); }
     } else {
         for (int l = lc; l < L - 1; l++) {
-            const LevDesc A = dT[base + l];
-            T *x = lds_level<T>(raw, dT, base, lc, l);
-            T *b = x + A.ncell;
-            for (int s = 0; s < nu_pre; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
-            const LevDesc C = dT[base + l + 1];
-            T *xc = b + A.ncell;
-            T *bc = xc + C.ncell;
-            for (int cc = threadIdx.x; cc < C.ncell; cc += blockDim.x) {
+            const LLev<T> v = lds_lev<T>(raw, dT, base, lc, l);
+            for (int s = 0; s < nu_pre; s++) { llev_sweep(v, 0); llev_sweep(v, 1); }
+            const LLev<T> cv = lds_lev<T>(raw, dT, base, lc, l + 1);
+            for (int cc = threadIdx.x; cc < cv.n; cc += blockDim.x) {
                 int I, J, K;
-                cell_ijk(C, cc, I, J, K);
+                llev_ijk(cv, cc, I, J, K);
+                const int c0 = 2 * I + v.nx * 2 * J + v.nxy * 2 * K;
                 T sum = 0;
-                for (int kk = 0; kk < 2; kk++)
-                    for (int jj = 0; jj < 2; jj++)
-                        for (int ii = 0; ii < 2; ii++) {
-                            const int i = 2 * I + ii, j = 2 * J + jj, k = 2 * K + kk;
-                            sum += lds_residual<T>(A, x, b, i + A.nx * j + A.nxy * k, i, j, k);
-                        }
-                lst(bc, cc, (C.has_mask && !gld(C.mask, cc)) ? (T)0 : (T)0.125 * sum);
-                lst(xc, cc, (T)0);
+                sum += llev_resid(v, c0);
+                sum += llev_resid(v, c0 + 1);
+                sum += llev_resid(v, c0 + v.nx);
+                sum += llev_resid(v, c0 + v.nx + 1);
+                sum += llev_resid(v, c0 + v.nxy);
+                sum += llev_resid(v, c0 + v.nxy + 1);
+                sum += llev_resid(v, c0 + v.nxy + v.nx);
+                sum += llev_resid(v, c0 + v.nxy + v.nx + 1);
+                lst(cv.b, cc, llev_valid(cv, cc) ? (T)0.125 * sum : (T)0);
+                lst(cv.x, cc, (T)0);
             }
             __syncthreads();
         }
         {
-            const LevDesc A = dT[base + L - 1];
-            const LevDesc A64 = d64[base + L - 1];
-            T *x = lds_level<T>(raw, dT, base, lc, L - 1);
-            size_t used = 0;
-            for (int m = lc; m < L; m++) used += 2 * sizeof(T) * (size_t)dT[base + m].ncell;
-            used = (used + 15) & ~(size_t)15;
-            wave_pcg<T, 3>(A64, x + A.ncell, x, (double *)(raw + used));
+            const LLev<T> v = lds_lev<T>(raw, dT, base, lc, L - 1);
+            if constexpr (sizeof(T) == 4) llev_pcg(v, pcg + 5 * ab, pcg + 5 * ab + v.n, pcg);
+            else llev_pcg(v, v.dg, v.w, pcg);
         }
         for (int l = L - 2; l >= lc; l--) {
-            const LevDesc A = dT[base + l];
-            const LevDesc C = dT[base + l + 1];
-            T *x = lds_level<T>(raw, dT, base, lc, l);
-            T *b = x + A.ncell;
-            const T *xc = b + A.ncell;
-            for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) {
-                if (A.has_mask && !gld(A.mask, c)) continue;
+            const LLev<T> v = lds_lev<T>(raw, dT, base, lc, l);
+            const LLev<T> cv = lds_lev<T>(raw, dT, base, lc, l + 1);
+            for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
+                if (!llev_valid(v, c)) continue;
                 int i, j, k;
-                cell_ijk(A, c, i, j, k);
-                lst(x, c, lld(x, c) + lld(xc, (i >> 1) + C.nx * (j >> 1) + C.nxy * (k >> 1)));
+                llev_ijk(v, c, i, j, k);
+                lst(v.x, c, lld(v.x, c) + lld(cv.x, (i >> 1) + cv.nx * (j >> 1) + cv.nxy * (k >> 1)));
             }
             __syncthreads();
-            for (int s = 0; s < nu_post; s++) { lds_sweep<T>(A, x, b, 0); lds_sweep<T>(A, x, b, 1); }
+            for (int s = 0; s < nu_post; s++) { llev_sweep(v, 0); llev_sweep(v, 1); }
         }
     }
     {
-        const LevDesc A = dT[base + lc];
-        const T *x = lds_level<T>(raw, dT, base, lc, lc);
-        T *gx = (T *)A.x;
-        for (int c = threadIdx.x; c < A.ncell; c += blockDim.x) gst(gx, c, lld(x, c));
+        const LLev<T> v = lds_lev<T>(raw, dT, base, lc, lc);
+        T *gx = (T *)dT[base + lc].x;
+        for (int c = threadIdx.x; c < v.n; c += blockDim.x) gst(gx, c, lld(v.x, c));
     }
+}
+
+// Assembled rows of every LDS-resident level (one workgroup per problem):
+// the diagonal, then the six neighbour weights in the order x-, x+, y-, y+,
+// z-, z+, by the same rules as row_terms.  FP32 hierarchies also get the
+// bottom level's FP64 row for the bottom CG.
+template <typename T>
+__device__ void stencil_rows(const LevDesc &L, T *out) {
+    const int n = L.ncell;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int i, j, k;
+        cell_ijk(L, c, i, j, k);
+        const int nx = L.nx, ny = L.ny, nz = L.nz;
+        T dg = L.var_alpha ? gld(Coef<T>::al(L), c) : (T)L.alpha_c;
+        const T bc = (T)L.beta_c;
+        const long fxrow = (long)(nx + 1) * (j + (long)ny * k);
+        const long fyrow = (long)nx * (j + (long)(ny + 1) * k);
+        const long fzpl = (long)nx * j;
+        const bool inside[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+        const int nbi[6] = {i > 0 ? c - 1 : c + nx - 1, i < nx - 1 ? c + 1 : c - (nx - 1),
+                            j > 0 ? c - nx : c + nx * (ny - 1), j < ny - 1 ? c + nx : c - nx * (ny - 1),
+                            k > 0 ? c - L.nxy : c + L.nxy * (nz - 1), k < nz - 1 ? c + L.nxy : c - L.nxy * (nz - 1)};
+#pragma unroll
+        for (int f = 0; f < 6; f++) {
+            T beta;
+            if (!L.var_beta) beta = bc;
+            else if (f == 0) beta = gld(Coef<T>::bx(L), fxrow + i);
+            else if (f == 1) beta = gld(Coef<T>::bx(L), fxrow + i + 1);
+            else if (f == 2) beta = gld(Coef<T>::by(L), fyrow + i);
+            else if (f == 3) beta = gld(Coef<T>::by(L), fyrow + i + nx);
+            else if (f == 4) beta = gld(Coef<T>::bz(L), fzpl + i + (long)L.nxy * k);
+            else beta = gld(Coef<T>::bz(L), fzpl + i + (long)L.nxy * (k + 1));
+            const T cf = beta * (T)(f < 2 ? L.idx2 : (f < 4 ? L.idy2 : L.idz2));
+            T wv = 0;
+            if (inside[f] || L.kind[f] == VD_BC_PERIODIC) {
+                if (L.has_mask && !gld(L.mask, nbi[f])) dg += (T)2 * cf;
+                else { dg += cf; wv = cf; }
+            } else if (L.kind[f] == VD_BC_DIRICHLET) {
+                dg += (T)2 * cf;
+            }
+            gst(out, (long)(f + 1) * n + c, wv);
+        }
+        gst(out, (long)c, dg);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_stencils(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
+                                                  const FusedDesc *__restrict__ fd) {
+    const FusedDesc f = fd[blockIdx.x];
+    for (int l = f.lc; l < f.L; l++) stencil_rows<T>(dT[f.base + l], (T *)dT[f.base + l].sten);
+    if constexpr (sizeof(T) == 4)
+        if (f.L >= 2) stencil_rows<double>(d64[f.base + f.L - 1], (double *)d64[f.base + f.L - 1].sten);
 }
 
 // -------------------------------------------------------- setup kernels
@@ -919,6 +1125,8 @@ struct HLevel {
     DevBuf<double> bx, by, bz, alpha, x, b;
     DevBuf<float> bx32, by32, bz32, alpha32, x32, b32;
     DevBuf<uint8_t> mask;
+    DevBuf<double> st64;     // assembled rows (LDS-resident levels; FP64 bottom of FP32 hierarchies)
+    DevBuf<float> st32;
 };
 
 struct HProblem {
@@ -958,11 +1166,16 @@ struct Solver {
     HPlan all0_25;                               // finest level as 2.5D tiles (residual norms), if usable
     std::vector<HPlan> pre25;                    // smoother levels as 2.5D tiles, if usable
     std::vector<char> key;                       // problem bytes the descriptors were built from
+    bool rows_valid = false;                     // assembled LDS rows match the descriptors
+    hipGraphExec_t gexec = nullptr;              // one captured cycle (VD_MG_GRAPH)
+    std::string gkey;                            // options the graph was captured with
+    bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
     bool aligned = true;                         // finest-level unknowns 16-byte aligned (row-pair loads)
     ~Solver() {
         if (pin64) (void)hipHostFree(pin64);
         if (pin32) (void)hipHostFree(pin32);
         if (pin_st) (void)hipHostFree(pin_st);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
 
@@ -1107,7 +1320,32 @@ static LevDesc make_desc(const HProblem &H, const vd_problem &P, int l, int prob
     if (fp32) { D.x = V.x32.p; D.b = V.b32.p; }
     else if (l == 0) { D.x = P.x; D.b = P.rhs; }
     else { D.x = V.x.p; D.b = V.b.p; }
+    D.sten = fp32 ? (void *)V.st32.p : (void *)V.st64.p;
     return D;
+}
+
+// 2.5D tiled plan over (descriptor id, level) items: usable when every
+// level has an even nx.  kz = planes per workgroup; 0 picks the deepest
+// tile that still gives a launch >= 2048 workgroups.
+static void build_plan25(vd_ctx *ctx, HPlan &out, const std::vector<std::pair<int, const HLevel *>> &items, int force_kz) {
+    out = HPlan{};
+    if (items.empty()) return;
+    for (auto &it : items) if (it.second->nx % 2) return;
+    int kz = force_kz;
+    if (kz <= 0) {
+        kz = 2;
+        for (int cand : {16, 8, 4, 2}) {
+            long tot = 0;
+            for (auto &it : items)
+                tot += (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
+            if (tot >= 2048 || cand == 2) { kz = cand; break; }
+        }
+    }
+    out.kz = kz;
+    for (auto &it : items)
+        plan_add(out, it.first, (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) *
+                                    ceil_div(it.second->nz, kz), 1);
+    upload_plan(out, ctx->stream);
 }
 
 static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
@@ -1147,18 +1385,17 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         for (int l = 0; l < H.L - 1; l++)
             if ((long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz <= kCoarseMax) { H.lc = l; break; }
         // LDS-resident coarse levels: the largest set of coarse levels whose
-        // unknowns, right-hand sides and CG vectors fit in one workgroup's LDS
+        // unknowns, right-hand sides, assembled rows and CG vectors fit in one
+        // workgroup's LDS
         {
             const size_t sT = ir ? sizeof(float) : sizeof(double);
             const long nb = H.L >= 2 ? (long)H.lv[H.L - 1].nx * H.lv[H.L - 1].ny * H.lv[H.L - 1].nz : 0;
             int best = -1;
             size_t best_bytes = 0;
             for (int l = H.L - 1; l >= 0; l--) {
-                const long nl = (long)H.lv[l].nx * H.lv[l].ny * H.lv[l].nz;
-                if (nl > kLdsMaxCells) break;
-                size_t need = 0;
-                for (int m = l; m < H.L; m++) need += 2 * sT * (size_t)H.lv[m].nx * H.lv[m].ny * H.lv[m].nz;
-                need = ((need + 15) & ~(size_t)15) + (H.L >= 2 ? 6 * sizeof(double) * (size_t)nb : 0);
+                size_t need = H.L >= 2 ? lds_pcg_bytes(nb, ir) : 0;
+                for (int m = l; m < H.L; m++)
+                    need += lds_level_bytes((long)H.lv[m].nx * H.lv[m].ny * H.lv[m].nz, sT, H.has_mask);
                 if (need > lds_limit) break;
                 best = l;
                 best_bytes = need;
@@ -1183,6 +1420,13 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
             for (auto &H : S->probs) {
                 H.lc = H.lds_lc >= 0 ? H.lds_lc : 1;
                 if (H.lds_lc >= 0) S->lds_bytes = std::max(S->lds_bytes, H.lds_bytes);
+                for (int l = H.lc; l < H.L; l++) {
+                    HLevel &V = H.lv[l];
+                    const size_t n7 = (size_t)7 * V.nx * V.ny * V.nz;
+                    if (ir) V.st32.alloc(n7);
+                    else V.st64.alloc(n7);
+                    if (ir && l == H.L - 1 && H.L >= 2) V.st64.alloc(n7);
+                }
             }
         }
     }
@@ -1223,23 +1467,8 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
             max_bottom = std::max(max_bottom, (long)Bt.nx * Bt.ny * Bt.nz);
         }
     }
-    // 2.5D tiled plans: usable when every level in the plan has an even nx;
-    // planes per workgroup chosen so that a launch has >= 2048 workgroups
     auto build25 = [&](HPlan &out, const std::vector<std::pair<int, const HLevel *>> &items) {
-        if (items.empty()) return;
-        for (auto &it : items) if (it.second->nx % 2) return;
-        int kz = 2;
-        for (int cand : {16, 8, 4, 2}) {
-            long tot = 0;
-            for (auto &it : items)
-                tot += (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
-            if (tot >= 2048 || cand == 2) { kz = cand; break; }
-        }
-        out.kz = kz;
-        for (auto &it : items)
-            plan_add(out, it.first, (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) *
-                                        ceil_div(it.second->nz, kz), 1);
-        upload_plan(out, ctx->stream);
+        build_plan25(ctx, out, items, 0);
     };
     {
         std::vector<std::pair<int, const HLevel *>> items;
@@ -1292,6 +1521,7 @@ static void refresh_descs(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *p
     for (int p = 0; p < nprob; p++)
         S.aligned = S.aligned && ((uintptr_t)probs[p].x % 16 == 0) && ((uintptr_t)probs[p].rhs % 16 == 0);
     S.key = std::move(key);
+    S.rows_valid = false;
 }
 
 // Coefficients of every level from the user's arrays (values may change
@@ -1326,6 +1556,17 @@ static void setup_coefficients(vd_ctx *ctx, Solver &S, const vd_problem *probs) 
                                                                     V.by32.p, V.bz32.p, V.alpha32.p);
             });
         }
+    }
+    // assembled rows of the LDS-resident levels (constant-coefficient rows
+    // depend only on the descriptors, so they are kept until those change)
+    bool var_any = false;
+    for (auto &H : S.probs) var_any = var_any || H.var_beta || H.var_alpha || H.has_mask;
+    if (S.lds_mode && S.nfused && (var_any || !S.rows_valid)) {
+        timed(ctx, "setup", 0.0, [&] {
+            if (ir) k_stencils<float><<<S.nfused, 256, 0, s>>>(S.d32.p, S.d64.p, S.fused.p);
+            else k_stencils<double><<<S.nfused, 256, 0, s>>>(S.d64.p, S.d64.p, S.fused.p);
+        });
+        S.rows_valid = true;
     }
 }
 
@@ -1455,6 +1696,124 @@ static int read_active(vd_ctx *ctx, Solver &S) {
     return n;
 }
 
+// One tolerance-mode iteration: residual check (which retires converged
+// problems on the device), then a V-cycle, or in IR mode ir_inner FP32
+// cycles and the FP64 update.
+static void one_cycle(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
+    if (S.prec != VD_FP32_IR) {
+        launch_norm(ctx, S, 1, 1);
+        launch_finalize(ctx, S, 1, o, 1);
+        vcycle<double>(ctx, S, S.d64.p, o);
+    } else {
+        launch_norm(ctx, S, 2, 1);
+        launch_finalize(ctx, S, 1, o, o->ir_inner);
+        for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, S, S.d32.p, o);
+        timed(ctx, "ir_update", plan_bytes(S, S.all0, false, 3) * 2.5, [&] {
+            k_ir_update<<<xcd_grid(S.all0.ntiles), kBlock, 0, ctx->stream>>>(S.d64.p, S.d32.p, S.all0.dev(), S.st.p);
+        });
+    }
+}
+
+// The iteration above captured once into a HIP graph (on a private
+// non-blocking stream, since the caller's stream may be the null stream)
+// and replayed on the caller's stream.  Kernel arguments are device
+// descriptor tables whose contents are refreshed outside the graph, so the
+// graph stays valid until the options, the tiling or the alignment change.
+static hipGraphExec_t cycle_graph(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
+    char kb[160];
+    snprintf(kb, sizeof(kb), "%d,%d,%d,%d,%.17g,%d,%d,%d", o->nu_pre, o->nu_post, o->ir_inner, o->max_cycles, o->rtol,
+             o->fixed_cycles, (int)S.aligned, (int)S.tuned);
+    std::string gk = kb;
+    for (int l = 0; l < S.Lmax; l++) gk += "," + std::to_string(S.pre25[l].kz);
+    if (S.gexec && S.gkey == gk) return S.gexec;
+    if (S.gexec) { (void)hipGraphExecDestroy(S.gexec); S.gexec = nullptr; }
+    if (!ctx->cap_stream) VD_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // the descriptor uploads above must land before the replay, which is
+    // ordered on the caller's stream; capture itself runs nothing
+    hipStream_t saved = ctx->stream;
+    hipGraph_t g = nullptr;
+    VD_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->stream = ctx->cap_stream;
+    try {
+        one_cycle(ctx, S, o);
+    } catch (...) {
+        ctx->stream = saved;
+        (void)hipStreamEndCapture(ctx->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    ctx->stream = saved;
+    VD_HIP(hipStreamEndCapture(ctx->cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { S.gexec = nullptr; throw Error{VD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)}; }
+    S.gkey = gk;
+    return S.gexec;
+}
+
+// Tile-depth autotuning of the 2.5D smoother: for each level, time both
+// colour passes for kz in {2, 4, 8, 16} and keep the fastest.  Every
+// level's unknowns are saved first and restored after, so the solve that
+// follows starts from the caller's iterate.
+template <typename T>
+static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vector<LevDesc> &hT) {
+    hipStream_t s = ctx->stream;
+    std::vector<std::pair<void *, size_t>> xs;
+    size_t total = 0;
+    for (int l = 0; l < S.Lmax; l++)
+        for (int id : S.pre[l].h_ids) { xs.push_back({hT[id].x, (size_t)hT[id].ncell * sizeof(T)}); total += xs.back().second; }
+    DevBuf<char> save;
+    save.alloc(total);
+    size_t off = 0;
+    for (auto &x : xs) { VD_HIP(hipMemcpyAsync(save.p + off, x.first, x.second, hipMemcpyDeviceToDevice, s)); off += x.second; }
+    hipEvent_t e0, e1;
+    VD_HIP(hipEventCreate(&e0));
+    VD_HIP(hipEventCreate(&e1));
+    for (int l = 0; l < S.Lmax; l++) {
+        if (!S.pre25[l].nd) continue;
+        std::vector<std::pair<int, const HLevel *>> items;
+        for (int id : S.pre[l].h_ids) items.push_back({id, &S.probs[id / S.Lmax].lv[id % S.Lmax]});
+        float best = 1e30f;
+        int best_kz = S.pre25[l].kz;
+        for (int kz : {2, 4, 8, 16}) {
+            HPlan cand;
+            build_plan25(ctx, cand, items, kz);
+            auto pass = [&] {
+                for (int col = 0; col < 2; col++)
+                    k_st25<T, 0><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz, col, nullptr, S.st.p, 1);
+            };
+            pass();   // warm
+            VD_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 3; r++) pass();
+            VD_HIP(hipEventRecord(e1, s));
+            VD_HIP(hipGetLastError());
+            VD_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            VD_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best * 0.97f) { best = ms; best_kz = kz; }
+        }
+        if (best_kz != S.pre25[l].kz) build_plan25(ctx, S.pre25[l], items, best_kz);
+    }
+    off = 0;
+    for (auto &x : xs) { VD_HIP(hipMemcpyAsync(x.first, save.p + off, x.second, hipMemcpyDeviceToDevice, s)); off += x.second; }
+    VD_HIP(hipStreamSynchronize(s));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+static void autotune(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
+    (void)o;
+    // the smoother kernels skip problems whose flag is clear; the state is
+    // re-initialised by the solve that follows
+    k_state_init<<<ceil_div(S.nprob, 64), 64, 0, ctx->stream>>>(S.st.p, S.nprob);
+    VD_HIP(hipGetLastError());
+    if (S.aligned) {
+        if (S.prec == VD_FP32_IR) autotune_t<float>(ctx, S, S.d32.p, S.h32);
+        else autotune_t<double>(ctx, S, S.d64.p, S.h64);
+    }
+    S.tuned = true;
+}
+
 // Full solve of a batch (the engine behind vd_poisson_solve,
 // vd_helmholtz_solve_batched and the implicit solves of vd_step).
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
@@ -1470,6 +1829,9 @@ vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const 
     }
     refresh_descs(ctx, *S, nprob, probs, o);
     setup_coefficients(ctx, *S, probs);
+    // tuning runs smoother passes on the caller's iterate (restored after),
+    // before the convergence state of this solve is initialised
+    if ((o->flags & VD_MG_AUTOTUNE) && !S->tuned) autotune(ctx, *S, o);
     hipStream_t s = ctx->stream;
     k_state_init<<<ceil_div(nprob, 64), 64, 0, s>>>(S->st.p, nprob);
     VD_HIP(hipGetLastError());
@@ -1480,11 +1842,15 @@ vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const 
     });
     const bool ir = S->prec == VD_FP32_IR;
     const bool async_fixed = o->fixed_cycles > 0 && infos == nullptr;
+    const bool use_graph = (o->flags & VD_MG_GRAPH) && !async_fixed && ctx->timing.families.empty();
+    hipGraphExec_t gexec = use_graph ? cycle_graph(ctx, *S, o) : nullptr;
     int iters = 0;
     const int chunk = async_fixed ? (o->fixed_cycles + 1) : 2;
     while (true) {
         for (int c = 0; c < chunk; c++) {
-            if (!ir) {
+            if (gexec) {
+                VD_HIP(hipGraphLaunch(gexec, s));
+            } else if (!ir) {
                 launch_norm(ctx, *S, 1, 1);
                 launch_finalize(ctx, *S, 1, o, 1);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }

@@ -81,6 +81,7 @@ struct LevDesc {
     const uint8_t *mask;
     void *x;                     // unknown (double or float by hierarchy)
     const void *b;               // right-hand side
+    void *sten;                  // assembled rows of an LDS-resident level (diagonal + 6 weight planes), else null
 };
 
 // Per-problem convergence state, device resident.
@@ -153,6 +154,7 @@ struct Timing {
 
 struct vd_ctx {
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;    // private stream for HIP graph capture
     std::string last_error;
     vd::Timing timing;
     std::map<std::string, std::shared_ptr<void>> cache;   // solver hierarchies by key

@@ -322,3 +322,52 @@ def test_cached_hierarchy_different_spacing(ctx, V, oracle):
         infos, st = ctx.vd_helmholtz_solve_batched([g], V.mg_opts(rtol=1e-10))
         assert st == 0
         _pinned_compare(oracle, prob, host(g["x"]), infos[0], 1e-10)
+
+
+# ------------------------------------------------ batch pins, graphs, autotune
+def _cfg4_small(count, sizes):
+    """The 64-problem sheath-jump recipe, at test sizes."""
+    return I.cfg4(seed=4, count=count, sizes=sizes)
+
+
+def test_batch_equals_alone(ctx, V):
+    """Batching does not change the arithmetic: every problem of a batch of
+    uneven sheath-jump problems equals the same problem solved alone at the
+    same cycle count."""
+    probs = _cfg4_small(8, (16, 32, 48))
+    gs = [gpu_problem(p) for p in probs]
+    say("batch vs alone", [p["grid"][0] for p in probs])
+    infos, st = ctx.vd_helmholtz_solve_batched(gs, V.mg_opts(rtol=1e-10))
+    assert st == 0
+    for p, prob in enumerate(probs):
+        g = gpu_problem(prob)
+        i1, s1 = ctx.vd_helmholtz_solve_batched([g], V.mg_opts(rtol=1e-10, fixed_cycles=infos[p]["cycles"]))
+        assert s1 == 0
+        assert rel_err(host(gs[p]["x"]), host(g["x"])) <= TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_replay_and_autotune(ctx, V, oracle, precision):
+    """Graph replay and tile autotuning reproduce the kernel-by-kernel
+    solve: same cycle counts, the same iterate to 1e-13; and the result is
+    pinned against the oracle like every other solve (FP64)."""
+    prec = V.FP64 if precision == "fp64" else V.FP32_IR
+    shapes = [(32, 32, 32), (48, 40, 32), (24, 24, 24)]
+    probs = [I.random_helmholtz(700 + p, s, beta_jump=True) for p, s in enumerate(shapes)]
+    ref = [gpu_problem(p) for p in probs]
+    say("graph/autotune", precision)
+    i_ref, st = ctx.vd_helmholtz_solve_batched(ref, V.mg_opts(rtol=1e-10, precision=prec))
+    assert st == 0
+    for opts in (dict(graph=True), dict(autotune=True), dict(graph=True, autotune=True)):
+        ctx2 = V.Context()
+        for rep in range(3):   # capture, then replays (with eager work in between)
+            gs = [gpu_problem(p) for p in probs]
+            infos, st = ctx2.vd_helmholtz_solve_batched(gs, V.mg_opts(rtol=1e-10, precision=prec, **opts))
+            assert st == 0
+            torch.cuda.synchronize()
+            for p in range(len(probs)):
+                assert infos[p]["cycles"] == i_ref[p]["cycles"], (opts, rep, p)
+                assert rel_err(host(gs[p]["x"]), host(ref[p]["x"])) <= 1e-13, (opts, rep, p)
+    if prec == V.FP64:
+        for p in range(len(probs)):
+            _pinned_compare(oracle, probs[p], host(ref[p]["x"]), i_ref[p], 1e-10)
