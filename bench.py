@@ -48,7 +48,62 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=112, help="grid edge of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (auto = dominant)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched Helmholtz timing")
+    ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
+
+
+def batch_bench(ctx, V, I, dev, reps):
+    """The 64-problem batch (edges 32..160 in steps of 16, unit cube, alpha 1,
+    a 1e-3..1 sheath jump, random Dirichlet/Neumann faces, N(0,1) rhs) solved
+    to 1e-10 from zero: one call per problem, one batched call, and the
+    batched call with graph replay and tile autotuning."""
+    import numpy as np
+    import torch
+    probs = I.cfg4()
+    cells = sum(p["grid"][0] ** 3 for p in probs)
+    log("[bench] batch: %d problems, %d cells" % (len(probs), cells))
+    gs = []
+    for p in probs:
+        gs.append({"grid": p["grid"], "bc": p["bc"], "mask": None, "alpha": None, "alpha_c": p["alpha_c"],
+                   "beta": torch.tensor(p["beta"], device=dev), "beta_c": 0.0,
+                   "rhs": torch.tensor(p["rhs"], device=dev), "x": torch.zeros(p["grid"][:3], dtype=torch.float64, device=dev)})
+        p["beta"] = p["rhs"] = None
+
+    def timed_solve(fn):
+        ts, out = [], None
+        for r in range(reps + 1):       # the first call builds hierarchies / captures / tunes
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if r > 0:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), out
+
+    def seq():
+        return [ctx.vd_helmholtz_solve_batched([g], V.mg_opts(rtol=1e-10, guess=V.GUESS_ZERO))[0][0] for g in gs]
+
+    def bat(**kw):
+        return lambda: ctx.vd_helmholtz_solve_batched(gs, V.mg_opts(rtol=1e-10, guess=V.GUESS_ZERO, **kw))[0]
+
+    res = {"problems": len(probs), "cells": cells, "rtol": 1e-10}
+    ms, infos = timed_solve(seq)
+    res["sequential_ms"] = round(ms, 3)
+    res["cycles_max"] = max(i["cycles"] for i in infos)
+    x_seq = [g["x"].clone() for g in gs]
+    for name, kw in (("batched_ms", {}), ("batched_graph_ms", {"graph": True}),
+                     ("batched_graph_autotune_ms", {"graph": True, "autotune": True})):
+        ms, infos = timed_solve(bat(**kw))
+        res[name] = round(ms, 3)
+        # batching changes no arithmetic: same iterate as the sequential solves
+        dmax = max(float((g["x"] - x).abs().max() / x.abs().max()) for g, x in zip(gs, x_seq))
+        res[name.replace("_ms", "_max_rel_diff_vs_sequential")] = dmax
+    res["cell_cycles_per_s_batched_graph"] = round(sum(i["cycles"] * p["grid"][0] ** 3 for i, p in zip(infos, probs))
+                                                   / (res["batched_graph_ms"] * 1e-3), 1)
+    log("[bench] batch: %s" % res)
+    return res
 
 
 def main():
@@ -157,6 +212,9 @@ def main():
     }
     log("[bench] poisson time-to-1e-10: %s" % poisson)
 
+    # ---- 64 uneven sheath-jump Helmholtz problems: sequential vs batched
+    batch = None if args.no_batch else batch_bench(ctx, V, I, dev, args.batch_reps)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +248,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "poisson_time_to_1e-10": poisson,
+        "batched_helmholtz_64": batch,
         "kernel_profile_warmup": prof,
     }
     print(json.dumps(out), flush=True)

@@ -241,3 +241,27 @@ def cfg4(seed: int = 4, count: int = 64, sizes=tuple(range(32, 161, 16))) -> lis
             "x0": np.zeros((n, n, n)),
         })
     return probs
+
+
+# ------------------------------------------------ warm-start network inputs
+NN_CFG = {"levels": 3, "ch": [8, 16, 32], "cin": 2}
+
+
+def nn_init(seed: int, cfg: dict = NN_CFG) -> np.ndarray:
+    """Seeded initial parameters of the warm-start U-Net as one FP32 vector:
+    per convolution (encoder a/b per level, then up/dec from the second
+    coarsest level to the finest, then the 1-channel output) He-normal
+    weights of shape (co, 3, 3, 3, ci) followed by zero biases."""
+    g = rng(seed)
+    L, ch, cin = cfg["levels"], list(cfg["ch"]), cfg.get("cin", 2)
+    shapes = []
+    for l in range(L):
+        shapes += [(cin if l == 0 else ch[l - 1], ch[l]), (ch[l], ch[l])]
+    for l in range(L - 2, -1, -1):
+        shapes += [(ch[l + 1], ch[l]), (ch[l], ch[l])]
+    shapes.append((ch[0], 1))
+    out = []
+    for ci, co in shapes:
+        out.append(g.standard_normal(co * 27 * ci) * np.sqrt(2.0 / (27 * ci)))
+        out.append(np.zeros(co))
+    return np.concatenate(out).astype(np.float32)
