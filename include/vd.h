@@ -248,6 +248,70 @@ typedef struct {
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
                   vd_step_info *info /* host, nullable */);
 
+/* ---- learned initial guess for the Poisson solve ----
+ * Not in the paper: a small 3D U-Net (bfloat16 storage, FP32 accumulation
+ * on the matrix cores) predicts phi from the charge density; the multigrid
+ * solve of vd_poisson_solve then runs from that guess (opts.guess =
+ * VD_GUESS_LEARNED) and still decides convergence.  Architecture: per level
+ * l < levels two 3x3x3 convolutions with ReLU (c_l channels; level l+1 on
+ * the 2x2x2 mean of level l); decoder per level l from levels-2 to 0: a
+ * 3x3x3 convolution c_{l+1} -> c_l with ReLU at level l+1, nearest
+ * upsampling, plus the encoder output of level l, a 3x3x3 convolution with
+ * ReLU; a final 3x3x3 convolution c_0 -> 1.  Zero padding, biases.
+ * Parameters: one FP32 vector, per convolution in that order (encoder a, b
+ * per level; then up, dec from level levels-2 down to 0; then the output)
+ * the weights [co][dz][dy][dx][ci] followed by the biases [co].
+ * Tensors: [cell][channel], cells in the [nz][ny][nx] order, device. */
+typedef struct {
+    int32_t levels;     /* 1..4 */
+    int32_t ch[4];      /* channels per level, 1..64 */
+    int32_t cin;        /* input channels (2 for the warm start) */
+} vd_nn_config;
+
+/* parameter count of a configuration, -1 if it is invalid */
+int64_t vd_nn_param_count(const vd_nn_config *cfg);
+
+/* create (or replace) the context's network; params: host FP32
+ * [param_count], NULL = zeros.  Adam moments start at zero. */
+vd_status vd_nn_create(vd_ctx *ctx, const vd_nn_config *cfg, const float *params);
+
+/* copy a host FP32 vector from (get) or into (set) the network: which = 0
+ * parameters, 1 gradients of the last train step, 2 / 3 Adam first / second
+ * moments */
+vd_status vd_nn_get(vd_ctx *ctx, int32_t which, float *host);
+vd_status vd_nn_set(vd_ctx *ctx, int32_t which, const float *host);
+
+/* inference: in [cells][cin] bfloat16 bits, out [cells] FP32 (device);
+ * every grid dimension divisible by 2^(levels-1) */
+vd_status vd_nn_forward(vd_ctx *ctx, const vd_grid *grid, const uint16_t *in_bf16, float *out);
+
+/* one training step on one sample: loss = mean((net(in) - target)^2),
+ * gradients by backpropagation, then (update != 0) one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8) with learning rate lr.  loss: host, nullable. */
+vd_status vd_nn_train_step(vd_ctx *ctx, const vd_grid *grid, const uint16_t *in_bf16, const float *target, float lr,
+                           int32_t update, double *loss);
+
+/* network input of the warm start for a potential problem: channel 0 =
+ * rho Lx^2 / (eps V), channel 1 = (linear ramp between the Dirichlet values
+ * of the two x faces, 0 unless both are Dirichlet) / V, with V the largest
+ * |Dirichlet value| of phi_bc (1 if none); out [cells][2] bfloat16 (device);
+ * vref (host, nullable) receives V.  The guess is phi = V * net output. */
+vd_status vd_nn_features(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const double *rho, double eps,
+                         uint16_t *out_bf16, double *vref);
+
+/* network file: 8-byte tag, vd_nn_config, int64 parameter count, FP32
+ * parameters; load creates the network */
+vd_status vd_nn_save(vd_ctx *ctx, const char *path);
+vd_status vd_nn_load(vd_ctx *ctx, const char *path);
+
+/* one 3x3x3 convolution (zero padding) and, if dy is given, its gradients:
+ * x [cells][ci] bfloat16 bits, w [co][27][ci] and b [co] FP32 (the weights
+ * are rounded to bfloat16, accumulation FP32), y [cells][co] FP32 (nullable;
+ * ReLU if relu), dy [cells][co] FP32 -> dx [cells][ci], dw [co][27][ci],
+ * db [co] FP32.  All device pointers; synchronises. */
+vd_status vd_nn_conv3d(vd_ctx *ctx, const vd_grid *grid, const uint16_t *x_bf16, int32_t ci, const float *w, const float *b,
+                       int32_t co, int32_t relu, float *y, const float *dy, float *dx, float *dw, float *db);
+
 /* ---- inspection entry points (tests and tuning) ---- */
 
 /* Per-cell flags of multigrid level `level` of a problem: bit 0 colour

@@ -172,12 +172,21 @@ def forward(params, x, cfg, rounding=True):
     return out, cache
 
 
-def backward(params, cache, dout, cfg):
+def backward(params, cache, dout, cfg, grad_rounding=False):
     """Gradient of sum(out * dout) with respect to the flat parameters (the
-    forward's rounding points are treated as identities, as in training)."""
+    forward's rounding points are treated as identities, as in training).
+    With grad_rounding the output gradient of each convolution is rounded to
+    bfloat16 where it feeds the input-gradient product (the device path runs
+    that product on bfloat16 operands); weight gradients use it unrounded."""
     L = cfg["levels"]
     W = cache["W"]
     g = {}
+
+    def conv3d_backward(x, w, dy):
+        dx = _conv_dx(w, bf16(dy) if grad_rounding else dy, x.shape)
+        _, dw, db = _conv3d_backward(x, w, dy)
+        return dx, dw, db
+
     w, _ = W["out"]
     dd, dw, db = conv3d_backward(cache["d0"], w, dout)
     g["out"] = (dw, db)
@@ -215,6 +224,13 @@ def backward(params, cache, dout, cfg):
         flat.append(dw.ravel())
         flat.append(db.ravel())
     return np.concatenate(flat)
+
+
+_conv3d_backward = conv3d_backward
+
+
+def _conv_dx(w, dy, xshape):
+    return conv3d_backward(np.zeros(xshape), w, dy)[0]
 
 
 def mse(out, target):

@@ -49,8 +49,24 @@ void timing_flush(vd_ctx *ctx) {
     T.pending.clear();
 }
 
+vd_status nn_create(vd_ctx *ctx, const vd_nn_config *cfg, const float *params);
+int64_t nn_param_count(const vd_nn_config *cfg);
+vd_status nn_params(vd_ctx *ctx, int which, float *host, int set);
+vd_status nn_forward(vd_ctx *ctx, const vd_grid *g, const uint16_t *in, float *out);
+vd_status nn_train_step(vd_ctx *ctx, const vd_grid *g, const uint16_t *in, const float *target, float lr, int update,
+                        double *loss);
+vd_status nn_features(vd_ctx *ctx, const vd_grid *g, const vd_bc *bc, const double *rho, double eps, uint16_t *out,
+                      double *vref);
+vd_status nn_guess(vd_ctx *ctx, const vd_grid *g, const vd_bc *bc, const double *rho, double eps, double *x);
+vd_status nn_save(vd_ctx *ctx, const char *path);
+vd_status nn_load(vd_ctx *ctx, const char *path);
+vd_status nn_conv3d(vd_ctx *ctx, const vd_grid *g, const uint16_t *x, int ci, const float *w, const float *b, int co, int relu,
+                    float *y, const float *dy, float *dx, float *dw, float *db);
+vd_status mg_solve_batch_guess(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                               const char *cache_tag);
 }  // namespace vd
 
+namespace vd {
 template <typename F>
 static vd_status guarded(vd_ctx *ctx, F &&fn) {
     if (!ctx) return VD_EINVAL;
@@ -66,6 +82,8 @@ static vd_status guarded(vd_ctx *ctx, F &&fn) {
         return VD_EHIP;
     }
 }
+}  // namespace vd
+using vd::guarded;
 
 extern "C" {
 
@@ -112,6 +130,10 @@ vd_status vd_poisson_solve(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc
         memset(&p, 0, sizeof(p));
         p.grid = *grid; p.bc = *phi_bc; p.mask = mask; p.beta = beta_cell; p.beta_c = beta_c;
         p.rhs = rho; p.x = phi;
+        if (opts->guess == VD_GUESS_LEARNED) {
+            vd::nn_guess(ctx, grid, phi_bc, rho, beta_c > 0.0 ? beta_c : 8.8541878128e-12, phi);
+            return vd::mg_solve_batch_guess(ctx, 1, &p, opts, info, "poisson:");
+        }
         return vd::mg_solve_batch(ctx, 1, &p, opts, info, "poisson:");
     });
 }
@@ -144,6 +166,49 @@ vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, i
 
 vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour) {
     return guarded(ctx, [&] { return vd::mg_smooth(ctx, prob, ncolour); });
+}
+
+int64_t vd_nn_param_count(const vd_nn_config *cfg) {
+    try { return vd::nn_param_count(cfg); } catch (...) { return -1; }
+}
+
+vd_status vd_nn_create(vd_ctx *ctx, const vd_nn_config *cfg, const float *params) {
+    return guarded(ctx, [&] { return vd::nn_create(ctx, cfg, params); });
+}
+
+vd_status vd_nn_get(vd_ctx *ctx, int32_t which, float *host) {
+    return guarded(ctx, [&] { return vd::nn_params(ctx, which, host, 0); });
+}
+
+vd_status vd_nn_set(vd_ctx *ctx, int32_t which, const float *host) {
+    return guarded(ctx, [&] { return vd::nn_params(ctx, which, const_cast<float *>(host), 1); });
+}
+
+vd_status vd_nn_forward(vd_ctx *ctx, const vd_grid *grid, const uint16_t *in_bf16, float *out) {
+    return guarded(ctx, [&] { return vd::nn_forward(ctx, grid, in_bf16, out); });
+}
+
+vd_status vd_nn_train_step(vd_ctx *ctx, const vd_grid *grid, const uint16_t *in_bf16, const float *target, float lr,
+                           int32_t update, double *loss) {
+    return guarded(ctx, [&] { return vd::nn_train_step(ctx, grid, in_bf16, target, lr, update, loss); });
+}
+
+vd_status vd_nn_features(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const double *rho, double eps,
+                         uint16_t *out_bf16, double *vref) {
+    return guarded(ctx, [&] { return vd::nn_features(ctx, grid, phi_bc, rho, eps, out_bf16, vref); });
+}
+
+vd_status vd_nn_save(vd_ctx *ctx, const char *path) {
+    return guarded(ctx, [&] { return vd::nn_save(ctx, path); });
+}
+
+vd_status vd_nn_load(vd_ctx *ctx, const char *path) {
+    return guarded(ctx, [&] { return vd::nn_load(ctx, path); });
+}
+
+vd_status vd_nn_conv3d(vd_ctx *ctx, const vd_grid *grid, const uint16_t *x_bf16, int32_t ci, const float *w, const float *b,
+                       int32_t co, int32_t relu, float *y, const float *dy, float *dx, float *dw, float *db) {
+    return guarded(ctx, [&] { return vd::nn_conv3d(ctx, grid, x_bf16, ci, w, b, co, relu, y, dy, dx, dw, db); });
 }
 
 vd_status vd_timing_select(vd_ctx *ctx, const char *kernels) {

@@ -424,6 +424,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Plan pl, const int *__restr
         return;
     }
     double rel = sqrt(tot) / s.bnorm;
+    if (mode == 2) {             // report only (residual of an initial guess)
+        s.rel = rel;
+        st[p] = s;
+        return;
+    }
     if (s.outer == 0) s.rel0 = rel;
     s.rel = rel;
     s.outer += 1;
@@ -1816,8 +1821,26 @@ static void autotune(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
 
 // Full solve of a batch (the engine behind vd_poisson_solve,
 // vd_helmholtz_solve_batched and the implicit solves of vd_step).
+static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                               const char *cache_tag, bool check_guess);
+
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
                          const char *cache_tag) {
+    return mg_solve_impl(ctx, nprob, probs, o, infos, cache_tag, false);
+}
+
+// As mg_solve_batch, starting from the guess already in x (a learned
+// prediction): if its relative residual is not below 1 (or not finite) the
+// guess is replaced by zero and infos[p].fallback is set.
+vd_status mg_solve_batch_guess(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                               const char *cache_tag) {
+    vd_mg_opts og = *o;
+    og.guess = VD_GUESS_GIVEN;
+    return mg_solve_impl(ctx, nprob, probs, &og, infos, cache_tag, true);
+}
+
+static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                               const char *cache_tag, bool check_guess) {
     validate(nprob, probs, o);
     std::string key = std::string(cache_tag ? cache_tag : "") + shape_key(nprob, probs, o);
     std::shared_ptr<Solver> S;
@@ -1840,6 +1863,22 @@ vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const 
     timed(ctx, "prep", 0.0, [&] {
         k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO);
     });
+    std::vector<int> fell_back(nprob, 0);
+    if (check_guess) {
+        launch_norm(ctx, *S, 1, 1);
+        launch_finalize(ctx, *S, 2, o, 0);
+        read_active(ctx, *S);
+        bool any = false;
+        for (int p = 0; p < nprob; p++)
+            if (S->pin_st[p].active && !(S->pin_st[p].rel < 1.0)) { fell_back[p] = 1; any = true; }
+        if (any) {
+            // zero every rejected guess (one problem per call on this path)
+            VD_CHECK(nprob == 1, "internal: guess fallback expects one problem");
+            timed(ctx, "prep", 0.0, [&] {
+                k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 1);
+            });
+        }
+    }
     const bool ir = S->prec == VD_FP32_IR;
     const bool async_fixed = o->fixed_cycles > 0 && infos == nullptr;
     const bool use_graph = (o->flags & VD_MG_GRAPH) && !async_fixed && ctx->timing.families.empty();
@@ -1883,6 +1922,7 @@ vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const 
             I.rel_res = q.rel;
             I.rel_res0 = q.rel0;
             I.bnorm = q.bnorm;
+            I.fallback = fell_back[p];
             if (q.status != VD_OK) worst = (vd_status)q.status;
         }
     } else if (!async_fixed) {

@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +30,9 @@ WALL_NONE, WALL_ELECTRON, WALL_ION, WALL_NEUTRAL = 0, 1, 2, 3
 
 EXPORTS = ["vd_ctx_create", "vd_ctx_destroy", "vd_ctx_set_stream", "vd_last_error", "vd_version",
            "vd_poisson_solve", "vd_helmholtz_solve_batched", "vd_species_flux", "vd_reaction_source",
-           "vd_step", "vd_cell_flags", "vd_smooth", "vd_timing_select", "vd_timing_read"]
+           "vd_step", "vd_cell_flags", "vd_smooth", "vd_timing_select", "vd_timing_read",
+           "vd_nn_param_count", "vd_nn_create", "vd_nn_get", "vd_nn_set", "vd_nn_forward", "vd_nn_train_step",
+           "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d"]
 
 
 class VDError(RuntimeError):
@@ -86,6 +90,15 @@ class StepParams(C.Structure):
                 ("eps_cell", C.c_void_p), ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts)]
 
 
+class NNConfig(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("ch", C.c_int32 * 4), ("cin", C.c_int32)]
+
+
+def nn_config(cfg):
+    ch = list(cfg["ch"]) + [0] * (4 - len(cfg["ch"]))
+    return NNConfig(int(cfg["levels"]), (C.c_int32 * 4)(*ch), int(cfg.get("cin", 2)))
+
+
 class State(C.Structure):
     _fields_ = [("n", C.c_void_p), ("phi", C.c_void_p), ("Te", C.c_void_p), ("Ee", C.c_void_p)]
 
@@ -122,6 +135,16 @@ def load():
         "vd_step": ([P, P, P, P], i32),
         "vd_cell_flags": ([P, P, i32, i32, P], i32),
         "vd_smooth": ([P, P, i32], i32),
+        "vd_nn_param_count": ([P], C.c_int64),
+        "vd_nn_create": ([P, P, P], i32),
+        "vd_nn_get": ([P, i32, P], i32),
+        "vd_nn_set": ([P, i32, P], i32),
+        "vd_nn_forward": ([P, P, P, P], i32),
+        "vd_nn_train_step": ([P, P, P, P, C.c_float, i32, C.POINTER(C.c_double)], i32),
+        "vd_nn_features": ([P, P, P, P, d, P, C.POINTER(C.c_double)], i32),
+        "vd_nn_save": ([P, C.c_char_p], i32),
+        "vd_nn_load": ([P, C.c_char_p], i32),
+        "vd_nn_conv3d": ([P, P, P, i32, P, P, i32, i32, P, P, P, P, P], i32),
         "vd_timing_select": ([P, C.c_char_p], i32),
         "vd_timing_read": ([P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
     }
@@ -147,6 +170,14 @@ def _dptr(t, shape=None, dtype=torch.float64, name="tensor"):
         raise ValueError("%s must be contiguous" % name)
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t.data_ptr()
+
+
+def _bf16_ptr(t, numel):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.bfloat16 or not t.is_contiguous():
+        raise ValueError("expected a contiguous bfloat16 tensor on the GPU")
+    if t.numel() < numel:
+        raise ValueError("bfloat16 tensor too small: %d < %d" % (t.numel(), numel))
     return t.data_ptr()
 
 
@@ -236,6 +267,88 @@ class Context:
         st = self.lib.vd_helmholtz_solve_batched(self.h, n, arr, C.byref(opts or mg_opts()), infos)
         self._check(st, (VD_ENOCONV,) if allow_fail else ())
         return [_info(infos[p]) for p in range(n)], st
+
+    # ------------------------------------------------- warm-start network
+    def vd_nn_create(self, cfg, params=None):
+        """cfg: {"levels", "ch", "cin"}; params: numpy FP32 vector or None."""
+        c = nn_config(cfg)
+        n = self.lib.vd_nn_param_count(C.byref(c))
+        if n < 0:
+            raise ValueError("invalid network configuration %r" % (cfg,))
+        buf = None
+        if params is not None:
+            params = np.ascontiguousarray(params, dtype=np.float32)
+            if params.size != n:
+                raise ValueError("expected %d parameters, got %d" % (n, params.size))
+            buf = params.ctypes.data
+        self._check(self.lib.vd_nn_create(self.h, C.byref(c), buf))
+        self._nn_n = int(n)
+        return int(n)
+
+    def vd_nn_get(self, which=0):
+        out = np.empty(self._nn_n, dtype=np.float32)
+        self._check(self.lib.vd_nn_get(self.h, int(which), out.ctypes.data))
+        return out
+
+    def vd_nn_set(self, params, which=0):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        if params.size != self._nn_n:
+            raise ValueError("expected %d values" % self._nn_n)
+        self._check(self.lib.vd_nn_set(self.h, int(which), params.ctypes.data))
+
+    def vd_nn_forward(self, g, x_bf16):
+        nx, ny, nz = g[:3]
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=x_bf16.device)
+        self._check(self.lib.vd_nn_forward(self.h, C.byref(grid(g)), _bf16_ptr(x_bf16, nx * ny * nz),
+                                           _dptr(out, dtype=torch.float32, name="out")))
+        return out
+
+    def vd_nn_train_step(self, g, x_bf16, target, lr, update=True):
+        nx, ny, nz = g[:3]
+        loss = C.c_double(0.0)
+        self._check(self.lib.vd_nn_train_step(self.h, C.byref(grid(g)), _bf16_ptr(x_bf16, nx * ny * nz),
+                                              _dptr(target, (nz, ny, nx), torch.float32, "target"), float(lr),
+                                              int(bool(update)), C.byref(loss)))
+        return loss.value
+
+    def vd_nn_features(self, g, phi_bc, rho, eps=8.8541878128e-12):
+        nx, ny, nz = g[:3]
+        out = torch.empty((nz, ny, nx, 2), dtype=torch.bfloat16, device=rho.device)
+        vref = C.c_double(0.0)
+        self._check(self.lib.vd_nn_features(self.h, C.byref(grid(g)), C.byref(bc(phi_bc)),
+                                            _dptr(rho, (nz, ny, nx), name="rho"), float(eps), out.data_ptr(),
+                                            C.byref(vref)))
+        return out, vref.value
+
+    def vd_nn_save(self, path):
+        self._check(self.lib.vd_nn_save(self.h, str(path).encode()))
+
+    def vd_nn_load(self, path):
+        self._check(self.lib.vd_nn_load(self.h, str(path).encode()))
+        with open(path, "rb") as f:
+            head = f.read(8 + 6 * 4 + 8)
+        self._nn_n = int(np.frombuffer(head[32:40], dtype=np.int64)[0])
+        return self._nn_n
+
+    def vd_nn_conv3d(self, g, x_bf16, w, b, relu=False, dy=None):
+        """One convolution: x [cells][ci] bf16, w [co][27][ci], b [co] FP32.
+        Returns y [cells][co] and, with dy, (dx, dw, db)."""
+        nx, ny, nz = g[:3]
+        n = nx * ny * nz
+        co, ci = int(w.shape[0]), int(w.shape[-1])
+        y = torch.empty((n, co), dtype=torch.float32, device=x_bf16.device)
+        dx = dw = db = None
+        if dy is not None:
+            dx = torch.empty((n, ci), dtype=torch.float32, device=x_bf16.device)
+            dw = torch.empty_like(w)
+            db = torch.empty_like(b)
+        self._check(self.lib.vd_nn_conv3d(
+            self.h, C.byref(grid(g)), _bf16_ptr(x_bf16, n * ci), ci, _dptr(w, dtype=torch.float32, name="w"),
+            _dptr(b, dtype=torch.float32, name="b"), co, int(bool(relu)), y.data_ptr(),
+            None if dy is None else _dptr(dy, (n, co), torch.float32, "dy"),
+            None if dx is None else dx.data_ptr(), None if dw is None else dw.data_ptr(),
+            None if db is None else db.data_ptr()))
+        return y if dy is None else (y, dx, dw, db)
 
     def vd_species_flux(self, g, phi_bc, species_bc, species, n, phi, mu, Te, Tg, consts):
         nx, ny, nz = g[:3]
