@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-steps/s at 160^3×15 species; Poisson time-to-1e-10 plain vs learned+FP32"
 HBM_PEAK_GBS = 8000.0
-FAMILIES = ["gsrb", "resid_restrict", "prolong", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
+FAMILIES = ["gsrb", "resid_restrict", "prolong", "copy", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
             "react", "transport", "rho", "setup"]
 QE = 1.602176634e-19
 
@@ -39,18 +39,48 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=160, help="grid edge (the workload is n^3)")
-    ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
-    ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
+    ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp64")
+    ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp64")
     ap.add_argument("--species-levels", type=int, default=1)
-    ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 0))
+    ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
     ap.add_argument("--ir-inner", type=int, default=2)
     ap.add_argument("--poisson-reps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=112, help="grid edge of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (auto = dominant)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched Helmholtz timing")
+    ap.add_argument("--nn-file", default=os.path.join(ROOT, "paper_2507_08200_amd", "warmstart_arh2_160.bin"),
+                    help="trained warm-start network (trained in the benchmark if absent)")
+    ap.add_argument("--nn-train-seconds", type=float, default=30.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess Poisson timing")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration under rocprofv3)")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
+
+
+def learned_guess(ctx, V, I, cfg, rho, args):
+    """Poisson time-to-1e-10 from the network's guess (inference included),
+    FP64 and FP32-refined, on the benchmark's own streamer state (a voltage
+    and seed position outside the training runs)."""
+    import torch
+    from paper_2507_08200_amd import warmstart as WS
+    n = cfg["grid"][0]
+    if os.path.exists(args.nn_file) and n == 160:
+        ctx.vd_nn_load(args.nn_file)
+        how = "loaded %s" % os.path.basename(args.nn_file)
+    else:
+        t = time.perf_counter()
+        data = WS.snapshots(ctx, I.warmstart_runs(5, 4), n, 20, 10)
+        rep = WS.train(ctx, data, I.NN_CFG, I.nn_init(1), args.nn_train_seconds, 1e-3)
+        how = "trained in the benchmark: %d snapshots, %d Adam steps, %.0f s" % (len(data), rep["steps"],
+                                                                                 time.perf_counter() - t)
+    log("[bench] warm-start network: %s" % how)
+    d = {"grid": cfg["grid"], "bc": cfg["phi_bc"], "rho": rho, "phi": torch.zeros_like(rho)}
+    out = {"learned_fp64": WS.time_to_tol(ctx, d, V.GUESS_LEARNED, V.FP64, reps=args.poisson_reps),
+           "learned_fp32_ir": WS.time_to_tol(ctx, d, V.GUESS_LEARNED, V.FP32_IR, reps=args.poisson_reps)}
+    out["learned_network"] = how
+    return out
 
 
 def batch_bench(ctx, V, I, dev, reps):
@@ -138,6 +168,14 @@ def main():
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
     ctx = V.Context()
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration: 3 copies of %d MiB" % args.calibrate_copy_mib)
 
     # ---- warmup, with every kernel family timed to find the dominant one
     ctx.vd_timing_select(",".join(FAMILIES))
@@ -208,8 +246,9 @@ def main():
         "fp32_ir_zero_guess": poisson_time(V.FP32_IR, V.GUESS_ZERO, zero, args.poisson_reps),
         "plain_fp64_previous_step": poisson_time(V.FP64, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
         "fp32_ir_previous_step": poisson_time(V.FP32_IR, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
-        "learned_fp32_ir": None,
     }
+    if not args.no_learned:
+        poisson.update(learned_guess(ctx, V, I, cfg, rho, args))
     log("[bench] poisson time-to-1e-10: %s" % poisson)
 
     # ---- 64 uneven sheath-jump Helmholtz problems: sequential vs batched

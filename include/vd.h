@@ -54,10 +54,15 @@ enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2 }; /* vd_mg_o
  * captured on the first call for this problem shape and options, instead of
  * being launched kernel by kernel (ignored while kernel timing is on).
  * VD_MG_AUTOTUNE: on the first solve of a problem shape, time each level's
- * smoother colour pass for the candidate tile depths and keep the fastest
- * (the iterate is restored afterwards; the arithmetic of a colour pass does
- * not depend on the tiling, so results are unchanged). */
-enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2 };
+ * smoother for the candidate tile depths and keep the fastest,
+ * and choose between two in-place colour passes and one out-of-place sweep
+ * (both colours in one launch, recomputing the red values of a one-cell
+ * ring around each tile) for each level (the iterate is restored
+ * afterwards; every variant computes the same values).  VD_MG_FUSED_SWEEP:
+ * use the out-of-place sweep on every tiled level without timing.  Tuning
+ * results and the forced choice stay with the context's cached hierarchy of
+ * that problem shape. */
+enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2, VD_MG_FUSED_SWEEP = 4 };
 enum { VD_TE_FIXED = 0, VD_TE_LFA = 1, VD_TE_ENERGY = 2 };          /* electron temperature */
 enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3 };
 /* mobility models (Table A.4 with the Einstein relation):

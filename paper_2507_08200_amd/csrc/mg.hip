@@ -117,12 +117,13 @@ __global__ void __launch_bounds__(kBlock) k_gsrb(const LevDesc *__restrict__ des
 // plan over COARSE descriptors; fine = descs[id - 1]
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__ descs, Plan pl,
-                                                     const ProbState *__restrict__ st) {
+                                                     const ProbState *__restrict__ st, int flip) {
     for_tiles(pl, [&](int d, int lt, int) {
         int id = pl.ids[d];
         const LevDesc C = descs[id];
         if (!gld(&st[C.prob].active, 0)) return;
-        const LevDesc F = descs[id - 1];
+        LevDesc F = descs[id - 1];
+        if (flip) F.x = F.x2;      // the fine iterate is in the alternate buffer
         for (int u = 0; u < kRestrictU; u++) {
             int cc = (lt * kRestrictU + u) * kBlock + threadIdx.x;
             if (cc >= C.ncell) break;
@@ -136,10 +137,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__
 // plan over FINE descriptors; coarse = descs[id + 1]
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const LevDesc *__restrict__ descs, Plan pl,
-                                                    const ProbState *__restrict__ st) {
+                                                    const ProbState *__restrict__ st, int flip) {
     for_tiles(pl, [&](int d, int lt, int) {
         int id = pl.ids[d];
-        const LevDesc F = descs[id];
+        LevDesc F = descs[id];
+        if (flip) F.x = F.x2;
         if (!gld(&st[F.prob].active, 0)) return;
         const LevDesc C = descs[id + 1];
         for (int u = 0; u < kProlongU; u++) {
@@ -159,13 +161,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const LevDesc *__restrict__ 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64, const LevDesc *__restrict__ d32,
                                                  Plan pl, double *__restrict__ partials,
-                                                 const ProbState *__restrict__ st, int check_active) {
+                                                 const ProbState *__restrict__ st, int check_active,
+                                                 double *__restrict__ partials_b) {
     __shared__ double lds[kBlock / 64];
     for_tiles(pl, [&](int d, int lt, int t) {
         int id = pl.ids[d];
         const LevDesc L = d64[id];
         if (check_active && !gld(&st[L.prob].active, 0)) return;
-        double v = 0.0;
+        double v = 0.0, vb = 0.0;
         for (int u = 0; u < kNormU; u++) {
             int c = (lt * kNormU + u) * kBlock + threadIdx.x;
             if (c >= L.ncell) break;
@@ -176,6 +179,10 @@ __global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64
             if (MODE == 0) r = valid ? load_b<double>(L, c, i, j, k) : 0.0;
             else r = residual_at<double>(L, c, i, j, k);
             v += r * r;
+            if (MODE != 0 && partials_b) {
+                const double bv = valid ? load_b<double>(L, c, i, j, k) : 0.0;
+                vb += bv * bv;
+            }
             if (MODE == 2) {
                 const LevDesc &E = d32[id];
                 gst((float *)E.b, c, (float)r);
@@ -184,16 +191,24 @@ __global__ void __launch_bounds__(kBlock) k_norm(const LevDesc *__restrict__ d64
         }
         double s = block_sum(v, lds);
         if (threadIdx.x == 0) gst(partials, t, s);
+        if (MODE != 0 && partials_b) {
+            const double sb = block_sum(vb, lds);
+            if (threadIdx.x == 0) gst(partials_b, t, sb);
+        }
     });
 }
 
 // x = 0 on covered cells, on problems whose right-hand side vanishes, and
-// everywhere for a zero initial guess.
+// everywhere for a zero initial guess.  when = 0: before ||b|| is known
+// (zero guess and covered cells only); 1: after it, on the problems whose
+// ||b|| is 0 only.
 __global__ void __launch_bounds__(kBlock) k_prep(const LevDesc *__restrict__ d64, Plan pl,
-                                                 const ProbState *__restrict__ st, int zero_guess) {
+                                                 const ProbState *__restrict__ st, int zero_guess, int when) {
     for_tiles(pl, [&](int d, int lt, int) {
         const LevDesc &L = d64[pl.ids[d]];
-        const bool all = zero_guess || gld(&st[L.prob].bnorm, 0) == 0.0;
+        const bool b0 = gld(&st[L.prob].bnorm, 0) == 0.0;
+        if (when == 1 && !b0) return;
+        const bool all = when == 1 || zero_guess;
         if (!all && !L.has_mask) return;
         for (int u = 0; u < kNormU; u++) {
             int c = (lt * kNormU + u) * kBlock + threadIdx.x;
@@ -292,7 +307,8 @@ __device__ __forceinline__ int halo_slot(int tid) {
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
                                                  int kz, int colour, double *__restrict__ partials,
-                                                 const ProbState *__restrict__ st, int check_active) {
+                                                 const ProbState *__restrict__ st, int check_active,
+                                                 double *__restrict__ partials_b) {
     __shared__ T xs[2][(kT25Y + 2) * kT25W];
     __shared__ double red[kBlock / 64];
     const int t = xcd_tile(pl.ntiles);
@@ -332,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         bc0 = bv.x;
         bc1 = bv.y;
     }
-    double v = 0.0;
+    double v = 0.0, vb = 0.0;
     for (int k = k0; k < k1; k++) {
         T *buf = xs[k & 1];
         buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
@@ -375,6 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                     const T xv = q == 0 ? xc0 : xc1;
                     const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
                     v += rv * rv;
+                    if (partials_b && valid) vb += (double)b * (double)b;
                     if (MODE == 2) {
                         gst(Eb, c, (float)rv);
                         gst(Ex, c, 0.0f);
@@ -391,7 +408,176 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     if (MODE != 0) {
         const double sum = block_sum(v, red);
         if (tid == 0) gst(partials, t, sum);
+        if (partials_b) {
+            const double sb = block_sum(vb, red);
+            if (tid == 0) gst(partials_b, t, sb);
+        }
     }
+}
+
+// ------------------------------------------- fused red-black sweep (2.5D)
+// One launch = one full Gauss-Seidel sweep (all red cells, then all black
+// cells), out of place: the old iterate is read from one buffer and the new
+// one written to the other, so no workgroup ever reads a value another
+// workgroup has already overwritten.  A workgroup owns a 32 x 16 tile and
+// marches its kz planes in z.  Red is computed on the tile plus a one-cell
+// ring (the ring's red values are also computed by the neighbouring tiles;
+// they are identical), from the old iterate held in LDS with a two-cell
+// ring; black is computed on the tile from the new red values in LDS.  The
+// red plane runs one plane ahead of the black plane.  Each cell's update is
+// the same expression as in the colour passes, so the result equals a red
+// pass followed by a black pass.
+constexpr int kSwOX = kT25X + 4, kSwOY = kT25Y + 4;   // old iterate, 2-cell ring
+constexpr int kSwRX = kT25X + 2, kSwRY = kT25Y + 2;   // new red values, 1-cell ring
+
+// wrapped coordinate of position p along a direction of n cells; false if
+// the position is not a cell (outside a non-periodic face, or further out
+// than the two-cell ring)
+__device__ __forceinline__ bool wrap_pos(int p, int n, bool periodic, int &w) {
+    if (p >= 0 && p < n) { w = p; return true; }
+    if (!periodic || p < -2 || p >= n + 2) return false;
+    w = p < 0 ? p + n : p - n;
+    return w >= 0 && w < n;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep25(const LevDesc *__restrict__ descs, Plan pl, int kz, int flip,
+                                                    const ProbState *__restrict__ st) {
+    __shared__ T xo[4][kSwOY * kSwOX];
+    __shared__ T xr[3][kSwRY * kSwRX];
+    const int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    const int d = plan_find(pl, t);
+    const LevDesc L = descs[pl.ids[d]];
+    if (!gld(&st[L.prob].active, 0)) return;
+    int lt = t - pl.prefix[d];
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int ntx = (nx + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
+    const int tx = lt % ntx;
+    lt /= ntx;
+    const int ty = lt % nty;
+    const int zc = lt / nty;
+    const int i0 = tx * kT25X, j0 = ty * kT25Y, k0 = zc * kz;
+    const int k1 = min(k0 + kz, nz);
+    const int tid = threadIdx.x;
+    const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
+    const T *__restrict__ X = (const T *)(flip ? L.x2 : L.x);
+    T *__restrict__ Y = (T *)(flip ? L.x : L.x2);
+    const T *__restrict__ B = (const T *)L.b;
+    const long nxy = L.nxy;
+
+    // old plane q (ring 2) into its slot; non-cells read as 0
+    auto load_old = [&](int q) {
+        T *s = xo[(q + 4) & 3];
+        int wk;
+        const bool zok = wrap_pos(q, nz, pz, wk);
+        for (int e = tid; e < kSwOY * kSwOX; e += kBlock) {
+            const int ri = e % kSwOX, rj = e / kSwOX;
+            int wi, wj;
+            T v = (T)0;
+            if (zok && wrap_pos(i0 - 2 + ri, nx, px, wi) && wrap_pos(j0 - 2 + rj, ny, py, wj))
+                v = gld(X, wi + (long)nx * wj + nxy * wk);
+            lst(s, e, v);
+        }
+    };
+
+    // new red values of plane p on the tile and its ring; the tile's own
+    // cells (of planes k0..k1-1) are stored to Y
+    auto red_plane = [&](int p) {
+        T *rs = xr[(p + 3) % 3];
+        const T *om = xo[(p + 3) & 3], *oc = xo[(p + 4) & 3], *op = xo[(p + 5) & 3];
+        int wk;
+        const bool zok = wrap_pos(p, nz, pz, wk);
+        const bool own_plane = p >= k0 && p < k1;
+        for (int m = tid; m < kSwRY * (kSwRX / 2); m += kBlock) {
+            const int rj = m / (kSwRX / 2), h = m - rj * (kSwRX / 2);
+            const int gj = j0 - 1 + rj;
+            const int ri = 2 * h + ((i0 - 1 + gj + p) & 1);    // red: (i + j + k) even
+            const int gi = i0 - 1 + ri;
+            int wi, wj;
+            T val = (T)0;
+            if (zok && wrap_pos(gi, nx, px, wi) && wrap_pos(gj, ny, py, wj)) {
+                const int c = wi + nx * wj + (int)nxy * wk;
+                const int o = (rj + 1) * kSwOX + ri + 1;
+                if (L.has_mask && !gld(L.mask, c)) {
+                    val = lld(oc, o);
+                } else {
+                    T nbv[6];
+                    nbv[0] = lld(oc, o - 1);
+                    nbv[1] = lld(oc, o + 1);
+                    nbv[2] = lld(oc, o - kSwOX);
+                    nbv[3] = lld(oc, o + kSwOX);
+                    nbv[4] = lld(om, o);
+                    nbv[5] = lld(op, o);
+                    T dg, of;
+                    row_terms_nb<T>(L, wi, wj, wk, c, nbv, dg, of);
+                    T bv = gld(B, c);
+                    if (L.lift) bv = (T)((double)bv + lift_term(L, wi, wj, wk));
+                    val = (bv + of) / dg;
+                }
+                if (own_plane && ri >= 1 && ri <= kT25X && rj >= 1 && rj <= kT25Y && gi < nx && gj < ny) gst(Y, c, val);
+            }
+            lst(rs, rj * kSwRX + ri, val);
+        }
+    };
+
+    // new black values of plane p on the tile (one per thread)
+    auto black_plane = [&](int p) {
+        const T *rm = xr[(p + 2) % 3], *rc = xr[(p + 3) % 3], *rp = xr[(p + 4) % 3];
+        const T *oc = xo[(p + 4) & 3];
+        const int r = tid >> 4, h = tid & 15;
+        const int gj = j0 + r;
+        const int gi = i0 + 2 * h + (((i0 + gj + p) & 1) ^ 1);   // black: (i + j + k) odd
+        if (gi >= nx || gj >= ny) return;
+        const int c = gi + nx * gj + (int)nxy * p;
+        const int ri = gi - i0 + 1, rj = r + 1;
+        T val;
+        if (L.has_mask && !gld(L.mask, c)) {
+            val = lld(oc, (rj + 1) * kSwOX + ri + 1);
+        } else {
+            const int o = rj * kSwRX + ri;
+            T nbv[6];
+            nbv[0] = lld(rc, o - 1);
+            nbv[1] = lld(rc, o + 1);
+            nbv[2] = lld(rc, o - kSwRX);
+            nbv[3] = lld(rc, o + kSwRX);
+            nbv[4] = lld(rm, o);
+            nbv[5] = lld(rp, o);
+            T dg, of;
+            row_terms_nb<T>(L, gi, gj, p, c, nbv, dg, of);
+            T bv = gld(B, c);
+            if (L.lift) bv = (T)((double)bv + lift_term(L, gi, gj, p));
+            val = (bv + of) / dg;
+        }
+        gst(Y, c, val);
+    };
+
+    load_old(k0 - 2);
+    load_old(k0 - 1);
+    load_old(k0);
+    __syncthreads();
+    for (int p = k0 - 1; p <= k1; p++) {
+        red_plane(p);
+        if (p + 2 <= k1 + 1) load_old(p + 2);   // slot of plane p - 2, no longer read
+        __syncthreads();
+        if (p - 1 >= k0) black_plane(p - 1);
+        __syncthreads();
+    }
+}
+
+// x <- x2 on every level of the plan (after an odd number of fused sweeps)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy_x2(const LevDesc *__restrict__ descs, Plan pl,
+                                                    const ProbState *__restrict__ st) {
+    for_tiles(pl, [&](int d, int lt, int) {
+        const LevDesc L = descs[pl.ids[d]];
+        if (!gld(&st[L.prob].active, 0)) return;
+        for (int u = 0; u < 2 * kGsrbU; u++) {
+            const int c = (lt * 2 * kGsrbU + u) * kBlock + threadIdx.x;
+            if (c >= L.ncell) break;
+            gst((T *)L.x, c, gld((const T *)L.x2, c));
+        }
+    });
 }
 
 __global__ void k_state_init(ProbState *st, int n) {
@@ -407,16 +593,25 @@ __global__ void k_state_init(ProbState *st, int n) {
 // stopping decision.  mode 0: ||b||; mode 1: residual check before a cycle.
 __global__ void __launch_bounds__(kBlock) k_finalize(Plan pl, const int *__restrict__ prob_of, const double *__restrict__ partials,
                                                      ProbState *__restrict__ st, int mode, double rtol, int max_cycles,
-                                                     int fixed, int inner) {
+                                                     int fixed, int inner, const double *__restrict__ partials_b) {
     __shared__ double lds[kBlock / 64];
     int d = blockIdx.x;
     int p = prob_of[d];
     ProbState s = st[p];
-    if (mode == 1 && !s.active) return;
-    double v = 0.0;
-    for (int q = pl.prefix[d] + threadIdx.x; q < pl.prefix[d + 1]; q += blockDim.x) v += gld(partials, q);
+    if ((mode == 1 || mode == 3) && !s.active) return;
+    double v = 0.0, vb = 0.0;
+    for (int q = pl.prefix[d] + threadIdx.x; q < pl.prefix[d + 1]; q += blockDim.x) {
+        v += gld(partials, q);
+        if (mode == 3) vb += gld(partials_b, q);
+    }
     double tot = block_sum(v, lds);
+    double totb = mode == 3 ? block_sum(vb, lds) : 0.0;
     if (threadIdx.x != 0) return;
+    if (mode == 3) {             // first check: ||b|| from the same pass
+        s.bnorm = sqrt(totb);
+        if (s.bnorm == 0.0) { s.active = 0; s.rel = 0.0; st[p] = s; return; }
+        mode = 1;
+    }
     if (mode == 0) {
         s.bnorm = sqrt(tot);
         if (s.bnorm == 0.0) { s.active = 0; s.rel = 0.0; }
@@ -1132,6 +1327,8 @@ struct HLevel {
     DevBuf<uint8_t> mask;
     DevBuf<double> st64;     // assembled rows (LDS-resident levels; FP64 bottom of FP32 hierarchies)
     DevBuf<float> st32;
+    DevBuf<double> x2;       // alternate iterate of the fused sweeps (levels smoothed by k_sweep25)
+    DevBuf<float> x2_32;
 };
 
 struct HProblem {
@@ -1159,7 +1356,7 @@ struct Solver {
     LevDesc *pin64 = nullptr, *pin32 = nullptr;   // pinned staging of the descriptors
     DevBuf<ProbState> st;
     ProbState *pin_st = nullptr;
-    DevBuf<double> partials;
+    DevBuf<double> partials, partials_b;
     DevBuf<FusedDesc> fused;
     int nfused = 0;
     size_t pcg_lds_bytes = 0;     // dynamic LDS of the fused kernel (0: CG vectors in global memory)
@@ -1175,6 +1372,7 @@ struct Solver {
     hipGraphExec_t gexec = nullptr;              // one captured cycle (VD_MG_GRAPH)
     std::string gkey;                            // options the graph was captured with
     bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
+    std::vector<int> use_fused;                  // per level: fused out-of-place sweeps instead of colour passes
     bool aligned = true;                         // finest-level unknowns 16-byte aligned (row-pair loads)
     ~Solver() {
         if (pin64) (void)hipHostFree(pin64);
@@ -1326,6 +1524,7 @@ static LevDesc make_desc(const HProblem &H, const vd_problem &P, int l, int prob
     else if (l == 0) { D.x = P.x; D.b = P.rhs; }
     else { D.x = V.x.p; D.b = V.b.p; }
     D.sten = fp32 ? (void *)V.st32.p : (void *)V.st64.p;
+    D.x2 = fp32 ? (void *)V.x2_32.p : (void *)V.x2.p;
     return D;
 }
 
@@ -1481,6 +1680,7 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         build25(S->all0_25, items);
     }
     S->pre25.resize(Lmax);
+    S->use_fused.assign(Lmax, 0);
     for (int l = 0; l < Lmax; l++) {
         std::vector<std::pair<int, const HLevel *>> items;
         for (int id : S->pre[l].h_ids) items.push_back({id, &S->probs[id / Lmax].lv[id % Lmax]});
@@ -1493,6 +1693,7 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         upload_plan(S->prolong[l], ctx->stream);
     }
     S->partials.alloc(std::max(1, std::max(S->all0.ntiles, S->all0_25.ntiles)));
+    S->partials_b.alloc(std::max(1, std::max(S->all0.ntiles, S->all0_25.ntiles)));
     S->nfused = (int)fds.size();
     S->pcg_lds_bytes = (max_bottom > 0 && max_bottom <= kPcgLdsCells) ? (size_t)6 * max_bottom * sizeof(double) : 0;
     if (S->nfused) {
@@ -1580,7 +1781,9 @@ static void setup_coefficients(vd_ctx *ctx, Solver &S, const vd_problem *probs) 
 // their b read and x written, the other colour's x read; every face
 // coefficient touches one updated cell); 1: residual + restriction into the
 // coarse level; 2: prolongation + correction; 3: norm of b; 4: residual
-// norm; 5: residual norm + FP32 copy.
+// norm; 5: residual norm + FP32 copy; 6: one fused out-of-place sweep (x
+// and b read, the alternate iterate written, every coefficient read once);
+// 7: copy of the alternate iterate back.
 static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) {
     double total = 0.0;
     const double sT = fp32 ? 4.0 : 8.0;
@@ -1595,6 +1798,8 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) 
                   total += 2.0 * NF * sT + 2.0 * N * sT + (F.var_beta ? 3.0 * NF * sT : 0.0) + (F.var_alpha ? NF * sT : 0.0) + (F.has_mask ? NF : 0.0);
                   break; }
         case 2: total += 2.0 * N * sT + N / 8.0 * sT; break;
+        case 6: total += 3.0 * N * sT + coef; break;          // full out-of-place sweep: x, b read, x2 written
+        case 7: total += 2.0 * N * sT; break;                 // copy
         case 3: total += N * 8.0; break;
         case 4: total += 2.0 * N * 8.0 + coef * 2.0; break;
         default: total += 2.0 * N * 8.0 + coef * 2.0 + 2.0 * N * 4.0; break;
@@ -1611,26 +1816,47 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
     hipStream_t s = ctx->stream;
     timed(ctx, "gsrb", plan_bytes(S, pp, sizeof(T) == 4, 0), [&] {
         if (p25.nd && S.aligned)
-            k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1);
+            k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1, nullptr);
         else
             k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
     });
+}
+
+// one full fused sweep of level l (every problem of the plan), reading the
+// iterate from x (flip 0) or x2 (flip 1) and writing the other
+template <typename T>
+static void sweep_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int flip) {
+    const HPlan &p25 = S.pre25[l];
+    timed(ctx, "gsrb", plan_bytes(S, S.pre[l], sizeof(T) == 4, 6), [&] {
+        k_sweep25<T><<<xcd_grid(p25.ntiles), kBlock, 0, ctx->stream>>>(dT, p25.dev(), p25.kz, flip, S.st.p);
+    });
+}
+
+// nu smoothing sweeps of level l; par tracks which buffer holds the iterate
+template <typename T>
+static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int nu, int &par) {
+    if (S.pre25[l].nd && S.use_fused[l]) {
+        for (int q = 0; q < nu; q++) {
+            sweep_pass<T>(ctx, S, l, dT, par);
+            par ^= 1;
+        }
+    } else {
+        for (int q = 0; q < nu; q++)
+            for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
+    }
 }
 
 template <typename T>
 static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o) {
     hipStream_t s = ctx->stream;
     const ProbState *st = S.st.p;
+    std::vector<int> par(S.Lmax, 0);
     for (int l = 0; l < S.Lmax; l++) {
-        const HPlan &pp = S.pre[l];
-        if (pp.nd) {
-            for (int q = 0; q < o->nu_pre; q++)
-                for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
-        }
+        if (S.pre[l].nd) smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l]);
         const HPlan &pr = S.restr[l];
         if (pr.nd)
             timed(ctx, "resid_restrict", plan_bytes(S, pr, sizeof(T) == 4, 1), [&] {
-                k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st);
+                k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st, par[l]);
             });
     }
     if (S.nfused && S.lds_mode)
@@ -1646,12 +1872,18 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
         const HPlan &pp = S.prolong[l];
         if (pp.nd)
             timed(ctx, "prolong", plan_bytes(S, pp, sizeof(T) == 4, 2), [&] {
-                k_prolong<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), st);
+                k_prolong<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), st, par[l]);
             });
         const HPlan &ps = S.pre[l];
         if (ps.nd) {
-            for (int q = 0; q < o->nu_post; q++)
-                for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
+            smooth_level<T>(ctx, S, l, dT, o->nu_post, par[l]);
+            if (par[l]) {
+                // an odd number of sweeps: the iterate goes back to x
+                timed(ctx, "copy", plan_bytes(S, ps, sizeof(T) == 4, 7), [&] {
+                    k_copy_x2<T><<<xcd_grid(ps.ntiles), kBlock, 0, s>>>(dT, ps.dev(), st);
+                });
+                par[l] = 0;
+            }
         }
     }
 }
@@ -1660,7 +1892,8 @@ static const HPlan &norm_plan(const Solver &S, int mode) {
     return (mode != 0 && S.all0_25.nd && S.aligned) ? S.all0_25 : S.all0;
 }
 
-static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
+static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool with_b = false) {
+    double *pb = with_b ? S.partials_b.p : nullptr;
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
     if (mode != 0 && S.all0_25.nd && S.aligned) {
@@ -1668,20 +1901,21 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active) {
         timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
             if (mode == 1)
                 k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
-                                                                          S.partials.p, S.st.p, check_active);
+                                                                          S.partials.p, S.st.p, check_active, pb);
             else
                 k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
-                                                                          S.partials.p, S.st.p, check_active);
+                                                                          S.partials.p, S.st.p, check_active, pb);
         });
         return;
     }
     timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
         if (mode == 0)
-            k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+            k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active,
+                                                             nullptr);
         else if (mode == 1)
-            k_norm<1><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+            k_norm<1><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active, pb);
         else
-            k_norm<2><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active);
+            k_norm<2><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active, pb);
     });
 }
 
@@ -1689,7 +1923,7 @@ static void launch_finalize(vd_ctx *ctx, Solver &S, int mode, const vd_mg_opts *
     const HPlan &pl = norm_plan(S, mode);
     timed(ctx, "finalize", 0.0, [&] {
         k_finalize<<<S.nprob, kBlock, 0, ctx->stream>>>(pl.dev(), S.prob_of.p, S.partials.p, S.st.p, mode, o->rtol,
-                                                        o->max_cycles, o->fixed_cycles, inner);
+                                                        o->max_cycles, o->fixed_cycles, inner, S.partials_b.p);
     });
 }
 
@@ -1729,7 +1963,7 @@ static hipGraphExec_t cycle_graph(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
     snprintf(kb, sizeof(kb), "%d,%d,%d,%d,%.17g,%d,%d,%d", o->nu_pre, o->nu_post, o->ir_inner, o->max_cycles, o->rtol,
              o->fixed_cycles, (int)S.aligned, (int)S.tuned);
     std::string gk = kb;
-    for (int l = 0; l < S.Lmax; l++) gk += "," + std::to_string(S.pre25[l].kz);
+    for (int l = 0; l < S.Lmax; l++) gk += "," + std::to_string(S.pre25[l].kz) + (S.use_fused[l] ? "f" : "c");
     if (S.gexec && S.gkey == gk) return S.gexec;
     if (S.gexec) { (void)hipGraphExecDestroy(S.gexec); S.gexec = nullptr; }
     if (!ctx->cap_stream) VD_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -1756,12 +1990,26 @@ static hipGraphExec_t cycle_graph(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
     return S.gexec;
 }
 
-// Tile-depth autotuning of the 2.5D smoother: for each level, time both
-// colour passes for kz in {2, 4, 8, 16} and keep the fastest.  Every
-// level's unknowns are saved first and restored after, so the solve that
-// follows starts from the caller's iterate.
-template <typename T>
-static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vector<LevDesc> &hT) {
+// alternate iterates of level l (fused out-of-place sweeps), in the
+// precision of the hierarchy that is smoothed; the descriptors are rebuilt
+// by the next refresh
+static void alloc_x2(Solver &S, int l) {
+    for (int id : S.pre[l].h_ids) {
+        HLevel &Vl = S.probs[id / S.Lmax].lv[id % S.Lmax];
+        const size_t n = (size_t)Vl.nx * Vl.ny * Vl.nz;
+        if (S.prec == VD_FP32_IR) Vl.x2_32.alloc(n);
+        else Vl.x2.alloc(n);
+    }
+    S.key.clear();
+}
+
+// Smoother autotuning: for each level with a tiled plan, time one sweep
+// as two in-place colour passes and as one fused out-of-place sweep, each
+// for kz in {2, 4, 8, 16}, and keep the fastest (all variants compute the
+// same values).  Every level's unknowns are saved first and restored after,
+// so the solve that follows starts from the caller's iterate.
+template <typename T, typename R>
+static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vector<LevDesc> &hT, R &&refresh) {
     hipStream_t s = ctx->stream;
     std::vector<std::pair<void *, size_t>> xs;
     size_t total = 0;
@@ -1779,26 +2027,48 @@ static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vec
         std::vector<std::pair<int, const HLevel *>> items;
         for (int id : S.pre[l].h_ids) items.push_back({id, &S.probs[id / S.Lmax].lv[id % S.Lmax]});
         float best = 1e30f;
-        int best_kz = S.pre25[l].kz;
-        for (int kz : {2, 4, 8, 16}) {
-            HPlan cand;
-            build_plan25(ctx, cand, items, kz);
-            auto pass = [&] {
-                for (int col = 0; col < 2; col++)
-                    k_st25<T, 0><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz, col, nullptr, S.st.p, 1);
-            };
-            pass();   // warm
-            VD_HIP(hipEventRecord(e0, s));
-            for (int r = 0; r < 3; r++) pass();
-            VD_HIP(hipEventRecord(e1, s));
-            VD_HIP(hipGetLastError());
-            VD_HIP(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            VD_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best * 0.97f) { best = ms; best_kz = kz; }
-        }
+        int best_kz = S.pre25[l].kz, best_fused = 0;
+        for (int fused = 0; fused < 2; fused++)
+            for (int kz : {2, 4, 8, 16}) {
+                if (fused && kz == 2) {
+                    // the fused sweep writes the alternate iterate: allocate
+                    // it and point this level's descriptors at it
+                    alloc_x2(S, l);
+                    refresh(ctx);
+                }
+                HPlan cand;
+                build_plan25(ctx, cand, items, kz);
+                auto pass = [&] {
+                    if (fused)
+                        k_sweep25<T><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, cand.dev(), cand.kz, 0, S.st.p);
+                    else
+                        for (int col = 0; col < 2; col++)
+                            k_st25<T, 0><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz, col,
+                                                                                   nullptr, S.st.p, 1, nullptr);
+                };
+                pass();   // warm
+                VD_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; r++) pass();
+                VD_HIP(hipEventRecord(e1, s));
+                VD_HIP(hipGetLastError());
+                VD_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                VD_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best * 0.97f) { best = ms; best_kz = kz; best_fused = fused; }
+            }
         if (best_kz != S.pre25[l].kz) build_plan25(ctx, S.pre25[l], items, best_kz);
+        S.use_fused[l] = best_fused;
+        if (!best_fused) {
+            VD_HIP(hipStreamSynchronize(s));
+            for (int id : S.pre[l].h_ids) {
+                HLevel &Vl = S.probs[id / S.Lmax].lv[id % S.Lmax];
+                Vl.x2.release();
+                Vl.x2_32.release();
+            }
+            S.key.clear();
+        }
     }
+    refresh(ctx);
     off = 0;
     for (auto &x : xs) { VD_HIP(hipMemcpyAsync(x.first, save.p + off, x.second, hipMemcpyDeviceToDevice, s)); off += x.second; }
     VD_HIP(hipStreamSynchronize(s));
@@ -1806,15 +2076,15 @@ static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vec
     (void)hipEventDestroy(e1);
 }
 
-static void autotune(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
-    (void)o;
+static void autotune(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
+    auto refresh = [&](vd_ctx *c) { refresh_descs(c, S, nprob, probs, o); };
     // the smoother kernels skip problems whose flag is clear; the state is
     // re-initialised by the solve that follows
     k_state_init<<<ceil_div(S.nprob, 64), 64, 0, ctx->stream>>>(S.st.p, S.nprob);
     VD_HIP(hipGetLastError());
     if (S.aligned) {
-        if (S.prec == VD_FP32_IR) autotune_t<float>(ctx, S, S.d32.p, S.h32);
-        else autotune_t<double>(ctx, S, S.d64.p, S.h64);
+        if (S.prec == VD_FP32_IR) autotune_t<float>(ctx, S, S.d32.p, S.h32, refresh);
+        else autotune_t<double>(ctx, S, S.d64.p, S.h64, refresh);
     }
     S.tuned = true;
 }
@@ -1854,15 +2124,30 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     setup_coefficients(ctx, *S, probs);
     // tuning runs smoother passes on the caller's iterate (restored after),
     // before the convergence state of this solve is initialised
-    if ((o->flags & VD_MG_AUTOTUNE) && !S->tuned) autotune(ctx, *S, o);
+    if ((o->flags & VD_MG_AUTOTUNE) && !S->tuned) autotune(ctx, *S, nprob, probs, o);
+    if ((o->flags & VD_MG_FUSED_SWEEP) && !S->tuned) {
+        bool any = false;
+        for (int l = 0; l < S->Lmax; l++)
+            if (S->pre25[l].nd && !S->use_fused[l]) { alloc_x2(*S, l); S->use_fused[l] = 1; any = true; }
+        if (any) refresh_descs(ctx, *S, nprob, probs, o);
+    }
     hipStream_t s = ctx->stream;
     k_state_init<<<ceil_div(nprob, 64), 64, 0, s>>>(S->st.p, nprob);
     VD_HIP(hipGetLastError());
-    launch_norm(ctx, *S, 0, 0);
-    launch_finalize(ctx, *S, 0, o, 0);
+    // ||b|| comes from the first residual pass, except on the guess-checking
+    // path, which needs it before that pass
+    const bool fuse_b = !check_guess;
+    if (!fuse_b) {
+        launch_norm(ctx, *S, 0, 0);
+        launch_finalize(ctx, *S, 0, o, 0);
+    }
     timed(ctx, "prep", 0.0, [&] {
-        k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO);
+        k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO, 0);
     });
+    if (!fuse_b)
+        timed(ctx, "prep", 0.0, [&] {
+            k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 0, 1);
+        });
     std::vector<int> fell_back(nprob, 0);
     if (check_guess) {
         launch_norm(ctx, *S, 1, 1);
@@ -1875,7 +2160,7 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
             // zero every rejected guess (one problem per call on this path)
             VD_CHECK(nprob == 1, "internal: guess fallback expects one problem");
             timed(ctx, "prep", 0.0, [&] {
-                k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 1);
+                k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 1, 0);
             });
         }
     }
@@ -1885,18 +2170,27 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     hipGraphExec_t gexec = use_graph ? cycle_graph(ctx, *S, o) : nullptr;
     int iters = 0;
     const int chunk = async_fixed ? (o->fixed_cycles + 1) : 2;
+    // the first check of a fused solve also finalises ||b||, then clears x
+    // of the problems whose right-hand side vanishes
+    auto check = [&](int nmode, int inner) {
+        const bool first = fuse_b && iters == 0;
+        launch_norm(ctx, *S, nmode, 1, first);
+        launch_finalize(ctx, *S, first ? 3 : 1, o, inner);
+        if (first)
+            timed(ctx, "prep", 0.0, [&] {
+                k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 0, 1);
+            });
+    };
     while (true) {
         for (int c = 0; c < chunk; c++) {
-            if (gexec) {
+            if (gexec && !(fuse_b && iters == 0)) {
                 VD_HIP(hipGraphLaunch(gexec, s));
             } else if (!ir) {
-                launch_norm(ctx, *S, 1, 1);
-                launch_finalize(ctx, *S, 1, o, 1);
+                check(1, 1);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
                 vcycle<double>(ctx, *S, S->d64.p, o);
             } else {
-                launch_norm(ctx, *S, 2, 1);
-                launch_finalize(ctx, *S, 1, o, o->ir_inner);
+                check(2, o->ir_inner);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
                 for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, *S, S->d32.p, o);
                 timed(ctx, "ir_update", plan_bytes(*S, S->all0, false, 3) * 2.5, [&] {

@@ -82,6 +82,7 @@ struct LevDesc {
     void *x;                     // unknown (double or float by hierarchy)
     const void *b;               // right-hand side
     void *sten;                  // assembled rows of an LDS-resident level (diagonal + 6 weight planes), else null
+    void *x2;                    // alternate iterate of the out-of-place fused sweeps, else null
 };
 
 // Per-problem convergence state, device resident.

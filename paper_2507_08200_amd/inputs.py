@@ -265,3 +265,17 @@ def nn_init(seed: int, cfg: dict = NN_CFG) -> np.ndarray:
         out.append(g.standard_normal(co * 27 * ci) * np.sqrt(2.0 / (27 * ci)))
         out.append(np.zeros(co))
     return np.concatenate(out).astype(np.float32)
+
+
+def warmstart_runs(seed: int, count: int, L: float = 0.0125) -> list:
+    """Seeded variations of the streamer state for the warm-start data:
+    electrode voltage U[5, 20] kV, seed centre x in U[0.5, 2] mm and y, z
+    within 2 mm of the axis, and a noise seed per run."""
+    g = rng(seed)
+    out = []
+    for r in range(count):
+        V = float(g.uniform(5e3, 20e3))
+        c = (float(g.uniform(0.5e-3, 2.0e-3)), float(L / 2 + g.uniform(-2e-3, 2e-3)),
+             float(L / 2 + g.uniform(-2e-3, 2e-3)))
+        out.append({"voltage": V, "centre": c, "seed": int(g.integers(1, 2 ** 31 - 1))})
+    return out

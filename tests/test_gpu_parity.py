@@ -348,9 +348,10 @@ def test_batch_equals_alone(ctx, V):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_graph_replay_and_autotune(ctx, V, oracle, precision):
-    """Graph replay and tile autotuning reproduce the kernel-by-kernel
-    solve: same cycle counts, the same iterate to 1e-13; and the result is
-    pinned against the oracle like every other solve (FP64)."""
+    """Graph replay, smoother autotuning and the fused out-of-place sweep
+    reproduce the kernel-by-kernel solve: same cycle counts, the same
+    iterate to 1e-13; and the result is pinned against the oracle like every
+    other solve (FP64)."""
     prec = V.FP64 if precision == "fp64" else V.FP32_IR
     shapes = [(32, 32, 32), (48, 40, 32), (24, 24, 24)]
     probs = [I.random_helmholtz(700 + p, s, beta_jump=True) for p, s in enumerate(shapes)]
@@ -358,7 +359,8 @@ def test_graph_replay_and_autotune(ctx, V, oracle, precision):
     say("graph/autotune", precision)
     i_ref, st = ctx.vd_helmholtz_solve_batched(ref, V.mg_opts(rtol=1e-10, precision=prec))
     assert st == 0
-    for opts in (dict(graph=True), dict(autotune=True), dict(graph=True, autotune=True)):
+    for opts in (dict(graph=True), dict(autotune=True), dict(graph=True, autotune=True), dict(fused_sweep=True),
+                 dict(fused_sweep=True, graph=True)):
         ctx2 = V.Context()
         for rep in range(3):   # capture, then replays (with eager work in between)
             gs = [gpu_problem(p) for p in probs]
