@@ -241,13 +241,13 @@ def main():
                 "rel_res": info["rel_res"]}
 
     zero = torch.zeros_like(phi_prev)
-    poisson = {
+    poisson = None if args.poisson_reps <= 0 else {
         "plain_fp64_zero_guess": poisson_time(V.FP64, V.GUESS_ZERO, zero, args.poisson_reps),
         "fp32_ir_zero_guess": poisson_time(V.FP32_IR, V.GUESS_ZERO, zero, args.poisson_reps),
         "plain_fp64_previous_step": poisson_time(V.FP64, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
         "fp32_ir_previous_step": poisson_time(V.FP32_IR, V.GUESS_GIVEN, phi_prev, args.poisson_reps),
     }
-    if not args.no_learned:
+    if poisson is not None and not args.no_learned:
         poisson.update(learned_guess(ctx, V, I, cfg, rho, args))
     log("[bench] poisson time-to-1e-10: %s" % poisson)
 

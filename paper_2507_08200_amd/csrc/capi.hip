@@ -36,6 +36,12 @@ void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1,
     if (T.pending.size() >= 8192) timing_flush(ctx);
 }
 
+void timing_add_units(vd_ctx *ctx, const char *family, double units) {
+    Timing &T = ctx->timing;
+    for (auto &f : T.families)
+        if (f == family) { T.acc[family].units += units; return; }
+}
+
 void timing_flush(vd_ctx *ctx) {
     Timing &T = ctx->timing;
     for (auto &pr : T.pending) {

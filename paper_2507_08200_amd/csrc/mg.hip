@@ -367,6 +367,10 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         }
         __syncthreads();
         if (own) {
+            // colour pass: the pair is stored whole (the other cell with its
+            // unchanged value, which no other thread writes in this pass), so
+            // every cache line is written in full
+            T out0 = xc0, out1 = xc1;
 #pragma unroll
             for (int q = 0; q < 2; q++) {
                 const int i = ia + q;
@@ -386,7 +390,8 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 T b = q == 0 ? bc0 : bc1;
                 if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
                 if (MODE == 0) {
-                    gst(X, c, (b + of) / dg);
+                    if (q == 0) out0 = (b + of) / dg;
+                    else out1 = (b + of) / dg;
                 } else {
                     const T xv = q == 0 ? xc0 : xc1;
                     const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
@@ -397,6 +402,12 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                         gst(Ex, c, 0.0f);
                     }
                 }
+            }
+            if (MODE == 0) {
+                typename Pair<T>::V pv;
+                pv.x = out0;
+                pv.y = out1;
+                *(VD_GAS typename Pair<T>::V *)(X + ia + rowoff + (long)L.nxy * k) = pv;
             }
         }
         xm0 = xc0; xm1 = xc1;
@@ -1373,6 +1384,11 @@ struct Solver {
     std::string gkey;                            // options the graph was captured with
     bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
     std::vector<int> use_fused;                  // per level: fused out-of-place sweeps instead of colour passes
+    // timed launches of the current solve, credited with the algorithmic
+    // bytes of the problems still active at that point once the solve ends
+    struct LaunchRec { const char *family; const HPlan *plan; bool fp32; int kind; double factor; int it, phase; };
+    std::vector<LaunchRec> recs;
+    int cur_it = 0, cur_phase = 2;     // phase 0: residual check of iteration it, 1: its cycle(s), 2: set-up
     bool aligned = true;                         // finest-level unknowns 16-byte aligned (row-pair loads)
     ~Solver() {
         if (pin64) (void)hipHostFree(pin64);
@@ -1784,10 +1800,11 @@ static void setup_coefficients(vd_ctx *ctx, Solver &S, const vd_problem *probs) 
 // norm; 5: residual norm + FP32 copy; 6: one fused out-of-place sweep (x
 // and b read, the alternate iterate written, every coefficient read once);
 // 7: copy of the alternate iterate back.
-static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) {
+static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind, const std::vector<char> *active = nullptr) {
     double total = 0.0;
     const double sT = fp32 ? 4.0 : 8.0;
     for (int id : pl.h_ids) {
+        if (active && !(*active)[id / S.Lmax]) continue;
         const LevDesc &D = fp32 ? S.h32[id] : S.h64[id];
         double N = (double)D.ncell;
         double coef = (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? N * sT : 0.0) + (D.has_mask ? N : 0.0);
@@ -1808,13 +1825,39 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind) 
     return total;
 }
 
+template <typename F>
+static void timed_mg(vd_ctx *ctx, Solver &S, const char *family, const HPlan &pl, bool fp32, int kind, double factor,
+                     F &&launch) {
+    timed(ctx, family, 0.0, launch);
+    if (!ctx->timing.families.empty()) S.recs.push_back({family, &pl, fp32, kind, factor, S.cur_it, S.cur_phase});
+}
+
+// Credit the recorded launches of a finished solve: a problem contributes
+// to a residual check of iteration it if it was checked then (it < outer
+// checks; every problem at it = 0), to the cycle launches of iteration it
+// if it was cycled then (it < cycles / inner), to set-up launches always.
+static void credit_launches(vd_ctx *ctx, Solver &S, int inner) {
+    if (S.recs.empty()) return;
+    std::vector<char> act(S.nprob);
+    for (auto &r : S.recs) {
+        for (int p = 0; p < S.nprob; p++) {
+            const ProbState &q = S.pin_st[p];
+            if (r.phase == 2) act[p] = 1;
+            else if (r.phase == 0) act[p] = r.it == 0 || q.outer > r.it;
+            else act[p] = q.cycles / inner > r.it;
+        }
+        timing_add_units(ctx, r.family, plan_bytes(S, *r.plan, r.fp32, r.kind, &act) * r.factor);
+    }
+    S.recs.clear();
+}
+
 // one Gauss-Seidel colour pass over level l of every problem in the plan
 template <typename T>
 static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
     const HPlan &pp = S.pre[l];
     const HPlan &p25 = S.pre25[l];
     hipStream_t s = ctx->stream;
-    timed(ctx, "gsrb", plan_bytes(S, pp, sizeof(T) == 4, 0), [&] {
+    timed_mg(ctx, S, "gsrb", pp, sizeof(T) == 4, 0, 1.0, [&] {
         if (p25.nd && S.aligned)
             k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1, nullptr);
         else
@@ -1827,7 +1870,7 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
 template <typename T>
 static void sweep_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int flip) {
     const HPlan &p25 = S.pre25[l];
-    timed(ctx, "gsrb", plan_bytes(S, S.pre[l], sizeof(T) == 4, 6), [&] {
+    timed_mg(ctx, S, "gsrb", S.pre[l], sizeof(T) == 4, 6, 1.0, [&] {
         k_sweep25<T><<<xcd_grid(p25.ntiles), kBlock, 0, ctx->stream>>>(dT, p25.dev(), p25.kz, flip, S.st.p);
     });
 }
@@ -1855,7 +1898,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
         if (S.pre[l].nd) smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l]);
         const HPlan &pr = S.restr[l];
         if (pr.nd)
-            timed(ctx, "resid_restrict", plan_bytes(S, pr, sizeof(T) == 4, 1), [&] {
+            timed_mg(ctx, S, "resid_restrict", pr, sizeof(T) == 4, 1, 1.0, [&] {
                 k_restrict<T><<<xcd_grid(pr.ntiles), kBlock, 0, s>>>(dT, pr.dev(), st, par[l]);
             });
     }
@@ -1871,7 +1914,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
     for (int l = S.Lmax - 1; l >= 0; l--) {
         const HPlan &pp = S.prolong[l];
         if (pp.nd)
-            timed(ctx, "prolong", plan_bytes(S, pp, sizeof(T) == 4, 2), [&] {
+            timed_mg(ctx, S, "prolong", pp, sizeof(T) == 4, 2, 1.0, [&] {
                 k_prolong<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), st, par[l]);
             });
         const HPlan &ps = S.pre[l];
@@ -1879,7 +1922,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
             smooth_level<T>(ctx, S, l, dT, o->nu_post, par[l]);
             if (par[l]) {
                 // an odd number of sweeps: the iterate goes back to x
-                timed(ctx, "copy", plan_bytes(S, ps, sizeof(T) == 4, 7), [&] {
+                timed_mg(ctx, S, "copy", ps, sizeof(T) == 4, 7, 1.0, [&] {
                     k_copy_x2<T><<<xcd_grid(ps.ntiles), kBlock, 0, s>>>(dT, ps.dev(), st);
                 });
                 par[l] = 0;
@@ -1898,7 +1941,7 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
     hipStream_t s = ctx->stream;
     if (mode != 0 && S.all0_25.nd && S.aligned) {
         const HPlan &p25 = S.all0_25;
-        timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
+        timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {
             if (mode == 1)
                 k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
                                                                           S.partials.p, S.st.p, check_active, pb);
@@ -1908,7 +1951,7 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
         });
         return;
     }
-    timed(ctx, "norm", plan_bytes(S, pl, false, 3 + mode), [&] {
+    timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {
         if (mode == 0)
             k_norm<0><<<xcd_grid(pl.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, pl.dev(), S.partials.p, S.st.p, check_active,
                                                              nullptr);
@@ -1947,7 +1990,7 @@ static void one_cycle(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
         launch_norm(ctx, S, 2, 1);
         launch_finalize(ctx, S, 1, o, o->ir_inner);
         for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, S, S.d32.p, o);
-        timed(ctx, "ir_update", plan_bytes(S, S.all0, false, 3) * 2.5, [&] {
+        timed_mg(ctx, S, "ir_update", S.all0, false, 3, 2.5, [&] {
             k_ir_update<<<xcd_grid(S.all0.ntiles), kBlock, 0, ctx->stream>>>(S.d64.p, S.d32.p, S.all0.dev(), S.st.p);
         });
     }
@@ -2132,6 +2175,9 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
         if (any) refresh_descs(ctx, *S, nprob, probs, o);
     }
     hipStream_t s = ctx->stream;
+    S->recs.clear();
+    S->cur_it = 0;
+    S->cur_phase = 2;
     k_state_init<<<ceil_div(nprob, 64), 64, 0, s>>>(S->st.p, nprob);
     VD_HIP(hipGetLastError());
     // ||b|| comes from the first residual pass, except on the guess-checking
@@ -2174,6 +2220,8 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     // of the problems whose right-hand side vanishes
     auto check = [&](int nmode, int inner) {
         const bool first = fuse_b && iters == 0;
+        S->cur_it = iters;
+        S->cur_phase = 0;
         launch_norm(ctx, *S, nmode, 1, first);
         launch_finalize(ctx, *S, first ? 3 : 1, o, inner);
         if (first)
@@ -2188,12 +2236,14 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
             } else if (!ir) {
                 check(1, 1);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
+                S->cur_phase = 1;
                 vcycle<double>(ctx, *S, S->d64.p, o);
             } else {
                 check(2, o->ir_inner);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
+                S->cur_phase = 1;
                 for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, *S, S->d32.p, o);
-                timed(ctx, "ir_update", plan_bytes(*S, S->all0, false, 3) * 2.5, [&] {
+                timed_mg(ctx, *S, "ir_update", S->all0, false, 3, 2.5, [&] {
                     k_ir_update<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->d32.p, S->all0.dev(), S->st.p);
                 });
             }
@@ -2202,6 +2252,10 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
         if (async_fixed) break;
         if (read_active(ctx, *S) == 0) break;
         if (iters > 4 * (o->max_cycles + 2) + 8) throw Error{VD_ENOCONV, "internal: convergence loop did not terminate"};
+    }
+    if (!S->recs.empty()) {
+        if (async_fixed) read_active(ctx, *S);
+        credit_launches(ctx, *S, ir ? o->ir_inner : 1);
     }
     vd_status worst = VD_OK;
     if (infos) {

@@ -201,6 +201,9 @@ bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *
 void timing_flush(vd_ctx *ctx);
 
 void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units);
+// algorithmic bytes credited to a family after the launches (work that is
+// known only once the device-side convergence state has been read)
+void timing_add_units(vd_ctx *ctx, const char *family, double units);
 
 template <typename F>
 inline void timed(vd_ctx *ctx, const char *family, double units, F &&launch) {

@@ -373,3 +373,23 @@ def test_graph_replay_and_autotune(ctx, V, oracle, precision):
     if prec == V.FP64:
         for p in range(len(probs)):
             _pinned_compare(oracle, probs[p], host(ref[p]["x"]), i_ref[p], 1e-10)
+
+
+def test_timing_credits_only_active_problems(V):
+    """The smoother's algorithmic bytes count the problems that were still
+    being cycled: a zero right-hand side added to a batch (inactive after
+    the first check) adds launches but no smoother bytes."""
+    prob = I.random_helmholtz(801, (32, 32, 32), beta_jump=True)
+    zero = I.random_helmholtz(802, (32, 32, 32), beta_jump=True)
+    zero["rhs"] = np.zeros_like(zero["rhs"])
+    zero["bc"] = I.bc(list(zero["bc"]["kind"]), [0.0] * 6)     # no lifting either: b = 0
+    res = []
+    for batch in ([prob], [prob, zero]):
+        c = V.Context()
+        c.vd_timing_select("gsrb")
+        infos, st = c.vd_helmholtz_solve_batched([gpu_problem(p) for p in batch], V.mg_opts(rtol=1e-10))
+        assert st == 0
+        res.append(c.vd_timing_read("gsrb"))
+        say("   gsrb launches / ms / bytes", res[-1])
+    assert res[0][0] == res[1][0] and res[0][2] > 0
+    assert res[1][2] == res[0][2]
