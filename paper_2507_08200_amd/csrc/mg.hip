@@ -19,6 +19,8 @@
 //     flags), so the host reads back one small state array per chunk.
 #include "vd_internal.hpp"
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdio>
 
@@ -299,6 +301,18 @@ __device__ __forceinline__ int halo_slot(int tid) {
     return (side ? kT25Y + 1 : 0) * kT25W + cc + 1;
 }
 
+// wrapped (periodic) or clamped index of position p along a direction of n
+// cells; ok tells whether the position stands for a cell (inside the
+// domain, or one wrap across a periodic face).  The index is always valid.
+__device__ __forceinline__ int wrap_idx(int p, int n, bool per, bool &ok) {
+    const bool in = p >= 0 && p < n;
+    const int w = p < 0 ? p + n : p - n;
+    const bool wrapped = per && !in && w >= 0 && w < n;
+    ok = in || wrapped;
+    const int c = p < 0 ? 0 : (p >= n ? n - 1 : p);
+    return in ? p : (wrapped ? w : c);
+}
+
 // MODE 0: one Gauss-Seidel colour pass (in place); MODE 1: FP64 residual
 // norm partials; MODE 2: same, also storing the FP32 residual and clearing
 // the FP32 unknown (iterative refinement).  Software-pipelined: while plane
@@ -336,35 +350,73 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const int hslot = halo_slot<T>(tid);
     T *__restrict__ X = (T *)L.x;
     const T *__restrict__ B = (const T *)L.b;
-    T xm0, xm1, xc0, xc1, xp0, xp1;
-    ld_slot<T>(L, X, ia, j, k0 - 1, own, xm0, xm1);
-    ld_slot<T>(L, X, ia, j, k0, own, xc0, xc1);
-    ld_slot<T>(L, X, ia, j, k0 + 1, own, xp0, xp1);
-    T hcur = halo_thread ? ld_halo<T>(L, X, tid, i0, j0, k0) : (T)0;
-    T bc0 = 0, bc1 = 0;
-    const long rowoff = (long)nx * j;
-    if (own) {
-        typename Pair<T>::V bv = *(const VD_GAS typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * k0);
-        bc0 = bv.x;
-        bc1 = bv.y;
+    // Branch-free loads: every thread issues the same loads on every plane
+    // (wrapped or clamped addresses, zeroed where the position is not a
+    // cell), so the compiler can count outstanding loads and the look-ahead
+    // really overlaps with the computation.  x / y parts are fixed per thread.
+    const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
+    bool okx, oky;
+    const int iw = min(wrap_idx(ia, nx, px, okx), nx - 2);
+    const int jw = wrap_idx(j, ny, py, oky);
+    const bool okxy = okx && oky;
+    const long pair_off = iw + (long)nx * jw;
+    const long b_off = min(ia, nx - 2) + (long)nx * min(j, ny - 1);
+    int hi, hj;
+    if (tid < 2 * kT25Y) {
+        hi = (tid / kT25Y) ? i0 + kT25X : i0 - 1;
+        hj = j0 + (tid & (kT25Y - 1));
+    } else {
+        const int q = tid - 2 * kT25Y;
+        hi = i0 + (q & (kT25X - 1));
+        hj = (q / kT25X) ? j0 + kT25Y : j0 - 1;
     }
+    bool okhi, okhj;
+    const long h_off = wrap_idx(hi, nx, px, okhi) + (long)nx * wrap_idx(hj, ny, py, okhj);
+    const bool okh = halo_thread && okhi && okhj;
+    const long nxy = L.nxy;
+    auto ld_pair = [&](int kk, T &a, T &b2) {
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(X + pair_off + nxy * kw);
+        const bool ok = okxy && okz;
+        a = ok ? v.x : (T)0;
+        b2 = ok ? v.y : (T)0;
+    };
+    auto ld_h = [&](int kk) -> T {
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const T v = gld(X, h_off + nxy * kw);
+        return (okh && okz) ? v : (T)0;
+    };
+    auto ld_b = [&](int kk, T &a, T &b2) {
+        const typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(B + b_off + nxy * min(kk, nz - 1));
+        const bool ok = own && kk < k1;
+        a = ok ? v.x : (T)0;
+        b2 = ok ? v.y : (T)0;
+    };
+    const long rowoff = (long)nx * j;
     double v = 0.0, vb = 0.0;
+    // the plane loop, instantiated twice: for uniform-coefficient levels
+    // (no coefficient or mask loads inside the pipeline) and in general
+    auto march = [&](auto uni_tag) {
+    constexpr bool UNI = decltype(uni_tag)::value;
+    T xm0, xm1, xc0, xc1, xp0, xp1;
+    ld_pair(k0 - 1, xm0, xm1);
+    ld_pair(k0, xc0, xc1);
+    ld_pair(k0 + 1, xp0, xp1);
+    T hcur = ld_h(k0);
+    T bc0, bc1;
+    ld_b(k0, bc0, bc1);
     for (int k = k0; k < k1; k++) {
         T *buf = xs[k & 1];
         buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
         buf[(r + 1) * kT25W + 2 * tp + 2] = xc1;
         if (halo_thread) buf[hslot] = hcur;
-        // prefetch for the next plane
-        T xq0, xq1, hnext = (T)0, bn0 = (T)0, bn1 = (T)0;
-        ld_slot<T>(L, X, ia, j, k + 2, own, xq0, xq1);
-        if (k + 1 < k1) {
-            if (halo_thread) hnext = ld_halo<T>(L, X, tid, i0, j0, k + 1);
-            if (own) {
-                typename Pair<T>::V bv = *(const VD_GAS typename Pair<T>::V *)(B + ia + rowoff + (long)L.nxy * (k + 1));
-                bn0 = bv.x;
-                bn1 = bv.y;
-            }
-        }
+        // look-ahead for the next plane
+        T xq0, xq1, bn0, bn1;
+        ld_pair(k + 2, xq0, xq1);
+        const T hnext = ld_h(k + 1);
+        ld_b(k + 1, bn0, bn1);
         __syncthreads();
         if (own) {
             // colour pass: the pair is stored whole (the other cell with its
@@ -376,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 const int i = ia + q;
                 if (MODE == 0 && ((i + j + k) & 1) != colour) continue;
                 const int c = i + nx * j + L.nxy * k;
-                const bool valid = !(L.has_mask && !gld(L.mask, c));
+                const bool valid = UNI || !(L.has_mask && !gld(L.mask, c));
                 if (MODE == 0 && !valid) continue;
                 T nbv[6];
                 nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
@@ -386,9 +438,10 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 nbv[4] = q == 0 ? xm0 : xm1;
                 nbv[5] = q == 0 ? xp0 : xp1;
                 T dg, of;
-                row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
+                if constexpr (UNI) row_terms_uni<T>(L, i, j, k, nbv, dg, of);
+                else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
                 T b = q == 0 ? bc0 : bc1;
-                if (L.lift) b = (T)((double)b + lift_term(L, i, j, k));
+                if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
                 if (MODE == 0) {
                     if (q == 0) out0 = (b + of) / dg;
                     else out1 = (b + of) / dg;
@@ -416,6 +469,9 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         hcur = hnext;
         bc0 = bn0; bc1 = bn1;
     }
+    };
+    if (!L.var_beta && !L.var_alpha && !L.has_mask) march(std::true_type{});
+    else march(std::false_type{});
     if (MODE != 0) {
         const double sum = block_sum(v, red);
         if (tid == 0) gst(partials, t, sum);

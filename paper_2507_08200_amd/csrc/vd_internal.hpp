@@ -363,6 +363,38 @@ __device__ __forceinline__ void row_terms_nb(const LevDesc &L, int i, int j, int
     off = of;
 }
 
+// Same row for a uniform-coefficient level (no coefficient arrays, no
+// mask): nothing is loaded, so it can sit inside a software pipeline.
+template <typename T>
+__device__ __forceinline__ void row_terms_uni(const LevDesc &L, int i, int j, int k, const T nbv[6], T &diag, T &off) {
+    T dg = (T)L.alpha_c;
+    T of = 0;
+    const T bc = (T)L.beta_c;
+    const bool inside[6] = {i > 0, i < L.nx - 1, j > 0, j < L.ny - 1, k > 0, k < L.nz - 1};
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        const T cf = bc * (T)(f < 2 ? L.idx2 : (f < 4 ? L.idy2 : L.idz2));
+        const int kd = f == 0 ? L.kind[0] : f == 1 ? L.kind[1] : f == 2 ? L.kind[2] : f == 3 ? L.kind[3] : f == 4 ? L.kind[4] : L.kind[5];
+        if (inside[f] || kd == VD_BC_PERIODIC) { dg += cf; of += cf * nbv[f]; }
+        else if (kd == VD_BC_DIRICHLET) dg += (T)2 * cf;
+    }
+    diag = dg;
+    off = of;
+}
+
+// Dirichlet lifting of a uniform-coefficient finest level (no loads)
+__device__ __forceinline__ double lift_term_uni(const LevDesc &L, int i, int j, int k) {
+    double v = 0.0;
+    const double bc = L.beta_c;
+    if (i == 0 && L.kind[0] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[0] * L.idx2;
+    if (i == L.nx - 1 && L.kind[1] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[1] * L.idx2;
+    if (j == 0 && L.kind[2] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[2] * L.idy2;
+    if (j == L.ny - 1 && L.kind[3] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[3] * L.idy2;
+    if (k == 0 && L.kind[4] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[4] * L.idz2;
+    if (k == L.nz - 1 && L.kind[5] == VD_BC_DIRICHLET) v += 2.0 * bc * L.gval[5] * L.idz2;
+    return v;
+}
+
 // Dirichlet lifting of the finest level: 2 beta_f g / h^2 per Dirichlet
 // face of a boundary cell, added to the right-hand side.
 __device__ __forceinline__ double lift_term(const LevDesc &L, int i, int j, int k) {
