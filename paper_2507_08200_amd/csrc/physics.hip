@@ -240,6 +240,48 @@ __device__ __forceinline__ double face_flux(const GridDev &G, const FieldDesc &F
     return face_drift(G, F, phi, d, (int)c0, 0, fidx);
 }
 
+// Value of field u at row position p (up to 3 outside), as u_at, with
+// every branch turned into a select: one load from a valid index, so the
+// loads of a face stencil are issued together.
+__device__ __forceinline__ double u_at_bf(const GridDev &G, const FieldDesc &F, int d, long c0, int p) {
+    const int n = G.n[d];
+    const bool lo = p < 0, hi = p >= n;
+    const int kd = lo ? (d == 0 ? F.kind[0] : d == 1 ? F.kind[2] : F.kind[4])
+                      : (d == 0 ? F.kind[1] : d == 1 ? F.kind[3] : F.kind[5]);
+    const bool per = kd == VD_BC_PERIODIC;
+    int q = lo ? (per ? p + n : -1 - p) : (hi ? (per ? p - n : 2 * n - 1 - p) : p);
+    q = q < 0 ? 0 : (q >= n ? n - 1 : q);
+    const double v = gld(F.u, c0 + q * G.stride[d]);
+    const double g = lo ? (d == 0 ? F.gval[0] : d == 1 ? F.gval[2] : F.gval[4])
+                        : (d == 0 ? F.gval[1] : d == 1 ? F.gval[3] : F.gval[5]);
+    return ((lo || hi) && kd == VD_BC_DIRICHLET) ? 2.0 * g - v : v;
+}
+
+// face_flux for an interior face (0 < fidx < n) without branches around
+// loads: phi at the two cells, the two cells' mobilities (the field itself
+// stands in as a valid address when the mobility is constant) and the six
+// stencil values of both upwind directions are loaded together, the upwind
+// side is then selected.  Domain faces fall back to face_flux.
+__device__ __forceinline__ double face_flux_fast(const GridDev &G, const FieldDesc &F, const double *__restrict__ phi,
+                                                 const double *__restrict__ Te, double Tg, double kB, double me, int d,
+                                                 long c0, int fidx, bool drift) {
+    const int n = G.n[d];
+    if (fidx == 0 || fidx == n) return face_flux(G, F, phi, Te, Tg, kB, me, d, c0, fidx);
+    if (!drift) return 0.0;
+    const long st = G.stride[d];
+    const long cl = c0 + (long)(fidx - 1) * st, cr = cl + st;
+    const double Ef = -(gld(phi, cr) - gld(phi, cl)) * G.ih[d];
+    const double *__restrict__ mup = F.mu ? F.mu : F.u;
+    const double ml = gld(mup, cl), mr = gld(mup, cr);
+    double w[6];
+#pragma unroll
+    for (int m = 0; m < 6; m++) w[m] = u_at_bf(G, F, d, c0, fidx - 3 + m);
+    const double muf = F.mu ? 0.5 * (ml + mr) : F.mu_c;
+    const double v = muf * F.mu_scale * Ef;
+    const bool up = v > 0.0;
+    return v * weno5(up ? w[0] : w[5], up ? w[1] : w[4], up ? w[2] : w[3], up ? w[3] : w[2], up ? w[4] : w[1]);
+}
+
 // Tiled drift divergence: a workgroup owns a kTX x kTY tile of an x-y plane
 // and marches kKZ planes in z.  Every face flux is evaluated once: x and y
 // faces go through LDS (the tile-edge faces are remapped onto the first
@@ -265,18 +307,19 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
     const long col = i + (long)nx * j;                  // (i, j, 0)
     // x faces: face f of row r of the tile, f in 0..kTX (kTY*(kTX+1) faces)
     const int nfx = kTY * (kTX + 1), nfy = (kTY + 1) * kTX;
-    double fz_lo = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k0);
+    const bool drift = F.mu || F.mu_c != 0.0;
+    double fz_lo = face_flux_fast(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k0, drift);
     for (int k = k0; k < k0 + kz; k++) {
         const long pl = nxy * k;
         for (int q = threadIdx.x; q < nfx; q += kBlock) {
             const int r = q / (kTX + 1), f = q - r * (kTX + 1);
-            fx[q] = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 0, pl + (long)nx * (j0 + r), i0 + f);
+            fx[q] = face_flux_fast(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 0, pl + (long)nx * (j0 + r), i0 + f, drift);
         }
         for (int q = threadIdx.x; q < nfy; q += kBlock) {
             const int r = q / kTX, f = q - r * kTX;
-            fy[q] = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 1, pl + i0 + f, j0 + r);
+            fy[q] = face_flux_fast(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 1, pl + i0 + f, j0 + r, drift);
         }
-        const double fz_hi = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k + 1);
+        const double fz_hi = face_flux_fast(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, 2, col, k + 1, drift);
         __syncthreads();
         const double div = (fx[ty * (kTX + 1) + tx + 1] - fx[ty * (kTX + 1) + tx]) * G.ihl[0] +
                            (fy[(ty + 1) * kTX + tx] - fy[ty * kTX + tx]) * G.ihl[1] + (fz_hi - fz_lo) * G.ihl[2];
