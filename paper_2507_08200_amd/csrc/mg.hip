@@ -318,7 +318,7 @@ __device__ __forceinline__ int wrap_idx(int p, int n, bool per, bool &ok) {
 // the FP32 unknown (iterative refinement).  Software-pipelined: while plane
 // k is computed, plane k+2's pair, plane k+1's halo and plane k+1's b are in
 // flight; the LDS tile is double-buffered so one barrier per plane suffices.
-template <typename T, int MODE>
+template <typename T, int MODE, bool UNIONLY = false>
 __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
                                                  int kz, int colour, double *__restrict__ partials,
                                                  const ProbState *__restrict__ st, int check_active,
@@ -398,8 +398,18 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     double v = 0.0, vb = 0.0;
     // the plane loop, instantiated twice: for uniform-coefficient levels
     // (no coefficient or mask loads inside the pipeline) and in general
-    auto march = [&](auto uni_tag) {
-    constexpr bool UNI = decltype(uni_tag)::value;
+    // variant 1: uniform coefficients, no mask (nothing loaded inside the
+    // pipeline); 2: coefficient arrays, no mask (faces and alpha of the pair
+    // loaded together, from clamped addresses); 0: general
+    auto march = [&](auto var_tag) {
+    constexpr int VAR = decltype(var_tag)::value;
+    constexpr bool UNI = VAR == 1;
+    const long jc = min(j, ny - 1);
+    const int ic = min(ia, nx - 2);
+    const T *__restrict__ BX = VAR == 2 && L.var_beta ? (const T *)Coef<T>::bx(L) : X;
+    const T *__restrict__ BY = VAR == 2 && L.var_beta ? (const T *)Coef<T>::by(L) : X;
+    const T *__restrict__ BZ = VAR == 2 && L.var_beta ? (const T *)Coef<T>::bz(L) : X;
+    const T *__restrict__ AL = VAR == 2 && L.var_alpha ? (const T *)Coef<T>::al(L) : X;
     T xm0, xm1, xc0, xc1, xp0, xp1;
     ld_pair(k0 - 1, xm0, xm1);
     ld_pair(k0, xc0, xc1);
@@ -418,6 +428,24 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         const T hnext = ld_h(k + 1);
         ld_b(k + 1, bn0, bn1);
         __syncthreads();
+        // coefficient arrays of this plane for the pair (variant 2): all
+        // issued together from clamped addresses
+        T fx0 = 0, fx1 = 0, fx2 = 0;
+        typename Pair<T>::V fyl{}, fyh{}, fzl{}, fzh{}, alp{};
+        if constexpr (VAR == 2) {
+            const long fxrow = (long)(nx + 1) * (jc + (long)ny * k);
+            const long fyrow = (long)nx * (jc + (long)(ny + 1) * k);
+            const long fz = (long)nx * jc + ic;
+            const bool fb = L.var_beta;
+            fx0 = gld(BX, fb ? fxrow + ic : pair_off);
+            fx1 = gld(BX, fb ? fxrow + ic + 1 : pair_off);
+            fx2 = gld(BX, fb ? fxrow + ic + 2 : pair_off);
+            fyl = *(const VD_GAS typename Pair<T>::V *)(BY + (fb ? fyrow + ic : pair_off));
+            fyh = *(const VD_GAS typename Pair<T>::V *)(BY + (fb ? fyrow + nx + ic : pair_off));
+            fzl = *(const VD_GAS typename Pair<T>::V *)(BZ + (fb ? fz + nxy * k : pair_off));
+            fzh = *(const VD_GAS typename Pair<T>::V *)(BZ + (fb ? fz + nxy * (k + 1) : pair_off));
+            alp = *(const VD_GAS typename Pair<T>::V *)(AL + (L.var_alpha ? ic + (long)nx * jc + nxy * k : pair_off));
+        }
         if (own) {
             // colour pass: the pair is stored whole (the other cell with its
             // unchanged value, which no other thread writes in this pass), so
@@ -428,7 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 const int i = ia + q;
                 if (MODE == 0 && ((i + j + k) & 1) != colour) continue;
                 const int c = i + nx * j + L.nxy * k;
-                const bool valid = UNI || !(L.has_mask && !gld(L.mask, c));
+                const bool valid = VAR != 0 || !(L.has_mask && !gld(L.mask, c));
                 if (MODE == 0 && !valid) continue;
                 T nbv[6];
                 nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
@@ -438,10 +466,25 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                 nbv[4] = q == 0 ? xm0 : xm1;
                 nbv[5] = q == 0 ? xp0 : xp1;
                 T dg, of;
-                if constexpr (UNI) row_terms_uni<T>(L, i, j, k, nbv, dg, of);
-                else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
                 T b = q == 0 ? bc0 : bc1;
-                if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
+                if constexpr (VAR == 2) {
+                    T fc[6];
+                    fc[0] = q == 0 ? fx0 : fx1;
+                    fc[1] = q == 0 ? fx1 : fx2;
+                    fc[2] = q == 0 ? fyl.x : fyl.y;
+                    fc[3] = q == 0 ? fyh.x : fyh.y;
+                    fc[4] = q == 0 ? fzl.x : fzl.y;
+                    fc[5] = q == 0 ? fzh.x : fzh.y;
+                    if (!L.var_beta) for (int f = 0; f < 6; f++) fc[f] = (T)L.beta_c;
+                    const T al = L.var_alpha ? (q == 0 ? alp.x : alp.y) : (T)L.alpha_c;
+                    double lf;
+                    row_terms_fc<T>(L, i, j, k, nbv, fc, al, dg, of, lf);
+                    if (L.lift) b = (T)((double)b + lf);
+                } else {
+                    if constexpr (UNI) row_terms_uni<T>(L, i, j, k, nbv, dg, of);
+                    else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
+                    if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
+                }
                 if (MODE == 0) {
                     if (q == 0) out0 = (b + of) / dg;
                     else out1 = (b + of) / dg;
@@ -470,8 +513,13 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         bc0 = bn0; bc1 = bn1;
     }
     };
-    if (!L.var_beta && !L.var_alpha && !L.has_mask) march(std::true_type{});
-    else march(std::false_type{});
+    if constexpr (UNIONLY) {
+        march(std::integral_constant<int, 1>{});   // every problem of the plan has uniform coefficients
+    } else {
+        if (!L.var_beta && !L.var_alpha && !L.has_mask) march(std::integral_constant<int, 1>{});
+        else if (!L.has_mask) march(std::integral_constant<int, 2>{});
+        else march(std::integral_constant<int, 0>{});
+    }
     if (MODE != 0) {
         const double sum = block_sum(v, red);
         if (tid == 0) gst(partials, t, sum);
@@ -532,104 +580,198 @@ __global__ void __launch_bounds__(kBlock) k_sweep25(const LevDesc *__restrict__ 
     T *__restrict__ Y = (T *)(flip ? L.x : L.x2);
     const T *__restrict__ B = (const T *)L.b;
     const long nxy = L.nxy;
+    constexpr int kOld = kSwOY * kSwOX;                 // 720 old values per plane
+    constexpr int kOldPer = (kOld + kBlock - 1) / kBlock;
+    constexpr int kRed = kSwRY * (kSwRX / 2);           // 306 red cells per ring plane
+    constexpr int kRedPer = (kRed + kBlock - 1) / kBlock;
 
-    // old plane q (ring 2) into its slot; non-cells read as 0
-    auto load_old = [&](int q) {
-        T *s = xo[(q + 4) & 3];
-        int wk;
-        const bool zok = wrap_pos(q, nz, pz, wk);
-        for (int e = tid; e < kSwOY * kSwOX; e += kBlock) {
-            const int ri = e % kSwOX, rj = e / kSwOX;
-            int wi, wj;
-            T v = (T)0;
-            if (zok && wrap_pos(i0 - 2 + ri, nx, px, wi) && wrap_pos(j0 - 2 + rj, ny, py, wj))
-                v = gld(X, wi + (long)nx * wj + nxy * wk);
-            lst(s, e, v);
-        }
-    };
-
-    // new red values of plane p on the tile and its ring; the tile's own
-    // cells (of planes k0..k1-1) are stored to Y
-    auto red_plane = [&](int p) {
-        T *rs = xr[(p + 3) % 3];
-        const T *om = xo[(p + 3) & 3], *oc = xo[(p + 4) & 3], *op = xo[(p + 5) & 3];
-        int wk;
-        const bool zok = wrap_pos(p, nz, pz, wk);
-        const bool own_plane = p >= k0 && p < k1;
-        for (int m = tid; m < kSwRY * (kSwRX / 2); m += kBlock) {
-            const int rj = m / (kSwRX / 2), h = m - rj * (kSwRX / 2);
-            const int gj = j0 - 1 + rj;
-            const int ri = 2 * h + ((i0 - 1 + gj + p) & 1);    // red: (i + j + k) even
-            const int gi = i0 - 1 + ri;
-            int wi, wj;
-            T val = (T)0;
-            if (zok && wrap_pos(gi, nx, px, wi) && wrap_pos(gj, ny, py, wj)) {
-                const int c = wi + nx * wj + (int)nxy * wk;
-                const int o = (rj + 1) * kSwOX + ri + 1;
-                if (L.has_mask && !gld(L.mask, c)) {
-                    val = lld(oc, o);
-                } else {
-                    T nbv[6];
-                    nbv[0] = lld(oc, o - 1);
-                    nbv[1] = lld(oc, o + 1);
-                    nbv[2] = lld(oc, o - kSwOX);
-                    nbv[3] = lld(oc, o + kSwOX);
-                    nbv[4] = lld(om, o);
-                    nbv[5] = lld(op, o);
-                    T dg, of;
-                    row_terms_nb<T>(L, wi, wj, wk, c, nbv, dg, of);
-                    T bv = gld(B, c);
-                    if (L.lift) bv = (T)((double)bv + lift_term(L, wi, wj, wk));
-                    val = (bv + of) / dg;
-                }
-                if (own_plane && ri >= 1 && ri <= kT25X && rj >= 1 && rj <= kT25Y && gi < nx && gj < ny) gst(Y, c, val);
-            }
-            lst(rs, rj * kSwRX + ri, val);
-        }
-    };
-
-    // new black values of plane p on the tile (one per thread)
-    auto black_plane = [&](int p) {
-        const T *rm = xr[(p + 2) % 3], *rc = xr[(p + 3) % 3], *rp = xr[(p + 4) % 3];
-        const T *oc = xo[(p + 4) & 3];
-        const int r = tid >> 4, h = tid & 15;
-        const int gj = j0 + r;
-        const int gi = i0 + 2 * h + (((i0 + gj + p) & 1) ^ 1);   // black: (i + j + k) odd
-        if (gi >= nx || gj >= ny) return;
-        const int c = gi + nx * gj + (int)nxy * p;
-        const int ri = gi - i0 + 1, rj = r + 1;
-        T val;
-        if (L.has_mask && !gld(L.mask, c)) {
-            val = lld(oc, (rj + 1) * kSwOX + ri + 1);
-        } else {
-            const int o = rj * kSwRX + ri;
-            T nbv[6];
-            nbv[0] = lld(rc, o - 1);
-            nbv[1] = lld(rc, o + 1);
-            nbv[2] = lld(rc, o - kSwRX);
-            nbv[3] = lld(rc, o + kSwRX);
-            nbv[4] = lld(rm, o);
-            nbv[5] = lld(rp, o);
-            T dg, of;
-            row_terms_nb<T>(L, gi, gj, p, c, nbv, dg, of);
-            T bv = gld(B, c);
-            if (L.lift) bv = (T)((double)bv + lift_term(L, gi, gj, p));
-            val = (bv + of) / dg;
-        }
-        gst(Y, c, val);
-    };
-
-    load_old(k0 - 2);
-    load_old(k0 - 1);
-    load_old(k0);
-    __syncthreads();
-    for (int p = k0 - 1; p <= k1; p++) {
-        red_plane(p);
-        if (p + 2 <= k1 + 1) load_old(p + 2);   // slot of plane p - 2, no longer read
-        __syncthreads();
-        if (p - 1 >= k0) black_plane(p - 1);
-        __syncthreads();
+    // per-thread x-y parts of every load (plane-invariant); a position that
+    // is not a cell reads a clamped valid address and is zeroed
+    long o_off[kOldPer];
+    bool o_ok[kOldPer];
+#pragma unroll
+    for (int m = 0; m < kOldPer; m++) {
+        const int e = tid + m * kBlock;
+        const int ri = e % kSwOX, rj = e / kSwOX;
+        bool oi, oj;
+        const int wi = wrap_idx(i0 - 2 + ri, nx, px, oi), wj = wrap_idx(j0 - 2 + rj, ny, py, oj);
+        o_off[m] = wi + (long)nx * wj;
+        o_ok[m] = e < kOld && oi && oj && (i0 - 2 + ri) >= -2 && (i0 - 2 + ri) < nx + 2 && (j0 - 2 + rj) >= -2 &&
+                  (j0 - 2 + rj) < ny + 2;
     }
+    // red cells of the ring: position depends on the plane's parity
+    int r_ri[2][kRedPer], r_rj[kRedPer];
+    long r_off[2][kRedPer];
+    bool r_ok[2][kRedPer], r_own[2][kRedPer];
+    int r_wi[2][kRedPer], r_wj[kRedPer];
+#pragma unroll
+    for (int m = 0; m < kRedPer; m++) {
+        const int mm = tid + m * kBlock;
+        const int rj = mm / (kSwRX / 2), h = mm - rj * (kSwRX / 2);
+        const int gj = j0 - 1 + rj;
+        bool oj;
+        const int wj = wrap_idx(gj, ny, py, oj);
+        r_rj[m] = rj;
+        r_wj[m] = wj;
+#pragma unroll
+        for (int par = 0; par < 2; par++) {
+            const int ri = 2 * h + ((i0 - 1 + gj + par) & 1);
+            const int gi = i0 - 1 + ri;
+            bool oi;
+            const int wi = wrap_idx(gi, nx, px, oi);
+            r_ri[par][m] = ri;
+            r_wi[par][m] = wi;
+            r_off[par][m] = wi + (long)nx * wj;
+            r_ok[par][m] = mm < kRed && oi && oj;
+            r_own[par][m] = r_ok[par][m] && ri >= 1 && ri <= kT25X && rj >= 1 && rj <= kT25Y && gi < nx && gj < ny;
+        }
+    }
+    // the black cell of the tile owned by this thread, per plane parity
+    const int b_r = tid >> 4, b_h = tid & 15;
+    const int b_gj = j0 + b_r;
+    int b_gi[2];
+    long b_off[2];
+    bool b_ok[2];
+#pragma unroll
+    for (int par = 0; par < 2; par++) {
+        b_gi[par] = i0 + 2 * b_h + (((i0 + b_gj + par) & 1) ^ 1);
+        b_ok[par] = b_gi[par] < nx && b_gj < ny;
+        b_off[par] = min(b_gi[par], nx - 1) + (long)nx * min(b_gj, ny - 1);
+    }
+
+    auto plane_of = [&](int q, bool &ok) { return wrap_idx(q, nz, pz, ok); };
+    auto ld_old = [&](int q, T v[kOldPer]) {
+        bool okz;
+        const long pz_off = nxy * plane_of(q, okz);
+#pragma unroll
+        for (int m = 0; m < kOldPer; m++) {
+            const T g = gld(X, o_off[m] + pz_off);
+            v[m] = (okz && o_ok[m]) ? g : (T)0;
+        }
+    };
+    auto st_old = [&](int q, const T v[kOldPer]) {
+        T *s = xo[(q + 4) & 3];
+#pragma unroll
+        for (int m = 0; m < kOldPer; m++) {
+            const int e = tid + m * kBlock;
+            if (e < kOld) lst(s, e, v[m]);
+        }
+    };
+    auto ld_bred = [&](int p, T v[kRedPer]) {
+        bool okz;
+        const long pz_off = nxy * plane_of(p, okz);
+        const int par = p & 1;
+#pragma unroll
+        for (int m = 0; m < kRedPer; m++) v[m] = gld(B, r_off[par][m] + pz_off);
+    };
+    auto ld_bblk = [&](int p) -> T {
+        const int pc = min(max(p, 0), nz - 1);
+        return gld(B, b_off[p & 1] + nxy * pc);
+    };
+
+    auto march = [&](auto uni_tag) {
+        constexpr bool UNI = decltype(uni_tag)::value;
+        T rowv[6];
+        auto cell_row = [&](int i, int j, int k, int c, T &dg, T &of) {
+            if constexpr (UNI) row_terms_uni<T>(L, i, j, k, rowv, dg, of);
+            else row_terms_nb<T>(L, i, j, k, c, rowv, dg, of);
+        };
+        auto lift = [&](int i, int j, int k) -> double {
+            if constexpr (UNI) return lift_term_uni(L, i, j, k);
+            else return lift_term(L, i, j, k);
+        };
+        // red values of plane p on the tile and its ring (own cells stored)
+        auto red_plane = [&](int p, const T bred[kRedPer]) {
+            T *rs = xr[(p + 3) % 3];
+            const T *om = xo[(p + 3) & 3], *oc = xo[(p + 4) & 3], *op = xo[(p + 5) & 3];
+            bool okz;
+            const int wk = plane_of(p, okz);
+            const bool own_plane = p >= k0 && p < k1;
+            const int par = p & 1;
+#pragma unroll
+            for (int m = 0; m < kRedPer; m++) {
+                if (tid + m * kBlock >= kRed) break;
+                const int ri = r_ri[par][m], rj = r_rj[m];
+                T val = (T)0;
+                if (okz && r_ok[par][m]) {
+                    const int wi = r_wi[par][m], wj = r_wj[m];
+                    const int c = wi + nx * wj + (int)nxy * wk;
+                    const int o = (rj + 1) * kSwOX + ri + 1;
+                    if (!UNI && L.has_mask && !gld(L.mask, c)) {
+                        val = lld(oc, o);
+                    } else {
+                        rowv[0] = lld(oc, o - 1);
+                        rowv[1] = lld(oc, o + 1);
+                        rowv[2] = lld(oc, o - kSwOX);
+                        rowv[3] = lld(oc, o + kSwOX);
+                        rowv[4] = lld(om, o);
+                        rowv[5] = lld(op, o);
+                        T dg, of;
+                        cell_row(wi, wj, wk, c, dg, of);
+                        T bv = bred[m];
+                        if (L.lift) bv = (T)((double)bv + lift(wi, wj, wk));
+                        val = (bv + of) / dg;
+                    }
+                    if (own_plane && r_own[par][m]) gst(Y, c, val);
+                }
+                lst(rs, rj * kSwRX + ri, val);
+            }
+        };
+        // black value of the thread's tile cell on plane p
+        auto black_plane = [&](int p, T bv) {
+            const int par = p & 1;
+            if (!b_ok[par]) return;
+            const T *rm = xr[(p + 2) % 3], *rc = xr[(p + 3) % 3], *rp = xr[(p + 4) % 3];
+            const int gi = b_gi[par];
+            const int c = gi + nx * b_gj + (int)nxy * p;
+            const int ri = gi - i0 + 1, rj = b_r + 1;
+            T val;
+            if (!UNI && L.has_mask && !gld(L.mask, c)) {
+                val = lld(xo[(p + 4) & 3], (rj + 1) * kSwOX + ri + 1);
+            } else {
+                const int o = rj * kSwRX + ri;
+                rowv[0] = lld(rc, o - 1);
+                rowv[1] = lld(rc, o + 1);
+                rowv[2] = lld(rc, o - kSwRX);
+                rowv[3] = lld(rc, o + kSwRX);
+                rowv[4] = lld(rm, o);
+                rowv[5] = lld(rp, o);
+                T dg, of;
+                cell_row(gi, b_gj, p, c, dg, of);
+                if (L.lift) bv = (T)((double)bv + lift(gi, b_gj, p));
+                val = (bv + of) / dg;
+            }
+            gst(Y, c, val);
+        };
+
+        // prologue: old planes k0-2 .. k0 in LDS, plane k0+1 and the
+        // right-hand sides of the first red plane in registers
+        T ov[kOldPer], bred[kRedPer], bblk = (T)0, bblk_next;
+        ld_old(k0 - 2, ov);
+        st_old(k0 - 2, ov);
+        ld_old(k0 - 1, ov);
+        st_old(k0 - 1, ov);
+        ld_old(k0, ov);
+        st_old(k0, ov);
+        ld_old(k0 + 1, ov);
+        ld_bred(k0 - 1, bred);
+        __syncthreads();
+        for (int p = k0 - 1; p <= k1; p++) {
+            red_plane(p, bred);
+            // plane p+2 goes to the slot of plane p-2; then the look-ahead
+            // loads for the next plane are issued
+            if (p + 2 <= k1 + 1) st_old(p + 2, ov);
+            if (p + 3 <= k1 + 1) ld_old(p + 3, ov);
+            ld_bred(p + 1, bred);
+            bblk_next = ld_bblk(p);
+            __syncthreads();
+            if (p - 1 >= k0) black_plane(p - 1, bblk);
+            bblk = bblk_next;
+            __syncthreads();
+        }
+    };
+    if (!L.var_beta && !L.var_alpha && !L.has_mask) march(std::true_type{});
+    else march(std::false_type{});
 }
 
 // x <- x2 on every level of the plan (after an odd number of fused sweeps)
@@ -1411,6 +1553,7 @@ struct HPlan {
     DevBuf<int> ids, prefix;
     int nd = 0, ntiles = 0;
     int kz = 0;                  // 2.5D tiled plans: planes per workgroup
+    bool uni = false;            // every problem in the plan has uniform coefficients and no mask
     std::vector<int> h_ids, h_prefix;
     Plan dev() const { return Plan{ids.p, prefix.p, nd, ntiles}; }
 };
@@ -1434,6 +1577,8 @@ struct Solver {
     std::vector<HPlan> pre, restr, prolong;      // per level
     HPlan all0_25;                               // finest level as 2.5D tiles (residual norms), if usable
     std::vector<HPlan> pre25;                    // smoother levels as 2.5D tiles, if usable
+    std::vector<HPlan> pre25u, pre25g;           // the same split into uniform-coefficient and other problems
+                                                 // (built only when a level mixes both)
     std::vector<char> key;                       // problem bytes the descriptors were built from
     bool rows_valid = false;                     // assembled LDS rows match the descriptors
     hipGraphExec_t gexec = nullptr;              // one captured cycle (VD_MG_GRAPH)
@@ -1624,6 +1769,25 @@ static void build_plan25(vd_ctx *ctx, HPlan &out, const std::vector<std::pair<in
     upload_plan(out, ctx->stream);
 }
 
+// A level whose tiled plan mixes uniform-coefficient problems with others
+// is also planned as two halves, so the uniform ones run in the leaner
+// kernel (same tile depth; the colour pass is launched once per half).
+static void split25(vd_ctx *ctx, Solver &S, int l) {
+    HPlan &P = S.pre25[l];
+    S.pre25u[l] = HPlan{};
+    S.pre25g[l] = HPlan{};
+    if (!P.nd || P.uni) return;
+    std::vector<std::pair<int, const HLevel *>> u, g;
+    for (int id : S.pre[l].h_ids) {
+        const HProblem &H = S.probs[id / S.Lmax];
+        (!H.var_beta && !H.var_alpha && !H.has_mask ? u : g).push_back({id, &H.lv[id % S.Lmax]});
+    }
+    if (u.empty() || g.empty()) return;
+    build_plan25(ctx, S.pre25u[l], u, P.kz);
+    S.pre25u[l].uni = true;
+    build_plan25(ctx, S.pre25g[l], g, P.kz);
+}
+
 static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
     auto S = std::make_shared<Solver>();
     S->nprob = nprob;
@@ -1758,6 +1922,18 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
         for (int id : S->pre[l].h_ids) items.push_back({id, &S->probs[id / Lmax].lv[id % Lmax]});
         build25(S->pre25[l], items);
     }
+    auto mark_uni = [&](HPlan &pl) {
+        pl.uni = pl.nd > 0;
+        for (int id : pl.h_ids) {
+            const HProblem &H = S->probs[id / Lmax];
+            pl.uni = pl.uni && !H.var_beta && !H.var_alpha && !H.has_mask;
+        }
+    };
+    mark_uni(S->all0_25);
+    for (int l = 0; l < Lmax; l++) mark_uni(S->pre25[l]);
+    S->pre25u.resize(Lmax);
+    S->pre25g.resize(Lmax);
+    for (int l = 0; l < Lmax; l++) split25(ctx, *S, l);
     upload_plan(S->all0, ctx->stream);
     for (int l = 0; l < Lmax; l++) {
         upload_plan(S->pre[l], ctx->stream);
@@ -1913,8 +2089,26 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
     const HPlan &pp = S.pre[l];
     const HPlan &p25 = S.pre25[l];
     hipStream_t s = ctx->stream;
-    timed_mg(ctx, S, "gsrb", pp, sizeof(T) == 4, 0, 1.0, [&] {
-        if (p25.nd && S.aligned)
+    const HPlan &pu = S.pre25u[l], &pg = S.pre25g[l];
+    if (S.aligned && pu.nd && pg.nd) {
+        // mixed level: the uniform problems in the lean kernel, the rest in
+        // the general one
+        timed_mg(ctx, S, "gsrb_uniform", pu, sizeof(T) == 4, 0, 1.0, [&] {
+            k_st25<T, 0, true><<<xcd_grid(pu.ntiles), kBlock, 0, s>>>(dT, nullptr, pu.dev(), pu.kz, col, nullptr, S.st.p, 1,
+                                                                      nullptr);
+        });
+        timed_mg(ctx, S, "gsrb", pg, sizeof(T) == 4, 0, 1.0, [&] {
+            k_st25<T, 0><<<xcd_grid(pg.ntiles), kBlock, 0, s>>>(dT, nullptr, pg.dev(), pg.kz, col, nullptr, S.st.p, 1, nullptr);
+        });
+        return;
+    }
+    // one timing family per kernel instantiation: the uniform-coefficient
+    // colour pass and the general one
+    timed_mg(ctx, S, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb", pp, sizeof(T) == 4, 0, 1.0, [&] {
+        if (p25.nd && S.aligned && p25.uni)
+            k_st25<T, 0, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1,
+                                                                       nullptr);
+        else if (p25.nd && S.aligned)
             k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1, nullptr);
         else
             k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
@@ -1926,7 +2120,7 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
 template <typename T>
 static void sweep_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int flip) {
     const HPlan &p25 = S.pre25[l];
-    timed_mg(ctx, S, "gsrb", S.pre[l], sizeof(T) == 4, 6, 1.0, [&] {
+    timed_mg(ctx, S, "sweep", S.pre[l], sizeof(T) == 4, 6, 1.0, [&] {
         k_sweep25<T><<<xcd_grid(p25.ntiles), kBlock, 0, ctx->stream>>>(dT, p25.dev(), p25.kz, flip, S.st.p);
     });
 }
@@ -1998,9 +2192,15 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
     if (mode != 0 && S.all0_25.nd && S.aligned) {
         const HPlan &p25 = S.all0_25;
         timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {
-            if (mode == 1)
+            if (mode == 1 && p25.uni)
+                k_st25<double, 1, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                                                                                S.partials.p, S.st.p, check_active, pb);
+            else if (mode == 1)
                 k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
                                                                           S.partials.p, S.st.p, check_active, pb);
+            else if (p25.uni)
+                k_st25<double, 2, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                                                                                S.partials.p, S.st.p, check_active, pb);
             else
                 k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
                                                                           S.partials.p, S.st.p, check_active, pb);
@@ -2141,9 +2341,14 @@ static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vec
                     if (fused)
                         k_sweep25<T><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, cand.dev(), cand.kz, 0, S.st.p);
                     else
-                        for (int col = 0; col < 2; col++)
-                            k_st25<T, 0><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz, col,
+                        for (int col = 0; col < 2; col++) {
+                            if (S.pre25[l].uni)
+                                k_st25<T, 0, true><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz,
+                                                                                         col, nullptr, S.st.p, 1, nullptr);
+                            else
+                                k_st25<T, 0><<<xcd_grid(cand.ntiles), kBlock, 0, s>>>(dT, nullptr, cand.dev(), cand.kz, col,
                                                                                    nullptr, S.st.p, 1, nullptr);
+                        }
                 };
                 pass();   // warm
                 VD_HIP(hipEventRecord(e0, s));
@@ -2155,7 +2360,12 @@ static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vec
                 VD_HIP(hipEventElapsedTime(&ms, e0, e1));
                 if (ms < best * 0.97f) { best = ms; best_kz = kz; best_fused = fused; }
             }
-        if (best_kz != S.pre25[l].kz) build_plan25(ctx, S.pre25[l], items, best_kz);
+        if (best_kz != S.pre25[l].kz) {
+            const bool uni = S.pre25[l].uni;
+            build_plan25(ctx, S.pre25[l], items, best_kz);
+            S.pre25[l].uni = uni;
+            split25(ctx, S, l);
+        }
         S.use_fused[l] = best_fused;
         if (!best_fused) {
             VD_HIP(hipStreamSynchronize(s));

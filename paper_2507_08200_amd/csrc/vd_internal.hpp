@@ -382,6 +382,30 @@ __device__ __forceinline__ void row_terms_uni(const LevDesc &L, int i, int j, in
     off = of;
 }
 
+// Same row with the six face coefficients and the diagonal coefficient
+// already loaded (no mask): cf_f = fc[f] / h^2; lift (finest level) from the
+// same faces.
+template <typename T>
+__device__ __forceinline__ void row_terms_fc(const LevDesc &L, int i, int j, int k, const T nbv[6], const T fc[6], T alpha,
+                                             T &diag, T &off, double &lift) {
+    T dg = alpha;
+    T of = 0;
+    double lf = 0.0;
+    const bool inside[6] = {i > 0, i < L.nx - 1, j > 0, j < L.ny - 1, k > 0, k < L.nz - 1};
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        const double ih2 = f < 2 ? L.idx2 : (f < 4 ? L.idy2 : L.idz2);
+        const T cf = fc[f] * (T)ih2;
+        const int kd = f == 0 ? L.kind[0] : f == 1 ? L.kind[1] : f == 2 ? L.kind[2] : f == 3 ? L.kind[3] : f == 4 ? L.kind[4] : L.kind[5];
+        const double g = f == 0 ? L.gval[0] : f == 1 ? L.gval[1] : f == 2 ? L.gval[2] : f == 3 ? L.gval[3] : f == 4 ? L.gval[4] : L.gval[5];
+        if (inside[f] || kd == VD_BC_PERIODIC) { dg += cf; of += cf * nbv[f]; }
+        else if (kd == VD_BC_DIRICHLET) { dg += (T)2 * cf; lf += 2.0 * (double)fc[f] * g * ih2; }
+    }
+    diag = dg;
+    off = of;
+    lift = lf;
+}
+
 // Dirichlet lifting of a uniform-coefficient finest level (no loads)
 __device__ __forceinline__ double lift_term_uni(const LevDesc &L, int i, int j, int k) {
     double v = 0.0;
