@@ -74,6 +74,45 @@ __device__ __forceinline__ void restrict_cell(const LevDesc &F, const LevDesc &C
     gst((T *)C.x, cc, (T)0);
 }
 
+// residual of a uniform-coefficient level (no mask) at (i, j, k): the six
+// neighbours are loaded from wrapped or clamped indices without branches
+// (an out-of-domain neighbour is ignored by the row), so all loads of a
+// coarse cell's eight children can be in flight together
+template <typename T>
+__device__ __forceinline__ T residual_uni(const LevDesc &F, const T *__restrict__ x, int i, int j, int k) {
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const long nxy = F.nxy;
+    auto w = [](int p, int n, bool per) { return p < 0 ? (per ? p + n : 0) : (p >= n ? (per ? p - n : n - 1) : p); };
+    const bool px = F.kind[0] == VD_BC_PERIODIC, py = F.kind[2] == VD_BC_PERIODIC, pz = F.kind[4] == VD_BC_PERIODIC;
+    const long row = (long)nx * j + nxy * k;
+    T nb[6];
+    nb[0] = gld(x, row + w(i - 1, nx, px));
+    nb[1] = gld(x, row + w(i + 1, nx, px));
+    nb[2] = gld(x, i + (long)nx * w(j - 1, ny, py) + nxy * k);
+    nb[3] = gld(x, i + (long)nx * w(j + 1, ny, py) + nxy * k);
+    nb[4] = gld(x, i + (long)nx * j + nxy * w(k - 1, nz, pz));
+    nb[5] = gld(x, i + (long)nx * j + nxy * w(k + 1, nz, pz));
+    const T xc = gld(x, row + i);
+    T bv = gld((const T *)F.b, row + i);
+    T dg, of;
+    row_terms_uni<T>(F, i, j, k, nb, dg, of);
+    if (F.lift) bv = (T)((double)bv + lift_term_uni(F, i, j, k));
+    return bv - (dg * xc - of);
+}
+
+template <typename T>
+__device__ __forceinline__ void restrict_cell_uni(const LevDesc &F, const LevDesc &C, int cc, int I, int J, int K) {
+    const T *x = (const T *)F.x;
+    T r[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) r[q] = residual_uni<T>(F, x, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2));
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) s += r[q];
+    gst((T *)C.b, cc, (T)0.125 * s);
+    gst((T *)C.x, cc, (T)0);
+}
+
 template <typename T>
 __device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C, int c, int i, int j, int k) {
     if (F.has_mask && !gld(F.mask, c)) return;
@@ -126,12 +165,14 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__
         if (!gld(&st[C.prob].active, 0)) return;
         LevDesc F = descs[id - 1];
         if (flip) F.x = F.x2;      // the fine iterate is in the alternate buffer
+        const bool uni = !F.var_beta && !F.var_alpha && !F.has_mask;
         for (int u = 0; u < kRestrictU; u++) {
             int cc = (lt * kRestrictU + u) * kBlock + threadIdx.x;
             if (cc >= C.ncell) break;
             int I, J, K;
             cell_ijk(C, cc, I, J, K);
-            restrict_cell<T>(F, C, cc, I, J, K);
+            if (uni) restrict_cell_uni<T>(F, C, cc, I, J, K);
+            else restrict_cell<T>(F, C, cc, I, J, K);
         }
     });
 }
@@ -332,6 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const LevDesc L = descs[id];
     if ((MODE == 0 || check_active) && !gld(&st[L.prob].active, 0)) return;
     int lt = t - pl.prefix[d];
+    const int slot = pl.gbase ? pl.gbase[d] + lt : t;    // partial slot of this tile
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int ntx = (nx + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
     const int tx = lt % ntx;
@@ -522,10 +564,10 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     }
     if (MODE != 0) {
         const double sum = block_sum(v, red);
-        if (tid == 0) gst(partials, t, sum);
+        if (tid == 0) gst(partials, slot, sum);
         if (partials_b) {
             const double sb = block_sum(vb, red);
-            if (tid == 0) gst(partials_b, t, sb);
+            if (tid == 0) gst(partials_b, slot, sb);
         }
     }
 }
@@ -1555,7 +1597,8 @@ struct HPlan {
     int kz = 0;                  // 2.5D tiled plans: planes per workgroup
     bool uni = false;            // every problem in the plan has uniform coefficients and no mask
     std::vector<int> h_ids, h_prefix;
-    Plan dev() const { return Plan{ids.p, prefix.p, nd, ntiles}; }
+    DevBuf<int> gbase;           // split norm plans: first partial slot of each descriptor in the full plan
+    Plan dev() const { return Plan{ids.p, prefix.p, nd, ntiles, gbase.p}; }
 };
 
 struct Solver {
@@ -1577,6 +1620,7 @@ struct Solver {
     std::vector<HPlan> pre, restr, prolong;      // per level
     HPlan all0_25;                               // finest level as 2.5D tiles (residual norms), if usable
     std::vector<HPlan> pre25;                    // smoother levels as 2.5D tiles, if usable
+    HPlan norm25u, norm25g;                      // all0_25 split the same way (partials keep the full plan's slots)
     std::vector<HPlan> pre25u, pre25g;           // the same split into uniform-coefficient and other problems
                                                  // (built only when a level mixes both)
     std::vector<char> key;                       // problem bytes the descriptors were built from
@@ -1934,6 +1978,28 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
     S->pre25u.resize(Lmax);
     S->pre25g.resize(Lmax);
     for (int l = 0; l < Lmax; l++) split25(ctx, *S, l);
+    if (S->all0_25.nd && !S->all0_25.uni) {
+        // finest-level residual norms split like the smoother; item p of
+        // the full plan is problem p
+        std::vector<std::pair<int, const HLevel *>> u, g;
+        std::vector<int> gu, gg;
+        for (int p = 0; p < nprob; p++) {
+            const HProblem &H = S->probs[p];
+            const bool uni = !H.var_beta && !H.var_alpha && !H.has_mask;
+            (uni ? u : g).push_back({p * Lmax, &H.lv[0]});
+            (uni ? gu : gg).push_back(S->all0_25.h_prefix[p]);
+        }
+        if (!u.empty() && !g.empty()) {
+            build_plan25(ctx, S->norm25u, u, S->all0_25.kz);
+            build_plan25(ctx, S->norm25g, g, S->all0_25.kz);
+            S->norm25u.uni = true;
+            for (auto *pr : {&S->norm25u, &S->norm25g}) {
+                const std::vector<int> &gb = pr == &S->norm25u ? gu : gg;
+                pr->gbase.alloc(gb.size());
+                VD_HIP(hipMemcpyAsync(pr->gbase.p, gb.data(), sizeof(int) * gb.size(), hipMemcpyHostToDevice, ctx->stream));
+            }
+        }
+    }
     upload_plan(S->all0, ctx->stream);
     for (int l = 0; l < Lmax; l++) {
         upload_plan(S->pre[l], ctx->stream);
@@ -2189,6 +2255,27 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
     double *pb = with_b ? S.partials_b.p : nullptr;
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
+    auto launch25 = [&](const HPlan &q, bool uni) {
+        if (mode == 1 && uni)
+            k_st25<double, 1, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p,
+                                                                          S.st.p, check_active, pb);
+        else if (mode == 1)
+            k_st25<double, 1><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
+                                                                    check_active, pb);
+        else if (uni)
+            k_st25<double, 2, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p,
+                                                                          S.st.p, check_active, pb);
+        else
+            k_st25<double, 2><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
+                                                                    check_active, pb);
+    };
+    if (mode != 0 && S.aligned && S.norm25u.nd && S.norm25g.nd) {
+        // mixed batch: uniform problems in the lean kernel; partial slots
+        // stay those of the full plan
+        timed_mg(ctx, S, "norm", S.norm25u, false, 3 + mode, 1.0, [&] { launch25(S.norm25u, true); });
+        timed_mg(ctx, S, "norm", S.norm25g, false, 3 + mode, 1.0, [&] { launch25(S.norm25g, false); });
+        return;
+    }
     if (mode != 0 && S.all0_25.nd && S.aligned) {
         const HPlan &p25 = S.all0_25;
         timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {

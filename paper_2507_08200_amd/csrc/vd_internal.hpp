@@ -101,6 +101,7 @@ struct Plan {
     const int *prefix;
     int nd;
     int ntiles;
+    const int *gbase;   // nullable: per descriptor, the first partial slot in the full plan (split norm launches)
 };
 
 constexpr int kBlock = 256;
