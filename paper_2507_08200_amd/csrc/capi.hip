@@ -27,12 +27,12 @@ bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *
     return true;
 }
 
-void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units) {
+void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units, int nlaunch) {
     Timing &T = ctx->timing;
     T.pending.push_back(TimingPending{family, ev0, ev1});
     TimingAcc &A = T.acc[family];
     A.units += units;
-    A.launches += 1;
+    A.launches += nlaunch;
     if (T.pending.size() >= 8192) timing_flush(ctx);
 }
 

@@ -261,6 +261,14 @@ __global__ void __launch_bounds__(kBlock) k_prep(const LevDesc *__restrict__ d64
     });
 }
 
+// x = 0 on the problems whose ||b|| is 0, once ||b|| is known: one
+// workgroup per problem, which returns at once in the common case
+__global__ void __launch_bounds__(kBlock) k_zero_b0(const LevDesc *__restrict__ d64, Plan pl, const ProbState *__restrict__ st) {
+    const LevDesc &L = d64[pl.ids[blockIdx.x]];
+    if (gld(&st[L.prob].bnorm, 0) != 0.0) return;
+    for (long c = threadIdx.x; c < L.ncell; c += blockDim.x) gst((double *)L.x, c, 0.0);
+}
+
 // x64 += e32 after the inner FP32 cycles of an outer refinement step.
 __global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict__ d64, const LevDesc *__restrict__ d32,
                                                       Plan pl, const ProbState *__restrict__ st) {
@@ -2194,14 +2202,22 @@ static void sweep_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int fli
 // nu smoothing sweeps of level l; par tracks which buffer holds the iterate
 template <typename T>
 static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int nu, int &par) {
-    if (S.pre25[l].nd && S.use_fused[l]) {
+    const HPlan &p25 = S.pre25[l];
+    if (p25.nd && S.use_fused[l]) {
+        timing_group_begin(ctx, "sweep");
         for (int q = 0; q < nu; q++) {
             sweep_pass<T>(ctx, S, l, dT, par);
             par ^= 1;
         }
+        timing_group_end(ctx);
     } else {
+        // the colour passes of one level are back-to-back launches of one
+        // kernel (unless the level is split): one event pair around them
+        const bool split = S.aligned && S.pre25u[l].nd && S.pre25g[l].nd;
+        if (!split) timing_group_begin(ctx, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb");
         for (int q = 0; q < nu; q++)
             for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
+        if (!split) timing_group_end(ctx);
     }
 }
 
@@ -2579,7 +2595,7 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
         launch_finalize(ctx, *S, first ? 3 : 1, o, inner);
         if (first)
             timed(ctx, "prep", 0.0, [&] {
-                k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 0, 1);
+                k_zero_b0<<<S->all0.nd, kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p);
             });
     };
     while (true) {

@@ -150,6 +150,11 @@ struct Timing {
     std::map<std::string, TimingAcc> acc;
     std::vector<TimingPending> pending;
     std::vector<hipEvent_t> pool;
+    // an open group: consecutive launches of one family bracketed by a
+    // single event pair (fewer events between back-to-back kernels)
+    std::string group;
+    int group_n = 0;
+    hipEvent_t ga = nullptr, gb = nullptr;
 };
 
 }  // namespace vd
@@ -201,13 +206,20 @@ inline const void *upload_blob(vd_ctx *ctx, const std::string &key, const void *
 bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *ev1);
 void timing_flush(vd_ctx *ctx);
 
-void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units);
+void timing_end(vd_ctx *ctx, const char *family, hipEvent_t ev0, hipEvent_t ev1, double units, int nlaunch = 1);
 // algorithmic bytes credited to a family after the launches (work that is
 // known only once the device-side convergence state has been read)
 void timing_add_units(vd_ctx *ctx, const char *family, double units);
 
 template <typename F>
 inline void timed(vd_ctx *ctx, const char *family, double units, F &&launch) {
+    Timing &T = ctx->timing;
+    if (!T.group.empty() && T.group == family) {     // inside an open group of this family
+        launch();
+        VD_HIP(hipGetLastError());
+        T.group_n += 1;
+        return;
+    }
     hipEvent_t a = nullptr, b = nullptr;
     bool on = !ctx->timing.families.empty() && timing_begin(ctx, family, &a, &b);
     if (on) VD_HIP(hipEventRecord(a, ctx->stream));
@@ -217,6 +229,28 @@ inline void timed(vd_ctx *ctx, const char *family, double units, F &&launch) {
         VD_HIP(hipEventRecord(b, ctx->stream));
         timing_end(ctx, family, a, b, units);
     }
+}
+
+// open / close a group of consecutive launches of one selected family
+inline void timing_group_begin(vd_ctx *ctx, const char *family) {
+    Timing &T = ctx->timing;
+    if (T.families.empty() || !T.group.empty()) return;
+    hipEvent_t a, b;
+    if (!timing_begin(ctx, family, &a, &b)) return;
+    VD_HIP(hipEventRecord(a, ctx->stream));
+    T.group = family;
+    T.group_n = 0;
+    T.ga = a;
+    T.gb = b;
+}
+
+inline void timing_group_end(vd_ctx *ctx) {
+    Timing &T = ctx->timing;
+    if (T.group.empty()) return;
+    VD_HIP(hipEventRecord(T.gb, ctx->stream));
+    const std::string f = T.group;
+    T.group.clear();
+    timing_end(ctx, f.c_str(), T.ga, T.gb, 0.0, T.group_n);
 }
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
