@@ -59,6 +59,26 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(family):
+    """HBM bytes per launch of the kernel family from the committed
+    rocprofv3 counter summary, while the kernel source it was taken from is
+    unchanged (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_hbm_traffic_arh2_160.txt" % family)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2507_08200_amd", "csrc", "mg.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def learned_guess(ctx, V, I, cfg, rho, args):
     """Poisson time-to-1e-10 from the network's guess (inference included),
     FP64 and FP32-refined, on the benchmark's own streamer state (a voltage
@@ -216,7 +236,7 @@ def main():
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
     roofline = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
                 "launches": launches, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": round(kbytes / launches) if launches else 0}
 

@@ -337,6 +337,272 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
     }
 }
 
+// ------------------------------------------- 2.5D LDS-staged WENO5 divergence
+// A workgroup owns a 32 x 8 tile of x-y planes of one field and marches kz
+// planes in z.  Per plane, the field (with a three-cell ring of ghost values:
+// mirror, odd reflection or wrap, as u_at), phi and the mobility (one-cell
+// rings) are staged in LDS from loads issued a plane ahead into registers;
+// the z stencil of each thread's column lives in registers.  Every face
+// flux is then arithmetic on staged values: domain faces are resolved by
+// selects (a Neumann or wall face carries no drift flux here; the wall
+// fluxes are added to the boundary cells by k_wall_div).  No global load
+// sits in a branch, so the look-ahead loads overlap the face computations.
+constexpr int kDX = 32, kDY = 8;
+constexpr int kUX = kDX + 6, kUY = kDY + 6;          // field tile, ring 3
+constexpr int kPX = kDX + 2, kPY = kDY + 2;          // phi / mobility tiles, ring 1
+constexpr int kUN = kUX * kUY, kPN = kPX * kPY;
+constexpr int kUPer = (kUN + kBlock - 1) / kBlock;   // 3
+constexpr int kPPer = (kPN + kBlock - 1) / kBlock;   // 2
+
+// ghost-mapped row position of the field along a direction: index of the
+// cell to read and whether the value is reflected about g (Dirichlet)
+__device__ __forceinline__ int ghost_pos(int p, int n, int klo, int khi, bool &odd, bool &hi_side) {
+    const bool lo = p < 0, hi = p >= n;
+    const int kd = lo ? klo : khi;
+    const bool per = kd == VD_BC_PERIODIC;
+    int q = lo ? (per ? p + n : -1 - p) : (hi ? (per ? p - n : 2 * n - 1 - p) : p);
+    q = q < 0 ? 0 : (q >= n ? n - 1 : q);
+    odd = (lo || hi) && kd == VD_BC_DIRICHLET;
+    hi_side = hi;
+    return q;
+}
+
+__device__ __forceinline__ int wrapc(int p, int n, bool per) {
+    int q = per ? (p < 0 ? p + n : (p >= n ? p - n : p)) : p;
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+// drift flux of one face from staged values: w the six stencil values
+// (positions -3..+2 around the face), phi / mobility of the two cells.
+// lo / hi mark a domain face; kf the field kind there, kp / gp phi's.
+__device__ __forceinline__ double drift_face(const FieldDesc &F, double w0, double w1, double w2, double w3, double w4,
+                                             double w5, double phl, double phr, double mul, double mur, double ih, bool lo,
+                                             bool hi, int kf, int kp, double gp) {
+    double Ef = -(phr - phl) * ih;
+    const bool per = kp == VD_BC_PERIODIC;
+    if ((lo || hi) && !per) Ef = kp == VD_BC_DIRICHLET ? (lo ? -(phr - gp) * (2.0 * ih) : -(gp - phl) * (2.0 * ih)) : 0.0;
+    double muf = F.mu ? 0.5 * (mul + mur) : F.mu_c;
+    if (F.mu && (lo || hi) && kf != VD_BC_PERIODIC) muf = lo ? mur : mul;
+    const double v = muf * F.mu_scale * Ef;
+    const bool up = v > 0.0;
+    const double fl = v * weno5(up ? w0 : w5, up ? w1 : w4, up ? w2 : w3, up ? w3 : w2, up ? w4 : w1);
+    const bool none = (lo || hi) && (kf == VD_BC_NEUMANN || kf == VD_BC_WALLFLUX);
+    return none ? 0.0 : fl;
+}
+
+__global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
+    __shared__ double U[kUN], P[kPN], M[kPN];
+    __shared__ double fx[kDY * (kDX + 1)];
+    __shared__ double fy[(kDY + 1) * kDX];
+    const GridDev &G = a.g;
+    const FieldDesc F = a.f[blockIdx.y];
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int tiles_x = nx / kDX, tiles_y = ny / kDY;
+    int b = blockIdx.x;
+    const int bx = b % tiles_x;
+    b /= tiles_x;
+    const int by = b % tiles_y;
+    const int bz = b / tiles_y;
+    const int tid = threadIdx.x;
+    const int tx = tid & (kDX - 1), ty = tid / kDX;
+    const int i0 = bx * kDX, j0 = by * kDY, k0 = bz * kz;
+    const int i = i0 + tx, j = j0 + ty;
+    const long nxy = G.nxy;
+    const long col = i + (long)nx * j;
+    const bool drift = F.mu || F.mu_c != 0.0;
+    const double *__restrict__ u = F.u;
+    const double *__restrict__ mup = F.mu ? F.mu : F.u;      // valid address when the mobility is constant
+    const double *__restrict__ phi = a.phi;
+    // per-thread x-y parts of the staged loads (plane-invariant)
+    long uo[kUPer], po[kPPer];
+    bool uodd[kUPer], uhi[kUPer];
+    int ud[kUPer];                                   // direction whose ghost rule applies (0 x, 1 y, -1 none)
+#pragma unroll
+    for (int m = 0; m < kUPer; m++) {
+        const int e = min(tid + m * kBlock, kUN - 1);
+        const int ri = e % kUX, rj = e / kUX;
+        const int gi = i0 - 3 + ri, gj = j0 - 3 + rj;
+        bool oi, hi_i, oj, hi_j;
+        const int qi = ghost_pos(gi, nx, F.kind[0], F.kind[1], oi, hi_i);
+        const int qj = ghost_pos(gj, ny, F.kind[2], F.kind[3], oj, hi_j);
+        uo[m] = qi + (long)nx * qj;
+        // corner ghosts are never read by a face stencil; an x ghost takes
+        // the x rule, a y ghost the y rule
+        ud[m] = (gi < 0 || gi >= nx) ? 0 : ((gj < 0 || gj >= ny) ? 1 : -1);
+        uodd[m] = ud[m] == 0 ? oi : (ud[m] == 1 ? oj : false);
+        uhi[m] = ud[m] == 0 ? hi_i : hi_j;
+    }
+    // phi's ring wraps by phi's boundary kinds, the mobility's by the field's
+    const bool pxp = G.phi_kind[0] == VD_BC_PERIODIC, pyp = G.phi_kind[2] == VD_BC_PERIODIC;
+    const bool fxp = F.kind[0] == VD_BC_PERIODIC, fyp = F.kind[2] == VD_BC_PERIODIC;
+    long mo[kPPer];
+#pragma unroll
+    for (int m = 0; m < kPPer; m++) {
+        const int e = min(tid + m * kBlock, kPN - 1);
+        const int ri = e % kPX, rj = e / kPX;
+        po[m] = wrapc(i0 - 1 + ri, nx, pxp) + (long)nx * wrapc(j0 - 1 + rj, ny, pyp);
+        mo[m] = wrapc(i0 - 1 + ri, nx, fxp) + (long)nx * wrapc(j0 - 1 + rj, ny, fyp);
+    }
+    const double gu_xlo = F.gval[0], gu_xhi = F.gval[1], gu_ylo = F.gval[2], gu_yhi = F.gval[3];
+    double gsel[kUPer];
+#pragma unroll
+    for (int m = 0; m < kUPer; m++) gsel[m] = ud[m] == 0 ? (uhi[m] ? gu_xhi : gu_xlo) : (uhi[m] ? gu_yhi : gu_ylo);
+    // staged tile values of one plane (registers) and their LDS store
+#define VD_STAGE(K, US0, US1, US2, PS0, PS1, MS0, MS1)                                      \
+    {                                                                                       \
+        const long pl_ = nxy * min(max((K), 0), nz - 1);                                    \
+        double v_;                                                                          \
+        v_ = gld(u, uo[0] + pl_); US0 = uodd[0] ? 2.0 * gsel[0] - v_ : v_;                  \
+        v_ = gld(u, uo[1] + pl_); US1 = uodd[1] ? 2.0 * gsel[1] - v_ : v_;                  \
+        v_ = gld(u, uo[2] + pl_); US2 = uodd[2] ? 2.0 * gsel[2] - v_ : v_;                  \
+        PS0 = gld(phi, po[0] + pl_); PS1 = gld(phi, po[1] + pl_);                           \
+        MS0 = gld(mup, mo[0] + pl_); MS1 = gld(mup, mo[1] + pl_);                           \
+    }
+    static_assert(kUPer == 3 && kPPer == 2, "staging is written for 3 + 2 values per thread");
+    // z column of this thread: field at planes k-3..k+3 (ghost rule in z),
+    // phi and mobility at planes k-1..k+1
+    bool zodd;
+    bool zhi;
+    auto zu = [&](int k) -> double {
+        const int q = ghost_pos(k, nz, F.kind[4], F.kind[5], zodd, zhi);
+        const double v = gld(u, col + nxy * q);
+        return zodd ? 2.0 * (zhi ? F.gval[5] : F.gval[4]) - v : v;
+    };
+    const bool pzp = G.phi_kind[4] == VD_BC_PERIODIC, fzp = F.kind[4] == VD_BC_PERIODIC;
+    auto zp = [&](int k) -> double { return gld(phi, col + nxy * wrapc(k, nz, pzp)); };
+    auto zm = [&](int k) -> double { return gld(mup, col + nxy * wrapc(k, nz, fzp)); };
+    const double ihx = G.ih[0], ihy = G.ih[1], ihz = G.ih[2];
+    // the z face above plane k from the column registers
+    // column registers: z1..z6 = field at planes k-2 .. k+3
+    double z1, z2, z3, z4, z5, z6;
+    auto zface = [&](double ph0, double ph1, double mu0, double mu1, int k) -> double {
+        const bool lo = (k + 1) == 0, hi = (k + 1) == nz;
+        const int kf = lo ? F.kind[4] : F.kind[5];
+        const int kp = lo ? G.phi_kind[4] : G.phi_kind[5];
+        const double gp = lo ? G.phi_val[4] : G.phi_val[5];
+        return drift_face(F, z1, z2, z3, z4, z5, z6, ph0, ph1, mu0, mu1, ihz, lo, hi, kf, kp, gp);
+    };
+    double ph_m = zp(k0 - 1), ph_c = zp(k0), ph_p = zp(k0 + 1);
+    double mu_m = zm(k0 - 1), mu_c = zm(k0), mu_p = zm(k0 + 1);
+    // flux below plane k0: face k0-1/2, stencil planes k0-3 .. k0+2
+    double fz_lo;
+    {
+        const double a3 = zu(k0 - 3), a2 = zu(k0 - 2), a1 = zu(k0 - 1), b0 = zu(k0), b1 = zu(k0 + 1), b2 = zu(k0 + 2);
+        fz_lo = drift_face(F, a3, a2, a1, b0, b1, b2, ph_m, ph_c, mu_m, mu_c, ihz, k0 == 0, false, F.kind[4], G.phi_kind[4],
+                           G.phi_val[4]);
+        if (!drift) fz_lo = 0.0;
+        z1 = a2; z2 = a1; z3 = b0; z4 = b1; z5 = b2;
+        z6 = zu(k0 + 3);
+    }
+    double us0, us1, us2, ps0, ps1, ms0, ms1;
+    VD_STAGE(k0, us0, us1, us2, ps0, ps1, ms0, ms1);
+    double u0v = 0.0, srcv = 0.0, exv = 0.0;
+    const double *__restrict__ u0p = F.u0 ? F.u0 : u;
+    const double *__restrict__ srcp = F.src ? F.src : u;
+    const double *__restrict__ exp_ = F.extra ? F.extra : u;
+    for (int k = k0; k < k0 + kz; k++) {
+        lst(U, tid, us0);
+        lst(U, tid + kBlock, us1);
+        if (tid + 2 * kBlock < kUN) lst(U, tid + 2 * kBlock, us2);
+        lst(P, tid, ps0);
+        lst(M, tid, ms0);
+        if (tid + kBlock < kPN) { lst(P, tid + kBlock, ps1); lst(M, tid + kBlock, ms1); }
+        // look-ahead loads: next plane's tiles, the column's next values,
+        // this plane's right-hand-side inputs
+        double nus0, nus1, nus2, nps0, nps1, nms0, nms1;
+        VD_STAGE(k + 1, nus0, nus1, nus2, nps0, nps1, nms0, nms1);
+        const double cnext = zu(k + 4);
+        const double ph_n = zp(k + 2), mu_n = zm(k + 2);
+        const long c = col + nxy * k;
+        u0v = gld(u0p, c);
+        srcv = gld(srcp, c);
+        exv = gld(exp_, c);
+        __syncthreads();
+        // x faces (tile rows 0..7, faces 0..32) and y faces (rows 0..8)
+        for (int q = tid; q < kDY * (kDX + 1); q += kBlock) {
+            const int r = q / (kDX + 1), f = q - r * (kDX + 1);
+            const int gi = i0 + f;                       // face between cells gi-1 and gi
+            const int ub = (r + 3) * kUX + f;            // U index of cell gi-3 in this row
+            const int pb = (r + 1) * kPX + f;            // P index of cell gi-1
+            const bool lo = gi == 0, hi = gi == nx;
+            const int kf = lo ? F.kind[0] : F.kind[1];
+            const int kp = lo ? G.phi_kind[0] : G.phi_kind[1];
+            const double gp = lo ? G.phi_val[0] : G.phi_val[1];
+            const double fl = drift_face(F, lld(U, ub), lld(U, ub + 1), lld(U, ub + 2), lld(U, ub + 3), lld(U, ub + 4),
+                                         lld(U, ub + 5), lld(P, pb), lld(P, pb + 1), lld(M, pb), lld(M, pb + 1), ihx, lo, hi, kf,
+                                         kp, gp);
+            lst(fx, q, drift ? fl : 0.0);
+        }
+        for (int q = tid; q < (kDY + 1) * kDX; q += kBlock) {
+            const int r = q / kDX, f = q - r * kDX;
+            const int gj = j0 + r;                       // face between rows gj-1 and gj
+            const int ub = r * kUX + f + 3;              // U index of row gj-3 in this column
+            const int pb = r * kPX + f + 1;              // P index of row gj-1
+            const bool lo = gj == 0, hi = gj == ny;
+            const int kf = lo ? F.kind[2] : F.kind[3];
+            const int kp = lo ? G.phi_kind[2] : G.phi_kind[3];
+            const double gp = lo ? G.phi_val[2] : G.phi_val[3];
+            const double fl = drift_face(F, lld(U, ub), lld(U, ub + kUX), lld(U, ub + 2 * kUX), lld(U, ub + 3 * kUX),
+                                         lld(U, ub + 4 * kUX), lld(U, ub + 5 * kUX), lld(P, pb), lld(P, pb + kPX), lld(M, pb),
+                                         lld(M, pb + kPX), ihy, lo, hi, kf, kp, gp);
+            lst(fy, q, drift ? fl : 0.0);
+        }
+        const double fz_hi = drift ? zface(ph_c, ph_p, mu_c, mu_p, k) : 0.0;
+        __syncthreads();
+        const double div = (lld(fx, ty * (kDX + 1) + tx + 1) - lld(fx, ty * (kDX + 1) + tx)) * G.ihl[0] +
+                           (lld(fy, (ty + 1) * kDX + tx) - lld(fy, ty * kDX + tx)) * G.ihl[1] + (fz_hi - fz_lo) * G.ihl[2];
+        if (a.mode == 0) {
+            gst(F.out, c, div);
+        } else {
+            double v = u0v * a.inv_dt - div;
+            if (F.src) v += srcv;
+            if (F.extra) v += exv;
+            gst(F.out, c, v);
+        }
+        fz_lo = fz_hi;
+        z1 = z2; z2 = z3; z3 = z4; z4 = z5; z5 = z6; z6 = cnext;
+        ph_m = ph_c; ph_c = ph_p; ph_p = ph_n;
+        mu_m = mu_c; mu_c = mu_p; mu_p = mu_n;
+        us0 = nus0; us1 = nus1; us2 = nus2;
+        ps0 = nps0; ps1 = nps1; ms0 = nms0; ms1 = nms1;
+    }
+#undef VD_STAGE
+}
+
+// Wall fluxes (Eqs. (13)-(15)) of the WALLFLUX domain faces along direction
+// d, added to the boundary cells' divergence after k_drift25 (mode 0: out +=
+// contribution; mode 1: out -= it).  One thread per boundary line handles
+// both ends, so no cell is updated twice in a launch.
+__global__ void __launch_bounds__(kBlock) k_wall_div(DriftArgs a, int d) {
+    const GridDev &G = a.g;
+    const FieldDesc F = a.f[blockIdx.y];
+    const int n = G.n[d];
+    const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+    const int na = G.n[da], nb = G.n[db];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= na * nb) return;
+    const int pa = t % na, pb = t / na;
+    long base = (long)pa * G.stride[da] + (long)pb * G.stride[db];
+    for (int side = 0; side < 2; side++) {
+        const int kd = side == 0 ? (d == 0 ? F.kind[0] : d == 1 ? F.kind[2] : F.kind[4])
+                                 : (d == 0 ? F.kind[1] : d == 1 ? F.kind[3] : F.kind[5]);
+        if (kd != VD_BC_WALLFLUX) continue;
+        const long cb = base + (side == 0 ? 0 : (long)(n - 1) * G.stride[d]);
+        const double Ef = e_face(G, a.phi, d, (int)base, 0, side == 0 ? 0 : n);
+        const double e_n = side == 0 ? -Ef : Ef;
+        double fl;
+        if (F.ne_wall)
+            fl = 2.0 * a.kB * gld(a.Te, cb) *
+                 wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, cb), 0.0, e_n, gld(a.Te, cb), a.Tg, a.me, a.kB, a.me);
+        else
+            fl = wall_flux(F.wall, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(a.Te, cb), a.Tg, F.mass, a.kB, a.me);
+        // flux along +d through the face, and its share of the cell's divergence
+        const double Fs = side == 0 ? -fl : fl;
+        const double contrib = (side == 0 ? -Fs : Fs) * G.ihl[d];
+        gst(F.out, cb, gld(F.out, cb) + (a.mode == 0 ? contrib : -contrib));
+    }
+}
+
 // blockIdx.y = field.  mode 0: out = div.  mode 1 (species / energy
 // right-hand side of the implicit solve): out = u0/dt - div + src + extra.
 __global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
@@ -635,7 +901,21 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
     }
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
     const int kz = (nz % 16 == 0) ? 16 : ((nz % 8 == 0) ? 8 : 0);
-    if (nx % kTX == 0 && ny % kTY == 0 && kz > 0) {
+    if (nx % kDX == 0 && ny % kDY == 0 && kz > 0 && nx >= 3 && ny >= 3 && nz >= 3) {
+        dim3 tg((nx / kDX) * (ny / kDY) * (nz / kz), nfields);
+        timed(ctx, "weno", bytes, [&] {
+            k_drift25<<<tg, kBlock, 0, ctx->stream>>>(a, kz);
+            // wall fluxes of the boundary cells, one direction per launch
+            bool any[3] = {false, false, false};
+            for (int f = 0; f < nfields; f++)
+                for (int s2 = 0; s2 < 6; s2++) any[s2 / 2] = any[s2 / 2] || fields[f].kind[s2] == VD_BC_WALLFLUX;
+            for (int d = 0; d < 3; d++) {
+                if (!any[d]) continue;
+                const long nl = (long)a.g.ncell / a.g.n[d];
+                k_wall_div<<<dim3(ceil_div(nl, kBlock), nfields), kBlock, 0, ctx->stream>>>(a, d);
+            }
+        });
+    } else if (nx % kTX == 0 && ny % kTY == 0 && kz > 0) {
         dim3 tg((nx / kTX) * (ny / kTY) * (nz / kz), nfields);
         timed(ctx, "weno", bytes, [&] { k_drift_tiled<<<tg, kBlock, 0, ctx->stream>>>(a, kz); });
     } else {
