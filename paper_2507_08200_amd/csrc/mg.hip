@@ -1010,9 +1010,30 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Sum over the 64 lanes of a wavefront (all lanes active), in every lane:
+// quad and row steps with DPP lane moves, then the four row sums read as
+// scalars.  No LDS round trips, unlike a shuffle tree.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x124>(v);   // row_ror 4
+    v += dpp_move<0x128>(v);   // row_ror 8: every lane holds its row's sum
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 template <typename T, int BAS>
@@ -1132,49 +1153,85 @@ __global__ void __launch_bounds__(kFusedThreads) k_coarse(const LevDesc *__restr
 
 // ------------------------------------------- LDS-resident coarse V-cycle
 // One workgroup per problem runs every level from lc down to the bottom
-// entirely out of LDS, then writes level lc's unknown back.  Each resident
-// level holds x, b and its assembled seven-point row (diagonal and six
-// neighbour weights, zero where the neighbour is absent), so a sweep is
-// branch-free LDS arithmetic; neighbour indices always wrap, an absent
-// neighbour having weight 0.  The rows are assembled once per solve by
+// entirely out of LDS, then writes level lc's unknown back.  A resident
+// level holds x and b; a level with variable coefficients or a mask also
+// holds its assembled seven-point row (diagonal and six neighbour weights,
+// zero where the neighbour is absent), assembled once per solve by
 // k_stencils from the same face logic as row_terms, in the hierarchy's
-// precision (the bottom CG also gets an FP64 copy in FP32 hierarchies).
-constexpr int kLdsThreads = 512;
+// precision (the bottom CG also gets an FP64 copy in FP32 hierarchies).  A
+// level with uniform coefficients and no mask forms its row on the fly from
+// the level descriptor (row_terms_uni), which leaves room for one more
+// level in LDS.  Neighbour indices always wrap; an absent neighbour has
+// weight 0.
+constexpr int kLdsThreads = 1024;
+constexpr int kPcgSlots = 2;     // register-resident bottom CG: up to 64 * kPcgSlots cells
 
 __host__ __device__ __forceinline__ size_t lds_al16(size_t b) { return (b + 15) & ~(size_t)15; }
-// bytes of one resident level: x, b, the row (diagonal then 6 weight
-// planes, contiguous as assembled), optional mask
-__host__ __device__ __forceinline__ size_t lds_level_bytes(long n, size_t sT, bool mask) {
-    return 2 * lds_al16((size_t)n * sT) + lds_al16((size_t)7 * n * sT) + (mask ? lds_al16((size_t)n) : 0);
+// bytes of one resident level: x (with a zero slot after the n cells), b,
+// then either the assembled row (diagonal then 6 weight planes, contiguous
+// as assembled) or the 64-entry diagonal and inverse-diagonal tables of a
+// uniform row, then the optional mask
+constexpr int kUniTab = 64;
+__host__ __device__ __forceinline__ size_t lds_level_bytes(long n, size_t sT, bool mask, bool rows) {
+    return lds_al16((size_t)(n + 1) * sT) + lds_al16((size_t)n * sT) +
+           (rows ? lds_al16((size_t)7 * n * sT) : lds_al16((size_t)2 * kUniTab * sT)) + (mask ? lds_al16((size_t)n) : 0);
 }
-// bytes of the bottom CG: r, z, p, q, x (+ FP64 row copy in FP32 hierarchies)
-__host__ __device__ __forceinline__ size_t lds_pcg_bytes(long nb, bool fp32) {
-    return 5 * lds_al16((size_t)nb * sizeof(double)) + (fp32 ? lds_al16((size_t)7 * nb * sizeof(double)) : 0);
+// bytes of the bottom CG: r, z, p, q, x (+ FP64 row copy in FP32 hierarchies
+// with assembled rows)
+__host__ __device__ __forceinline__ size_t lds_pcg_bytes(long nb, bool fp32_rows) {
+    return 5 * lds_al16((size_t)nb * sizeof(double)) + (fp32_rows ? lds_al16((size_t)7 * nb * sizeof(double)) : 0);
 }
 
 template <typename T>
 struct LLev {
-    T *x, *b, *dg, *w;        // w: 6 weight planes of n values
+    T *x, *b, *dg, *w;        // w: 6 weight planes of n values; dg null: uniform row
+    T *tab;                   // uniform row: diagonal, then its inverse, by the faces that join the sum
     const uint8_t *m;         // covered-cell mask in LDS (null: all valid)
     int nx, ny, nz, nxy, n;
+    int half;                 // n / 2 when held split by the parity of i (even nx), else 0
     float inx, inxy;
+    T a0, cx, cy, cz;         // uniform row: alpha and beta / h^2 per direction
+    int per, dir;             // uniform row: bit f set when face f is periodic / Dirichlet
 };
+
+// LDS slot of cell c.  A level with an even nx is held as two halves, the
+// cells of even i then those of odd i, so the unit-stride pair walks of the
+// colour passes touch consecutive slots (no bank conflicts).
+template <typename T>
+__device__ __forceinline__ int lslot(const LLev<T> &v, int c) {
+    return v.half ? (c >> 1) + (c & 1) * v.half : c;
+}
 
 template <typename T>
 __device__ __forceinline__ LLev<T> lds_lev(char *raw, const LevDesc *dT, int base, int lc, int l) {
     size_t off = 0;
-    for (int m = lc; m < l; m++) off += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask);
+    for (int m = lc; m < l; m++)
+        off += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask, dT[base + m].sten != nullptr);
     const LevDesc &D = dT[base + l];
     LLev<T> v;
-    const size_t a = lds_al16((size_t)D.ncell * sizeof(T));
+    const size_t ax = lds_al16((size_t)(D.ncell + 1) * sizeof(T)), a = lds_al16((size_t)D.ncell * sizeof(T));
+    const bool rows = D.sten != nullptr;
     v.x = (T *)(raw + off);
-    v.b = (T *)(raw + off + a);
-    v.dg = (T *)(raw + off + 2 * a);
-    v.w = v.dg + D.ncell;
-    v.m = D.has_mask ? (const uint8_t *)(raw + off + 2 * a + lds_al16((size_t)7 * D.ncell * sizeof(T))) : nullptr;
+    v.b = (T *)(raw + off + ax);
+    v.dg = rows ? (T *)(raw + off + ax + a) : nullptr;
+    v.w = rows ? v.dg + D.ncell : nullptr;
+    v.tab = rows ? nullptr : (T *)(raw + off + ax + a);
+    const size_t rb = rows ? lds_al16((size_t)7 * D.ncell * sizeof(T)) : lds_al16((size_t)2 * kUniTab * sizeof(T));
+    v.m = D.has_mask ? (const uint8_t *)(raw + off + ax + a + rb) : nullptr;
     v.nx = D.nx; v.ny = D.ny; v.nz = D.nz; v.nxy = D.nxy; v.n = D.ncell;
+    v.half = (D.nx & 1) ? 0 : D.ncell >> 1;
     v.inx = 1.0f / (float)D.nx;
     v.inxy = 1.0f / (float)D.nxy;
+    v.a0 = (T)D.alpha_c;
+    v.cx = (T)D.beta_c * (T)D.idx2;
+    v.cy = (T)D.beta_c * (T)D.idy2;
+    v.cz = (T)D.beta_c * (T)D.idz2;
+    v.per = 0;
+    v.dir = 0;
+    for (int f = 0; f < 6; f++) {
+        v.per |= D.kind[f] == VD_BC_PERIODIC ? 1 << f : 0;
+        v.dir |= D.kind[f] == VD_BC_DIRICHLET ? 1 << f : 0;
+    }
     return v;
 }
 
@@ -1188,33 +1245,91 @@ __device__ __forceinline__ void llev_ijk(const LLev<T> &v, int c, int &i, int &j
     i = r - j * v.nx;
 }
 
+// the six neighbour slots of cell c (indices wrap; an absent neighbour has
+// weight 0) and the faces that join the sum of a uniform row
 template <typename T>
-__device__ __forceinline__ T llev_off(const LLev<T> &v, const T *x, int c, int i, int j, int k) {
-    const int n = v.n;
-    const int xm = i > 0 ? c - 1 : c + v.nx - 1, xp = i < v.nx - 1 ? c + 1 : c - (v.nx - 1);
-    const int ym = j > 0 ? c - v.nx : c + v.nx * (v.ny - 1), yp = j < v.ny - 1 ? c + v.nx : c - v.nx * (v.ny - 1);
-    const int zm = k > 0 ? c - v.nxy : c + v.nxy * (v.nz - 1), zp = k < v.nz - 1 ? c + v.nxy : c - v.nxy * (v.nz - 1);
-    T of = 0;
-    of += lld(v.w, c) * lld(x, xm);
-    of += lld(v.w, n + c) * lld(x, xp);
-    of += lld(v.w, 2 * n + c) * lld(x, ym);
-    of += lld(v.w, 3 * n + c) * lld(x, yp);
-    of += lld(v.w, 4 * n + c) * lld(x, zm);
-    of += lld(v.w, 5 * n + c) * lld(x, zp);
-    return of;
+__device__ __forceinline__ int llev_nbrs(const LLev<T> &v, int c, int i, int j, int k, int nb[6]) {
+    nb[0] = lslot(v, i > 0 ? c - 1 : c + v.nx - 1);
+    nb[1] = lslot(v, i < v.nx - 1 ? c + 1 : c - (v.nx - 1));
+    nb[2] = lslot(v, j > 0 ? c - v.nx : c + v.nx * (v.ny - 1));
+    nb[3] = lslot(v, j < v.ny - 1 ? c + v.nx : c - v.nx * (v.ny - 1));
+    nb[4] = lslot(v, k > 0 ? c - v.nxy : c + v.nxy * (v.nz - 1));
+    nb[5] = lslot(v, k < v.nz - 1 ? c + v.nxy : c - v.nxy * (v.nz - 1));
+    return v.per | (i > 0 ? 1 : 0) | (i < v.nx - 1 ? 2 : 0) | (j > 0 ? 4 : 0) | (j < v.ny - 1 ? 8 : 0) |
+           (k > 0 ? 16 : 0) | (k < v.nz - 1 ? 32 : 0);
+}
+
+// diagonal of a uniform row from the faces that join the sum (a Dirichlet
+// domain face adds 2 beta / h^2, a Neumann one nothing)
+template <typename T>
+__device__ __forceinline__ T llev_diag_uni(const LLev<T> &v, int use) {
+    T m[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) m[f] = (use >> f) & 1 ? (T)1 : ((v.dir >> f) & 1 ? (T)2 : (T)0);
+    return v.a0 + v.cx * (m[0] + m[1]) + v.cy * (m[2] + m[3]) + v.cz * (m[4] + m[5]);
+}
+
+// diagonal and neighbour sum of cell c's row applied to x (slot-indexed)
+template <typename T>
+__device__ __forceinline__ void llev_row(const LLev<T> &v, const T *x, int c, int i, int j, int k, T &dg, T &of) {
+    int nb[6];
+    const int use = llev_nbrs(v, c, i, j, k, nb);
+    T e[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) e[f] = lld(x, nb[f]);
+    if (v.dg) {
+        const int sc = lslot(v, c), n = v.n;
+        T s = 0;
+#pragma unroll
+        for (int f = 0; f < 6; f++) s += lld(v.w, f * n + sc) * e[f];
+        dg = lld(v.dg, sc);
+        of = s;
+    } else {
+#pragma unroll
+        for (int f = 0; f < 6; f++) e[f] = (use >> f) & 1 ? e[f] : (T)0;
+        dg = llev_diag_uni(v, use);
+        of = v.cx * (e[0] + e[1]) + v.cy * (e[2] + e[3]) + v.cz * (e[4] + e[5]);
+    }
+}
+
+// the row of cell c applied to the level's own iterate: an absent
+// non-periodic neighbour of a uniform row reads the zero slot, and the
+// diagonal and its inverse come from the level's tables
+template <typename T>
+__device__ __forceinline__ void llev_row_x(const LLev<T> &v, int c, int i, int j, int k, T &dg, T &idg, T &of) {
+    if (v.dg) {
+        llev_row(v, v.x, c, i, j, k, dg, of);
+        idg = (T)0;
+        return;
+    }
+    const int z = v.n;
+    const bool u0 = i > 0 || (v.per & 1), u1 = i < v.nx - 1 || (v.per & 2);
+    const bool u2 = j > 0 || (v.per & 4), u3 = j < v.ny - 1 || (v.per & 8);
+    const bool u4 = k > 0 || (v.per & 16), u5 = k < v.nz - 1 || (v.per & 32);
+    const int s0 = u0 ? lslot(v, i > 0 ? c - 1 : c + v.nx - 1) : z;
+    const int s1 = u1 ? lslot(v, i < v.nx - 1 ? c + 1 : c - (v.nx - 1)) : z;
+    const int s2 = u2 ? lslot(v, j > 0 ? c - v.nx : c + v.nx * (v.ny - 1)) : z;
+    const int s3 = u3 ? lslot(v, j < v.ny - 1 ? c + v.nx : c - v.nx * (v.ny - 1)) : z;
+    const int s4 = u4 ? lslot(v, k > 0 ? c - v.nxy : c + v.nxy * (v.nz - 1)) : z;
+    const int s5 = u5 ? lslot(v, k < v.nz - 1 ? c + v.nxy : c - v.nxy * (v.nz - 1)) : z;
+    const int use = (u0 ? 1 : 0) | (u1 ? 2 : 0) | (u2 ? 4 : 0) | (u3 ? 8 : 0) | (u4 ? 16 : 0) | (u5 ? 32 : 0);
+    const T *x = v.x;
+    of = v.cx * (lld(x, s0) + lld(x, s1)) + v.cy * (lld(x, s2) + lld(x, s3)) + v.cz * (lld(x, s4) + lld(x, s5));
+    dg = lld(v.tab, use);
+    idg = lld(v.tab, kUniTab + use);
 }
 
 template <typename T>
 __device__ __forceinline__ bool llev_valid(const LLev<T> &v, int c) {
-    return !v.m || lld(v.m, c) != 0;
+    return !v.m || lld(v.m, lslot(v, c)) != 0;
 }
 
 // one colour pass; with an even nx the two cells of a pair are one of each
 // colour, so every thread updates a cell
 template <typename T>
 __device__ __forceinline__ void llev_sweep(const LLev<T> &v, int colour) {
-    if ((v.nx & 1) == 0) {
-        const int np = v.n >> 1;
+    if (v.half) {
+        const int np = v.half;
         for (int p = threadIdx.x; p < np; p += blockDim.x) {
             int i, j, k;
             llev_ijk(v, 2 * p, i, j, k);
@@ -1222,16 +1337,19 @@ __device__ __forceinline__ void llev_sweep(const LLev<T> &v, int colour) {
             const int c = 2 * p + s;
             i += s;
             if (!llev_valid(v, c)) continue;
-            const T of = llev_off(v, v.x, c, i, j, k);
-            lst(v.x, c, (lld(v.b, c) + of) / lld(v.dg, c));
+            T dg, idg, of;
+            llev_row_x(v, c, i, j, k, dg, idg, of);
+            const int sc = p + s * np;
+            lst(v.x, sc, v.dg ? (lld(v.b, sc) + of) / dg : (lld(v.b, sc) + of) * idg);
         }
     } else {
         for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
             int i, j, k;
             llev_ijk(v, c, i, j, k);
             if (((i + j + k) & 1) != colour || !llev_valid(v, c)) continue;
-            const T of = llev_off(v, v.x, c, i, j, k);
-            lst(v.x, c, (lld(v.b, c) + of) / lld(v.dg, c));
+            T dg, idg, of;
+            llev_row_x(v, c, i, j, k, dg, idg, of);
+            lst(v.x, c, v.dg ? (lld(v.b, c) + of) / dg : (lld(v.b, c) + of) * idg);
         }
     }
     __syncthreads();
@@ -1242,60 +1360,166 @@ __device__ __forceinline__ T llev_resid(const LLev<T> &v, int c) {
     if (!llev_valid(v, c)) return (T)0;
     int i, j, k;
     llev_ijk(v, c, i, j, k);
-    const T of = llev_off(v, v.x, c, i, j, k);
-    return lld(v.b, c) - (lld(v.dg, c) * lld(v.x, c) - of);
+    T dg, idg, of;
+    llev_row_x(v, c, i, j, k, dg, idg, of);
+    const int sc = lslot(v, c);
+    return lld(v.b, sc) - (dg * lld(v.x, sc) - of);
 }
 
-// Jacobi-preconditioned CG on the bottom level, one wavefront, FP64, the
-// row (dg, w) and the vectors in LDS; b and x are the level's LDS arrays
+// Jacobi-preconditioned CG on the bottom level, one wavefront, FP64; vd
+// gives the FP64 row (assembled in LDS or uniform), b and x are the level's
+// LDS arrays, vec holds the CG vectors (slot-indexed like the level).
+// Bottom levels of up to 64 * kPcgSlots cells keep r, z, p, x and their
+// rows in registers (lane l owns cells l, l + 64, ...) and publish only p
+// to LDS for the product; larger ones keep every vector in LDS.  The
+// stopping test ||r|| <= tol ||b|| is taken on the squares.
 template <typename T>
-__device__ void llev_pcg(const LLev<T> &v, const double *dg, const double *w, double *vec) {
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x, n = v.n;
-        const size_t a = lds_al16((size_t)n * sizeof(double)) / sizeof(double);
-        double *r = vec, *z = vec + a, *p = vec + 2 * a, *q = vec + 3 * a, *xb = vec + 4 * a;
+__device__ __forceinline__ void llev_pcg(const LLev<T> &v, const LLev<double> &vd, double *vec) {
+    const int lane = threadIdx.x, n = v.n;
+    const double tol2 = kBottomTol * kBottomTol;
+    if (lane >= 64) {
+        // the other wavefronts wait at the closing barrier
+    } else if (n <= 64 * kPcgSlots) {
+        double *pl = vec;
+        double r[kPcgSlots], z[kPcgSlots], p[kPcgSlots], x[kPcgSlots], dg[kPcgSlots], idg[kPcgSlots], w[kPcgSlots][6];
+        int nb[kPcgSlots][6], sl[kPcgSlots];
         double rr = 0.0, rz = 0.0;
-        for (int c = lane; c < n; c += 64) {
-            const bool valid = llev_valid(v, c);
-            const double rc = valid ? (double)lld(v.b, c) : 0.0;
-            const double zz = valid ? rc / lld(dg, c) : 0.0;
-            lst(r, c, rc);
-            lst(z, c, zz);
-            lst(p, c, zz);
-            lst(xb, c, 0.0);
-            rr += rc * rc;
-            rz += rc * zz;
+#pragma unroll
+        for (int s = 0; s < kPcgSlots; s++) {
+            const int c0 = lane + 64 * s;
+            const bool ok = c0 < n && llev_valid(v, c0);
+            const int c = c0 < n ? c0 : 0;
+            int i, j, k;
+            llev_ijk(vd, c, i, j, k);
+            const int use = llev_nbrs(vd, c, i, j, k, nb[s]);
+            sl[s] = lslot(vd, c);
+            if (vd.dg) {
+#pragma unroll
+                for (int f = 0; f < 6; f++) w[s][f] = lld(vd.w, f * n + sl[s]);
+                dg[s] = lld(vd.dg, sl[s]);
+            } else {
+                const double cf[3] = {vd.cx, vd.cy, vd.cz};
+#pragma unroll
+                for (int f = 0; f < 6; f++) w[s][f] = (use >> f) & 1 ? cf[f >> 1] : 0.0;
+                dg[s] = llev_diag_uni(vd, use);
+            }
+            // a masked or absent cell: no row, zero residual
+            if (!ok) {
+#pragma unroll
+                for (int f = 0; f < 6; f++) w[s][f] = 0.0;
+                dg[s] = 0.0;
+            }
+            idg[s] = ok ? 1.0 / dg[s] : 0.0;
+            r[s] = ok ? (double)lld(v.b, sl[s]) : 0.0;
+            z[s] = r[s] * idg[s];
+            p[s] = z[s];
+            x[s] = 0.0;
+            rr += r[s] * r[s];
+            rz += r[s] * z[s];
         }
         rr = wave_sum(rr);
         rz = wave_sum(rz);
-        wave_sync();
-        const double bn = sqrt(rr);
-        const LLev<double> vd{nullptr, nullptr, const_cast<double *>(dg), const_cast<double *>(w), v.m,
-                              v.nx, v.ny, v.nz, v.nxy, v.n, v.inx, v.inxy};
+        const double lim = tol2 * rr;
         for (int it = 0; it < kBottomMaxIt; it++) {
-            if (!(sqrt(rr) > kBottomTol * bn)) break;
-            double pq = 0.0;
-            for (int c = lane; c < n; c += 64) {
-                const double pc = lld(p, c);
-                double qq = 0.0;
-                if (llev_valid(v, c)) {
-                    int i, j, k;
-                    llev_ijk(vd, c, i, j, k);
-                    qq = lld(dg, c) * pc - llev_off(vd, (const double *)p, c, i, j, k);
-                }
-                lst(q, c, qq);
-                pq += pc * qq;
+            if (!(rr > lim)) break;
+#pragma unroll
+            for (int s = 0; s < kPcgSlots; s++)
+                if (lane + 64 * s < n) lst(pl, sl[s], p[s]);
+            wave_sync();
+            double q[kPcgSlots], pq = 0.0;
+#pragma unroll
+            for (int s = 0; s < kPcgSlots; s++) {
+                double of = 0.0;
+#pragma unroll
+                for (int f = 0; f < 6; f++) of += w[s][f] * lld(pl, nb[s][f]);
+                q[s] = dg[s] * p[s] - of;
+                pq += p[s] * q[s];
             }
             pq = wave_sum(pq);
             if (pq == 0.0) break;
             const double al = rz / pq;
             double rz_new = 0.0, rr_new = 0.0;
+#pragma unroll
+            for (int s = 0; s < kPcgSlots; s++) {
+                x[s] = x[s] + al * p[s];
+                r[s] = r[s] - al * q[s];
+                z[s] = r[s] * idg[s];
+                rz_new += r[s] * z[s];
+                rr_new += r[s] * r[s];
+            }
+            rz_new = wave_sum(rz_new);
+            rr_new = wave_sum(rr_new);
+            const double bcoef = rz_new / rz;
+            rz = rz_new;
+            rr = rr_new;
+#pragma unroll
+            for (int s = 0; s < kPcgSlots; s++) p[s] = z[s] + bcoef * p[s];
+            wave_sync();
+        }
+#pragma unroll
+        for (int s = 0; s < kPcgSlots; s++)
+            if (lane + 64 * s < n) lst(v.x, sl[s], (T)x[s]);
+    } else {
+        const size_t a = lds_al16((size_t)n * sizeof(double)) / sizeof(double);
+        double *r = vec, *z = vec + a, *p = vec + 2 * a, *q = vec + 3 * a, *xb = vec + 4 * a;
+        double rr = 0.0, rz = 0.0;
+        for (int c = lane; c < n; c += 64) lst(p, lslot(vd, c), 0.0);
+        wave_sync();
+        // q holds 1 / diagonal (0 for a masked cell) throughout
+        for (int c = lane; c < n; c += 64) {
+            const bool valid = llev_valid(v, c);
+            const int sc = lslot(vd, c);
+            int i, j, k;
+            llev_ijk(vd, c, i, j, k);
+            double d, of;
+            llev_row(vd, (const double *)p, c, i, j, k, d, of);
+            const double id = valid ? 1.0 / d : 0.0;
+            const double rc = valid ? (double)lld(v.b, sc) : 0.0;
+            lst(r, sc, rc);
+            lst(z, sc, id);
+            lst(xb, sc, 0.0);
+            rr += rc * rc;
+            rz += rc * rc * id;
+        }
+        wave_sync();
+        for (int c = lane; c < n; c += 64) {
+            const int sc = lslot(vd, c);
+            lst(q, sc, lld(z, sc));
+            lst(p, sc, lld(r, sc) * lld(z, sc));
+        }
+        rr = wave_sum(rr);
+        rz = wave_sum(rz);
+        wave_sync();
+        const double lim = tol2 * rr;
+        double *Ap = z;   // z is recomputed from r and q each iteration
+        for (int it = 0; it < kBottomMaxIt; it++) {
+            if (!(rr > lim)) break;
+            double pq = 0.0;
             for (int c = lane; c < n; c += 64) {
-                lst(xb, c, lld(xb, c) + al * lld(p, c));
-                const double rc = lld(r, c) - al * lld(q, c);
-                lst(r, c, rc);
-                const double zz = llev_valid(v, c) ? rc / lld(dg, c) : 0.0;
-                lst(z, c, zz);
+                const int sc = lslot(vd, c);
+                const double pc = lld(p, sc);
+                double aq = 0.0;
+                if (llev_valid(v, c)) {
+                    int i, j, k;
+                    llev_ijk(vd, c, i, j, k);
+                    double d, of;
+                    llev_row(vd, (const double *)p, c, i, j, k, d, of);
+                    aq = d * pc - of;
+                }
+                lst(Ap, sc, aq);
+                pq += pc * aq;
+            }
+            pq = wave_sum(pq);
+            if (pq == 0.0) break;
+            const double al = rz / pq;
+            double rz_new = 0.0, rr_new = 0.0;
+            wave_sync();
+            for (int c = lane; c < n; c += 64) {
+                const int sc = lslot(vd, c);
+                lst(xb, sc, lld(xb, sc) + al * lld(p, sc));
+                const double rc = lld(r, sc) - al * lld(Ap, sc);
+                lst(r, sc, rc);
+                const double zz = rc * lld(q, sc);
                 rz_new += rc * zz;
                 rr_new += rc * rc;
             }
@@ -1304,17 +1528,35 @@ __device__ void llev_pcg(const LLev<T> &v, const double *dg, const double *w, do
             const double bcoef = rz_new / rz;
             rz = rz_new;
             rr = rr_new;
-            for (int c = lane; c < n; c += 64) lst(p, c, lld(z, c) + bcoef * lld(p, c));
+            wave_sync();
+            for (int c = lane; c < n; c += 64) {
+                const int sc = lslot(vd, c);
+                lst(p, sc, lld(r, sc) * lld(q, sc) + bcoef * lld(p, sc));
+            }
             wave_sync();
         }
-        for (int c = lane; c < n; c += 64) lst(v.x, c, (T)lld(xb, c));
+        for (int c = lane; c < n; c += 64) lst(v.x, lslot(v, c), (T)lld(xb, lslot(vd, c)));
     }
     __syncthreads();
 }
 
+// global (cell order) -> LDS (slot order), four loads in flight per thread
 template <typename T>
-__device__ __forceinline__ void lds_copy_in(T *dst, const T *src, int n) {
-    for (int c = threadIdx.x; c < n; c += blockDim.x) lst(dst, c, gld(src, c));
+__device__ __forceinline__ void lds_copy_in(const LLev<T> &v, T *dst, const T *src, int planes) {
+    const int n = v.n, tot = planes * n, step = blockDim.x;
+    auto slot = [&](int e) {
+        const int pl = e / n, c = e - pl * n;
+        return pl * n + lslot(v, c);
+    };
+    int e = threadIdx.x;
+    for (; e + 3 * step < tot; e += 4 * step) {
+        const T v0 = gld(src, e), v1 = gld(src, e + step), v2 = gld(src, e + 2 * step), v3 = gld(src, e + 3 * step);
+        lst(dst, slot(e), v0);
+        lst(dst, slot(e + step), v1);
+        lst(dst, slot(e + 2 * step), v2);
+        lst(dst, slot(e + 3 * step), v3);
+    }
+    for (; e < tot; e += step) lst(dst, slot(e), gld(src, e));
 }
 
 template <typename T>
@@ -1327,33 +1569,50 @@ __global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__res
     if (!gld(&st[f.prob].active, 0)) return;
     const int base = f.base, lc = f.lc, L = f.L;
     // load: level lc's x and b (b + Dirichlet lifting on a finest level), every
-    // resident level's row and mask
+    // resident level's assembled row and mask
     for (int l = lc; l < L; l++) {
         const LevDesc &D = dT[base + l];
         const LLev<T> v = lds_lev<T>(raw, dT, base, lc, l);
-        const T *sg = (const T *)D.sten;
-        lds_copy_in(v.dg, sg, 7 * v.n);   // dg and the weight planes are contiguous
-        if (v.m) for (int c = threadIdx.x; c < v.n; c += blockDim.x) lst(const_cast<uint8_t *>(v.m), c, gld(D.mask, c));
+        if (v.dg) lds_copy_in(v, v.dg, (const T *)D.sten, 7);   // dg and the weight planes are contiguous
+        if (v.tab && threadIdx.x < kUniTab) {
+            const T d = llev_diag_uni(v, (int)threadIdx.x);
+            lst(v.tab, threadIdx.x, d);
+            lst(v.tab, kUniTab + threadIdx.x, (T)1 / d);
+        }
+        if (threadIdx.x == 0) lst(v.x, v.n, (T)0);
+        if (v.m)
+            for (int c = threadIdx.x; c < v.n; c += blockDim.x) lst(const_cast<uint8_t *>(v.m), lslot(v, c), gld(D.mask, c));
         if (l == lc) {
-            lds_copy_in(v.x, (const T *)D.x, v.n);
-            for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
-                T bv = gld((const T *)D.b, c);
-                if (D.lift) {
+            // a coarse level enters with the zero iterate the restriction wrote
+            if (lc == 0) lds_copy_in(v, v.x, (const T *)D.x, 1);
+            else for (int c = threadIdx.x; c < v.n; c += blockDim.x) lst(v.x, c, (T)0);
+            if (D.lift) {
+                for (int c = threadIdx.x; c < v.n; c += blockDim.x) {
                     int i, j, k;
                     cell_ijk(D, c, i, j, k);
-                    bv = (T)((double)bv + lift_term(D, i, j, k));
+                    lst(v.b, lslot(v, c), (T)((double)gld((const T *)D.b, c) + lift_term(D, i, j, k)));
                 }
-                lst(v.b, c, bv);
+            } else {
+                lds_copy_in(v, v.b, (const T *)D.b, 1);
             }
         }
     }
     size_t used = 0;
-    for (int m = lc; m < L; m++) used += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask);
+    for (int m = lc; m < L; m++)
+        used += lds_level_bytes(dT[base + m].ncell, sizeof(T), dT[base + m].has_mask, dT[base + m].sten != nullptr);
     double *pcg = (double *)(raw + used);
     const LevDesc &B64 = d64[base + L - 1];
     const size_t ab = lds_al16((size_t)B64.ncell * sizeof(double)) / sizeof(double);
-    if constexpr (sizeof(T) == 4)
-        if (L >= 2) lds_copy_in(pcg + 5 * ab, (const double *)B64.sten, 7 * B64.ncell);
+    LLev<double> vd = lds_lev<double>(raw, d64, base, L - 1, L - 1);   // FP64 view of the bottom row
+    if constexpr (sizeof(T) == 4) {
+        vd.dg = nullptr;
+        vd.w = nullptr;
+        if (L >= 2 && B64.sten) {
+            vd.dg = pcg + 5 * ab;
+            vd.w = vd.dg + B64.ncell;
+            lds_copy_in(vd, vd.dg, (const double *)B64.sten, 7);
+        }
+    }
     __syncthreads();
     if (L == 1) {
         const LLev<T> v = lds_lev<T>(raw, dT, base, 0, 0);
@@ -1376,15 +1635,16 @@ __global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__res
                 sum += llev_resid(v, c0 + v.nxy + 1);
                 sum += llev_resid(v, c0 + v.nxy + v.nx);
                 sum += llev_resid(v, c0 + v.nxy + v.nx + 1);
-                lst(cv.b, cc, llev_valid(cv, cc) ? (T)0.125 * sum : (T)0);
-                lst(cv.x, cc, (T)0);
+                const int sc = lslot(cv, cc);
+                lst(cv.b, sc, llev_valid(cv, cc) ? (T)0.125 * sum : (T)0);
+                lst(cv.x, sc, (T)0);
             }
             __syncthreads();
         }
         {
             const LLev<T> v = lds_lev<T>(raw, dT, base, lc, L - 1);
-            if constexpr (sizeof(T) == 4) llev_pcg(v, pcg + 5 * ab, pcg + 5 * ab + v.n, pcg);
-            else llev_pcg(v, v.dg, v.w, pcg);
+            if constexpr (sizeof(T) == 4) llev_pcg(v, vd, pcg);
+            else llev_pcg(v, v, pcg);
         }
         for (int l = L - 2; l >= lc; l--) {
             const LLev<T> v = lds_lev<T>(raw, dT, base, lc, l);
@@ -1393,7 +1653,8 @@ __global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__res
                 if (!llev_valid(v, c)) continue;
                 int i, j, k;
                 llev_ijk(v, c, i, j, k);
-                lst(v.x, c, lld(v.x, c) + lld(cv.x, (i >> 1) + cv.nx * (j >> 1) + cv.nxy * (k >> 1)));
+                const int sc = lslot(v, c);
+                lst(v.x, sc, lld(v.x, sc) + lld(cv.x, lslot(cv, (i >> 1) + cv.nx * (j >> 1) + cv.nxy * (k >> 1))));
             }
             __syncthreads();
             for (int s = 0; s < nu_post; s++) { llev_sweep(v, 0); llev_sweep(v, 1); }
@@ -1402,7 +1663,7 @@ __global__ void __launch_bounds__(kLdsThreads) k_coarse_lds(const LevDesc *__res
     {
         const LLev<T> v = lds_lev<T>(raw, dT, base, lc, lc);
         T *gx = (T *)dT[base + lc].x;
-        for (int c = threadIdx.x; c < v.n; c += blockDim.x) gst(gx, c, lld(v.x, c));
+        for (int c = threadIdx.x; c < v.n; c += blockDim.x) gst(gx, c, lld(v.x, lslot(v, c)));
     }
 }
 
@@ -1454,9 +1715,11 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_stencils(const LevDesc *__restrict__ dT, const LevDesc *__restrict__ d64,
                                                   const FusedDesc *__restrict__ fd) {
     const FusedDesc f = fd[blockIdx.x];
-    for (int l = f.lc; l < f.L; l++) stencil_rows<T>(dT[f.base + l], (T *)dT[f.base + l].sten);
+    for (int l = f.lc; l < f.L; l++)
+        if (dT[f.base + l].sten) stencil_rows<T>(dT[f.base + l], (T *)dT[f.base + l].sten);
     if constexpr (sizeof(T) == 4)
-        if (f.L >= 2) stencil_rows<double>(d64[f.base + f.L - 1], (double *)d64[f.base + f.L - 1].sten);
+        if (f.L >= 2 && d64[f.base + f.L - 1].sten)
+            stencil_rows<double>(d64[f.base + f.L - 1], (double *)d64[f.base + f.L - 1].sten);
 }
 
 // -------------------------------------------------------- setup kernels
@@ -1823,7 +2086,8 @@ static void build_plan25(vd_ctx *ctx, HPlan &out, const std::vector<std::pair<in
 
 // A level whose tiled plan mixes uniform-coefficient problems with others
 // is also planned as two halves, so the uniform ones run in the leaner
-// kernel (same tile depth; the colour pass is launched once per half).
+// kernel (the colour pass is launched once per half).  Each half picks its
+// own tile depth, so a half of few problems still fills the device.
 static void split25(vd_ctx *ctx, Solver &S, int l) {
     HPlan &P = S.pre25[l];
     S.pre25u[l] = HPlan{};
@@ -1835,9 +2099,9 @@ static void split25(vd_ctx *ctx, Solver &S, int l) {
         (!H.var_beta && !H.var_alpha && !H.has_mask ? u : g).push_back({id, &H.lv[id % S.Lmax]});
     }
     if (u.empty() || g.empty()) return;
-    build_plan25(ctx, S.pre25u[l], u, P.kz);
+    build_plan25(ctx, S.pre25u[l], u, 0);
     S.pre25u[l].uni = true;
-    build_plan25(ctx, S.pre25g[l], g, P.kz);
+    build_plan25(ctx, S.pre25g[l], g, 0);
 }
 
 static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o) {
@@ -1884,10 +2148,11 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
             const long nb = H.L >= 2 ? (long)H.lv[H.L - 1].nx * H.lv[H.L - 1].ny * H.lv[H.L - 1].nz : 0;
             int best = -1;
             size_t best_bytes = 0;
+            const bool rows = H.var_beta || H.var_alpha || H.has_mask;
             for (int l = H.L - 1; l >= 0; l--) {
-                size_t need = H.L >= 2 ? lds_pcg_bytes(nb, ir) : 0;
+                size_t need = H.L >= 2 ? lds_pcg_bytes(nb, ir && rows) : 0;
                 for (int m = l; m < H.L; m++)
-                    need += lds_level_bytes((long)H.lv[m].nx * H.lv[m].ny * H.lv[m].nz, sT, H.has_mask);
+                    need += lds_level_bytes((long)H.lv[m].nx * H.lv[m].ny * H.lv[m].nz, sT, H.has_mask, rows);
                 if (need > lds_limit) break;
                 best = l;
                 best_bytes = need;
@@ -1912,6 +2177,8 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
             for (auto &H : S->probs) {
                 H.lc = H.lds_lc >= 0 ? H.lds_lc : 1;
                 if (H.lds_lc >= 0) S->lds_bytes = std::max(S->lds_bytes, H.lds_bytes);
+                // uniform-coefficient problems form their rows on the fly
+                if (!(H.var_beta || H.var_alpha || H.has_mask)) continue;
                 for (int l = H.lc; l < H.L; l++) {
                     HLevel &V = H.lv[l];
                     const size_t n7 = (size_t)7 * V.nx * V.ny * V.nz;

@@ -410,6 +410,40 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
     const long nxy = G.nxy;
     const long col = i + (long)nx * j;
     const bool drift = F.mu || F.mu_c != 0.0;
+    if (!drift) {
+        // a field without mobility has no drift flux: its divergence is 0;
+        // four planes' loads are issued before their stores
+        const long c0 = col + nxy * k0;
+        double *__restrict__ out = F.out;
+        const double *__restrict__ pu0 = F.u0 ? F.u0 : F.u;
+        const double *__restrict__ psrc = F.src;
+        const double *__restrict__ pex = F.extra;
+        for (int k = 0; k < kz; k += 4) {
+            double v[4];
+            if (a.mode == 0) {
+#pragma unroll
+                for (int m = 0; m < 4; m++) v[m] = 0.0;
+            } else {
+                double s0[4], e0[4];
+#pragma unroll
+                for (int m = 0; m < 4; m++) {
+                    const long c = c0 + nxy * (k + m);
+                    v[m] = gld(pu0, c);
+                    s0[m] = psrc ? gld(psrc, c) : 0.0;
+                    e0[m] = pex ? gld(pex, c) : 0.0;
+                }
+#pragma unroll
+                for (int m = 0; m < 4; m++) {
+                    v[m] = v[m] * a.inv_dt - 0.0;
+                    if (psrc) v[m] += s0[m];
+                    if (pex) v[m] += e0[m];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; m++) gst(out, c0 + nxy * (k + m), v[m]);
+        }
+        return;
+    }
     const double *__restrict__ u = F.u;
     const double *__restrict__ mup = F.mu ? F.mu : F.u;      // valid address when the mobility is constant
     const double *__restrict__ phi = a.phi;
