@@ -59,13 +59,15 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(family):
-    """HBM bytes per launch of the kernel family from the committed
-    rocprofv3 counter summary, while the kernel source it was taken from is
-    unchanged (else None)."""
+def measured_traffic(family, alg_bytes_per_launch):
+    """HBM bytes per launch of the kernel family: the committed rocprofv3
+    counter summary gives the ratio of measured traffic (FETCH_SIZE and
+    WRITE_SIZE, each scaled by a plain copy's reading) to algorithmic bytes
+    over the same dispatches; it applies while the kernel source it was taken
+    from is unchanged (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_hbm_traffic_arh2_160.txt" % family)
-    if not os.path.exists(path):
+    if not os.path.exists(path) or not alg_bytes_per_launch:
         return None
     fields = {}
     for line in open(path):
@@ -74,9 +76,9 @@ def measured_traffic(family):
             fields[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2507_08200_amd", "csrc", "mg.hip")
     sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha1") != sha or "traffic_to_algorithmic_ratio" not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return round(float(fields["traffic_to_algorithmic_ratio"]) * alg_bytes_per_launch)
 
 
 def learned_guess(ctx, V, I, cfg, rho, args):
@@ -236,7 +238,8 @@ def main():
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
     roofline = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kernel, kbytes / launches if launches else 0.0),
                 "launches": launches, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": round(kbytes / launches) if launches else 0}
 
