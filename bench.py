@@ -39,13 +39,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=160, help="grid edge (the workload is n^3)")
-    ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp64")
-    ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp64")
+    # the 160^3 workload runs its multigrid smoothing in FP32 inside FP64
+    # iterative refinement; the all-FP64 step is timed beside it
+    ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
+    ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
+    ap.add_argument("--no-fp64-variant", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--species-levels", type=int, default=1)
     ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
     ap.add_argument("--ir-inner", type=int, default=2)
     ap.add_argument("--poisson-reps", type=int, default=5)
-    ap.add_argument("--cpu-n", type=int, default=112, help="grid edge of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=0,
+                    help="grid edge of the oracle's timed sample (0: the workload's own grid, which also gives the "
+                         "per-field error of the GPU step against the oracle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (auto = dominant)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched Helmholtz timing")
@@ -189,6 +194,10 @@ def main():
                       nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1)
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
+    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10),
+                        species_mg=V.mg_opts(rtol=1e-10, n_levels=args.species_levels, nu_pre=args.species_nu[0],
+                                             nu_post=args.species_nu[1]))
+    state0 = {k: v.clone() for k, v in state.items()}
     ctx = V.Context()
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib * 2 ** 18, dtype=torch.float32, device=dev)
@@ -235,6 +244,25 @@ def main():
     value = ncell * args.steps / elapsed
     log("[bench] %d steps in %.3f s: %.3f ms/step, %.4g cell-steps/s" % (args.steps, elapsed, ms_per_step, value))
 
+    # the same steps with every solve in FP64, from the same initial state
+    fp64_variant = None
+    if not args.no_fp64_variant:
+        st64 = {k: v.clone() for k, v in state0.items()}
+        for w in range(args.warmup):
+            ctx.vd_step(P64, st64, want_info=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(args.steps):
+            ctx.vd_step(P64, st64, want_info=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        i64 = ctx.vd_step(P64, st64)
+        fp64_variant = {"value": round(ncell * args.steps / el, 1), "ms_per_step": round(el * 1e3 / args.steps, 4),
+                        "poisson_cycles_last_step": i64["poisson_cycles"],
+                        "species_cycles_last_step": i64["species_cycles"]}
+        del st64
+        log("[bench] all-FP64 variant: %s" % fp64_variant)
+
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
     roofline = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -277,29 +305,50 @@ def main():
     # ---- 64 uneven sheath-jump Helmholtz problems: sequential vs batched
     batch = None if args.no_batch else batch_bench(ctx, V, I, dev, args.batch_reps)
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample
+    # ---- CPU baseline: the FP64 oracle on a bounded sample (one step of the
+    # workload from its initial state), and the per-field error of the GPU
+    # step from the same state against it
     cpu = None
+    errors = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         O.build()
-        cn = args.cpu_n
-        ccfg = I.cfg3(n=cn)
+        cn = args.cpu_n if args.cpu_n > 0 else n
+        ccfg = cfg if cn == n else I.cfg3(n=cn)
         log("[bench] oracle: one step at %d^3 on one host core" % cn)
         t = time.perf_counter()
         r = O.step(ccfg, O.species_arh2_15(), poisson=O.mg_opts(rtol=1e-10), species_mg=O.mg_opts(rtol=1e-10))
         dt_cpu = time.perf_counter() - t
         assert r["status"] == 0
         cpu = {"value": round(cn ** 3 / dt_cpu, 1), "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-               "sample": "one FP64 oracle step of the same Ar-H2 streamer workload at %d^3 (%d cells, cold Poisson start, "
-                         "%d Poisson cycles), single-threaded, %.1f s; scaled per cell" %
+               "sample": "one FP64 oracle step of the same Ar-H2 streamer workload at %d^3 (%d cells) from its initial "
+                         "state (cold Poisson start, %d Poisson cycles), single-threaded, %.1f s; scaled per cell" %
                          (cn, cn ** 3, r["info"]["poisson_cycles"], dt_cpu),
                "host_cpus_available": len(os.sched_getaffinity(0))}
         log("[bench] oracle %.2f s -> %.4g cell-steps/s" % (dt_cpu, cpu["value"]))
+        if cn == n:
+            errors = {}
+            for tag, PP in (("fp32_ir_step", P), ("fp64_step", P64)):
+                st = {k: v.clone() for k, v in state0.items()}
+                inf = ctx.vd_step(PP, st)
+                assert inf["status"] == 0
+
+                def rel(a, b):
+                    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+                e = {"phi": rel(st["phi"].cpu().numpy(), r["phi"]), "Te": rel(st["Te"].cpu().numpy(), r["Te"])}
+                nn = st["n"].cpu().numpy()
+                for k2, sp in enumerate(M.ARH2_NAMES):
+                    e["n_" + sp] = rel(nn[k2], r["n"][k2])
+                errors[tag] = {f: float("%.3g" % v) for f, v in e.items()}
+                errors[tag]["max"] = max(errors[tag].values())
+                del st, nn
+            log("[bench] error vs the FP64 oracle (max |gpu - oracle| / max |oracle| per field): %s" % errors)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64+f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
+        "data": "synthetic",
         "config": {"workload": "Ar-H2 15-species streamer step, %d^3 cells, dt 1e-12 s, LFA Te, 15 kV plates" % n,
                    "grid": [n, n, n], "species": 15, "dt": 1e-12,
                    "poisson": "%s rtol 1e-10 warm start" % args.poisson_precision,
@@ -309,6 +358,8 @@ def main():
                    "poisson_cycles_last_step": cyc_p, "species_cycles_last_step": cyc_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fp64_variant": fp64_variant,
+        "error_vs_fp64_oracle": errors,
         "poisson_time_to_1e-10": poisson,
         "batched_helmholtz_64": batch,
         "kernel_profile_warmup": prof,

@@ -363,10 +363,15 @@ __device__ __forceinline__ int wrap_idx(int p, int n, bool per, bool &ok) {
 }
 
 // MODE 0: one Gauss-Seidel colour pass (in place); MODE 1: FP64 residual
-// norm partials; MODE 2: same, also storing the FP32 residual and clearing
-// the FP32 unknown (iterative refinement).  Software-pipelined: while plane
-// k is computed, plane k+2's pair, plane k+1's halo and plane k+1's b are in
-// flight; the LDS tile is double-buffered so one barrier per plane suffices.
+// norm partials; MODE 2: same, also storing the FP32 residual and, unless
+// colour is 1, clearing the FP32 unknown (iterative refinement).  MODE 4:
+// the first colour pass of a correction solve, from a zero iterate (no
+// loads of x; the pair is stored with the other colour 0).  MODE 5: the
+// last colour pass of a correction solve, which adds the final correction
+// pair to the FP64 unknown (d32 then holds the FP64 descriptors) instead of
+// storing it.  Software-pipelined: while plane k is computed, plane k+2's
+// pair, plane k+1's halo and plane k+1's b are in flight; the LDS tile is
+// double-buffered so one barrier per plane suffices.
 template <typename T, int MODE, bool UNIONLY = false>
 __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
                                                  int kz, int colour, double *__restrict__ partials,
@@ -379,7 +384,8 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const int d = plan_find(pl, t);
     const int id = pl.ids[d];
     const LevDesc L = descs[id];
-    if ((MODE == 0 || check_active) && !gld(&st[L.prob].active, 0)) return;
+    constexpr bool PASS = MODE == 0 || MODE == 4 || MODE == 5;
+    if ((PASS || check_active) && !gld(&st[L.prob].active, 0)) return;
     int lt = t - pl.prefix[d];
     const int slot = pl.gbase ? pl.gbase[d] + lt : t;    // partial slot of this tile
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -425,6 +431,10 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const bool okh = halo_thread && okhi && okhj;
     const long nxy = L.nxy;
     auto ld_pair = [&](int kk, T &a, T &b2) {
+        if constexpr (MODE == 4) {
+            a = b2 = (T)0;
+            return;
+        }
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
         const typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(X + pair_off + nxy * kw);
@@ -433,6 +443,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         b2 = ok ? v.y : (T)0;
     };
     auto ld_h = [&](int kk) -> T {
+        if constexpr (MODE == 4) return (T)0;
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
         const T v = gld(X, h_off + nxy * kw);
@@ -477,6 +488,8 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         ld_pair(k + 2, xq0, xq1);
         const T hnext = ld_h(k + 1);
         ld_b(k + 1, bn0, bn1);
+        PairD x64v{};
+        if constexpr (MODE == 5) x64v = *(const VD_GAS PairD *)((const double *)d32[id].x + b_off + nxy * k);
         __syncthreads();
         // coefficient arrays of this plane for the pair (variant 2): all
         // issued together from clamped addresses
@@ -504,10 +517,10 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
 #pragma unroll
             for (int q = 0; q < 2; q++) {
                 const int i = ia + q;
-                if (MODE == 0 && ((i + j + k) & 1) != colour) continue;
+                if (PASS && ((i + j + k) & 1) != colour) continue;
                 const int c = i + nx * j + L.nxy * k;
                 const bool valid = VAR != 0 || !(L.has_mask && !gld(L.mask, c));
-                if (MODE == 0 && !valid) continue;
+                if (PASS && !valid) continue;
                 T nbv[6];
                 nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
                 nbv[1] = q == 0 ? xc1 : buf[(r + 1) * kT25W + 2 * tp + 3];
@@ -535,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                     else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
                     if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
                 }
-                if (MODE == 0) {
+                if (PASS) {
                     if (q == 0) out0 = (b + of) / dg;
                     else out1 = (b + of) / dg;
                 } else {
@@ -545,15 +558,19 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                     if (partials_b && valid) vb += (double)b * (double)b;
                     if (MODE == 2) {
                         gst(Eb, c, (float)rv);
-                        gst(Ex, c, 0.0f);
+                        if (colour != 1) gst(Ex, c, 0.0f);
                     }
                 }
             }
-            if (MODE == 0) {
+            if (MODE == 0 || MODE == 4) {
                 typename Pair<T>::V pv;
                 pv.x = out0;
                 pv.y = out1;
                 *(VD_GAS typename Pair<T>::V *)(X + ia + rowoff + (long)L.nxy * k) = pv;
+            } else if (MODE == 5) {
+                x64v.x = x64v.x + (double)out0;
+                x64v.y = x64v.y + (double)out1;
+                *(VD_GAS PairD *)((double *)d32[id].x + ia + rowoff + (long)L.nxy * k) = x64v;
             }
         }
         xm0 = xc0; xm1 = xc1;
@@ -570,7 +587,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
         else if (!L.has_mask) march(std::integral_constant<int, 2>{});
         else march(std::integral_constant<int, 0>{});
     }
-    if (MODE != 0) {
+    if (!PASS) {
         const double sum = block_sum(v, red);
         if (tid == 0) gst(partials, slot, sum);
         if (partials_b) {
@@ -2392,6 +2409,9 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind, 
         case 7: total += 2.0 * N * sT; break;                 // copy
         case 3: total += N * 8.0; break;
         case 4: total += 2.0 * N * 8.0 + coef * 2.0; break;
+        case 8: total += 1.0 * N * sT + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
+        case 9: total += 1.5 * N * sT + 16.0 * N + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
+        case 10: total += 2.0 * N * 8.0 + coef * 2.0 + N * 4.0; break;
         default: total += 2.0 * N * 8.0 + coef * 2.0 + 2.0 * N * 4.0; break;
         }
     }
@@ -2426,33 +2446,44 @@ static void credit_launches(vd_ctx *ctx, Solver &S, int inner) {
 
 // one Gauss-Seidel colour pass over level l of every problem in the plan
 template <typename T>
-static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col) {
+static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col, int pmode = 0) {
     const HPlan &pp = S.pre[l];
     const HPlan &p25 = S.pre25[l];
     hipStream_t s = ctx->stream;
     const HPlan &pu = S.pre25u[l], &pg = S.pre25g[l];
+    // pmode 4 / 5 (FP32 corrections of the refinement, level 0 only): the
+    // zero-start first pass and the last pass that updates the FP64 unknown
+    const LevDesc *alt = pmode == 5 ? S.d64.p : nullptr;
+    const int kind = pmode == 4 ? 8 : (pmode == 5 ? 9 : 0);
+    auto st25 = [&](const HPlan &q, bool uni) {
+        if (uni) {
+            if (pmode == 4)
+                k_st25<T, 4, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+            else if (pmode == 5)
+                k_st25<T, 5, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+            else
+                k_st25<T, 0, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+        } else {
+            if (pmode == 4)
+                k_st25<T, 4><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+            else if (pmode == 5)
+                k_st25<T, 5><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+            else
+                k_st25<T, 0><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
+        }
+    };
     if (S.aligned && pu.nd && pg.nd) {
         // mixed level: the uniform problems in the lean kernel, the rest in
         // the general one
-        timed_mg(ctx, S, "gsrb_uniform", pu, sizeof(T) == 4, 0, 1.0, [&] {
-            k_st25<T, 0, true><<<xcd_grid(pu.ntiles), kBlock, 0, s>>>(dT, nullptr, pu.dev(), pu.kz, col, nullptr, S.st.p, 1,
-                                                                      nullptr);
-        });
-        timed_mg(ctx, S, "gsrb", pg, sizeof(T) == 4, 0, 1.0, [&] {
-            k_st25<T, 0><<<xcd_grid(pg.ntiles), kBlock, 0, s>>>(dT, nullptr, pg.dev(), pg.kz, col, nullptr, S.st.p, 1, nullptr);
-        });
+        timed_mg(ctx, S, "gsrb_uniform", pu, sizeof(T) == 4, kind, 1.0, [&] { st25(pu, true); });
+        timed_mg(ctx, S, "gsrb", pg, sizeof(T) == 4, kind, 1.0, [&] { st25(pg, false); });
         return;
     }
     // one timing family per kernel instantiation: the uniform-coefficient
     // colour pass and the general one
-    timed_mg(ctx, S, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb", pp, sizeof(T) == 4, 0, 1.0, [&] {
-        if (p25.nd && S.aligned && p25.uni)
-            k_st25<T, 0, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1,
-                                                                       nullptr);
-        else if (p25.nd && S.aligned)
-            k_st25<T, 0><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(dT, nullptr, p25.dev(), p25.kz, col, nullptr, S.st.p, 1, nullptr);
-        else
-            k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
+    timed_mg(ctx, S, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb", pp, sizeof(T) == 4, kind, 1.0, [&] {
+        if (p25.nd && S.aligned) st25(p25, p25.uni);
+        else k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
     });
 }
 
@@ -2468,7 +2499,8 @@ static void sweep_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int fli
 
 // nu smoothing sweeps of level l; par tracks which buffer holds the iterate
 template <typename T>
-static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int nu, int &par) {
+static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int nu, int &par, bool zero_first = false,
+                         bool update_last = false) {
     const HPlan &p25 = S.pre25[l];
     if (p25.nd && S.use_fused[l]) {
         timing_group_begin(ctx, "sweep");
@@ -2483,18 +2515,22 @@ static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int n
         const bool split = S.aligned && S.pre25u[l].nd && S.pre25g[l].nd;
         if (!split) timing_group_begin(ctx, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb");
         for (int q = 0; q < nu; q++)
-            for (int col = 0; col < 2; col++) gs_pass<T>(ctx, S, l, dT, col);
+            for (int col = 0; col < 2; col++) {
+                const int pm = (zero_first && q == 0 && col == 0) ? 4 : ((update_last && q == nu - 1 && col == 1) ? 5 : 0);
+                gs_pass<T>(ctx, S, l, dT, col, pm);
+            }
         if (!split) timing_group_end(ctx);
     }
 }
 
 template <typename T>
-static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o) {
+static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *o, bool zero_start = false,
+                   bool final_update = false) {
     hipStream_t s = ctx->stream;
     const ProbState *st = S.st.p;
     std::vector<int> par(S.Lmax, 0);
     for (int l = 0; l < S.Lmax; l++) {
-        if (S.pre[l].nd) smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l]);
+        if (S.pre[l].nd) smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l], l == 0 && zero_start);
         const HPlan &pr = S.restr[l];
         if (pr.nd)
             timed_mg(ctx, S, "resid_restrict", pr, sizeof(T) == 4, 1, 1.0, [&] {
@@ -2518,7 +2554,7 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
             });
         const HPlan &ps = S.pre[l];
         if (ps.nd) {
-            smooth_level<T>(ctx, S, l, dT, o->nu_post, par[l]);
+            smooth_level<T>(ctx, S, l, dT, o->nu_post, par[l], false, l == 0 && final_update);
             if (par[l]) {
                 // an odd number of sweeps: the iterate goes back to x
                 timed_mg(ctx, S, "copy", ps, sizeof(T) == 4, 7, 1.0, [&] {
@@ -2534,8 +2570,12 @@ static const HPlan &norm_plan(const Solver &S, int mode) {
     return (mode != 0 && S.all0_25.nd && S.aligned) ? S.all0_25 : S.all0;
 }
 
-static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool with_b = false) {
+// keep_e (mode 2): leave the FP32 correction as it is, for a correction
+// solve that starts from zero without reading it
+static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool with_b = false, bool keep_e = false) {
     double *pb = with_b ? S.partials_b.p : nullptr;
+    const int ksel = (mode == 2 && keep_e) ? 1 : 0;
+    const int kind = (mode == 2 && keep_e) ? 10 : 3 + mode;
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
     auto launch25 = [&](const HPlan &q, bool uni) {
@@ -2546,22 +2586,22 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
             k_st25<double, 1><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
                                                                     check_active, pb);
         else if (uni)
-            k_st25<double, 2, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p,
+            k_st25<double, 2, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, ksel, S.partials.p,
                                                                           S.st.p, check_active, pb);
         else
-            k_st25<double, 2><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
+            k_st25<double, 2><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, ksel, S.partials.p, S.st.p,
                                                                     check_active, pb);
     };
     if (mode != 0 && S.aligned && S.norm25u.nd && S.norm25g.nd) {
         // mixed batch: uniform problems in the lean kernel; partial slots
         // stay those of the full plan
-        timed_mg(ctx, S, "norm", S.norm25u, false, 3 + mode, 1.0, [&] { launch25(S.norm25u, true); });
-        timed_mg(ctx, S, "norm", S.norm25g, false, 3 + mode, 1.0, [&] { launch25(S.norm25g, false); });
+        timed_mg(ctx, S, "norm", S.norm25u, false, kind, 1.0, [&] { launch25(S.norm25u, true); });
+        timed_mg(ctx, S, "norm", S.norm25g, false, kind, 1.0, [&] { launch25(S.norm25g, false); });
         return;
     }
     if (mode != 0 && S.all0_25.nd && S.aligned) {
         const HPlan &p25 = S.all0_25;
-        timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {
+        timed_mg(ctx, S, "norm", pl, false, kind, 1.0, [&] {
             if (mode == 1 && p25.uni)
                 k_st25<double, 1, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
                                                                                 S.partials.p, S.st.p, check_active, pb);
@@ -2569,10 +2609,10 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
                 k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
                                                                           S.partials.p, S.st.p, check_active, pb);
             else if (p25.uni)
-                k_st25<double, 2, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                k_st25<double, 2, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, ksel,
                                                                                 S.partials.p, S.st.p, check_active, pb);
             else
-                k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
+                k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, ksel,
                                                                           S.partials.p, S.st.p, check_active, pb);
         });
         return;
@@ -2604,6 +2644,28 @@ static int read_active(vd_ctx *ctx, Solver &S) {
     return n;
 }
 
+// The FP32 corrections of a refinement step can start from zero without
+// clearing them and add themselves to the FP64 unknown in their last colour
+// pass when every problem's finest level is smoothed by the tiled colour
+// passes before and after the coarse correction.
+static bool ir_fusable(const Solver &S, const vd_mg_opts *o) {
+    if (S.prec != VD_FP32_IR || !S.aligned || !S.pre25[0].nd || S.use_fused[0]) return false;
+    if (o->nu_pre < 1 || o->nu_post < 1 || S.pre[0].nd != S.nprob) return false;
+    for (const HProblem &H : S.probs)
+        if (H.lc < 1) return false;
+    return true;
+}
+
+// One refinement step's corrections: ir_inner FP32 cycles, then the FP64
+// update (inside the last cycle's last pass when fusable).
+static void ir_corrections(vd_ctx *ctx, Solver &S, const vd_mg_opts *o, bool fused) {
+    for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, S, S.d32.p, o, fused && q == 0, fused && q == o->ir_inner - 1);
+    if (!fused)
+        timed_mg(ctx, S, "ir_update", S.all0, false, 3, 2.5, [&] {
+            k_ir_update<<<xcd_grid(S.all0.ntiles), kBlock, 0, ctx->stream>>>(S.d64.p, S.d32.p, S.all0.dev(), S.st.p);
+        });
+}
+
 // One tolerance-mode iteration: residual check (which retires converged
 // problems on the device), then a V-cycle, or in IR mode ir_inner FP32
 // cycles and the FP64 update.
@@ -2613,12 +2675,10 @@ static void one_cycle(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
         launch_finalize(ctx, S, 1, o, 1);
         vcycle<double>(ctx, S, S.d64.p, o);
     } else {
-        launch_norm(ctx, S, 2, 1);
+        const bool fz = ir_fusable(S, o);
+        launch_norm(ctx, S, 2, 1, false, fz);
         launch_finalize(ctx, S, 1, o, o->ir_inner);
-        for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, S, S.d32.p, o);
-        timed_mg(ctx, S, "ir_update", S.all0, false, 3, 2.5, [&] {
-            k_ir_update<<<xcd_grid(S.all0.ntiles), kBlock, 0, ctx->stream>>>(S.d64.p, S.d32.p, S.all0.dev(), S.st.p);
-        });
+        ir_corrections(ctx, S, o, fz);
     }
 }
 
@@ -2854,11 +2914,12 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     const int chunk = async_fixed ? (o->fixed_cycles + 1) : 2;
     // the first check of a fused solve also finalises ||b||, then clears x
     // of the problems whose right-hand side vanishes
+    const bool ir_fz = ir && ir_fusable(*S, o);
     auto check = [&](int nmode, int inner) {
         const bool first = fuse_b && iters == 0;
         S->cur_it = iters;
         S->cur_phase = 0;
-        launch_norm(ctx, *S, nmode, 1, first);
+        launch_norm(ctx, *S, nmode, 1, first, nmode == 2 && ir_fz);
         launch_finalize(ctx, *S, first ? 3 : 1, o, inner);
         if (first)
             timed(ctx, "prep", 0.0, [&] {
@@ -2878,10 +2939,7 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
                 check(2, o->ir_inner);
                 if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
                 S->cur_phase = 1;
-                for (int q = 0; q < o->ir_inner; q++) vcycle<float>(ctx, *S, S->d32.p, o);
-                timed_mg(ctx, *S, "ir_update", S->all0, false, 3, 2.5, [&] {
-                    k_ir_update<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->d32.p, S->all0.dev(), S->st.p);
-                });
+                ir_corrections(ctx, *S, o, ir_fz);
             }
             iters++;
         }

@@ -375,6 +375,37 @@ def test_graph_replay_and_autotune(ctx, V, oracle, precision):
             _pinned_compare(oracle, probs[p], host(ref[p]["x"]), i_ref[p], 1e-10)
 
 
+def test_ir_fused_corrections_match_cleared(ctx, V, oracle):
+    """FP32 corrections that start from zero without being cleared and add
+    themselves to the FP64 unknown inside their last colour pass give the
+    same solve as clearing them and adding them in a separate pass (forced
+    here by the fused-sweep option, which smooths without colour passes):
+    same cycle counts, same iterate to 1e-13, for a mixed batch (uniform,
+    variable-coefficient and masked problems) in tolerance mode and as
+    single-level smoothing at a fixed cycle count; the uniform problem's
+    tolerance-mode residual is recomputed by the oracle."""
+    probs = [I.random_helmholtz(910, (32, 32, 32), alpha_kind="const", beta_kind="const"),
+             I.random_helmholtz(911, (48, 32, 40), beta_jump=True),
+             I.random_helmholtz(912, (32, 32, 32), mask_holes=2)]
+    for opts in (dict(), dict(n_levels=1, nu_pre=1, nu_post=1, fixed_cycles=6)):
+        ref = [gpu_problem(p) for p in probs]
+        i_ref, st = ctx.vd_helmholtz_solve_batched(ref, V.mg_opts(rtol=1e-10, precision=V.FP32_IR, **opts))
+        assert st == 0
+        gs = [gpu_problem(p) for p in probs]
+        infos, st = V.Context().vd_helmholtz_solve_batched(
+            gs, V.mg_opts(rtol=1e-10, precision=V.FP32_IR, fused_sweep=True, **opts))
+        assert st == 0
+        for p in range(len(probs)):
+            say("   ir fused", opts, p, i_ref[p]["cycles"], infos[p]["cycles"], i_ref[p]["rel_res"])
+            assert infos[p]["cycles"] == i_ref[p]["cycles"]
+            assert rel_err(host(gs[p]["x"]), host(ref[p]["x"])) <= 1e-13
+        if not opts:
+            x = host(ref[0]["x"])
+            r = oracle.residual(probs[0], probs[0]["rhs"], x)
+            b = oracle.residual(probs[0], probs[0]["rhs"], np.zeros_like(x))
+            assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10 * (1 + 1e-6)
+
+
 def test_timing_credits_only_active_problems(V):
     """The smoother's algorithmic bytes count the problems that were still
     being cycled: a zero right-hand side added to a batch (inactive after
