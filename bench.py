@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--no-fp64-variant", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--species-levels", type=int, default=1)
     ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
-    ap.add_argument("--ir-inner", type=int, default=2)
+    ap.add_argument("--ir-inner", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default smoother tiling")
     ap.add_argument("--poisson-reps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=0,
                     help="grid edge of the oracle's timed sample (0: the workload's own grid, which also gives the "
@@ -189,14 +190,15 @@ def main():
     lfa = dict(cfg["lfa"])
     lfa["te_K"] = torch.tensor(cfg["lfa"]["te_K"], device=dev)
     prec = {"fp64": V.FP64, "fp32_ir": V.FP32_IR}
-    popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner)
+    tune = not args.no_autotune
+    popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune)
     sopts = V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
-                      nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1)
+                      nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune)
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
-    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10),
+    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune),
                         species_mg=V.mg_opts(rtol=1e-10, n_levels=args.species_levels, nu_pre=args.species_nu[0],
-                                             nu_post=args.species_nu[1]))
+                                             nu_post=args.species_nu[1], autotune=tune))
     state0 = {k: v.clone() for k, v in state.items()}
     ctx = V.Context()
     if args.calibrate_copy_mib > 0:
@@ -351,7 +353,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Ar-H2 15-species streamer step, %d^3 cells, dt 1e-12 s, LFA Te, 15 kV plates" % n,
                    "grid": [n, n, n], "species": 15, "dt": 1e-12,
-                   "poisson": "%s rtol 1e-10 warm start" % args.poisson_precision,
+                   "poisson": "%s%s rtol 1e-10 warm start%s" % (
+                       args.poisson_precision, " inner %d" % args.ir_inner if args.poisson_precision == "fp32_ir" else "",
+                       ", autotuned tiles" if tune else ""),
                    "species_solve": "%s levels %d nu %s rtol 1e-10" % (args.species_precision, args.species_levels,
                                                                        list(args.species_nu)),
                    "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",

@@ -16,9 +16,11 @@ bool timing_begin(vd_ctx *ctx, const char *family, hipEvent_t *ev0, hipEvent_t *
     for (auto &f : T.families) sel = sel || f == family;
     if (!sel) return false;
     if (T.pool.size() < 2) {
+        // timing-only events: no system-scope fence (no cache writeback and
+        // invalidation around the timed kernels); read after a stream sync
         for (int q = 0; q < 1024; q++) {
             hipEvent_t e;
-            VD_HIP(hipEventCreate(&e));
+            VD_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             T.pool.push_back(e);
         }
     }
