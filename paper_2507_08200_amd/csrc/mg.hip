@@ -84,16 +84,17 @@ __device__ __forceinline__ T residual_uni(const LevDesc &F, const T *__restrict_
     const long nxy = F.nxy;
     auto w = [](int p, int n, bool per) { return p < 0 ? (per ? p + n : 0) : (p >= n ? (per ? p - n : n - 1) : p); };
     const bool px = F.kind[0] == VD_BC_PERIODIC, py = F.kind[2] == VD_BC_PERIODIC, pz = F.kind[4] == VD_BC_PERIODIC;
-    const long row = (long)nx * j + nxy * k;
+    (void)nxy;
     T nb[6];
-    nb[0] = gld(x, row + w(i - 1, nx, px));
-    nb[1] = gld(x, row + w(i + 1, nx, px));
-    nb[2] = gld(x, i + (long)nx * w(j - 1, ny, py) + nxy * k);
-    nb[3] = gld(x, i + (long)nx * w(j + 1, ny, py) + nxy * k);
-    nb[4] = gld(x, i + (long)nx * j + nxy * w(k - 1, nz, pz));
-    nb[5] = gld(x, i + (long)nx * j + nxy * w(k + 1, nz, pz));
-    const T xc = gld(x, row + i);
-    T bv = gld((const T *)F.b, row + i);
+    nb[0] = gld(x, cell_pos(F, w(i - 1, nx, px), j, k));
+    nb[1] = gld(x, cell_pos(F, w(i + 1, nx, px), j, k));
+    nb[2] = gld(x, cell_pos(F, i, w(j - 1, ny, py), k));
+    nb[3] = gld(x, cell_pos(F, i, w(j + 1, ny, py), k));
+    nb[4] = gld(x, cell_pos(F, i, j, w(k - 1, nz, pz)));
+    nb[5] = gld(x, cell_pos(F, i, j, w(k + 1, nz, pz)));
+    const long cp = cell_pos(F, i, j, k);
+    const T xc = gld(x, cp);
+    T bv = gld((const T *)F.b, cp);
     T dg, of;
     row_terms_uni<T>(F, i, j, k, nb, dg, of);
     if (F.lift) bv = (T)((double)bv + lift_term_uni(F, i, j, k));
@@ -117,7 +118,8 @@ template <typename T>
 __device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C, int c, int i, int j, int k) {
     if (F.has_mask && !gld(F.mask, c)) return;
     int cc = (i >> 1) + C.nx * (j >> 1) + C.nxy * (k >> 1);
-    gst((T *)F.x, c, gld((T *)F.x, c) + gld((const T *)C.x, cc));
+    const long fp = F.rb ? cell_pos(F, i, j, k) : (long)c;
+    gst((T *)F.x, fp, gld((T *)F.x, fp) + gld((const T *)C.x, cc));
 }
 
 // ------------------------------------------------------------ grid kernels
@@ -403,6 +405,7 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
     float *__restrict__ Eb = MODE == 2 ? (float *)d32[id].b : nullptr;
     float *__restrict__ Ex = MODE == 2 ? (float *)d32[id].x : nullptr;
+    const bool rbE = MODE == 2 && d32[id].rb;
     const int hslot = halo_slot<T>(tid);
     T *__restrict__ X = (T *)L.x;
     const T *__restrict__ B = (const T *)L.b;
@@ -557,8 +560,9 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
                     v += rv * rv;
                     if (partials_b && valid) vb += (double)b * (double)b;
                     if (MODE == 2) {
-                        gst(Eb, c, (float)rv);
-                        if (colour != 1) gst(Ex, c, 0.0f);
+                        const long ce = rbE ? cell_pos(d32[id], i, j, k) : (long)c;
+                        gst(Eb, ce, (float)rv);
+                        if (colour != 1) gst(Ex, ce, 0.0f);
                     }
                 }
             }
@@ -594,6 +598,168 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
             const double sb = block_sum(vb, red);
             if (tid == 0) gst(partials_b, slot, sb);
         }
+    }
+}
+
+// ------------------------- parity-split colour pass (refinement corrections)
+// The FP32 corrections of the finest level of uniform-coefficient problems
+// are held parity-split by row (cell_pos): a colour pass then reads only
+// the other colour's values and the right-hand side of the updated colour,
+// and writes only the updated colour, half the bytes of a pass over the
+// lexicographic layout.  A workgroup owns 32 half-row positions x 16 rows
+// and marches kz planes; a thread updates two cells of its row (half-row
+// positions m, m+1), and holds the other colour's values at those positions
+// for planes k-1..k+1 in registers; the other colour's x-y neighbours of
+// plane k come from LDS.  In a row whose updated cells sit at i = 2m + s,
+// the x-neighbours of cell m are the other colour's positions m-1+s and
+// m+s, the y- and z-neighbours its position m in the adjacent rows.  Each
+// update is the same expression as in the lexicographic colour pass.
+// PM 4: the first (red) pass from a zero correction (nothing of the other
+// colour is read); 0: a colour pass; 5: the last (black) pass, which adds
+// the final correction of the thread's four consecutive cells to the FP64
+// unknown (d64) instead of storing it.  Needs nx % 4 == 0.
+template <int PM>
+__global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d64, Plan pl,
+                                                 int kz, int colour, const ProbState *__restrict__ st) {
+    __shared__ float xs[2][(kT25Y + 2) * kT25W];
+    const int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    const int d = plan_find(pl, t);
+    const int id = pl.ids[d];
+    const LevDesc L = descs[id];
+    if (!gld(&st[L.prob].active, 0)) return;
+    int lt = t - pl.prefix[d];
+    const int nx = L.nx, ny = L.ny, nz = L.nz, nh = nx >> 1;
+    const int ntx = (nh + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
+    const int tx = lt % ntx;
+    lt /= ntx;
+    const int ty = lt % nty;
+    const int zc = lt / nty;
+    const int m0 = tx * kT25X, j0 = ty * kT25Y, k0 = zc * kz;
+    const int k1 = min(k0 + kz, nz);
+    const int tid = threadIdx.x;
+    const int tp = tid & 15, r = tid >> 4;
+    const int ma = m0 + 2 * tp, j = j0 + r;
+    const bool own = ma < nh && j < ny;      // nh is even, so the pair (ma, ma + 1) is whole
+    const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
+    const int hslot = halo_slot<float>(tid);
+    float *__restrict__ X = (float *)L.x;
+    const float *__restrict__ B = (const float *)L.b;
+    const long nxy = L.nxy;
+    const int oofs = (1 - colour) * nh, uofs = colour * nh;   // half-row offsets: other / updated colour
+    const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
+    // the thread's pair of the other colour: wrapped (a partial tile's
+    // positions past the row end hold the row's first ones when periodic)
+    // or zeroed
+    bool okm, oky;
+    const int mw = min(wrap_idx(ma, nh, px, okm), nh - 2);
+    const int jw = wrap_idx(j, ny, py, oky);
+    const bool okp = okm && oky;
+    const long pair_off = oofs + mw + (long)nx * jw;
+    const long b_off = uofs + min(ma, nh - 2) + (long)nx * min(j, ny - 1);
+    int hm, hj;
+    if (tid < 2 * kT25Y) {
+        hm = (tid / kT25Y) ? m0 + kT25X : m0 - 1;
+        hj = j0 + (tid & (kT25Y - 1));
+    } else {
+        const int q = tid - 2 * kT25Y;
+        hm = m0 + (q & (kT25X - 1));
+        hj = (q / kT25X) ? j0 + kT25Y : j0 - 1;
+    }
+    // a half-row position wraps with the row: position -1 of the other
+    // colour is its last one, position nh its first
+    bool okhm, okhj;
+    const long h_off = oofs + wrap_idx(hm, nh, px, okhm) + (long)nx * wrap_idx(hj, ny, py, okhj);
+    const bool okh = halo_thread && okhm && okhj;
+    auto ld_pair = [&](int kk, float &a, float &b2) {
+        if constexpr (PM == 4) {
+            a = b2 = 0.0f;
+            return;
+        }
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const PairF v = *(const VD_GAS PairF *)(X + pair_off + nxy * kw);
+        const bool ok = okp && okz;
+        a = ok ? v.x : 0.0f;
+        b2 = ok ? v.y : 0.0f;
+    };
+    auto ld_h = [&](int kk) -> float {
+        if constexpr (PM == 4) return 0.0f;
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const float v = gld(X, h_off + nxy * kw);
+        return (okh && okz) ? v : 0.0f;
+    };
+    auto ld_b = [&](int kk, float &a, float &b2) {
+        const PairF v = *(const VD_GAS PairF *)(B + b_off + nxy * min(kk, nz - 1));
+        const bool ok = own && kk < k1;
+        a = ok ? v.x : 0.0f;
+        b2 = ok ? v.y : 0.0f;
+    };
+    float xm0, xm1, xc0, xc1, xp0, xp1;
+    ld_pair(k0 - 1, xm0, xm1);
+    ld_pair(k0, xc0, xc1);
+    ld_pair(k0 + 1, xp0, xp1);
+    float hcur = ld_h(k0);
+    float bc0, bc1;
+    ld_b(k0, bc0, bc1);
+    const long q_off = 2 * (long)min(ma, nh - 2) + (long)nx * min(j, ny - 1);   // first of the four cells (FP64)
+    for (int k = k0; k < k1; k++) {
+        float *buf = xs[k & 1];
+        buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
+        buf[(r + 1) * kT25W + 2 * tp + 2] = xc1;
+        if (halo_thread) buf[hslot] = hcur;
+        float xq0, xq1, bn0, bn1;
+        ld_pair(k + 2, xq0, xq1);
+        const float hnext = ld_h(k + 1);
+        ld_b(k + 1, bn0, bn1);
+        PairD xa{}, xb{};
+        if constexpr (PM == 5) {
+            const double *x64 = (const double *)d64[id].x + q_off + nxy * k;
+            xa = *(const VD_GAS PairD *)x64;
+            xb = *(const VD_GAS PairD *)(x64 + 2);
+        }
+        __syncthreads();
+        if (own) {
+            const int s = (j + k + colour) & 1;      // updated cells at i = 2m + s
+            float out[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const int i = 2 * (ma + q) + s;
+                float nbv[6];
+                const int lc = (r + 1) * kT25W + 2 * tp + 1 + q;    // LDS slot of position ma + q
+                nbv[0] = s ? buf[lc] : buf[lc - 1];
+                nbv[1] = s ? buf[lc + 1] : buf[lc];
+                nbv[2] = buf[lc - kT25W];
+                nbv[3] = buf[lc + kT25W];
+                nbv[4] = q == 0 ? xm0 : xm1;
+                nbv[5] = q == 0 ? xp0 : xp1;
+                float dg, of;
+                row_terms_uni<float>(L, i, j, k, nbv, dg, of);
+                out[q] = ((q == 0 ? bc0 : bc1) + of) / dg;
+            }
+            if constexpr (PM == 5) {
+                // cells 2ma .. 2ma+3: updated at offsets s and s+2, the other
+                // colour (this plane's values xc) at 1-s and 3-s
+                xa.x = xa.x + (double)(s ? xc0 : out[0]);
+                xa.y = xa.y + (double)(s ? out[0] : xc0);
+                xb.x = xb.x + (double)(s ? xc1 : out[1]);
+                xb.y = xb.y + (double)(s ? out[1] : xc1);
+                double *x64 = (double *)d64[id].x + q_off + nxy * k;
+                *(VD_GAS PairD *)x64 = xa;
+                *(VD_GAS PairD *)(x64 + 2) = xb;
+            } else {
+                PairF pv;
+                pv.x = out[0];
+                pv.y = out[1];
+                *(VD_GAS PairF *)(X + uofs + ma + (long)nx * j + nxy * k) = pv;
+            }
+        }
+        xm0 = xc0; xm1 = xc1;
+        xc0 = xp0; xc1 = xp1;
+        xp0 = xq0; xp1 = xq1;
+        hcur = hnext;
+        bc0 = bn0; bc1 = bn1;
     }
 }
 
@@ -1902,6 +2068,8 @@ struct Solver {
     int nfused = 0;
     size_t pcg_lds_bytes = 0;     // dynamic LDS of the fused kernel (0: CG vectors in global memory)
     bool lds_mode = false;        // coarse levels held in LDS (k_coarse_lds)
+    HPlan rb0;                    // finest levels of the uniform problems, parity-split FP32 corrections (k_rb32)
+    bool rb_on = false;           // those corrections are currently held parity-split
     size_t lds_bytes = 0;         // its dynamic LDS
     DevBuf<int> prob_of;
     HPlan all0;                                  // finest level, every problem
@@ -2270,6 +2438,35 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
     S->pre25u.resize(Lmax);
     S->pre25g.resize(Lmax);
     for (int l = 0; l < Lmax; l++) split25(ctx, *S, l);
+    // refinement corrections of the uniform problems' finest levels held
+    // parity-split: every such problem smoothed by the tiled passes needs
+    // nx % 4 == 0 (whole position pairs per half-row)
+    if (ir && Lmax > 0) {
+        std::vector<std::pair<int, const HLevel *>> items;
+        bool ok = true;
+        for (int id : S->pre[0].h_ids) {
+            const HProblem &H = S->probs[id / Lmax];
+            if (H.var_beta || H.var_alpha || H.has_mask) continue;
+            const HLevel &V = H.lv[0];
+            ok = ok && V.nx % 4 == 0;
+            items.push_back({id, &V});
+        }
+        if (ok && !items.empty()) {
+            int kz = 2;
+            for (int cand : {16, 8, 4, 2}) {
+                long tot = 0;
+                for (auto &it : items)
+                    tot += (long)ceil_div(it.second->nx / 2, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
+                if (tot >= 2048 || cand == 2) { kz = cand; break; }
+            }
+            S->rb0.kz = kz;
+            for (auto &it : items)
+                plan_add(S->rb0, it.first, (long)ceil_div(it.second->nx / 2, kT25X) * ceil_div(it.second->ny, kT25Y) *
+                                               ceil_div(it.second->nz, kz), 1);
+            upload_plan(S->rb0, ctx->stream);
+            S->rb0.uni = true;
+        }
+    }
     if (S->all0_25.nd && !S->all0_25.uni) {
         // finest-level residual norms split like the smoother; item p of
         // the full plan is problem p
@@ -2334,6 +2531,7 @@ static void refresh_descs(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *p
         S.aligned = S.aligned && ((uintptr_t)probs[p].x % 16 == 0) && ((uintptr_t)probs[p].rhs % 16 == 0);
     S.key = std::move(key);
     S.rows_valid = false;
+    S.rb_on = false;     // rebuilt descriptors are lexicographic
 }
 
 // Coefficients of every level from the user's arrays (values may change
@@ -2472,6 +2670,23 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col, i
                 k_st25<T, 0><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
         }
     };
+    if constexpr (sizeof(T) == 4) {
+        if (l == 0 && S.rb_on) {
+            // parity-split corrections of the uniform problems; the others
+            // (if any) in the general kernel
+            const HPlan &rb = S.rb0;
+            timed_mg(ctx, S, "gsrb_uniform", rb, true, kind, 1.0, [&] {
+                if (pmode == 4)
+                    k_rb32<4><<<xcd_grid(rb.ntiles), kBlock, 0, s>>>(dT, S.d64.p, rb.dev(), rb.kz, col, S.st.p);
+                else if (pmode == 5)
+                    k_rb32<5><<<xcd_grid(rb.ntiles), kBlock, 0, s>>>(dT, S.d64.p, rb.dev(), rb.kz, col, S.st.p);
+                else
+                    k_rb32<0><<<xcd_grid(rb.ntiles), kBlock, 0, s>>>(dT, S.d64.p, rb.dev(), rb.kz, col, S.st.p);
+            });
+            if (pg.nd && pu.nd) timed_mg(ctx, S, "gsrb", pg, true, kind, 1.0, [&] { st25(pg, false); });
+            return;
+        }
+    }
     if (S.aligned && pu.nd && pg.nd) {
         // mixed level: the uniform problems in the lean kernel, the rest in
         // the general one
@@ -2654,6 +2869,18 @@ static bool ir_fusable(const Solver &S, const vd_mg_opts *o) {
     for (const HProblem &H : S.probs)
         if (H.lc < 1) return false;
     return true;
+}
+
+// Hold the uniform problems' finest FP32 corrections parity-split while the
+// fused refinement path is in use (and lexicographic otherwise).
+static void set_rb(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
+    const bool on = S.rb0.nd > 0 && ir_fusable(S, o);
+    if (on == S.rb_on) return;
+    for (int id : S.rb0.h_ids) S.h32[id].rb = on ? 1 : 0;
+    VD_HIP(hipStreamSynchronize(ctx->stream));
+    memcpy(S.pin32, S.h32.data(), sizeof(LevDesc) * S.h32.size());
+    VD_HIP(hipMemcpyAsync(S.d32.p, S.pin32, sizeof(LevDesc) * S.h32.size(), hipMemcpyHostToDevice, ctx->stream));
+    S.rb_on = on;
 }
 
 // One refinement step's corrections: ir_inner FP32 cycles, then the FP64
@@ -2870,6 +3097,7 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
             if (S->pre25[l].nd && !S->use_fused[l]) { alloc_x2(*S, l); S->use_fused[l] = 1; any = true; }
         if (any) refresh_descs(ctx, *S, nprob, probs, o);
     }
+    if (S->prec == VD_FP32_IR) set_rb(ctx, *S, o);
     hipStream_t s = ctx->stream;
     S->recs.clear();
     S->cur_it = 0;

@@ -83,7 +83,17 @@ struct LevDesc {
     const void *b;               // right-hand side
     void *sten;                  // assembled rows of an LDS-resident level (diagonal + 6 weight planes), else null
     void *x2;                    // alternate iterate of the out-of-place fused sweeps, else null
+    int rb;                      // x and b held parity-split by row (FP32 refinement corrections, finest level)
+    int pad_;
 };
+
+// Position of cell (i, j, k) in a level's x / b: lexicographic, or, when the
+// level is held parity-split by row, the row's red cells ((i+j+k) even, in
+// order of i) followed by its black cells.
+__host__ __device__ __forceinline__ long cell_pos(const LevDesc &L, int i, int j, int k) {
+    const long row = (long)L.nx * j + (long)L.nxy * k;
+    return L.rb ? row + (((i + j + k) & 1) ? (L.nx >> 1) : 0) + (i >> 1) : row + i;
+}
 
 // Per-problem convergence state, device resident.
 struct ProbState {
