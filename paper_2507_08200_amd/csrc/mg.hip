@@ -2457,7 +2457,7 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
                 long tot = 0;
                 for (auto &it : items)
                     tot += (long)ceil_div(it.second->nx / 2, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
-                if (tot >= 2048 || cand == 2) { kz = cand; break; }
+                if (tot >= 1024 || cand == 2) { kz = cand; break; }
             }
             S->rb0.kz = kz;
             for (auto &it : items)
@@ -3015,7 +3015,10 @@ static void autotune_t(vd_ctx *ctx, Solver &S, const LevDesc *dT, const std::vec
                 VD_HIP(hipEventSynchronize(e1));
                 float ms = 0.0f;
                 VD_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best * 0.97f) { best = ms; best_kz = kz; best_fused = fused; }
+                // the fused sweep is taken only when clearly faster: timed
+                // alone it gains from a warm cache that it does not keep
+                // inside a cycle
+                if (ms < best * (fused ? 0.85f : 0.97f)) { best = ms; best_kz = kz; best_fused = fused; }
             }
         if (best_kz != S.pre25[l].kz) {
             const bool uni = S.pre25[l].uni;
