@@ -22,6 +22,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add contraction only within an expression, so every kernel
+    # rounds a shared formula the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 
