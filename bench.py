@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-steps/s at 160^3×15 species; Poisson time-to-1e-10 plain vs learned+FP32"
 HBM_PEAK_GBS = 8000.0
-FAMILIES = ["gsrb", "gsrb_uniform", "sweep", "resid_restrict", "prolong", "copy", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
+FAMILIES = ["gsrb", "gsrb_fine", "gsrb_uniform", "sweep", "resid_restrict", "prolong", "copy", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
             "react", "transport", "rho", "setup"]
 QE = 1.602176634e-19
 

@@ -2675,7 +2675,7 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col, i
             // parity-split corrections of the uniform problems; the others
             // (if any) in the general kernel
             const HPlan &rb = S.rb0;
-            timed_mg(ctx, S, "gsrb_uniform", rb, true, kind, 1.0, [&] {
+            timed_mg(ctx, S, "gsrb_fine", rb, true, kind, 1.0, [&] {
                 if (pmode == 4)
                     k_rb32<4><<<xcd_grid(rb.ntiles), kBlock, 0, s>>>(dT, S.d64.p, rb.dev(), rb.kz, col, S.st.p);
                 else if (pmode == 5)
@@ -2690,13 +2690,14 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col, i
     if (S.aligned && pu.nd && pg.nd) {
         // mixed level: the uniform problems in the lean kernel, the rest in
         // the general one
-        timed_mg(ctx, S, "gsrb_uniform", pu, sizeof(T) == 4, kind, 1.0, [&] { st25(pu, true); });
+        timed_mg(ctx, S, l == 0 ? "gsrb_fine" : "gsrb_uniform", pu, sizeof(T) == 4, kind, 1.0, [&] { st25(pu, true); });
         timed_mg(ctx, S, "gsrb", pg, sizeof(T) == 4, kind, 1.0, [&] { st25(pg, false); });
         return;
     }
     // one timing family per kernel instantiation: the uniform-coefficient
     // colour pass and the general one
-    timed_mg(ctx, S, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb", pp, sizeof(T) == 4, kind, 1.0, [&] {
+    timed_mg(ctx, S, (p25.nd && S.aligned && p25.uni) ? (l == 0 ? "gsrb_fine" : "gsrb_uniform") : "gsrb", pp, sizeof(T) == 4, kind,
+             1.0, [&] {
         if (p25.nd && S.aligned) st25(p25, p25.uni);
         else k_gsrb<T><<<xcd_grid(pp.ntiles), kBlock, 0, s>>>(dT, pp.dev(), col, S.st.p);
     });
@@ -2728,7 +2729,11 @@ static void smooth_level(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int n
         // the colour passes of one level are back-to-back launches of one
         // kernel (unless the level is split): one event pair around them
         const bool split = S.aligned && S.pre25u[l].nd && S.pre25g[l].nd;
-        if (!split) timing_group_begin(ctx, (p25.nd && S.aligned && p25.uni) ? "gsrb_uniform" : "gsrb");
+        // timing families: uniform-coefficient colour passes of the finest
+        // level (bandwidth-bound) and of the coarser ones (latency-bound),
+        // and the general passes
+        if (!split)
+            timing_group_begin(ctx, (p25.nd && S.aligned && p25.uni) ? (l == 0 ? "gsrb_fine" : "gsrb_uniform") : "gsrb");
         for (int q = 0; q < nu; q++)
             for (int col = 0; col < 2; col++) {
                 const int pm = (zero_first && q == 0 && col == 0) ? 4 : ((update_last && q == nu - 1 && col == 1) ? 5 : 0);
