@@ -553,33 +553,28 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
         exv = gld(exp_, c);
         __syncthreads();
         // x faces (tile rows 0..7, faces 0..32) and y faces (rows 0..8)
-        for (int q = tid; q < kDY * (kDX + 1); q += kBlock) {
-            const int r = q / (kDX + 1), f = q - r * (kDX + 1);
-            const int gi = i0 + f;                       // face between cells gi-1 and gi
-            const int ub = (r + 3) * kUX + f;            // U index of cell gi-3 in this row
-            const int pb = (r + 1) * kPX + f;            // P index of cell gi-1
-            const bool lo = gi == 0, hi = gi == nx;
-            const int kf = lo ? F.kind[0] : F.kind[1];
-            const int kp = lo ? G.phi_kind[0] : G.phi_kind[1];
-            const double gp = lo ? G.phi_val[0] : G.phi_val[1];
-            const double fl = drift_face(F, lld(U, ub), lld(U, ub + 1), lld(U, ub + 2), lld(U, ub + 3), lld(U, ub + 4),
-                                         lld(U, ub + 5), lld(P, pb), lld(P, pb + 1), lld(M, pb), lld(M, pb + 1), ihx, lo, hi, kf,
-                                         kp, gp);
-            lst(fx, q, drift ? fl : 0.0);
-        }
-        for (int q = tid; q < (kDY + 1) * kDX; q += kBlock) {
-            const int r = q / kDX, f = q - r * kDX;
-            const int gj = j0 + r;                       // face between rows gj-1 and gj
-            const int ub = r * kUX + f + 3;              // U index of row gj-3 in this column
-            const int pb = r * kPX + f + 1;              // P index of row gj-1
-            const bool lo = gj == 0, hi = gj == ny;
-            const int kf = lo ? F.kind[2] : F.kind[3];
-            const int kp = lo ? G.phi_kind[2] : G.phi_kind[3];
-            const double gp = lo ? G.phi_val[2] : G.phi_val[3];
-            const double fl = drift_face(F, lld(U, ub), lld(U, ub + kUX), lld(U, ub + 2 * kUX), lld(U, ub + 3 * kUX),
-                                         lld(U, ub + 4 * kUX), lld(U, ub + 5 * kUX), lld(P, pb), lld(P, pb + kPX), lld(M, pb),
-                                         lld(M, pb + kPX), ihy, lo, hi, kf, kp, gp);
-            lst(fy, q, drift ? fl : 0.0);
+        // x faces (tile rows 0..7, faces 0..32) then y faces (rows 0..8) in
+        // one loop, with the direction chosen by selects: a wavefront
+        // holding both kinds evaluates each face once
+        constexpr int kNFX = kDY * (kDX + 1), kNFY = (kDY + 1) * kDX;
+        for (int q = tid; q < kNFX + kNFY; q += kBlock) {
+            const bool xf = q < kNFX;
+            const int qy = q - kNFX;
+            const int r = xf ? q / (kDX + 1) : qy / kDX;
+            const int f = xf ? q - r * (kDX + 1) : qy - r * kDX;
+            const int g = xf ? i0 + f : j0 + r;            // face between cells g-1 and g along the direction
+            const int ub = xf ? (r + 3) * kUX + f : r * kUX + f + 3;   // U index of cell g-3
+            const int us = xf ? 1 : kUX;
+            const int pb = xf ? (r + 1) * kPX + f : r * kPX + f + 1;   // P index of cell g-1
+            const int ps = xf ? 1 : kPX;
+            const bool lo = g == 0, hi = g == (xf ? nx : ny);
+            const int kf = xf ? (lo ? F.kind[0] : F.kind[1]) : (lo ? F.kind[2] : F.kind[3]);
+            const int kp = xf ? (lo ? G.phi_kind[0] : G.phi_kind[1]) : (lo ? G.phi_kind[2] : G.phi_kind[3]);
+            const double gp = xf ? (lo ? G.phi_val[0] : G.phi_val[1]) : (lo ? G.phi_val[2] : G.phi_val[3]);
+            const double fl = drift_face(F, lld(U, ub), lld(U, ub + us), lld(U, ub + 2 * us), lld(U, ub + 3 * us),
+                                         lld(U, ub + 4 * us), lld(U, ub + 5 * us), lld(P, pb), lld(P, pb + ps), lld(M, pb),
+                                         lld(M, pb + ps), xf ? ihx : ihy, lo, hi, kf, kp, gp);
+            lst(xf ? fx : fy, xf ? q : qy, drift ? fl : 0.0);
         }
         const double fz_hi = drift ? zface(ph_c, ph_p, mu_c, mu_p, k) : 0.0;
         __syncthreads();
