@@ -2084,6 +2084,7 @@ struct Solver {
     hipGraphExec_t gexec = nullptr;              // one captured cycle (VD_MG_GRAPH)
     std::string gkey;                            // options the graph was captured with
     bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
+    int last_iters = 2;                          // cycles (refinement steps) the previous solve needed
     std::vector<int> use_fused;                  // per level: fused out-of-place sweeps instead of colour passes
     // timed launches of the current solve, credited with the algorithmic
     // bytes of the problems still active at that point once the solve ends
@@ -3162,26 +3163,58 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
                 k_zero_b0<<<S->all0.nd, kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p);
             });
     };
-    while (true) {
-        for (int c = 0; c < chunk; c++) {
-            if (gexec && !(fuse_b && iters == 0)) {
-                VD_HIP(hipGraphLaunch(gexec, s));
-            } else if (!ir) {
-                check(1, 1);
-                if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
-                S->cur_phase = 1;
-                vcycle<double>(ctx, *S, S->d64.p, o);
-            } else {
-                check(2, o->ir_inner);
-                if (async_fixed && iters == o->fixed_cycles) { iters++; break; }
-                S->cur_phase = 1;
-                ir_corrections(ctx, *S, o, ir_fz);
+    if (gexec) {
+        while (true) {
+            for (int c = 0; c < chunk; c++) {
+                if (!(fuse_b && iters == 0)) {
+                    VD_HIP(hipGraphLaunch(gexec, s));
+                } else if (!ir) {
+                    check(1, 1);
+                    S->cur_phase = 1;
+                    vcycle<double>(ctx, *S, S->d64.p, o);
+                } else {
+                    check(2, o->ir_inner);
+                    S->cur_phase = 1;
+                    ir_corrections(ctx, *S, o, ir_fz);
+                }
+                iters++;
             }
-            iters++;
+            if (read_active(ctx, *S) == 0) break;
+            if (iters > 4 * (o->max_cycles + 2) + 8) throw Error{VD_ENOCONV, "internal: convergence loop did not terminate"};
         }
-        if (async_fixed) break;
-        if (read_active(ctx, *S) == 0) break;
-        if (iters > 4 * (o->max_cycles + 2) + 8) throw Error{VD_ENOCONV, "internal: convergence loop did not terminate"};
+    } else {
+        // the cycles the previous solve of this hierarchy needed (or the
+        // fixed count) are issued without a host synchronisation, ending
+        // with a check; then one cycle per check until every problem has
+        // retired
+        const int pred = async_fixed ? o->fixed_cycles : std::max(1, S->last_iters);
+        auto do_check = [&] {
+            if (!ir) check(1, 1);
+            else check(2, o->ir_inner);
+        };
+        auto do_cycle = [&] {
+            S->cur_phase = 1;
+            if (!ir) vcycle<double>(ctx, *S, S->d64.p, o);
+            else ir_corrections(ctx, *S, o, ir_fz);
+            iters++;
+        };
+        for (int c = 0; c <= pred; c++) {
+            do_check();
+            if (c == pred) break;
+            do_cycle();
+        }
+        if (async_fixed) {
+            iters++;
+        } else {
+            while (read_active(ctx, *S) != 0) {
+                do_cycle();
+                do_check();
+                if (iters > 4 * (o->max_cycles + 2) + 8) throw Error{VD_ENOCONV, "internal: convergence loop did not terminate"};
+            }
+            int need = 0;
+            for (int p = 0; p < nprob; p++) need = std::max(need, S->pin_st[p].outer - 1);
+            S->last_iters = need;
+        }
     }
     if (!S->recs.empty()) {
         if (async_fixed) read_active(ctx, *S);
