@@ -3120,9 +3120,14 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
         launch_norm(ctx, *S, 0, 0);
         launch_finalize(ctx, *S, 0, o, 0);
     }
-    timed(ctx, "prep", 0.0, [&] {
-        k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO, 0);
-    });
+    // zero guess, or covered cells of a given guess set to 0 (nothing to do
+    // for a given guess without masks)
+    bool any_mask = false;
+    for (const HProblem &H : S->probs) any_mask = any_mask || H.has_mask;
+    if (o->guess == VD_GUESS_ZERO || any_mask)
+        timed(ctx, "prep", 0.0, [&] {
+            k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, o->guess == VD_GUESS_ZERO, 0);
+        });
     if (!fuse_b)
         timed(ctx, "prep", 0.0, [&] {
             k_prep<<<xcd_grid(S->all0.ntiles), kBlock, 0, s>>>(S->d64.p, S->all0.dev(), S->st.p, 0, 1);
