@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-steps/s at 160^3×15 species; Poisson time-to-1e-10 plain vs learned+FP32"
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["gsrb", "gsrb_fine", "gsrb_uniform", "sweep", "resid_restrict", "prolong", "copy", "coarse", "norm", "finalize", "prep", "ir_update", "weno",
-            "react", "transport", "rho", "setup"]
+            "react", "transport", "rho", "guess", "setup"]
 QE = 1.602176634e-19
 
 
@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--poisson-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
     ap.add_argument("--species-precision", choices=["fp64", "fp32_ir"], default="fp32_ir")
     ap.add_argument("--no-fp64-variant", action="store_true", help="skip the all-FP64 comparison run")
+    ap.add_argument("--poisson-guess", choices=["extrap", "previous"], default="extrap",
+                    help="Poisson initial guess: extrapolated in time from the last three potentials, or the "
+                         "previous potential")
+    ap.add_argument("--no-guess-variant", action="store_true",
+                    help="skip the comparison run with the previous potential as the Poisson guess")
     ap.add_argument("--species-levels", type=int, default=1)
     ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
     ap.add_argument("--ir-inner", type=int, default=1)
@@ -191,12 +196,14 @@ def main():
     lfa["te_K"] = torch.tensor(cfg["lfa"]["te_K"], device=dev)
     prec = {"fp64": V.FP64, "fp32_ir": V.FP32_IR}
     tune = not args.no_autotune
-    popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune)
+    pguess = V.GUESS_EXTRAP if args.poisson_guess == "extrap" else V.GUESS_GIVEN
+    popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune,
+                      guess=pguess)
     sopts = V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
                       nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune)
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
-    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune),
+    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune, guess=pguess),
                         species_mg=V.mg_opts(rtol=1e-10, n_levels=args.species_levels, nu_pre=args.species_nu[0],
                                              nu_post=args.species_nu[1], autotune=tune))
     state0 = {k: v.clone() for k, v in state.items()}
@@ -264,6 +271,27 @@ def main():
                         "species_cycles_last_step": i64["species_cycles"]}
         del st64
         log("[bench] all-FP64 variant: %s" % fp64_variant)
+
+    # the same steps with the previous potential as the Poisson guess
+    guess_variant = None
+    if args.poisson_guess == "extrap" and not args.no_guess_variant:
+        PG = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(
+            rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune), species_mg=sopts)
+        stg = {k: v.clone() for k, v in state0.items()}
+        for w in range(args.warmup):
+            ctx.vd_step(PG, stg, want_info=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(args.steps):
+            ctx.vd_step(PG, stg, want_info=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ig = ctx.vd_step(PG, stg)
+        guess_variant = {"value": round(ncell * args.steps / el, 1), "ms_per_step": round(el * 1e3 / args.steps, 4),
+                         "poisson_cycles_last_step": ig["poisson_cycles"],
+                         "species_cycles_last_step": ig["species_cycles"]}
+        del stg
+        log("[bench] previous-potential guess variant: %s" % guess_variant)
 
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
@@ -353,9 +381,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Ar-H2 15-species streamer step, %d^3 cells, dt 1e-12 s, LFA Te, 15 kV plates" % n,
                    "grid": [n, n, n], "species": 15, "dt": 1e-12,
-                   "poisson": "%s%s rtol 1e-10 warm start%s" % (
+                   "poisson": "%s%s rtol 1e-10, guess %s%s" % (
                        args.poisson_precision, " inner %d" % args.ir_inner if args.poisson_precision == "fp32_ir" else "",
-                       ", autotuned tiles" if tune else ""),
+                       "extrapolated from the last three potentials" if args.poisson_guess == "extrap"
+                       else "the previous potential", ", autotuned tiles" if tune else ""),
                    "species_solve": "%s levels %d nu %s rtol 1e-10" % (args.species_precision, args.species_levels,
                                                                        list(args.species_nu)),
                    "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
@@ -363,6 +392,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_variant": fp64_variant,
+        "previous_potential_guess_variant": guess_variant,
         "error_vs_fp64_oracle": errors,
         "poisson_time_to_1e-10": poisson,
         "batched_helmholtz_64": batch,

@@ -48,7 +48,11 @@ typedef enum {
 enum { VD_BC_DIRICHLET = 0, VD_BC_NEUMANN = 1, VD_BC_WALLFLUX = 2, VD_BC_PERIODIC = 3 };
 
 enum { VD_FP64 = 0, VD_FP32_IR = 1 };                               /* vd_mg_opts.precision */
-enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2 }; /* vd_mg_opts.guess */
+/* vd_mg_opts.guess.  VD_GUESS_EXTRAP (vd_step's Poisson solve only; not in
+ * the paper): the solve starts from a polynomial extrapolation in time of
+ * the potentials passed in by this context's earlier vd_step calls, see
+ * vd_step. */
+enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2, VD_GUESS_EXTRAP = 3 };
 /* vd_mg_opts.flags.  VD_MG_GRAPH: in tolerance mode each cycle (residual
  * check + V-cycle, or the IR outer step) is replayed from a HIP graph
  * captured on the first call for this problem shape and options, instead of
@@ -249,7 +253,19 @@ typedef struct {
  *   (+ extra_source);  u^{n+1} = u^{n_t}.
  * The species solves of each corrector go through one batched multigrid
  * solve.  No host copies happen inside the step besides the per-solve
- * convergence words. */
+ * convergence words.
+ * poisson.guess = VD_GUESS_EXTRAP (not in the paper): the context keeps the
+ * phi arrays passed in by its last two such calls (h1 the previous, h2 the
+ * one before) for the same phi pointer, grid and dt; a change of any of
+ * these restarts the history, and the phi of the first call after a restart
+ * (the caller's initial guess rather than a step result) is not kept.  The
+ * first corrector's Poisson solve then starts from 2 phi - h1 (one array
+ * kept) or 3 phi - 3 h1 + h2 (two; each product and sum rounded on its
+ * own, in that order) instead of phi, and still stops on the same residual
+ * test, so the result differs from a VD_GUESS_GIVEN step only within the
+ * solver tolerance.  The history holds the arrays as passed in: the phi a
+ * step returns, unless the caller changed it between calls.  Costs two cell
+ * arrays of device memory. */
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
                   vd_step_info *info /* host, nullable */);
 

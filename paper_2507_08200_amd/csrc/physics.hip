@@ -824,6 +824,31 @@ __global__ void __launch_bounds__(kBlock) k_mid(const double *__restrict__ u0, c
     if (c < n) gst(out, c, 0.5 * (gld(u0, c) + gld(u, c)));
 }
 
+// Poisson guess extrapolated in time from the potentials passed in by
+// earlier steps: a = phi on entry, h1 the previous step's, h2 the one
+// before (held in hdst).  order 1: 2a - h1; order 2: 3a - 3h1 + h2, every
+// product and sum a statement of its own (rounded separately, no fused
+// multiply-add); order 0 leaves phi.  a is then kept in hdst, which becomes
+// the newest history slot.
+__global__ void __launch_bounds__(kBlock) k_extrap(double *__restrict__ phi, const double *__restrict__ h1,
+                                                   double *__restrict__ hdst, int order, long n) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double a = gld(phi, c);
+    if (order == 1) {
+        const double t = 2.0 * a;
+        const double g = t - gld(h1, c);
+        gst(phi, c, g);
+    } else if (order == 2) {
+        const double t0 = 3.0 * a;
+        const double t1 = 3.0 * gld(h1, c);
+        const double t2 = t0 - t1;
+        const double g = t2 + gld(hdst, c);
+        gst(phi, c, g);
+    }
+    gst(hdst, c, a);
+}
+
 // ------------------------------------------------------ electron energy
 // Central diffusive flux along +d at face fidx: -beta_f (u_R - u_L)/h with
 // the harmonic-mean face coefficient; Dirichlet face: one-sided over half a
@@ -962,6 +987,11 @@ void launch_rho(vd_ctx *ctx, const RhoArgs &a) {
 
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
     timed(ctx, "energy", (double)a.g.ncell, [&] { k_energy_rhs<<<ceil_div(a.g.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n) {
+    const double bytes = (double)n * (order == 0 ? 16.0 : (order == 1 ? 32.0 : 40.0));
+    timed(ctx, "guess", bytes, [&] { k_extrap<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(phi, h1, hdst, order, n); });
 }
 
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n) {

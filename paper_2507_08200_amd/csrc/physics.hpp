@@ -98,6 +98,8 @@ void launch_react(vd_ctx *ctx, const ReactArgs &a);
 void launch_rho(vd_ctx *ctx, const RhoArgs &a);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
+// Poisson guess extrapolated from earlier steps' potentials (order 0..2)
+void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n);
 
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
                          const char *cache_tag);

@@ -14,6 +14,19 @@ struct StepBuffers {
     DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
 };
 
+// phi arrays passed in by the previous steps with an extrapolated Poisson
+// guess, except the first call after a restart (its phi is the caller's
+// initial guess, not a step result): slot[newest] the last one,
+// slot[1 - newest] the one before (valid when count is 2); count -1 right
+// after a restart.  Keyed by the phi pointer, the grid and dt.
+struct PhiHistory {
+    DevBuf<double> slot[2];
+    int count = -1, newest = 0;
+    const double *phi = nullptr;
+    int nx = 0, ny = 0, nz = 0;
+    double dt = 0.0;
+};
+
 static void validate_step(const vd_step_params *P, const vd_state *st) {
     VD_CHECK(P && st, "null params or state");
     const vd_grid &g = P->grid;
@@ -24,6 +37,8 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
     VD_CHECK(P->species && P->species_bc, "species and species_bc are required");
     VD_CHECK(st->n && st->phi && st->Te, "state n, phi and Te are required");
     VD_CHECK(P->te_mode >= VD_TE_FIXED && P->te_mode <= VD_TE_ENERGY, "unknown te_mode");
+    VD_CHECK(P->poisson.guess == VD_GUESS_GIVEN || P->poisson.guess == VD_GUESS_ZERO || P->poisson.guess == VD_GUESS_EXTRAP,
+             "the step's Poisson guess must be GIVEN, ZERO or EXTRAP");
     if (P->te_mode == VD_TE_LFA) VD_CHECK(P->lfa_te && P->lfa_n >= 2 && P->lfa_ln_max > P->lfa_ln_min, "LFA table required");
     if (P->te_mode == VD_TE_ENERGY) {
         VD_CHECK(st->Ee, "Ee required in energy mode");
@@ -124,6 +139,34 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
     if (want_info) for (auto &e : ev) VD_HIP(hipEventCreate(&e));
     double ms_poisson = 0, ms_transport = 0, ms_energy = 0, ms_species = 0;
 
+    // Poisson guess of the first corrector extrapolated in time from the
+    // phi arrays of the previous steps (history restarted on a new array,
+    // grid or dt)
+    vd_mg_opts popt = P->poisson;
+    if (popt.guess == VD_GUESS_EXTRAP) {
+        std::shared_ptr<PhiHistory> H;
+        auto ih = ctx->cache.find("phi_history");
+        if (ih != ctx->cache.end()) H = std::static_pointer_cast<PhiHistory>(ih->second);
+        else { H = std::make_shared<PhiHistory>(); ctx->cache["phi_history"] = H; }
+        if (H->phi != st->phi || H->nx != g.nx || H->ny != g.ny || H->nz != g.nz || H->dt != P->dt) {
+            H->count = -1;
+            H->newest = 0;
+            H->phi = st->phi;
+            H->nx = g.nx; H->ny = g.ny; H->nz = g.nz;
+            H->dt = P->dt;
+        }
+        if (H->count < 0) {
+            H->count = 0;
+        } else {
+            H->slot[0].alloc(N);
+            H->slot[1].alloc(N);
+            launch_extrap(ctx, st->phi, H->slot[H->newest].p, H->slot[1 - H->newest].p, H->count, N);
+            H->newest = 1 - H->newest;
+            H->count = H->count < 2 ? H->count + 1 : 2;
+        }
+        popt.guess = VD_GUESS_GIVEN;
+    }
+
     for (int m = 0; m < P->n_t; m++) {
         // ---- u* = (u^n + u^m)/2
         const double *nst = st->n;
@@ -145,7 +188,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         pp.grid = g; pp.bc = P->phi_bc; pp.beta = P->eps_cell; pp.beta_c = P->consts.eps0;
         pp.rhs = B->rho.p; pp.x = st->phi;
         vd_solve_info pinfo;
-        mg_solve_batch(ctx, 1, &pp, &P->poisson, &pinfo, "poisson:");
+        mg_solve_batch(ctx, 1, &pp, &popt, &pinfo, "poisson:");
         I.poisson_cycles += pinfo.cycles;
         I.poisson_rel = pinfo.rel_res;
         if (want_info) VD_HIP(hipEventRecord(ev[1], s));

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libvd.so")
 VD_OK, VD_EINVAL, VD_ENOMEM, VD_EHIP, VD_ENOCONV, VD_ESINGULAR = 0, -1, -2, -3, -4, -5
 BC_DIRICHLET, BC_NEUMANN, BC_WALLFLUX, BC_PERIODIC = 0, 1, 2, 3
 FP64, FP32_IR = 0, 1
-GUESS_GIVEN, GUESS_ZERO, GUESS_LEARNED = 0, 1, 2
+GUESS_GIVEN, GUESS_ZERO, GUESS_LEARNED, GUESS_EXTRAP = 0, 1, 2, 3
 MG_GRAPH, MG_AUTOTUNE, MG_FUSED_SWEEP = 1, 2, 4
 TE_FIXED, TE_LFA, TE_ENERGY = 0, 1, 2
 MECH_NONE, MECH_DECAY, MECH_AR3, MECH_ARH2_15 = 0, 1, 2, 3

@@ -1,0 +1,157 @@
+"""Poisson guess of vd_step extrapolated in time (VD_GUESS_EXTRAP): each
+step equals, bit for bit, a VD_GUESS_GIVEN step whose phi is the stated
+polynomial of the potentials passed in by the earlier steps (computed here
+in numpy, one rounding per operation); the history restarts on a new dt or
+a new phi array; and a step from the extrapolated guess matches the FP64
+oracle started from that guess."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import dev, host, rel_err, say  # noqa: E402
+from paper_2507_08200_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_08200_amd import vd
+    vd.load()
+    return vd
+
+
+def _setup(V, cfg, guess, **popts):
+    from paper_2507_08200_amd import mechanisms as M
+    lfa = dict(cfg["lfa"])
+    lfa["te_K"] = dev(cfg["lfa"]["te_K"])
+    sp = dict(n_levels=1, nu_pre=1, nu_post=1)
+    P = V.step_params(cfg, M.arh2_15(), lfa=lfa, poisson=V.mg_opts(guess=guess, **popts),
+                      species_mg=V.mg_opts(rtol=1e-10, **sp))
+    return P
+
+
+def _guess(a, hist):
+    """The extrapolation from the inputs of the earlier calls (newest last)."""
+    if not hist:
+        return a
+    if len(hist) == 1:
+        return 2.0 * a - hist[-1]
+    t0 = 3.0 * a
+    t1 = 3.0 * hist[-1]
+    return (t0 - t1) + hist[-2]
+
+
+def _same(sa, sb):
+    return all(torch.equal(sa[k], sb[k]) for k in ("n", "phi", "Te"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_extrap_equals_given_polynomial(V, precision):
+    cfg = I.cfg3(n=32)
+    prec = V.FP64 if precision == "fp64" else V.FP32_IR
+    PX = _setup(V, cfg, V.GUESS_EXTRAP, rtol=1e-10, precision=prec, ir_inner=1)
+    PG = _setup(V, cfg, V.GUESS_GIVEN, rtol=1e-10, precision=prec, ir_inner=1)
+    ca, cb = V.Context(), V.Context()
+    sa = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    sb = {k: v.clone() for k, v in sa.items()}
+    hist = []
+    cycles = []
+    for step in range(6):
+        say("extrap step", step, precision)
+        a = host(sb["phi"])
+        sb["phi"].copy_(dev(_guess(a, hist)))
+        if step > 0:
+            # the first call's phi (the initial guess) is not kept
+            hist = (hist + [a])[-2:]
+        ia = ca.vd_step(PX, sa)
+        ib = cb.vd_step(PG, sb)
+        assert ia["status"] == 0 and ib["status"] == 0
+        assert ia["poisson_cycles"] == ib["poisson_cycles"]
+        cycles.append(ia["poisson_cycles"])
+        assert _same(sa, sb), step
+    say("   poisson cycles", cycles)
+
+
+def test_extrap_history_restarts(V):
+    cfg = I.cfg3(n=24)
+    PX = _setup(V, cfg, V.GUESS_EXTRAP, rtol=1e-10)
+    PG = _setup(V, cfg, V.GUESS_GIVEN, rtol=1e-10)
+    ctx, cg = V.Context(), V.Context()
+    s = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    for _ in range(3):
+        assert ctx.vd_step(PX, s)["status"] == 0
+    # a new dt: the first step after it starts from phi itself
+    cfg2 = dict(cfg)
+    cfg2["dt"] = 0.5 * cfg["dt"]
+    PX2 = _setup(V, cfg2, V.GUESS_EXTRAP, rtol=1e-10)
+    PG2 = _setup(V, cfg2, V.GUESS_GIVEN, rtol=1e-10)
+    sg = {k: v.clone() for k, v in s.items()}
+    ctx.vd_step(PX2, s)
+    cg.vd_step(PG2, sg)
+    assert _same(s, sg)
+    # the second keeps its phi and starts from it; the third extrapolates
+    # linearly from the second's phi
+    a = host(s["phi"])
+    ctx.vd_step(PX2, s)
+    cg.vd_step(PG2, sg)
+    assert _same(s, sg)
+    b = host(sg["phi"])
+    sg["phi"].copy_(dev(_guess(b, [a])))
+    ctx.vd_step(PX2, s)
+    cg.vd_step(PG2, sg)
+    assert _same(s, sg)
+    # a different phi array restarts it as well
+    s2 = {k: v.clone() for k, v in s.items()}
+    sg2 = {k: v.clone() for k, v in s.items()}
+    ctx.vd_step(PX2, s2)
+    cg.vd_step(PG2, sg2)
+    assert _same(s2, sg2)
+    # the other guess kinds of the step are refused with a clear error
+    with pytest.raises(Exception):
+        ctx.vd_step(_setup(V, cfg, V.GUESS_LEARNED, rtol=1e-10), s)
+
+
+def test_extrap_step_matches_oracle(V, oracle):
+    cfg = I.cfg3(n=24)
+    PX = _setup(V, cfg, V.GUESS_EXTRAP, rtol=1e-10)
+    ctx = V.Context()
+    s = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    hist = []
+    for k in range(3):
+        if k > 0:
+            hist.append(host(s["phi"]))
+        assert ctx.vd_step(PX, s)["status"] == 0
+    # fourth step in fixed-cycle mode (cycles of a tolerance-mode probe)
+    probe = {k: v.clone() for k, v in s.items()}
+    cp = V.Context()
+    g = _guess(host(s["phi"]), hist)
+    probe["phi"].copy_(dev(g))
+    ip = cp.vd_step(_setup(V, cfg, V.GUESS_GIVEN, rtol=1e-10), probe)
+    pc, sc = max(ip["poisson_cycles"], 1), ip["species_cycles"]
+    from paper_2507_08200_amd import mechanisms as M
+    lfa = dict(cfg["lfa"])
+    lfa["te_K"] = dev(cfg["lfa"]["te_K"])
+    sp = dict(n_levels=1, nu_pre=1, nu_post=1)
+    PF = V.step_params(cfg, M.arh2_15(), lfa=lfa, poisson=V.mg_opts(fixed_cycles=pc, guess=V.GUESS_EXTRAP),
+                       species_mg=V.mg_opts(fixed_cycles=sc, **sp))
+    cfg_in = dict(cfg)
+    cfg_in["n"] = host(s["n"])
+    cfg_in["Te"] = host(s["Te"])
+    cfg_in["phi"] = g
+    assert ctx.vd_step(PF, s)["status"] == 0
+    say("   oracle replays", pc, sc, "cycles from the extrapolated guess")
+    ref = oracle.step(cfg_in, oracle.species_arh2_15(), poisson=oracle.mg_opts(fixed_cycles=pc),
+                      species_mg=oracle.mg_opts(fixed_cycles=sc, **sp))
+    assert ref["status"] == 0
+    errs = {"phi": rel_err(host(s["phi"]), ref["phi"]), "Te": rel_err(host(s["Te"]), ref["Te"])}
+    n = host(s["n"])
+    for k in range(15):
+        errs["n%d" % k] = rel_err(n[k], ref["n"][k])
+    say("   errors", {k: "%.1e" % v for k, v in errs.items()})
+    assert max(errs.values()) <= TOL
