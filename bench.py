@@ -47,8 +47,11 @@ def parse():
     ap.add_argument("--poisson-guess", choices=["extrap", "previous"], default="extrap",
                     help="Poisson initial guess: extrapolated in time from the last three potentials, or the "
                          "previous potential")
+    ap.add_argument("--species-guess", choices=["extrap", "previous"], default="extrap",
+                    help="species initial guesses: extrapolated linearly from the last two steps, or the current "
+                         "densities")
     ap.add_argument("--no-guess-variant", action="store_true",
-                    help="skip the comparison run with the previous potential as the Poisson guess")
+                    help="skip the comparison run with the previous step's values as the guesses")
     ap.add_argument("--species-levels", type=int, default=1)
     ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
     ap.add_argument("--ir-inner", type=int, default=1)
@@ -199,13 +202,14 @@ def main():
     pguess = V.GUESS_EXTRAP if args.poisson_guess == "extrap" else V.GUESS_GIVEN
     popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune,
                       guess=pguess)
+    sguess = V.GUESS_EXTRAP if args.species_guess == "extrap" else V.GUESS_GIVEN
     sopts = V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
-                      nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune)
+                      nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune, guess=sguess)
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
     P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune, guess=pguess),
                         species_mg=V.mg_opts(rtol=1e-10, n_levels=args.species_levels, nu_pre=args.species_nu[0],
-                                             nu_post=args.species_nu[1], autotune=tune))
+                                             nu_post=args.species_nu[1], autotune=tune, guess=sguess))
     state0 = {k: v.clone() for k, v in state.items()}
     ctx = V.Context()
     if args.calibrate_copy_mib > 0:
@@ -272,11 +276,13 @@ def main():
         del st64
         log("[bench] all-FP64 variant: %s" % fp64_variant)
 
-    # the same steps with the previous potential as the Poisson guess
+    # the same steps with the previous step's values as the guesses
     guess_variant = None
-    if args.poisson_guess == "extrap" and not args.no_guess_variant:
+    if "extrap" in (args.poisson_guess, args.species_guess) and not args.no_guess_variant:
         PG = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(
-            rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune), species_mg=sopts)
+            rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune),
+            species_mg=V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
+                                 nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune))
         stg = {k: v.clone() for k, v in state0.items()}
         for w in range(args.warmup):
             ctx.vd_step(PG, stg, want_info=False)
@@ -291,7 +297,7 @@ def main():
                          "poisson_cycles_last_step": ig["poisson_cycles"],
                          "species_cycles_last_step": ig["species_cycles"]}
         del stg
-        log("[bench] previous-potential guess variant: %s" % guess_variant)
+        log("[bench] previous-values guess variant: %s" % guess_variant)
 
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
@@ -385,14 +391,16 @@ def main():
                        args.poisson_precision, " inner %d" % args.ir_inner if args.poisson_precision == "fp32_ir" else "",
                        "extrapolated from the last three potentials" if args.poisson_guess == "extrap"
                        else "the previous potential", ", autotuned tiles" if tune else ""),
-                   "species_solve": "%s levels %d nu %s rtol 1e-10" % (args.species_precision, args.species_levels,
-                                                                       list(args.species_nu)),
+                   "species_solve": "%s levels %d nu %s rtol 1e-10, guess %s" % (
+                       args.species_precision, args.species_levels, list(args.species_nu),
+                       "extrapolated from the last two steps" if args.species_guess == "extrap"
+                       else "the current densities"),
                    "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
                    "poisson_cycles_last_step": cyc_p, "species_cycles_last_step": cyc_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_variant": fp64_variant,
-        "previous_potential_guess_variant": guess_variant,
+        "previous_values_guess_variant": guess_variant,
         "error_vs_fp64_oracle": errors,
         "poisson_time_to_1e-10": poisson,
         "batched_helmholtz_64": batch,

@@ -48,10 +48,10 @@ typedef enum {
 enum { VD_BC_DIRICHLET = 0, VD_BC_NEUMANN = 1, VD_BC_WALLFLUX = 2, VD_BC_PERIODIC = 3 };
 
 enum { VD_FP64 = 0, VD_FP32_IR = 1 };                               /* vd_mg_opts.precision */
-/* vd_mg_opts.guess.  VD_GUESS_EXTRAP (vd_step's Poisson solve only; not in
- * the paper): the solve starts from a polynomial extrapolation in time of
- * the potentials passed in by this context's earlier vd_step calls, see
- * vd_step. */
+/* vd_mg_opts.guess.  VD_GUESS_EXTRAP (vd_step's Poisson and species solves
+ * only; not in the paper): the solve starts from a polynomial extrapolation
+ * in time of the arrays passed in by this context's earlier vd_step calls,
+ * see vd_step. */
 enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2, VD_GUESS_EXTRAP = 3 };
 /* vd_mg_opts.flags.  VD_MG_GRAPH: in tolerance mode each cycle (residual
  * check + V-cycle, or the IR outer step) is replayed from a HIP graph
@@ -265,7 +265,13 @@ typedef struct {
  * test, so the result differs from a VD_GUESS_GIVEN step only within the
  * solver tolerance.  The history holds the arrays as passed in: the phi a
  * step returns, unless the caller changed it between calls.  Costs two cell
- * arrays of device memory. */
+ * arrays of device memory.
+ * species_mg.guess = VD_GUESS_EXTRAP: the same for the transported species
+ * with a linear extrapolation: the context keeps n of the last call (for the
+ * same n pointer, grid, S, dt and set of transported species; restarted and
+ * skipped as above), and once the first corrector's right-hand sides are
+ * built (they hold n^n), its species solves start from 2 n - h1 instead of
+ * n.  Costs S cell arrays.  energy_mg.guess must be GIVEN or ZERO. */
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
                   vd_step_info *info /* host, nullable */);
 

@@ -80,7 +80,8 @@ class StepParams(C.Structure):
                 ("lfa_te", C.c_void_p), ("lfa_ln_min", C.c_double), ("lfa_ln_max", C.c_double),
                 ("lfa_n", C.c_int32), ("pad1", C.c_int32),
                 ("extra_source", C.c_void_p), ("extra_energy", C.c_void_p), ("eps_cell", C.c_void_p),
-                ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts)]
+                ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts),
+                ("species_guess", C.c_void_p)]
 
 
 class StepInfo(C.Structure):
@@ -296,8 +297,10 @@ def species_flux(g, phi_bc, sp_bcs, species, n, phi, mu, Te, Tg, consts=PHYS):
 
 def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poisson=None, species_mg=None,
          energy_mg=None, extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0,
-         k_decay=0.0):
-    """One step of the semi-implicit scheme on a workload dict (see inputs)."""
+         k_decay=0.0, species_guess=None):
+    """One step of the semi-implicit scheme on a workload dict (see inputs).
+    species_guess ([S][cells], optional): starting iterate of the first
+    corrector's species solves in place of n^n."""
     n = _f64(cfg["n"] if n is None else n).copy()
     phi = _f64(cfg["phi"] if phi is None else phi).copy()
     Te = _f64(cfg["Te"] if Te is None else Te).copy()
@@ -333,7 +336,8 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
         P.lfa_ln_min = cfg["lfa"]["ln_en_min"]
         P.lfa_ln_max = cfg["lfa"]["ln_en_max"]
         P.lfa_n = cfg["lfa"]["npts"]
-    for name, arr in (("extra_source", extra_source), ("extra_energy", extra_energy), ("eps_cell", eps_cell)):
+    for name, arr in (("extra_source", extra_source), ("extra_energy", extra_energy), ("eps_cell", eps_cell),
+                      ("species_guess", species_guess)):
         if arr is not None:
             a = _f64(arr)
             keep.append(a)

@@ -102,6 +102,8 @@ typedef struct {
     const double *extra_energy;     /* [cells] or NULL */
     const double *eps_cell;         /* permittivity field or NULL (eps0) */
     or_mg_opts poisson, species_mg, energy_mg;
+    const double *species_guess;    /* [S][cells] or NULL: starting iterate of the first corrector's
+                                       species solves instead of n^n (a solver started elsewhere) */
 } or_step_params;
 
 typedef struct {
@@ -1348,6 +1350,8 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             int varD = P->species[k].mob_kind == OR_MOB_ELECTRON_FIT;
             or_problem SP = { *g, P->species_bc[k], NULL, NULL, 1.0 / dt, varD ? Dk + k * nc : NULL, Dk[k * nc] };
             for (int f = 0; f < 6; f++) if (SP.bc.kind[f] == OR_WALL) SP.bc.kind[f] = OR_NEU;
+            if (m == 0 && P->species_guess)
+                for (size_t c = 0; c < nc; c++) n[k * nc + c] = P->species_guess[k * nc + c];
             int st2 = or_mg_solve(&SP, rhs, n + k * nc, &P->species_mg, &mi);
             if (mi.cycles > info->species_cycles) info->species_cycles = mi.cycles;
             if (st2 != OR_OK) { status = st2; goto out; }

@@ -849,6 +849,23 @@ __global__ void __launch_bounds__(kBlock) k_extrap(double *__restrict__ phi, con
     gst(hdst, c, a);
 }
 
+// Species guesses extrapolated linearly in time, one species per
+// blockIdx.y: a = n on entry, h the previous step's n; n <- 2a - h (when
+// have_h) and h <- a.
+__global__ void __launch_bounds__(kBlock) k_extrap_species(ExtrapSet e, int have_h, long n) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double *__restrict__ x = e.x[blockIdx.y];
+    double *__restrict__ h = e.h[blockIdx.y];
+    const double a = gld(x, c);
+    if (have_h) {
+        const double t = 2.0 * a;
+        const double g = t - gld(h, c);
+        gst(x, c, g);
+    }
+    gst(h, c, a);
+}
+
 // ------------------------------------------------------ electron energy
 // Central diffusive flux along +d at face fidx: -beta_f (u_R - u_L)/h with
 // the harmonic-mean face coefficient; Dirichlet face: one-sided over half a
@@ -992,6 +1009,14 @@ void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
 void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n) {
     const double bytes = (double)n * (order == 0 ? 16.0 : (order == 1 ? 32.0 : 40.0));
     timed(ctx, "guess", bytes, [&] { k_extrap<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(phi, h1, hdst, order, n); });
+}
+
+void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int have_h, long n) {
+    if (count == 0) return;
+    const double bytes = (double)n * count * (have_h ? 32.0 : 16.0);
+    timed(ctx, "guess", bytes, [&] {
+        k_extrap_species<<<dim3(ceil_div(n, kBlock), count), kBlock, 0, ctx->stream>>>(e, have_h, n);
+    });
 }
 
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n) {

@@ -27,6 +27,19 @@ struct PhiHistory {
     double dt = 0.0;
 };
 
+// species arrays passed in by the previous steps with extrapolated species
+// guesses (same restart rule as PhiHistory): h holds the last one per
+// species; count -1 right after a restart, 0 nothing kept yet, 1 kept.
+// Keyed by the n pointer, the grid, S, dt and the transported species.
+struct SpeciesHistory {
+    DevBuf<double> h;
+    int count = -1;
+    const double *n = nullptr;
+    int nx = 0, ny = 0, nz = 0, S = 0;
+    double dt = 0.0;
+    uint32_t transported = 0;
+};
+
 static void validate_step(const vd_step_params *P, const vd_state *st) {
     VD_CHECK(P && st, "null params or state");
     const vd_grid &g = P->grid;
@@ -39,6 +52,11 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
     VD_CHECK(P->te_mode >= VD_TE_FIXED && P->te_mode <= VD_TE_ENERGY, "unknown te_mode");
     VD_CHECK(P->poisson.guess == VD_GUESS_GIVEN || P->poisson.guess == VD_GUESS_ZERO || P->poisson.guess == VD_GUESS_EXTRAP,
              "the step's Poisson guess must be GIVEN, ZERO or EXTRAP");
+    VD_CHECK(P->species_mg.guess == VD_GUESS_GIVEN || P->species_mg.guess == VD_GUESS_ZERO ||
+                 P->species_mg.guess == VD_GUESS_EXTRAP,
+             "the step's species guess must be GIVEN, ZERO or EXTRAP");
+    VD_CHECK(P->energy_mg.guess == VD_GUESS_GIVEN || P->energy_mg.guess == VD_GUESS_ZERO,
+             "the step's energy guess must be GIVEN or ZERO");
     if (P->te_mode == VD_TE_LFA) VD_CHECK(P->lfa_te && P->lfa_n >= 2 && P->lfa_ln_max > P->lfa_ln_min, "LFA table required");
     if (P->te_mode == VD_TE_ENERGY) {
         VD_CHECK(st->Ee, "Ee required in energy mode");
@@ -166,6 +184,25 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         }
         popt.guess = VD_GUESS_GIVEN;
     }
+    // species guesses of the first corrector: history kept the same way
+    vd_mg_opts sopt = P->species_mg;
+    std::shared_ptr<SpeciesHistory> SH;
+    if (sopt.guess == VD_GUESS_EXTRAP) {
+        auto ih = ctx->cache.find("species_history");
+        if (ih != ctx->cache.end()) SH = std::static_pointer_cast<SpeciesHistory>(ih->second);
+        else { SH = std::make_shared<SpeciesHistory>(); ctx->cache["species_history"] = SH; }
+        uint32_t tmask = 0;
+        for (int k = 0; k < S; k++) if (P->species[k].transported) tmask |= 1u << k;
+        if (SH->n != st->n || SH->nx != g.nx || SH->ny != g.ny || SH->nz != g.nz || SH->S != S || SH->dt != P->dt ||
+            SH->transported != tmask) {
+            SH->count = -1;
+            SH->n = st->n;
+            SH->nx = g.nx; SH->ny = g.ny; SH->nz = g.nz; SH->S = S;
+            SH->dt = P->dt;
+            SH->transported = tmask;
+        }
+        sopt.guess = VD_GUESS_GIVEN;
+    }
 
     for (int m = 0; m < P->n_t; m++) {
         // ---- u* = (u^n + u^m)/2
@@ -287,10 +324,30 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             nf++;
         }
         launch_drift(ctx, da, fds, nf, "step");
+        // the right-hand sides hold u^n now: the first corrector's species
+        // iterates may start from the extrapolated guesses
+        if (SH && m == 0) {
+            if (SH->count < 0) {
+                SH->count = 0;
+            } else {
+                SH->h.alloc((size_t)N * S);
+                ExtrapSet e;
+                memset(&e, 0, sizeof(e));
+                int q = 0;
+                for (int k = 0; k < S; k++) {
+                    if (!P->species[k].transported) continue;
+                    e.x[q] = st->n + (long)k * N;
+                    e.h[q] = SH->h.p + (long)k * N;
+                    q++;
+                }
+                launch_extrap_species(ctx, e, q, SH->count, N);
+                SH->count = 1;
+            }
+        }
         if (want_info) VD_HIP(hipEventRecord(ev[4], s));
         if (nf) {
             vd_solve_info sinfo[32];
-            mg_solve_batch(ctx, nf, sp, &P->species_mg, want_info ? sinfo : nullptr, "species:");
+            mg_solve_batch(ctx, nf, sp, &sopt, want_info ? sinfo : nullptr, "species:");
             if (want_info)
                 for (int q = 0; q < nf; q++) I.species_cycles = std::max(I.species_cycles, sinfo[q].cycles);
         }
