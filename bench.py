@@ -48,7 +48,7 @@ def parse():
                     help="Poisson initial guess: extrapolated in time from the last three potentials, or the "
                          "previous potential")
     ap.add_argument("--species-guess", choices=["extrap", "previous"], default="extrap",
-                    help="species initial guesses: extrapolated linearly from the last two steps, or the current "
+                    help="species initial guesses: extrapolated from the last three steps, or the current "
                          "densities")
     ap.add_argument("--no-guess-variant", action="store_true",
                     help="skip the comparison run with the previous step's values as the guesses")
@@ -393,7 +393,7 @@ def main():
                        else "the previous potential", ", autotuned tiles" if tune else ""),
                    "species_solve": "%s levels %d nu %s rtol 1e-10, guess %s" % (
                        args.species_precision, args.species_levels, list(args.species_nu),
-                       "extrapolated from the last two steps" if args.species_guess == "extrap"
+                       "extrapolated from the last three steps" if args.species_guess == "extrap"
                        else "the current densities"),
                    "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
                    "poisson_cycles_last_step": cyc_p, "species_cycles_last_step": cyc_s},

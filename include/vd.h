@@ -266,12 +266,14 @@ typedef struct {
  * solver tolerance.  The history holds the arrays as passed in: the phi a
  * step returns, unless the caller changed it between calls.  Costs two cell
  * arrays of device memory.
- * species_mg.guess = VD_GUESS_EXTRAP: the same for the transported species
- * with a linear extrapolation: the context keeps n of the last call (for the
- * same n pointer, grid, S, dt and set of transported species; restarted and
+ * species_mg.guess = VD_GUESS_EXTRAP: the same for the transported species:
+ * the context keeps n of the last two calls rounded to FP32 (for the same n
+ * pointer, grid, S, dt and set of transported species; restarted and
  * skipped as above), and once the first corrector's right-hand sides are
- * built (they hold n^n), its species solves start from 2 n - h1 instead of
- * n.  Costs S cell arrays.  energy_mg.guess must be GIVEN or ZERO. */
+ * built (they hold n^n), its species solves start from 2 n - h1 or
+ * 3 n - 3 h1 + h2 (h widened to FP64; rounded as for phi) instead of n.
+ * Costs S cell arrays of device memory.  energy_mg.guess must be GIVEN or
+ * ZERO. */
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
                   vd_step_info *info /* host, nullable */);
 

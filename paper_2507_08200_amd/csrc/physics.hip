@@ -849,21 +849,30 @@ __global__ void __launch_bounds__(kBlock) k_extrap(double *__restrict__ phi, con
     gst(hdst, c, a);
 }
 
-// Species guesses extrapolated linearly in time, one species per
-// blockIdx.y: a = n on entry, h the previous step's n; n <- 2a - h (when
-// have_h) and h <- a.
-__global__ void __launch_bounds__(kBlock) k_extrap_species(ExtrapSet e, int have_h, long n) {
+// Species guesses extrapolated in time, one species per blockIdx.y, with
+// the history in FP32 (its rounding, ~1e-7 of n, is far below what the
+// guess needs): a = n on entry, h1 the previous step's n, h2 the one before
+// (held in hd).  order 1: n <- 2a - h1; order 2: n <- 3a - 3h1 + h2, every
+// product and sum a statement of its own; order 0 leaves n.  hd <- (float)a.
+__global__ void __launch_bounds__(kBlock) k_extrap_species(ExtrapSet e, int order, long n) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     double *__restrict__ x = e.x[blockIdx.y];
-    double *__restrict__ h = e.h[blockIdx.y];
+    const float *__restrict__ h1 = e.h1[blockIdx.y];
+    float *__restrict__ hd = e.hd[blockIdx.y];
     const double a = gld(x, c);
-    if (have_h) {
+    if (order == 1) {
         const double t = 2.0 * a;
-        const double g = t - gld(h, c);
+        const double g = t - (double)gld(h1, c);
+        gst(x, c, g);
+    } else if (order == 2) {
+        const double t0 = 3.0 * a;
+        const double t1 = 3.0 * (double)gld(h1, c);
+        const double t2 = t0 - t1;
+        const double g = t2 + (double)gld(hd, c);
         gst(x, c, g);
     }
-    gst(h, c, a);
+    gst(hd, c, (float)a);
 }
 
 // ------------------------------------------------------ electron energy
@@ -1011,11 +1020,11 @@ void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int
     timed(ctx, "guess", bytes, [&] { k_extrap<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(phi, h1, hdst, order, n); });
 }
 
-void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int have_h, long n) {
+void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int order, long n) {
     if (count == 0) return;
-    const double bytes = (double)n * count * (have_h ? 32.0 : 16.0);
+    const double bytes = (double)n * count * (order == 0 ? 12.0 : (order == 1 ? 24.0 : 28.0));
     timed(ctx, "guess", bytes, [&] {
-        k_extrap_species<<<dim3(ceil_div(n, kBlock), count), kBlock, 0, ctx->stream>>>(e, have_h, n);
+        k_extrap_species<<<dim3(ceil_div(n, kBlock), count), kBlock, 0, ctx->stream>>>(e, order, n);
     });
 }
 

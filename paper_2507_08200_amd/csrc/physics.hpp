@@ -100,13 +100,15 @@ void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
 // Poisson guess extrapolated from earlier steps' potentials (order 0..2)
 void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n);
-// species guesses extrapolated linearly: x[q] <- 2 x[q] - h[q] (have_h),
-// h[q] <- x[q], for q < count
+// species guesses extrapolated in time (order 0..2) from FP32 histories:
+// x[q] the species array, h1[q] the previous step's, hd[q] the one before
+// (overwritten with x[q]), for q < count
 struct ExtrapSet {
     double *x[32];
-    double *h[32];
+    const float *h1[32];
+    float *hd[32];
 };
-void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int have_h, long n);
+void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int order, long n);
 
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
                          const char *cache_tag);

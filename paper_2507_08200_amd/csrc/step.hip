@@ -28,12 +28,13 @@ struct PhiHistory {
 };
 
 // species arrays passed in by the previous steps with extrapolated species
-// guesses (same restart rule as PhiHistory): h holds the last one per
-// species; count -1 right after a restart, 0 nothing kept yet, 1 kept.
-// Keyed by the n pointer, the grid, S, dt and the transported species.
+// guesses, rounded to FP32 (same restart rule as PhiHistory): per species,
+// slot[newest] the last one, slot[1 - newest] the one before (valid when
+// count is 2); count -1 right after a restart.  Keyed by the n pointer, the
+// grid, S, dt and the transported species.
 struct SpeciesHistory {
-    DevBuf<double> h;
-    int count = -1;
+    DevBuf<float> slot[2];
+    int count = -1, newest = 0;
     const double *n = nullptr;
     int nx = 0, ny = 0, nz = 0, S = 0;
     double dt = 0.0;
@@ -196,6 +197,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         if (SH->n != st->n || SH->nx != g.nx || SH->ny != g.ny || SH->nz != g.nz || SH->S != S || SH->dt != P->dt ||
             SH->transported != tmask) {
             SH->count = -1;
+            SH->newest = 0;
             SH->n = st->n;
             SH->nx = g.nx; SH->ny = g.ny; SH->nz = g.nz; SH->S = S;
             SH->dt = P->dt;
@@ -330,18 +332,21 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             if (SH->count < 0) {
                 SH->count = 0;
             } else {
-                SH->h.alloc((size_t)N * S);
+                SH->slot[0].alloc((size_t)N * S);
+                SH->slot[1].alloc((size_t)N * S);
                 ExtrapSet e;
                 memset(&e, 0, sizeof(e));
                 int q = 0;
                 for (int k = 0; k < S; k++) {
                     if (!P->species[k].transported) continue;
                     e.x[q] = st->n + (long)k * N;
-                    e.h[q] = SH->h.p + (long)k * N;
+                    e.h1[q] = SH->slot[SH->newest].p + (long)k * N;
+                    e.hd[q] = SH->slot[1 - SH->newest].p + (long)k * N;
                     q++;
                 }
                 launch_extrap_species(ctx, e, q, SH->count, N);
-                SH->count = 1;
+                SH->newest = 1 - SH->newest;
+                SH->count = SH->count < 2 ? SH->count + 1 : 2;
             }
         }
         if (want_info) VD_HIP(hipEventRecord(ev[4], s));

@@ -157,6 +157,11 @@ def test_extrap_step_matches_oracle(V, oracle):
     assert max(errs.values()) <= TOL
 
 
+def _f32(a):
+    """The FP32 rounding the species history keeps, widened back."""
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
 def _setup_species(V, cfg, sguess, **sopts):
     from paper_2507_08200_amd import mechanisms as M
     lfa = dict(cfg["lfa"])
@@ -193,7 +198,7 @@ def test_species_extrap_matches_oracle(V, oracle):
     guess = n_in.copy()
     for k, spc in enumerate(M.arh2_15()):
         if spc.get("transported", 1):
-            guess[k] = 2.0 * n_in[k] - h1_in[k]
+            guess[k] = 2.0 * n_in[k] - _f32(h1_in[k])
     cfg_in = dict(cfg)
     cfg_in["n"], cfg_in["phi"], cfg_in["Te"] = n_in, phi_in, te_in
     sp = dict(n_levels=1, nu_pre=1, nu_post=1)
@@ -234,3 +239,38 @@ def test_species_extrap_tolerance(V, oracle, precision):
         cyc.append((info["poisson_cycles"], info["species_cycles"]))
     say("   cycles (poisson, species)", cyc)
     assert all(np.isfinite(host(s[k])).all() for k in ("n", "phi", "Te"))
+
+
+def test_species_extrap_guess_exact(V):
+    """With a tolerance every starting iterate meets (relative residual
+    1e300), the species solves take no cycle and return the guesses
+    themselves: bit for bit 2 n - h1 and then 3 n - 3 h1 + h2 of the FP32
+    histories (numpy, one rounding per operation); species that are not
+    transported keep their values."""
+    from paper_2507_08200_amd import mechanisms as M
+    cfg = I.cfg3(n=24)
+    PX = _setup_species(V, cfg, V.GUESS_EXTRAP, rtol=1e-10)
+    PL = _setup_species(V, cfg, V.GUESS_EXTRAP, rtol=1e300)
+    ctx = V.Context()
+    s = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    ctx.vd_step(PX, s)                  # nothing kept
+    h2 = host(s["n"])
+    ctx.vd_step(PX, s)                  # keeps h2
+    h1 = host(s["n"])
+    info = ctx.vd_step(PL, s)           # from 2 n - h1, no cycle
+    assert info["species_cycles"] == 0
+    tr = [bool(spc.get("transported", 1)) for spc in M.arh2_15()]
+    got = host(s["n"])
+    for k in range(15):
+        want = 2.0 * h1[k] - _f32(h2[k]) if tr[k] else h1[k]
+        assert np.array_equal(got[k], want), k
+    a = got
+    info = ctx.vd_step(PL, s)           # from 3 n - 3 h1 + h2
+    assert info["species_cycles"] == 0
+    got = host(s["n"])
+    for k in range(15):
+        if tr[k]:
+            want = (3.0 * a[k] - 3.0 * _f32(h1[k])) + _f32(h2[k])
+        else:
+            want = a[k]
+        assert np.array_equal(got[k], want), k
