@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-guess-variant", action="store_true",
                     help="skip the comparison run with the previous step's values as the guesses")
     ap.add_argument("--species-levels", type=int, default=1)
-    ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 1))
+    ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 0))
     ap.add_argument("--ir-inner", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default smoother tiling")
     ap.add_argument("--poisson-reps", type=int, default=5)

@@ -2751,7 +2751,9 @@ static void vcycle(vd_ctx *ctx, Solver &S, const LevDesc *dT, const vd_mg_opts *
     const ProbState *st = S.st.p;
     std::vector<int> par(S.Lmax, 0);
     for (int l = 0; l < S.Lmax; l++) {
-        if (S.pre[l].nd) smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l], l == 0 && zero_start);
+        if (S.pre[l].nd)
+            smooth_level<T>(ctx, S, l, dT, o->nu_pre, par[l], l == 0 && zero_start,
+                            l == 0 && final_update && o->nu_post == 0 && S.Lmax == 1);
         const HPlan &pr = S.restr[l];
         if (pr.nd)
             timed_mg(ctx, S, "resid_restrict", pr, sizeof(T) == 4, 1, 1.0, [&] {
@@ -2871,7 +2873,11 @@ static int read_active(vd_ctx *ctx, Solver &S) {
 // passes before and after the coarse correction.
 static bool ir_fusable(const Solver &S, const vd_mg_opts *o) {
     if (S.prec != VD_FP32_IR || !S.aligned || !S.pre25[0].nd || S.use_fused[0]) return false;
-    if (o->nu_pre < 1 || o->nu_post < 1 || S.pre[0].nd != S.nprob) return false;
+    // the correction's first pass is a pre-smoothing pass; its last pass is
+    // the last post-smoothing pass, or without post-smoothing the last
+    // pre-smoothing pass of a single-level solve (no coarse correction
+    // follows it)
+    if (o->nu_pre < 1 || (o->nu_post < 1 && S.Lmax > 1) || S.pre[0].nd != S.nprob) return false;
     for (const HProblem &H : S.probs)
         if (H.lc < 1) return false;
     return true;

@@ -382,12 +382,16 @@ def test_ir_fused_corrections_match_cleared(ctx, V, oracle):
     here by the fused-sweep option, which smooths without colour passes):
     same cycle counts, same iterate to 1e-13, for a mixed batch (uniform,
     variable-coefficient and masked problems) in tolerance mode and as
-    single-level smoothing at a fixed cycle count; the uniform problem's
+    single-level smoothing (with and without post-smoothing, where the last
+    pre-smoothing pass makes the update) at a fixed cycle count; the uniform
+    problem's
     tolerance-mode residual is recomputed by the oracle."""
     probs = [I.random_helmholtz(910, (32, 32, 32), alpha_kind="const", beta_kind="const"),
              I.random_helmholtz(911, (48, 32, 40), beta_jump=True),
              I.random_helmholtz(912, (32, 32, 32), mask_holes=2)]
-    for opts in (dict(), dict(n_levels=1, nu_pre=1, nu_post=1, fixed_cycles=6)):
+    for opts in (dict(), dict(n_levels=1, nu_pre=1, nu_post=1, fixed_cycles=6),
+                 dict(n_levels=1, nu_pre=1, nu_post=0, fixed_cycles=6),
+                 dict(n_levels=1, nu_pre=2, nu_post=0, fixed_cycles=4)):
         ref = [gpu_problem(p) for p in probs]
         i_ref, st = ctx.vd_helmholtz_solve_batched(ref, V.mg_opts(rtol=1e-10, precision=V.FP32_IR, **opts))
         assert st == 0
