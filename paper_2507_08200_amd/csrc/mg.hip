@@ -2607,11 +2607,14 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind, 
         case 6: total += 3.0 * N * sT + coef; break;          // full out-of-place sweep: x, b read, x2 written
         case 7: total += 2.0 * N * sT; break;                 // copy
         case 3: total += N * 8.0; break;
-        case 4: total += 2.0 * N * 8.0 + coef * 2.0; break;
+        // FP64 residual checks (FP64 descriptors: coef counts the FP64
+        // coefficient arrays once): x and b read; 10 also stores the FP32
+        // residual, the default also clears the FP32 correction
+        case 4: total += 2.0 * N * 8.0 + coef; break;
         case 8: total += 1.0 * N * sT + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
         case 9: total += 1.5 * N * sT + 16.0 * N + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
-        case 10: total += 2.0 * N * 8.0 + coef * 2.0 + N * 4.0; break;
-        default: total += 2.0 * N * 8.0 + coef * 2.0 + 2.0 * N * 4.0; break;
+        case 10: total += 2.0 * N * 8.0 + coef + N * 4.0; break;
+        default: total += 2.0 * N * 8.0 + coef + 2.0 * N * 4.0; break;
         }
     }
     return total;
