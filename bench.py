@@ -54,6 +54,7 @@ def parse():
                     help="skip the comparison run with the previous step's values as the guesses")
     ap.add_argument("--species-levels", type=int, default=1)
     ap.add_argument("--species-nu", type=int, nargs=2, default=(1, 0))
+    ap.add_argument("--poisson-nu", type=int, nargs=2, default=(2, 2))
     ap.add_argument("--ir-inner", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default smoother tiling")
     ap.add_argument("--poisson-reps", type=int, default=5)
@@ -201,13 +202,14 @@ def main():
     tune = not args.no_autotune
     pguess = V.GUESS_EXTRAP if args.poisson_guess == "extrap" else V.GUESS_GIVEN
     popts = V.mg_opts(rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune,
-                      guess=pguess)
+                      guess=pguess, nu_pre=args.poisson_nu[0], nu_post=args.poisson_nu[1])
     sguess = V.GUESS_EXTRAP if args.species_guess == "extrap" else V.GUESS_GIVEN
     sopts = V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
                       nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune, guess=sguess)
     species = M.arh2_15()
     P = V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts)
-    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune, guess=pguess),
+    P64 = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(rtol=1e-10, autotune=tune, guess=pguess,
+                                                                 nu_pre=args.poisson_nu[0], nu_post=args.poisson_nu[1]),
                         species_mg=V.mg_opts(rtol=1e-10, n_levels=args.species_levels, nu_pre=args.species_nu[0],
                                              nu_post=args.species_nu[1], autotune=tune, guess=sguess))
     state0 = {k: v.clone() for k, v in state.items()}
@@ -280,7 +282,8 @@ def main():
     guess_variant = None
     if "extrap" in (args.poisson_guess, args.species_guess) and not args.no_guess_variant:
         PG = V.step_params(cfg, species, lfa=lfa, poisson=V.mg_opts(
-            rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune),
+            rtol=1e-10, precision=prec[args.poisson_precision], ir_inner=args.ir_inner, autotune=tune,
+            nu_pre=args.poisson_nu[0], nu_post=args.poisson_nu[1]),
             species_mg=V.mg_opts(rtol=1e-10, precision=prec[args.species_precision], n_levels=args.species_levels,
                                  nu_pre=args.species_nu[0], nu_post=args.species_nu[1], ir_inner=1, autotune=tune))
         stg = {k: v.clone() for k, v in state0.items()}
@@ -387,8 +390,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Ar-H2 15-species streamer step, %d^3 cells, dt 1e-12 s, LFA Te, 15 kV plates" % n,
                    "grid": [n, n, n], "species": 15, "dt": 1e-12,
-                   "poisson": "%s%s rtol 1e-10, guess %s%s" % (
+                   "poisson": "%s%s V(%d,%d) rtol 1e-10, guess %s%s" % (
                        args.poisson_precision, " inner %d" % args.ir_inner if args.poisson_precision == "fp32_ir" else "",
+                       args.poisson_nu[0], args.poisson_nu[1],
                        "extrapolated from the last three potentials" if args.poisson_guess == "extrap"
                        else "the previous potential", ", autotuned tiles" if tune else ""),
                    "species_solve": "%s levels %d nu %s rtol 1e-10, guess %s" % (
