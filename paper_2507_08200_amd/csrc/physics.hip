@@ -980,7 +980,14 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
         bytes += per * a.g.ncell;
     }
     const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
-    const int kz = (nz % 16 == 0) ? 16 : ((nz % 8 == 0) ? 8 : 0);
+    // planes per workgroup: the deepest of 32, 16, 8 that divides nz and
+    // still gives 2048 workgroups (else the shallowest that divides nz)
+    int kz = 0;
+    for (int cand : {32, 16, 8}) {
+        if (nz % cand) continue;
+        kz = cand;
+        if ((long)(nx / kDX) * (ny / kDY) * (nz / cand) * nfields >= 2048) break;
+    }
     if (nx % kDX == 0 && ny % kDY == 0 && kz > 0 && nx >= 3 && ny >= 3 && nz >= 3) {
         dim3 tg((nx / kDX) * (ny / kDY) * (nz / kz), nfields);
         timed(ctx, "weno", bytes, [&] {
