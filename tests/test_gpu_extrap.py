@@ -244,14 +244,15 @@ def test_species_extrap_tolerance(V, oracle, precision, nu_post):
     assert all(np.isfinite(host(s[k])).all() for k in ("n", "phi", "Te"))
 
 
-def test_species_extrap_guess_exact(V):
+@pytest.mark.parametrize("n", [24, 21])
+def test_species_extrap_guess_exact(V, n):
     """With a tolerance every starting iterate meets (relative residual
     1e300), the species solves take no cycle and return the guesses
     themselves: bit for bit 2 n - h1 and then 3 n - 3 h1 + h2 of the FP32
     histories (numpy, one rounding per operation); species that are not
-    transported keep their values."""
+    transported keep their values (an even and an odd cell count)."""
     from paper_2507_08200_amd import mechanisms as M
-    cfg = I.cfg3(n=24)
+    cfg = I.cfg3(n=n)
     PX = _setup_species(V, cfg, V.GUESS_EXTRAP, rtol=1e-10)
     PL = _setup_species(V, cfg, V.GUESS_EXTRAP, rtol=1e300)
     ctx = V.Context()
