@@ -117,6 +117,8 @@ def lib():
         _lib.or_cell_flags.argtypes = [P, C.c_int, C.c_int, P]
         _lib.or_arh2_stoich.argtypes = [C.c_int, P]
         _lib.or_step.argtypes = [P, P, P, P, P, P]
+        _lib.or_transport.argtypes = [P, P, d, d, d, d, P, P]
+        _lib.or_transport.restype = None
     return _lib
 
 
@@ -278,6 +280,15 @@ def species_array(species):
 
 
 PHYS = {"qe": 1.602176634e-19, "eps0": 8.8541878128e-12, "kB": 1.380649e-23, "me": 9.1093837015e-31}
+
+
+def transport(sp, en_td, Te, Tg, N, consts=PHYS):
+    """(signed mobility, diffusion) of one species dict at E/N (Td), Te, Tg (K), N."""
+    arr = species_array([sp])
+    cs = Consts(**consts)
+    mu, D = C.c_double(), C.c_double()
+    lib().or_transport(arr, C.byref(cs), float(en_td), float(Te), float(Tg), float(N), C.byref(mu), C.byref(D))
+    return mu.value, D.value
 
 
 def species_flux(g, phi_bc, sp_bcs, species, n, phi, mu, Te, Tg, consts=PHYS):

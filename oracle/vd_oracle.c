@@ -18,9 +18,9 @@
  *   - Species continuity and drift-diffusion flux: Sec. 2.1, Eqs. (1)-(2).
  *   - Poisson equation and E = -grad(phi): Sec. 2.1, Eqs. (3)-(4).
  *   - Electron energy equation, its flux and source: Sec. 2.1, Eqs. (5)-(8).
- *   - Wall fluxes: Sec. 2.2, Eqs. (13)-(15) and the neutral variant.
- *   - Mid-point corrector iteration: Sec. 3, Eqs. (17)-(18).
- *   - Adaptive time step: Sec. 3, Eq. (19).
+ *   - Wall fluxes: Sec. 2.2, the electron, electron-energy and ion wall
+ *     fluxes (Eqs. (14)-(16)) and the neutral variant stated after them.
+ *   - Mid-point corrector iteration: Sec. 3, Eqs. (18)-(19).
  *   - Helmholtz-form multigrid per equation: Sec. 4.
  *   - Cell masking: Sec. 3 (masking paragraph).
  *   - Mechanism and transport: Appendix A, Tables A.1-A.4.
@@ -788,6 +788,14 @@ static void transport(const or_species *sp, const or_consts *cs, double en_td, d
     }
 }
 
+/* Exported for the tests: mobility and diffusion of one species at the
+ * given reduced field (Td), temperatures (K) and gas density. */
+void or_transport(const or_species *sp, const or_consts *cs, double en_td, double Te, double Tg, double N,
+                  double *mu, double *D)
+{
+    transport(sp, cs, en_td, Te, Tg, N, mu, D);
+}
+
 /* Local-field electron temperature: linear interpolation in ln(E/N) on a
  * uniform table, clamped at both ends. */
 double or_te_lfa(const double *tab, int npts, double ln_min, double ln_max, double en_td)
@@ -875,9 +883,9 @@ static double wall_flux(int wk, double uc, double mu, double e_n, double Te, dou
  * part) with signed cell mobility mu[c]: face velocity v = mu_f E_f with
  * mu_f the arithmetic mean of the two cells (the boundary cell's value on a
  * domain face); flux = v * upwind WENO5 value.  Wall faces carry the wall
- * flux of model wk instead (Eqs. (13)-(15)); when ne_wall is given the field
- * is the electron energy and its wall flux is 2 kB Te times the electron
- * wall flux of density ne_wall (Eq. (14)).
+ * flux of model wk instead (Sec. 2.2, Eqs. (14) and (16)); when ne_wall is
+ * given the field is the electron energy and its wall flux is 2 kB Te times
+ * the electron wall flux of density ne_wall (Eq. (15)).
  * Neumann faces carry no flux. */
 static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const double *u, const double *mu,
                              int wk, double mass, const double *ne_wall, double *div)
@@ -1160,7 +1168,7 @@ int or_arh2_stoich(int q, int out[15])
 
 /* ------------------------------------------------------------------ */
 /* Time step (Sec. 3): segregated semi-implicit Backward Euler with the */
-/* mid-point corrector iteration of Eqs. (17)-(18).                     */
+/* mid-point corrector iteration of Eqs. (18)-(19).                     */
 /* ------------------------------------------------------------------ */
 /* Reading of the step (the paper gives the scheme, not its sequencing):
  *   for m = 0 .. n_t-1:
