@@ -353,6 +353,23 @@ vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, i
  * problem, with the Dirichlet lifting; x updated in place. */
 vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour);
 
+/* Host-side check of the memory accesses of the 2.5D tiled passes (no GPU
+ * call): for a level of nx x ny x nz cells (periodic: bit d set when
+ * direction d wraps) and tiles of kz planes, walks every load and store
+ * that every thread of every tile issues in the lexicographic colour /
+ * residual pass in all its modes (kernel 0: x and b pairs with their look-
+ * ahead planes, halo elements, FP64 unknown pairs of the fused last colour
+ * pass, FP32 residual stores in both row layouts, LDS slots) or in the
+ * parity-split FP32 colour pass (kernel 1, both colours: other-colour
+ * pairs, halo, b, the four FP64 cells of the fused last pass, stores), with
+ * the kernels' own index functions, and counts the accesses (accesses) and
+ * those outside the level's arrays or the LDS tile, or misaligned for a
+ * vector access (violations; also 1 if the workgroup-to-tile mapping does
+ * not take every tile once).  VD_EINVAL for nx odd (kernel 0) or not a
+ * multiple of 4 (kernel 1), kz < 1, or null outputs. */
+vd_status vd_check_tiles25(int32_t nx, int32_t ny, int32_t nz, int32_t periodic, int32_t kz, int32_t kernel,
+                           int64_t *accesses, int64_t *violations);
+
 /* Kernel timing: bracket every launch of the selected kernel families
  * (comma-separated, e.g. "gsrb,weno,coarse"; NULL or "" turns timing off)
  * with HIP events on the context stream, and read back per family the

@@ -18,6 +18,7 @@
 //     convergence decisions are taken on the device (per-problem active
 //     flags), so the host reads back one small state array per chunk.
 #include "vd_internal.hpp"
+#include "tile25.hpp"
 
 #include <type_traits>
 
@@ -294,7 +295,6 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(const LevDesc *__restrict_
 // k+1 (wide loads); the x-y neighbours of plane k come from an LDS copy of
 // the tile with a one-cell halo.  Every element is fetched from memory once
 // per pass (plus the halo).  Needs an even nx (row pairs).
-constexpr int kT25X = 32, kT25Y = 16, kT25W = kT25X + 2;
 
 typedef double PairD __attribute__((ext_vector_type(2)));
 typedef float PairF __attribute__((ext_vector_type(2)));
@@ -342,27 +342,7 @@ __device__ __forceinline__ T ld_halo(const LevDesc &L, const T *__restrict__ X, 
     return ld_wrap<T>(L, X, i0 + cc, side ? j0 + kT25Y : j0 - 1, k);
 }
 
-template <typename T>
-__device__ __forceinline__ int halo_slot(int tid) {
-    if (tid < 2 * kT25Y) {
-        const int rr = tid & (kT25Y - 1), side = tid / kT25Y;
-        return (rr + 1) * kT25W + (side ? kT25X + 1 : 0);
-    }
-    const int q = tid - 2 * kT25Y, cc = q & (kT25X - 1), side = q / kT25X;
-    return (side ? kT25Y + 1 : 0) * kT25W + cc + 1;
-}
 
-// wrapped (periodic) or clamped index of position p along a direction of n
-// cells; ok tells whether the position stands for a cell (inside the
-// domain, or one wrap across a periodic face).  The index is always valid.
-__device__ __forceinline__ int wrap_idx(int p, int n, bool per, bool &ok) {
-    const bool in = p >= 0 && p < n;
-    const int w = p < 0 ? p + n : p - n;
-    const bool wrapped = per && !in && w >= 0 && w < n;
-    ok = in || wrapped;
-    const int c = p < 0 ? 0 : (p >= n ? n - 1 : p);
-    return in ? p : (wrapped ? w : c);
-}
 
 // MODE 0: one Gauss-Seidel colour pass (in place); MODE 1: FP64 residual
 // norm partials; MODE 2: same, also storing the FP32 residual and, unless
@@ -388,25 +368,17 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const LevDesc L = descs[id];
     constexpr bool PASS = MODE == 0 || MODE == 4 || MODE == 5;
     if ((PASS || check_active) && !gld(&st[L.prob].active, 0)) return;
-    int lt = t - pl.prefix[d];
+    const int lt = t - pl.prefix[d];
     const int slot = pl.gbase ? pl.gbase[d] + lt : t;    // partial slot of this tile
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int ntx = (nx + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
-    const int tx = lt % ntx;
-    lt /= ntx;
-    const int ty = lt % nty;
-    const int zc = lt / nty;
-    const int i0 = tx * kT25X, j0 = ty * kT25Y, k0 = zc * kz;
-    const int k1 = min(k0 + kz, nz);
+    const Tile25 T25 = tile25(lt, nx, ny, nz, kz);
+    const int k0 = T25.k0, k1 = T25.k1;
     const int tid = threadIdx.x;
     const int tp = tid & 15, r = tid >> 4;
-    const int ia = i0 + 2 * tp, j = j0 + r;
-    const bool own = ia < nx && j < ny;
-    const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
     float *__restrict__ Eb = MODE == 2 ? (float *)d32[id].b : nullptr;
     float *__restrict__ Ex = MODE == 2 ? (float *)d32[id].x : nullptr;
     const bool rbE = MODE == 2 && d32[id].rb;
-    const int hslot = halo_slot<T>(tid);
+    const int hslot = halo_slot(tid);
     T *__restrict__ X = (T *)L.x;
     const T *__restrict__ B = (const T *)L.b;
     // Branch-free loads: every thread issues the same loads on every plane
@@ -414,24 +386,11 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     // cell), so the compiler can count outstanding loads and the look-ahead
     // really overlaps with the computation.  x / y parts are fixed per thread.
     const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
-    bool okx, oky;
-    const int iw = min(wrap_idx(ia, nx, px, okx), nx - 2);
-    const int jw = wrap_idx(j, ny, py, oky);
-    const bool okxy = okx && oky;
-    const long pair_off = iw + (long)nx * jw;
-    const long b_off = min(ia, nx - 2) + (long)nx * min(j, ny - 1);
-    int hi, hj;
-    if (tid < 2 * kT25Y) {
-        hi = (tid / kT25Y) ? i0 + kT25X : i0 - 1;
-        hj = j0 + (tid & (kT25Y - 1));
-    } else {
-        const int q = tid - 2 * kT25Y;
-        hi = i0 + (q & (kT25X - 1));
-        hj = (q / kT25X) ? j0 + kT25Y : j0 - 1;
-    }
-    bool okhi, okhj;
-    const long h_off = wrap_idx(hi, nx, px, okhi) + (long)nx * wrap_idx(hj, ny, py, okhj);
-    const bool okh = halo_thread && okhi && okhj;
+    const Thr25 H = thr25(T25, tid, nx, nx, ny, px, py, 0, 0);
+    const int ia = H.ua, j = H.j;
+    const bool own = H.own, halo_thread = H.halo;
+    const bool okxy = H.okp, okh = H.okh;
+    const long pair_off = H.pair_off, b_off = H.b_off, h_off = H.h_off;
     const long nxy = L.nxy;
     auto ld_pair = [&](int kk, T &a, T &b2) {
         if constexpr (MODE == 4) {
@@ -628,21 +587,13 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     const int id = pl.ids[d];
     const LevDesc L = descs[id];
     if (!gld(&st[L.prob].active, 0)) return;
-    int lt = t - pl.prefix[d];
+    const int lt = t - pl.prefix[d];
     const int nx = L.nx, ny = L.ny, nz = L.nz, nh = nx >> 1;
-    const int ntx = (nh + kT25X - 1) / kT25X, nty = (ny + kT25Y - 1) / kT25Y;
-    const int tx = lt % ntx;
-    lt /= ntx;
-    const int ty = lt % nty;
-    const int zc = lt / nty;
-    const int m0 = tx * kT25X, j0 = ty * kT25Y, k0 = zc * kz;
-    const int k1 = min(k0 + kz, nz);
+    const Tile25 T25 = tile25(lt, nh, ny, nz, kz);
+    const int k0 = T25.k0, k1 = T25.k1;
     const int tid = threadIdx.x;
     const int tp = tid & 15, r = tid >> 4;
-    const int ma = m0 + 2 * tp, j = j0 + r;
-    const bool own = ma < nh && j < ny;      // nh is even, so the pair (ma, ma + 1) is whole
-    const bool halo_thread = tid < 2 * kT25Y + 2 * kT25X;
-    const int hslot = halo_slot<float>(tid);
+    const int hslot = halo_slot(tid);
     float *__restrict__ X = (float *)L.x;
     const float *__restrict__ B = (const float *)L.b;
     const long nxy = L.nxy;
@@ -650,27 +601,14 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
     // the thread's pair of the other colour: wrapped (a partial tile's
     // positions past the row end hold the row's first ones when periodic)
-    // or zeroed
-    bool okm, oky;
-    const int mw = min(wrap_idx(ma, nh, px, okm), nh - 2);
-    const int jw = wrap_idx(j, ny, py, oky);
-    const bool okp = okm && oky;
-    const long pair_off = oofs + mw + (long)nx * jw;
-    const long b_off = uofs + min(ma, nh - 2) + (long)nx * min(j, ny - 1);
-    int hm, hj;
-    if (tid < 2 * kT25Y) {
-        hm = (tid / kT25Y) ? m0 + kT25X : m0 - 1;
-        hj = j0 + (tid & (kT25Y - 1));
-    } else {
-        const int q = tid - 2 * kT25Y;
-        hm = m0 + (q & (kT25X - 1));
-        hj = (q / kT25X) ? j0 + kT25Y : j0 - 1;
-    }
-    // a half-row position wraps with the row: position -1 of the other
-    // colour is its last one, position nh its first
-    bool okhm, okhj;
-    const long h_off = oofs + wrap_idx(hm, nh, px, okhm) + (long)nx * wrap_idx(hj, ny, py, okhj);
-    const bool okh = halo_thread && okhm && okhj;
+    // or zeroed; a halo position wraps with the row (position -1 of the
+    // other colour is its last one, position nh its first)
+    const Thr25 H = thr25(T25, tid, nh, nx, ny, px, py, oofs, uofs);
+    const int ma = H.ua, j = H.j;
+    const bool own = H.own;      // nh is even, so the pair (ma, ma + 1) is whole
+    const bool halo_thread = H.halo;
+    const bool okp = H.okp, okh = H.okh;
+    const long pair_off = H.pair_off, b_off = H.b_off, h_off = H.h_off;
     auto ld_pair = [&](int kk, float &a, float &b2) {
         if constexpr (PM == 4) {
             a = b2 = 0.0f;
@@ -703,7 +641,7 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     float hcur = ld_h(k0);
     float bc0, bc1;
     ld_b(k0, bc0, bc1);
-    const long q_off = 2 * (long)min(ma, nh - 2) + (long)nx * min(j, ny - 1);   // first of the four cells (FP64)
+    const long q_off = quad_off25(ma, j, nh, nx, ny);   // first of the four cells (FP64)
     for (int k = k0; k < k1; k++) {
         float *buf = xs[k & 1];
         buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;

@@ -32,7 +32,7 @@ EXPORTS = ["vd_ctx_create", "vd_ctx_destroy", "vd_ctx_set_stream", "vd_last_erro
            "vd_poisson_solve", "vd_helmholtz_solve_batched", "vd_species_flux", "vd_reaction_source",
            "vd_step", "vd_cell_flags", "vd_smooth", "vd_timing_select", "vd_timing_read",
            "vd_nn_param_count", "vd_nn_create", "vd_nn_get", "vd_nn_set", "vd_nn_forward", "vd_nn_train_step",
-           "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d"]
+           "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d", "vd_check_tiles25"]
 
 
 class VDError(RuntimeError):
@@ -146,6 +146,7 @@ def load():
         "vd_nn_load": ([P, C.c_char_p], i32),
         "vd_nn_conv3d": ([P, P, P, i32, P, P, i32, i32, P, P, P, P, P], i32),
         "vd_timing_select": ([P, C.c_char_p], i32),
+        "vd_check_tiles25": ([i32, i32, i32, i32, i32, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], i32),
         "vd_timing_read": ([P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
     }
     for name, (args, res) in sig.items():
@@ -416,6 +417,16 @@ class Context:
         n, ms, u = C.c_int64(), C.c_double(), C.c_double()
         self._check(self.lib.vd_timing_read(self.h, kernel.encode(), C.byref(n), C.byref(ms), C.byref(u)))
         return n.value, ms.value, u.value
+
+
+def check_tiles25(nx, ny, nz, periodic, kz, kernel):
+    """(accesses, violations) of the host-side walk over a 2.5D tiled pass
+    (vd_check_tiles25; no GPU needed)."""
+    a, v = C.c_int64(), C.c_int64()
+    st = load().vd_check_tiles25(int(nx), int(ny), int(nz), int(periodic), int(kz), int(kernel), C.byref(a), C.byref(v))
+    if st != VD_OK:
+        raise VDError(st, "vd_check_tiles25 rejected the shape")
+    return a.value, v.value
 
 
 def species_array(species):
