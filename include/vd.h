@@ -76,7 +76,8 @@ enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3
  *   ION_N0:       |mu| = mob_coef N0/N, mu = sign(Z)|mu|, D = |mu| kB Tg / e
  *   NEUTRAL_N0:   mu = 0, D = mob_coef (N0/N) kB Tg / e (the ionic counterpart's) */
 enum { VD_MOB_CONST = 0, VD_MOB_ELECTRON_FIT = 1, VD_MOB_ION_N0 = 2, VD_MOB_NEUTRAL_N0 = 3 };
-/* wall-flux models at WALLFLUX faces (Sec. 2.2, Eqs. (13)-(15)):
+/* wall-flux models at WALLFLUX faces (Sec. 2.2, Eqs. (14) and (16), and the
+ * neutral variant stated after them):
  *   ELECTRON: n/4 sqrt(8 kB Te/(pi m_e)); ION: max(mu n E.n, 0);
  *   NEUTRAL: n/4 sqrt(8 kB Tg/(pi m)); NONE: no flux (background gas). */
 enum { VD_WALL_NONE = 0, VD_WALL_ELECTRON = 1, VD_WALL_ION = 2, VD_WALL_NEUTRAL = 3 };
@@ -182,13 +183,25 @@ vd_status vd_helmholtz_solve_batched(vd_ctx *ctx, int32_t nprob, const vd_proble
  * mobilities; flux = v times the upwind WENO5 value (ghosts: mirror at
  * Neumann/wall faces, odd reflection at Dirichlet faces, wrap at periodic).
  * WALLFLUX faces of species_bc[k] carry the wall flux of species[k].wall_kind
- * at the boundary cell instead.
+ * at the boundary cell instead (Sec. 2.2: electron and ion wall fluxes,
+ * Eqs. (14) and (16), and the neutral variant with Tg).
  *   n, mu: device [S][cells]; phi, Te_K: device cells; Tg: gas temperature.
- *   div_drift: device [S][cells] output. */
+ *   div_drift: device [S][cells] output.
+ * Optional total face flux of species flux_species (face_flux non-NULL;
+ * then D, device [S][cells] cell diffusion coefficients, is required and
+ * 0 <= flux_species < S): Gamma . e_d = drift part as above (the wall flux,
+ * with the outward normal's sign, at a WALLFLUX face; 0 at a Neumann face)
+ * plus the central diffusive part -D_f (n_R - n_L)/h of Sec. 3 (D_f the
+ * harmonic mean of the two cells' D; a Dirichlet face over half a cell with
+ * the boundary cell's D; 0 at Neumann and WALLFLUX faces), the flux Gamma_e
+ * whose cell mean enters the Joule term of Eq. (8).  face_flux: device FP64
+ * x faces [nz][ny][nx+1], then y faces [nz][ny+1][nx], then z faces
+ * [nz+1][ny][nx].  D may be NULL and flux_species anything when face_flux
+ * is NULL. */
 vd_status vd_species_flux(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const vd_bc *species_bc /* host[S] */,
                           int32_t S, const vd_species *species /* host[S] */, const double *n, const double *phi,
-                          const double *mu, const double *Te_K, double Tg, const vd_consts *consts,
-                          double *div_drift);
+                          const double *mu, const double *D, const double *Te_K, double Tg, const vd_consts *consts,
+                          double *div_drift, int32_t flux_species, double *face_flux);
 
 /* Chemical production rates G_k = sum_i nu_ik r_i, r_i = k_i(Te) prod n
  * (#/m^3/s) and electron inelastic loss sum_i dE_i e r_i (J/m^3/s) of the
@@ -206,7 +219,7 @@ vd_status vd_reaction_source(vd_ctx *ctx, int32_t mech, int64_t ncells, int32_t 
 typedef struct {
     vd_grid grid;
     double dt;
-    int32_t n_t;            /* mid-point corrector iterations, Eqs. (17)-(18) (1 = Backward Euler) */
+    int32_t n_t;            /* mid-point corrector iterations, Eqs. (18)-(19) (1 = Backward Euler) */
     int32_t mech;           /* VD_MECH_* */
     int32_t S;              /* species count, 1..32 */
     int32_t te_mode;        /* VD_TE_* */
@@ -276,6 +289,14 @@ typedef struct {
  * ZERO. */
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state,
                   vd_step_info *info /* host, nullable */);
+
+/* Forget the potentials and densities this context keeps for
+ * VD_GUESS_EXTRAP: the next vd_step starts its histories afresh, as after
+ * a change of array, grid or dt.  A caller that writes an unrelated state
+ * into the arrays it passed before (or whose allocator may hand a freed
+ * array's address to a new state) calls this first, or the next step would
+ * extrapolate across two trajectories.  Enqueues nothing. */
+vd_status vd_step_reset(vd_ctx *ctx);
 
 /* ---- learned initial guess for the Poisson solve ----
  * Not in the paper: a small 3D U-Net (bfloat16 storage, FP32 accumulation

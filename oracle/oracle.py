@@ -81,7 +81,8 @@ class StepParams(C.Structure):
                 ("lfa_n", C.c_int32), ("pad1", C.c_int32),
                 ("extra_source", C.c_void_p), ("extra_energy", C.c_void_p), ("eps_cell", C.c_void_p),
                 ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts),
-                ("species_guess", C.c_void_p)]
+                ("species_guess", C.c_void_p), ("phi_fixed", C.c_int32), ("pad2", C.c_int32),
+                ("check_n", C.c_void_p), ("check_Ee", C.c_void_p), ("check_res", C.c_void_p)]
 
 
 class StepInfo(C.Structure):
@@ -117,6 +118,7 @@ def lib():
         _lib.or_cell_flags.argtypes = [P, C.c_int, C.c_int, P]
         _lib.or_arh2_stoich.argtypes = [C.c_int, P]
         _lib.or_step.argtypes = [P, P, P, P, P, P]
+        _lib.or_face_flux.argtypes = [P, P, P, P, P, P, P, P, P, d, P, P, P, P]
         _lib.or_transport.argtypes = [P, P, d, d, d, d, P, P]
         _lib.or_transport.restype = None
     return _lib
@@ -306,12 +308,33 @@ def species_flux(g, phi_bc, sp_bcs, species, n, phi, mu, Te, Tg, consts=PHYS):
     return div
 
 
+def face_flux(g, phi_bc, sp_bc, sp, u, phi, mu, D, Te, Tg, consts=PHYS):
+    """Total face flux (drift + diffusion) of one species: (fx, fy, fz)
+    shaped (nz, ny, nx+1), (nz, ny+1, nx), (nz+1, ny, nx)."""
+    nx, ny, nz = g[:3]
+    G, PB, UB = grid(g), bc(phi_bc), bc(sp_bc)
+    SP = species_array([sp])
+    cs = Consts(**consts)
+    u, phi, mu, D, Te = _f64(u), _f64(phi), _f64(mu), _f64(D), _f64(Te)
+    fx = np.empty((nz, ny, nx + 1))
+    fy = np.empty((nz, ny + 1, nx))
+    fz = np.empty((nz + 1, ny, nx))
+    st = lib().or_face_flux(C.byref(G), C.byref(PB), C.byref(UB), SP, _ptr(u), _ptr(phi), _ptr(mu), _ptr(D),
+                            _ptr(Te), float(Tg), C.byref(cs), _ptr(fx), _ptr(fy), _ptr(fz))
+    assert st == OK
+    return fx, fy, fz
+
+
 def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poisson=None, species_mg=None,
          energy_mg=None, extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0,
-         k_decay=0.0, species_guess=None):
+         k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None):
     """One step of the semi-implicit scheme on a workload dict (see inputs).
     species_guess ([S][cells], optional): starting iterate of the first
-    corrector's species solves in place of n^n."""
+    corrector's species solves in place of n^n.
+    Checking a step computed elsewhere (n_t = 1): phi_fixed takes phi as the
+    Poisson result (its relative residual in info["poisson_rel"]); check_n /
+    check_Ee replace the species / energy solves by the relative residuals
+    of those iterates, returned as "check_res" ([S] species, then energy)."""
     n = _f64(cfg["n"] if n is None else n).copy()
     phi = _f64(cfg["phi"] if phi is None else phi).copy()
     Te = _f64(cfg["Te"] if Te is None else Te).copy()
@@ -353,13 +376,21 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
             a = _f64(arr)
             keep.append(a)
             setattr(P, name, _ptr(a))
+    P.phi_fixed = 1 if phi_fixed else 0
+    res = np.zeros(S + 1)
+    for name, arr in (("check_n", check_n), ("check_Ee", check_Ee)):
+        if arr is not None:
+            a = _f64(arr)
+            keep.append(a)
+            setattr(P, name, _ptr(a))
+    P.check_res = _ptr(res)
     P.poisson = poisson or mg_opts()
     P.species_mg = species_mg or mg_opts()
     P.energy_mg = energy_mg or mg_opts()
     info = StepInfo()
     st = lib().or_step(C.byref(P), _ptr(n), _ptr(phi), _ptr(Te), _ptr(Ee), C.byref(info))
     d = {k: getattr(info, k) for k, _ in StepInfo._fields_}
-    return {"n": n, "phi": phi, "Te": Te, "Ee": Ee, "info": d, "status": st}
+    return {"n": n, "phi": phi, "Te": Te, "Ee": Ee, "info": d, "status": st, "check_res": res}
 
 
 # ---------------------------------------------------------------------------

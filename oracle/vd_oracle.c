@@ -104,6 +104,17 @@ typedef struct {
     or_mg_opts poisson, species_mg, energy_mg;
     const double *species_guess;    /* [S][cells] or NULL: starting iterate of the first corrector's
                                        species solves instead of n^n (a solver started elsewhere) */
+    /* Checking a step computed elsewhere (n_t = 1 only).  phi_fixed: the
+     * potential passed in is taken as the Poisson result (no solve); its
+     * relative residual goes to info.poisson_rel.  check_n ([S][cells]) /
+     * check_Ee ([cells]): instead of solving, the relative residual
+     * ||b - A x|| / ||b|| of these iterates in this step's species /
+     * energy equations goes to check_res[k] / check_res[S], and they become
+     * the step's result. */
+    int32_t phi_fixed, pad2;
+    const double *check_n;
+    const double *check_Ee;
+    double *check_res;              /* [S + 1] */
 } or_step_params;
 
 typedef struct {
@@ -646,6 +657,24 @@ int or_residual(const or_problem *P, const double *rhs, const double *x, double 
     return OR_OK;
 }
 
+/* ||b - A x||_2 / ||b||_2 over valid cells (b with the lifting), the
+ * solver's stopping quantity; 0 when b vanishes. */
+static double rel_residual(const or_problem *P, const double *rhs, const double *x)
+{
+    size_t n = (size_t)P->grid.nx * P->grid.ny * P->grid.nz;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *b = (double *)malloc(sizeof(double) * n);
+    if (!r || !b) { free(r); free(b); return NAN; }
+    or_level *lv = build_levels(P, 1);
+    if (!lv) { free(r); free(b); return NAN; }
+    lift_rhs(&lv[0], &P->bc, rhs, b);
+    residual(&lv[0], x, b, r);
+    double bn = norm2(b, n), rn = norm2(r, n);
+    free_levels(lv, 1);
+    free(r); free(b);
+    return bn == 0.0 ? 0.0 : rn / bn;
+}
+
 /* ncolour half-sweeps on the fine level, red first, with lifting. */
 int or_smooth(const or_problem *P, const double *rhs, double *x, int ncolour)
 {
@@ -879,14 +908,67 @@ static double wall_flux(int wk, double uc, double mu, double e_n, double Te, dou
     }
 }
 
-/* Drift-flux divergence of field u (species continuity, Eq. (2), drift
- * part) with signed cell mobility mu[c]: face velocity v = mu_f E_f with
- * mu_f the arithmetic mean of the two cells (the boundary cell's value on a
- * domain face); flux = v * upwind WENO5 value.  Wall faces carry the wall
- * flux of model wk instead (Sec. 2.2, Eqs. (14) and (16)); when ne_wall is
- * given the field is the electron energy and its wall flux is 2 kB Te times
- * the electron wall flux of density ne_wall (Eq. (15)).
- * Neumann faces carry no flux. */
+/* Drift flux along +d (species continuity, Eq. (2), drift part) through
+ * face fidx (0..n_d) of the row through (i,j,k), for field u with signed
+ * cell mobility mu[]: face velocity v = mu_f E_f with mu_f the arithmetic
+ * mean of the two cells (the boundary cell's value on a domain face);
+ * flux = v * upwind WENO5 value.  Wall faces carry the wall flux of model
+ * wk instead (Sec. 2.2, Eqs. (14) and (16)), with the sign of the outward
+ * normal folded in; when ne_wall is given the field is the electron energy
+ * and its wall flux is 2 kB Te times the electron wall flux of density
+ * ne_wall (Eq. (15)).  Neumann faces carry no flux. */
+static double drift_face_flux(const or_flux_ctx *X, const or_bc *ubc, const double *u, const double *mu,
+                              int wk, double mass, const double *ne_wall, int d, int i, int j, int k, int fidx)
+{
+    const or_grid *g = X->g;
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    int n_d = d == 0 ? nx : (d == 1 ? ny : nz);
+    int pos = d == 0 ? i : (d == 1 ? j : k);
+    size_t c = IDX(i, j, k, nx, ny);
+    int boundary = (fidx == 0 || fidx == n_d);
+    int kind = ubc->kind[boundary ? (fidx == 0 ? 2 * d : 2 * d + 1) : 2 * d + (fidx - pos)];
+    if (boundary && kind == OR_NEU) return 0.0;
+    double Ef = e_face(g, X->phi_bc, X->phi, d, i, j, k, fidx);
+    if (boundary && kind == OR_WALL) {
+        /* the boundary cell of this face */
+        size_t cb = d == 0 ? IDX(fidx == 0 ? 0 : nx - 1, j, k, nx, ny)
+                  : (d == 1 ? IDX(i, fidx == 0 ? 0 : ny - 1, k, nx, ny) : IDX(i, j, fidx == 0 ? 0 : nz - 1, nx, ny));
+        (void)c;
+        double e_n = fidx == 0 ? -Ef : Ef;
+        double fl;
+        if (ne_wall) /* energy: 2 kB Te times the electron wall flux */
+            fl = 2.0 * X->cs->kB * X->Te[cb] * wall_flux(OR_WALL_ELECTRON, ne_wall[cb], 0.0, e_n, X->Te[cb], X->Tg, X->cs->me, X->cs);
+        else
+            fl = wall_flux(wk, u[cb], mu[cb], e_n, X->Te[cb], X->Tg, mass, X->cs);
+        return fidx == 0 ? -fl : fl;   /* flux in +d direction */
+    }
+    /* cells left and right of the face along d */
+    int pl = fidx - 1, pr = fidx;
+    double mul, mur;
+    {
+        int ql = pl, qr = pr;
+        if (boundary && kind == OR_PER) { if (ql < 0) ql += n_d; if (qr >= n_d) qr -= n_d; }
+        size_t cl = d == 0 ? IDX(ql < 0 ? 0 : ql, j, k, nx, ny) : (d == 1 ? IDX(i, ql < 0 ? 0 : ql, k, nx, ny) : IDX(i, j, ql < 0 ? 0 : ql, nx, ny));
+        size_t cr = d == 0 ? IDX(qr >= n_d ? n_d - 1 : qr, j, k, nx, ny) : (d == 1 ? IDX(i, qr >= n_d ? n_d - 1 : qr, k, nx, ny) : IDX(i, j, qr >= n_d ? n_d - 1 : qr, nx, ny));
+        mul = mu[cl];
+        mur = mu[cr];
+    }
+    double muf;
+    if (boundary && kind != OR_PER) muf = fidx == 0 ? mur : mul;
+    else muf = 0.5 * (mul + mur);
+    double v = muf * Ef;
+    if (v == 0.0) return 0.0;
+    double s[5];
+    if (v > 0.0) {
+        for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pl - 2 + m);
+    } else {
+        for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pr + 2 - m);
+    }
+    return v * or_weno5(s);
+}
+
+/* Drift-flux divergence of field u: the two face fluxes of drift_face_flux
+ * per direction, differenced over the cell. */
 static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const double *u, const double *mu,
                              int wk, double mass, const double *ne_wall, double *div)
 {
@@ -898,51 +980,11 @@ static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const doubl
                 size_t c = IDX(i, j, k, nx, ny);
                 double total = 0.0;
                 for (int d = 0; d < 3; d++) {
-                    int n_d = d == 0 ? nx : (d == 1 ? ny : nz);
                     int pos = d == 0 ? i : (d == 1 ? j : k);
                     double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
                     double F[2];
-                    for (int side = 0; side < 2; side++) {
-                        int fidx = pos + side;          /* face index along d */
-                        int f = 2 * d + side;
-                        int boundary = (fidx == 0 || fidx == n_d);
-                        int kind = ubc->kind[boundary ? (fidx == 0 ? 2 * d : 2 * d + 1) : f];
-                        if (boundary && kind == OR_NEU) { F[side] = 0.0; continue; }
-                        double Ef = e_face(g, X->phi_bc, X->phi, d, i, j, k, fidx);
-                        if (boundary && kind == OR_WALL) {
-                            double e_n = fidx == 0 ? -Ef : Ef;
-                            double fl;
-                            if (ne_wall) /* energy: 2 kB Te times the electron wall flux */
-                                fl = 2.0 * X->cs->kB * X->Te[c] * wall_flux(OR_WALL_ELECTRON, ne_wall[c], 0.0, e_n, X->Te[c], X->Tg, X->cs->me, X->cs);
-                            else
-                                fl = wall_flux(wk, u[c], mu[c], e_n, X->Te[c], X->Tg, mass, X->cs);
-                            F[side] = fidx == 0 ? -fl : fl;   /* flux in +d direction */
-                            continue;
-                        }
-                        /* cells left and right of the face along d */
-                        int pl = fidx - 1, pr = fidx;
-                        double mul, mur;
-                        {
-                            int ql = pl, qr = pr;
-                            if (boundary && kind == OR_PER) { if (ql < 0) ql += n_d; if (qr >= n_d) qr -= n_d; }
-                            size_t cl = d == 0 ? IDX(ql < 0 ? 0 : ql, j, k, nx, ny) : (d == 1 ? IDX(i, ql < 0 ? 0 : ql, k, nx, ny) : IDX(i, j, ql < 0 ? 0 : ql, nx, ny));
-                            size_t cr = d == 0 ? IDX(qr >= n_d ? n_d - 1 : qr, j, k, nx, ny) : (d == 1 ? IDX(i, qr >= n_d ? n_d - 1 : qr, k, nx, ny) : IDX(i, j, qr >= n_d ? n_d - 1 : qr, nx, ny));
-                            mul = mu[cl];
-                            mur = mu[cr];
-                        }
-                        double muf;
-                        if (boundary && kind != OR_PER) muf = fidx == 0 ? mur : mul;
-                        else muf = 0.5 * (mul + mur);
-                        double v = muf * Ef;
-                        if (v == 0.0) { F[side] = 0.0; continue; }
-                        double s[5];
-                        if (v > 0.0) {
-                            for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pl - 2 + m);
-                        } else {
-                            for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pr + 2 - m);
-                        }
-                        F[side] = v * or_weno5(s);
-                    }
+                    for (int side = 0; side < 2; side++)
+                        F[side] = drift_face_flux(X, ubc, u, mu, wk, mass, ne_wall, d, i, j, k, pos + side);
                     total += (F[1] - F[0]) / h;
                 }
                 div[c] = total;
@@ -984,6 +1026,38 @@ int or_species_flux(const or_grid *g, const or_bc *phi_bc, const or_bc *sp_bc, i
     or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs };
     for (int s = 0; s < S; s++)
         drift_divergence(&X, &sp_bc[s], n + s * nc, mu + s * nc, sp[s].wall_kind, sp[s].mass, NULL, div + s * nc);
+    return OR_OK;
+}
+
+/* Face flux of one species for the tests: total flux along +d through
+ * every face, the drift part of drift_face_flux (WENO5, or the wall flux at
+ * a wall face) plus the central diffusive part of diff_face with the
+ * species' cell diffusion D (Eq. (2): Gamma = mu n E - D grad n).  Face
+ * arrays: fx (nx+1) ny nz, fy nx (ny+1) nz, fz nx ny (nz+1). */
+int or_face_flux(const or_grid *g, const or_bc *phi_bc, const or_bc *ubc, const or_species *sp, const double *u,
+                 const double *phi, const double *mu, const double *D, const double *Te, double Tg,
+                 const or_consts *cs, double *fx, double *fy, double *fz)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs };
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i <= nx; i++)
+                fx[(size_t)i + (size_t)(nx + 1) * (j + (size_t)ny * k)] =
+                    drift_face_flux(&X, ubc, u, mu, sp->wall_kind, sp->mass, NULL, 0, i < nx ? i : nx - 1, j, k, i) +
+                    diff_face(g, ubc, u, D, 0, i < nx ? i : nx - 1, j, k, i);
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i < nx; i++)
+                fy[(size_t)i + (size_t)nx * (j + (size_t)(ny + 1) * k)] =
+                    drift_face_flux(&X, ubc, u, mu, sp->wall_kind, sp->mass, NULL, 1, i, j < ny ? j : ny - 1, k, j) +
+                    diff_face(g, ubc, u, D, 1, i, j < ny ? j : ny - 1, k, j);
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++)
+                fz[(size_t)i + (size_t)nx * (j + (size_t)ny * k)] =
+                    drift_face_flux(&X, ubc, u, mu, sp->wall_kind, sp->mass, NULL, 2, i, j, k < nz ? k : nz - 1, k) +
+                    diff_face(g, ubc, u, D, 2, i, j, k < nz ? k : nz - 1, k);
     return OR_OK;
 }
 
@@ -1194,6 +1268,8 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     size_t nc = (size_t)g->nx * g->ny * g->nz;
     if (S < 1 || S > 32 || P->n_t < 1) return info->status = OR_EINVAL;
     if (P->te_mode == OR_TE_ENERGY && (!Ee || P->electron < 0)) return info->status = OR_EINVAL;
+    if ((P->phi_fixed || P->check_n || P->check_Ee) && P->n_t != 1) return info->status = OR_EINVAL;
+    if ((P->check_n || P->check_Ee) && !P->check_res) return info->status = OR_EINVAL;
     const or_consts *cs = &P->c;
     double *n0 = (double *)malloc(sizeof(double) * nc * S);
     double *ns = (double *)malloc(sizeof(double) * nc * S);
@@ -1233,9 +1309,14 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
         }
         or_problem PP = { *g, P->phi_bc, NULL, NULL, 0.0, P->eps_cell, cs->eps0 };
         or_mg_info mi;
-        int st = or_mg_solve(&PP, rho, phi, &P->poisson, &mi);
-        info->poisson_cycles += mi.cycles;
-        info->poisson_rel = mi.rel_res;
+        int st = OR_OK;
+        if (P->phi_fixed) {
+            info->poisson_rel = rel_residual(&PP, rho, phi);
+        } else {
+            st = or_mg_solve(&PP, rho, phi, &P->poisson, &mi);
+            info->poisson_cycles += mi.cycles;
+            info->poisson_rel = mi.rel_res;
+        }
         if (st != OR_OK) { status = st; goto out; }
         /* E/N and Te at u* */
         for (int k = 0; k < g->nz; k++)
@@ -1338,9 +1419,14 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             free(Gam);
             or_problem EP = { *g, P->energy_bc, NULL, NULL, 1.0 / dt, beta, 0.0 };
             for (int f = 0; f < 6; f++) if (EP.bc.kind[f] == OR_WALL) EP.bc.kind[f] = OR_NEU;
-            st = or_mg_solve(&EP, rhs, Ee, &P->energy_mg, &mi);
-            if (mi.cycles > info->energy_cycles) info->energy_cycles = mi.cycles;
-            if (st != OR_OK) { status = st; goto out; }
+            if (P->check_Ee) {
+                for (size_t c = 0; c < nc; c++) Ee[c] = P->check_Ee[c];
+                P->check_res[S] = rel_residual(&EP, rhs, Ee);
+            } else {
+                st = or_mg_solve(&EP, rhs, Ee, &P->energy_mg, &mi);
+                if (mi.cycles > info->energy_cycles) info->energy_cycles = mi.cycles;
+                if (st != OR_OK) { status = st; goto out; }
+            }
         }
         /* species (Eq. (1)) */
         for (int k = 0; k < S; k++) {
@@ -1358,6 +1444,11 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             int varD = P->species[k].mob_kind == OR_MOB_ELECTRON_FIT;
             or_problem SP = { *g, P->species_bc[k], NULL, NULL, 1.0 / dt, varD ? Dk + k * nc : NULL, Dk[k * nc] };
             for (int f = 0; f < 6; f++) if (SP.bc.kind[f] == OR_WALL) SP.bc.kind[f] = OR_NEU;
+            if (P->check_n) {
+                for (size_t c = 0; c < nc; c++) n[k * nc + c] = P->check_n[k * nc + c];
+                P->check_res[k] = rel_residual(&SP, rhs, n + k * nc);
+                continue;
+            }
             if (m == 0 && P->species_guess)
                 for (size_t c = 0; c < nc; c++) n[k * nc + c] = P->species_guess[k * nc + c];
             int st2 = or_mg_solve(&SP, rhs, n + k * nc, &P->species_mg, &mi);

@@ -4,9 +4,10 @@
 
 namespace vd {
 vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step_info *info);
+vd_status step_reset(vd_ctx *ctx);
 vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const vd_bc *sp_bc, int S, const vd_species *sp,
-                       const double *n, const double *phi, const double *mu, const double *Te, double Tg, const vd_consts *c,
-                       double *div);
+                       const double *n, const double *phi, const double *mu, const double *D, const double *Te, double Tg,
+                       const vd_consts *c, double *div, int flux_species, double *face_flux);
 vd_status reaction_source(vd_ctx *ctx, int mech, long ncell, int S, const double *n, const double *Te, const double *bg,
                           double qe, double *G, double *S_inel);
 
@@ -152,10 +153,12 @@ vd_status vd_helmholtz_solve_batched(vd_ctx *ctx, int32_t nprob, const vd_proble
 }
 
 vd_status vd_species_flux(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const vd_bc *species_bc, int32_t S,
-                          const vd_species *species, const double *n, const double *phi, const double *mu, const double *Te_K,
-                          double Tg, const vd_consts *consts, double *div_drift) {
+                          const vd_species *species, const double *n, const double *phi, const double *mu, const double *D,
+                          const double *Te_K, double Tg, const vd_consts *consts, double *div_drift, int32_t flux_species,
+                          double *face_flux) {
     return guarded(ctx, [&] {
-        return vd::species_flux(ctx, grid, phi_bc, species_bc, S, species, n, phi, mu, Te_K, Tg, consts, div_drift);
+        return vd::species_flux(ctx, grid, phi_bc, species_bc, S, species, n, phi, mu, D, Te_K, Tg, consts, div_drift,
+                                flux_species, face_flux);
     });
 }
 
@@ -166,6 +169,10 @@ vd_status vd_reaction_source(vd_ctx *ctx, int32_t mech, int64_t ncells, int32_t 
 
 vd_status vd_step(vd_ctx *ctx, const vd_step_params *params, const vd_state *state, vd_step_info *info) {
     return guarded(ctx, [&] { return vd::step(ctx, params, state, info); });
+}
+
+vd_status vd_step_reset(vd_ctx *ctx) {
+    return guarded(ctx, [&] { return vd::step_reset(ctx); });
 }
 
 vd_status vd_cell_flags(vd_ctx *ctx, const vd_problem *prob, int32_t n_levels, int32_t level, uint8_t *out) {

@@ -598,7 +598,7 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
 #undef VD_STAGE
 }
 
-// Wall fluxes (Eqs. (13)-(15)) of the WALLFLUX domain faces along direction
+// Wall fluxes (Sec. 2.2, Eqs. (14)-(16)) of the WALLFLUX domain faces along direction
 // d, added to the boundary cells' divergence after k_drift25 (mode 0: out +=
 // contribution; mode 1: out -= it).  One thread per boundary line handles
 // both ends, so no cell is updated twice in a launch.
@@ -954,6 +954,37 @@ __global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
     gst(a.out, c, gld(a.Ee0, c) * a.inv_dt - divE + src);
 }
 
+// ------------------------------------------------------ face fluxes
+// Total flux along +d through every face of one field: the drift part of
+// face_flux (upwind WENO5, the wall flux at a wall face, nothing at a
+// Neumann face) plus the central diffusive part of diff_face.  One thread
+// per face; face arrays x ((nx+1) ny nz), then y (nx (ny+1) nz), then z
+// (nx ny (nz+1)).
+__global__ void __launch_bounds__(kBlock) k_face_flux(DriftArgs a, const double *__restrict__ D, double *__restrict__ out) {
+    const GridDev &G = a.g;
+    const FieldDesc &F = a.f[0];
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const long nfx = (long)(nx + 1) * ny * nz, nfy = (long)nx * (ny + 1) * nz, nfz = (long)nx * ny * (nz + 1);
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nfx + nfy + nfz) return;
+    const long slot = q;
+    int d, i, j, k;
+    if (q < nfx) {
+        d = 0; i = (int)(q % (nx + 1)); q /= nx + 1; j = (int)(q % ny); k = (int)(q / ny);
+    } else if ((q -= nfx) < nfy) {
+        d = 1; i = (int)(q % nx); q /= nx; j = (int)(q % (ny + 1)); k = (int)(q / (ny + 1));
+    } else {
+        q -= nfy;
+        d = 2; i = (int)(q % nx); q /= nx; j = (int)(q % ny); k = (int)(q / ny);
+    }
+    const int fidx = d == 0 ? i : (d == 1 ? j : k);
+    // start of the row through the face along d
+    const long c0 = (d == 0 ? 0 : i) + (long)nx * (d == 1 ? 0 : j) + (long)G.nxy * (d == 2 ? 0 : k);
+    const double drift = face_flux(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, d, c0, fidx);
+    const double diff = diff_face(G, F.kind, F.gval, F.u, D, 0.0, d, (int)c0, 0, fidx);
+    gst(out, slot, drift + diff);
+}
+
 // ----------------------------------------------------- host launchers
 void launch_transport(vd_ctx *ctx, const TransportArgs &a) {
     // phi read, Te written (table or energy mode), mu and D written per field-dependent species
@@ -1037,6 +1068,15 @@ void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int order
 
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n) {
     timed(ctx, "mid", (double)n * 24.0, [&] { k_mid<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(u0, u, out, n); });
+}
+
+void launch_face_flux(vd_ctx *ctx, DriftArgs a, const FieldDesc &field, const double *D, double *out) {
+    a.f = (const FieldDesc *)upload_blob(ctx, "fields:faces", &field, sizeof(FieldDesc));
+    const long nf = (long)(a.g.n[0] + 1) * a.g.n[1] * a.g.n[2] + (long)a.g.n[0] * (a.g.n[1] + 1) * a.g.n[2] +
+                    (long)a.g.n[0] * a.g.n[1] * (a.g.n[2] + 1);
+    timed(ctx, "faces", 8.0 * (4.0 * a.g.ncell + nf), [&] {
+        k_face_flux<<<ceil_div(nf, kBlock), kBlock, 0, ctx->stream>>>(a, D, out);
+    });
 }
 
 GridDev make_grid(const vd_grid &g, const vd_bc &phi_bc) {

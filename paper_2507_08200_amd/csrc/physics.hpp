@@ -94,6 +94,8 @@ struct EnergyArgs {
 GridDev make_grid(const vd_grid &g, const vd_bc &phi_bc);
 void launch_transport(vd_ctx *ctx, const TransportArgs &a);
 void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields, const char *tag);
+// total face flux (drift + central diffusion with cell diffusion D) of one field
+void launch_face_flux(vd_ctx *ctx, DriftArgs a, const FieldDesc &field, const double *D, double *out);
 void launch_react(vd_ctx *ctx, const ReactArgs &a);
 void launch_rho(vd_ctx *ctx, const RhoArgs &a);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);

@@ -1,7 +1,7 @@
 // One semi-implicit step of the plasma-fluid model (Sec. 3 of the paper):
 // segregated Poisson -> electron energy -> species, explicit WENO5 drift and
 // chemistry at the mid-point state u*, implicit central diffusion, with the
-// mid-point corrector iteration of Eqs. (17)-(18).
+// mid-point corrector iteration of Eqs. (18)-(19).
 #include "physics.hpp"
 
 #include <chrono>
@@ -387,13 +387,32 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
     return VD_OK;
 }
 
-// Standalone drift divergence (vd_species_flux).
+// Forget both histories of extrapolated guesses: the next vd_step with
+// VD_GUESS_EXTRAP starts as after a restart.
+vd_status step_reset(vd_ctx *ctx) {
+    auto ih = ctx->cache.find("phi_history");
+    if (ih != ctx->cache.end()) {
+        auto H = std::static_pointer_cast<PhiHistory>(ih->second);
+        H->count = -1; H->newest = 0; H->phi = nullptr;
+    }
+    auto is = ctx->cache.find("species_history");
+    if (is != ctx->cache.end()) {
+        auto H = std::static_pointer_cast<SpeciesHistory>(is->second);
+        H->count = -1; H->newest = 0; H->n = nullptr;
+    }
+    return VD_OK;
+}
+
+// Standalone drift divergence (vd_species_flux), and the total face flux
+// of one species when asked for.
 vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const vd_bc *sp_bc, int S, const vd_species *sp,
-                       const double *n, const double *phi, const double *mu, const double *Te, double Tg, const vd_consts *c,
-                       double *div) {
+                       const double *n, const double *phi, const double *mu, const double *D, const double *Te, double Tg,
+                       const vd_consts *c, double *div, int flux_species, double *face_flux) {
     VD_CHECK(g && phi_bc && sp_bc && sp && n && phi && mu && Te && c && div, "null argument");
     VD_CHECK(S >= 1 && S <= kMaxFields, "S out of range");
     VD_CHECK(g->nx >= 3 && g->ny >= 3 && g->nz >= 3, "WENO5 ghosts need at least 3 cells per direction");
+    VD_CHECK(!face_flux || (flux_species >= 0 && flux_species < S && D),
+             "face fluxes need a species index in 0..S-1 and the diffusion coefficients");
     const long N = (long)g->nx * g->ny * g->nz;
     DriftArgs da;
     memset(&da, 0, sizeof(da));
@@ -412,6 +431,7 @@ vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const
         F.out = div + (long)k * N;
     }
     launch_drift(ctx, da, fds, S, "flux");
+    if (face_flux) launch_face_flux(ctx, da, fds[flux_species], D + (long)flux_species * N, face_flux);
     return VD_OK;
 }
 

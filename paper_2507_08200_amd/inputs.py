@@ -15,6 +15,11 @@ Workloads (all SI units unless stated):
   101325 Pa, 300 K); electron/Ar+ Gaussian seed (peak 1e19 m^-3, sigma
   0.5 mm) centred 1 mm from the x = 0 electrode at 15 kV; background 1e13
   m^-3 with 1 % noise; Te from the reduced-field table; dt = 1e-12 s.
+* ``cfg2``: manufactured solution on the unit cube (the method of Sec. 5.1 in
+  3D): 8 species with signed constant mobilities and constant diffusion, a
+  charge pair that sustains an analytic potential, nondimensional constants;
+  the exact source that makes the analytic fields steady is passed to the
+  step as its extra species source.
 * ``cfg4``: 64 independent Helmholtz problems of uneven size (edges drawn
   from {32, 48, ..., 160}), log-uniform beta with a sheath-like slab jump,
   random Dirichlet/Neumann faces, N(0,1) right-hand sides.
@@ -126,29 +131,33 @@ def cfg1(seed: int = 1, n: int = 32) -> dict:
 
 
 def cfg3(seed: int = 3, n: int = 160, L: float = 0.0125, voltage: float = 15e3,
-         seed_centre=None) -> dict:
-    """15-species Ar-H2 streamer-shaped state on an n^3 grid."""
+         seed_centre=None, ny: int = 0, nz: int = 0) -> dict:
+    """15-species Ar-H2 streamer-shaped state on an n^3 grid (n x ny x nz
+    cells of edge L/n when ny, nz are given; the seed sits 1 mm from the
+    x = 0 electrode on the transverse axis)."""
     h = L / n
+    ny = ny or n
+    nz = nz or n
     g = rng(seed)
-    X, Y, Z = cell_centres(n, n, n, h, h, h)
-    c = seed_centre if seed_centre is not None else (1.0e-3, L / 2, L / 2)
+    X, Y, Z = cell_centres(n, ny, nz, h, h, h)
+    c = seed_centre if seed_centre is not None else (1.0e-3, ny * h / 2, nz * h / 2)
     shape = _blob(X, Y, Z, c, 0.5e-3)
     base = 1e13 + 1e19 * shape
     S = 15
     N = N_1ATM_300K
-    dens = np.zeros((S, n, n, n))
+    dens = np.zeros((S, nz, ny, n))
     dens[0] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))    # e
     dens[1] = base * (1.0 + 0.01 * g.uniform(-1, 1, base.shape))    # Ar+
     dens[13] = 0.95 * N                                               # Ar
     dens[14] = 0.05 * N                                               # H2
     wall = [BC_WALLFLUX, BC_WALLFLUX, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN]
     return {
-        "name": "cfg3-arh2-%d" % n,
-        "grid": (n, n, n, h, h, h),
+        "name": "cfg3-arh2-%d" % n if ny == n and nz == n else "cfg3-arh2-%dx%dx%d" % (n, ny, nz),
+        "grid": (n, ny, nz, h, h, h),
         "mech": MECH_ARH2_15,
         "n": dens,
-        "phi": np.zeros((n, n, n)),
-        "Te": np.full((n, n, n), 300.0),
+        "phi": np.zeros((nz, ny, n)),
+        "Te": np.full((nz, ny, n), 300.0),
         "te_mode": TE_LFA,
         "phi_bc": bc([BC_DIRICHLET, BC_DIRICHLET] + [BC_NEUMANN] * 4, [voltage, 0, 0, 0, 0, 0]),
         "species_bc": [bc(wall)] * S,
@@ -159,6 +168,82 @@ def cfg3(seed: int = 3, n: int = 160, L: float = 0.0125, voltage: float = 15e3,
         "N_gas": N,
         "bg": [],
         "lfa": lfa_table(),
+    }
+
+
+UNIT_CONSTS = {"qe": 1.0, "eps0": 1.0, "kB": 1.0, "me": 1.0}
+
+
+def cfg2(seed: int = 2, n: int = 128, S: int = 8, levels: int = 4) -> dict:
+    """Manufactured steady solution on the unit cube with n^3 cells.
+
+    With s(x) = sin 2 pi x sin 2 pi y sin 2 pi z the species densities are
+    n_k = a_k (1 + c_k s / 2) (a_k ~ U[1, 2], c_k ~ U[0.5, 1]), the
+    potential phi = B s and Te = 1 + s / 10; species 0 and 1 carry charge
+    +1 and -1 with a_0 = a_1, the others none, so that with e = eps0 = 1
+    Poisson's equation -lap phi = sum_k Z_k n_k holds exactly for
+    B = a_0 (c_0 - c_1) / (24 pi^2) (lap s = -12 pi^2 s).  Mobilities are
+    signed constants, |mu_k| ~ U[0.1, 1] with a random sign, D_k ~
+    U[0.05, 0.5].  x faces are Dirichlet with the exact values (s = 0 there:
+    phi = 0, n_k = a_k), y and z periodic.  The exact source is the
+    continuous drift-diffusion divergence of the analytic fields,
+    div(mu_k n_k E) - D_k lap n_k with E = -grad phi (Eqs. (1)-(2); no
+    chemistry), evaluated in closed form at the cell centres, so that the
+    analytic fields are a steady solution of the continuous problem.
+    Returned "exact" holds the analytic n and phi at the cell centres."""
+    g = rng(seed)
+    h = 1.0 / n
+    X, Y, Z = cell_centres(n, n, n, h, h, h)
+    tp = 2.0 * np.pi
+    sx, sy, sz = np.sin(tp * X), np.sin(tp * Y), np.sin(tp * Z)
+    cx, cy, cz = np.cos(tp * X), np.cos(tp * Y), np.cos(tp * Z)
+    s = sx * sy * sz
+    grad_s = (tp * cx * sy * sz, tp * sx * cy * sz, tp * sx * sy * cz)
+    grad_s2 = grad_s[0] ** 2 + grad_s[1] ** 2 + grad_s[2] ** 2
+    lap_s = -3.0 * tp * tp * s
+    a = g.uniform(1.0, 2.0, S)
+    a[1] = a[0]
+    c = g.uniform(0.5, 1.0, S)
+    mu = g.uniform(0.1, 1.0, S) * np.where(g.uniform(0, 1, S) < 0.5, -1.0, 1.0)
+    D = g.uniform(0.05, 0.5, S)
+    Zc = np.zeros(S)
+    Zc[0], Zc[1] = 1.0, -1.0
+    B = a[0] * (c[0] - c[1]) / (24.0 * np.pi ** 2)
+    phi = B * s
+    dens = np.empty((S, n, n, n))
+    src = np.empty((S, n, n, n))
+    for k in range(S):
+        dens[k] = a[k] * (1.0 + 0.5 * c[k] * s)
+        # grad n . E = -(a c / 2) B |grad s|^2 ;  div E = -B lap s
+        gradn_dot_E = -0.5 * a[k] * c[k] * B * grad_s2
+        div_E = -B * lap_s
+        lap_n = 0.5 * a[k] * c[k] * lap_s
+        src[k] = mu[k] * (gradn_dot_E + dens[k] * div_E) - D[k] * lap_n
+    species = [{"Z": float(Zc[k]), "mass": 1.0, "mob_kind": 0, "wall_kind": 0, "mu_const": float(mu[k]),
+                "D_const": float(D[k]), "transported": 1} for k in range(S)]
+    sbc = [bc([BC_DIRICHLET, BC_DIRICHLET, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC],
+              [a[k], a[k], 0, 0, 0, 0]) for k in range(S)]
+    per_x_dir = [BC_DIRICHLET, BC_DIRICHLET, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC]
+    return {
+        "name": "cfg2-mms-%d" % n,
+        "grid": (n, n, n, h, h, h),
+        "mech": MECH_NONE,
+        "n": dens.copy(),
+        "phi": phi.copy(),
+        "Te": 1.0 + 0.1 * s,
+        "te_mode": TE_FIXED,
+        "phi_bc": bc(per_x_dir),
+        "species_bc": sbc,
+        "energy_bc": bc(per_x_dir),
+        "dt": 0.05,
+        "n_t": 1,
+        "Tg": 1.0,
+        "N_gas": 1.0,
+        "bg": [],
+        "levels": levels,
+        "species": species,
+        "extra_source": src,
+        "exact": {"n": dens, "phi": phi},
     }
 
 

@@ -32,7 +32,7 @@ EXPORTS = ["vd_ctx_create", "vd_ctx_destroy", "vd_ctx_set_stream", "vd_last_erro
            "vd_poisson_solve", "vd_helmholtz_solve_batched", "vd_species_flux", "vd_reaction_source",
            "vd_step", "vd_cell_flags", "vd_smooth", "vd_timing_select", "vd_timing_read",
            "vd_nn_param_count", "vd_nn_create", "vd_nn_get", "vd_nn_set", "vd_nn_forward", "vd_nn_train_step",
-           "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d", "vd_check_tiles25"]
+           "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d", "vd_check_tiles25", "vd_step_reset"]
 
 
 class VDError(RuntimeError):
@@ -130,9 +130,10 @@ def load():
         "vd_version": ([], C.c_char_p),
         "vd_poisson_solve": ([P, P, P, P, P, d, P, P, P, P], i32),
         "vd_helmholtz_solve_batched": ([P, i32, P, P, P], i32),
-        "vd_species_flux": ([P, P, P, P, i32, P, P, P, P, P, d, P, P], i32),
+        "vd_species_flux": ([P, P, P, P, i32, P, P, P, P, P, P, d, P, P, i32, P], i32),
         "vd_reaction_source": ([P, i32, C.c_int64, i32, P, P, P, d, P, P], i32),
         "vd_step": ([P, P, P, P], i32),
+        "vd_step_reset": ([P], i32),
         "vd_cell_flags": ([P, P, i32, i32, P], i32),
         "vd_smooth": ([P, P, i32], i32),
         "vd_nn_param_count": ([P], C.c_int64),
@@ -352,19 +353,32 @@ class Context:
             None if db is None else db.data_ptr()))
         return y if dy is None else (y, dx, dw, db)
 
-    def vd_species_flux(self, g, phi_bc, species_bc, species, n, phi, mu, Te, Tg, consts):
+    def vd_species_flux(self, g, phi_bc, species_bc, species, n, phi, mu, Te, Tg, consts, D=None, flux_species=-1):
+        """Drift divergence [S][cells]; with flux_species >= 0 (and D) also
+        the total face flux of that species as (fx, fy, fz)."""
         nx, ny, nz = g[:3]
         S = len(species)
         shp = (nz, ny, nx)
         out = torch.empty((S,) + shp, dtype=torch.float64, device=n.device)
+        faces = None
+        if flux_species >= 0:
+            nf = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+            faces = torch.empty(nf, dtype=torch.float64, device=n.device)
         SB = (BC * S)(*[bc(b) for b in species_bc])
         SP = species_array(species)
         st = self.lib.vd_species_flux(self.h, C.byref(grid(g)), C.byref(bc(phi_bc)), SB, S, SP,
                                       _dptr(n, (S,) + shp, name="n"), _dptr(phi, shp, name="phi"),
-                                      _dptr(mu, (S,) + shp, name="mu"), _dptr(Te, shp, name="Te"), float(Tg),
-                                      C.byref(Consts(**consts)), _dptr(out, name="div"))
+                                      _dptr(mu, (S,) + shp, name="mu"),
+                                      None if D is None else _dptr(D, (S,) + shp, name="D"),
+                                      _dptr(Te, shp, name="Te"), float(Tg),
+                                      C.byref(Consts(**consts)), _dptr(out, name="div"), int(flux_species),
+                                      None if faces is None else faces.data_ptr())
         self._check(st)
-        return out
+        if faces is None:
+            return out
+        a, b = (nx + 1) * ny * nz, nx * (ny + 1) * nz
+        return out, (faces[:a].view(nz, ny, nx + 1), faces[a:a + b].view(nz, ny + 1, nx),
+                     faces[a + b:].view(nz + 1, ny, nx))
 
     def vd_reaction_source(self, mech, n, Te, bg=(), qe=1.602176634e-19):
         S = n.shape[0]
@@ -390,6 +404,9 @@ class Context:
         return _info(info) if want_info else None
 
     # ------------------------------------------------------- inspection
+    def vd_step_reset(self):
+        self._check(self.lib.vd_step_reset(self.h))
+
     def vd_cell_flags(self, problem, level, n_levels=0):
         nx, ny, nz = problem["grid"][:3]
         shp = (nz, ny, nx)

@@ -28,6 +28,18 @@ def rel_err(got, want):
     return float(np.abs(got - want).max() / scale)
 
 
+def rel_err_pointwise(got, want, floor=1e-6):
+    """max over cells of |got - want| / max(|want|, floor * max |want|): the
+    relative error of every cell whose value is at least floor of the
+    field's largest, and an absolute error at that level below it."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    scale = np.abs(want).max()
+    if scale == 0:
+        return float(np.abs(got).max())
+    return float((np.abs(got - want) / np.maximum(np.abs(want), floor * scale)).max())
+
+
 def gpu_problem(prob, x=None):
     """Device copy of an inputs.random_helmholtz-style problem dict."""
     return {

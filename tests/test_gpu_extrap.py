@@ -278,3 +278,31 @@ def test_species_extrap_guess_exact(V, n):
         else:
             want = a[k]
         assert np.array_equal(got[k], want), k
+
+
+def test_reset_history_for_a_state_written_in_place(V):
+    """A new, unrelated state written into the same tensors after steps with
+    extrapolated guesses: after vd_step_reset the next step starts afresh
+    and equals, bit for bit, a step with the given values as the guesses."""
+    from paper_2507_08200_amd import mechanisms as M
+    cfg = I.cfg3(n=32)
+    other = I.cfg3(n=32, seed=9, voltage=8e3, seed_centre=(2.0e-3, 0.005, 0.007))
+    lfa = dict(cfg["lfa"])
+    lfa["te_K"] = dev(cfg["lfa"]["te_K"])
+    sp = dict(rtol=1e-10, n_levels=1, nu_pre=1, nu_post=0, precision=V.FP32_IR, ir_inner=1)
+    po = dict(rtol=1e-10, precision=V.FP32_IR, ir_inner=1)
+    PX = V.step_params(cfg, M.arh2_15(), lfa=lfa, poisson=V.mg_opts(guess=V.GUESS_EXTRAP, **po),
+                       species_mg=V.mg_opts(guess=V.GUESS_EXTRAP, **sp))
+    PG = V.step_params(cfg, M.arh2_15(), lfa=lfa, poisson=V.mg_opts(**po), species_mg=V.mg_opts(**sp))
+    ca, cb = V.Context(), V.Context()
+    s = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    for _ in range(3):
+        assert ca.vd_step(PX, s)["status"] == 0
+    for k in ("n", "phi", "Te"):
+        s[k].copy_(dev(other[k]))
+    ca.vd_step_reset()
+    assert ca.vd_step(PX, s)["status"] == 0
+    r = {k: dev(other[k]) for k in ("n", "phi", "Te")}
+    assert cb.vd_step(PG, r)["status"] == 0
+    say("reset history: in-place state equals a fresh given-guess step")
+    assert _same(s, r)

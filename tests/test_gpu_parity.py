@@ -7,7 +7,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from gpu_util import dev, gpu_problem, host, rel_err, say  # noqa: E402
+from gpu_util import rel_err_pointwise, dev, gpu_problem, host, rel_err, say  # noqa: E402
 from paper_2507_08200_amd import inputs as I  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -214,11 +214,22 @@ def test_species_flux(ctx, oracle, kinds, shape):
                    3e-3 * np.ones((nz, ny, nx))])
     pbc = I.bc([0, 0, 1, 1, 3, 3], (30.0, -10.0, 0, 0, 0, 0))
     sbc = [I.bc(kinds, rng.uniform(1e14, 1e16, 6)) for _ in range(S)]
-    say("species flux", kinds)
+    D = np.stack([0.05 * (1 + 0.5 * rng.uniform(-1, 1, (nz, ny, nx))) for _ in range(S)])
+    say("species flux", kinds, shape)
     got = host(ctx.vd_species_flux(g, pbc, sbc, species, dev(n), dev(phi), dev(mu), dev(Te), 300.0, PHYS))
     want = oracle.species_flux(g, pbc, sbc, species, n, phi, mu, Te, 300.0, PHYS)
     for s in range(S):
         assert rel_err(got[s], want[s]) <= TOL, (s, rel_err(got[s], want[s]))
+    # total face flux (drift + central diffusion) of the electrons and an ion
+    for fs in (0, 1):
+        div, faces = ctx.vd_species_flux(g, pbc, sbc, species, dev(n), dev(phi), dev(mu), dev(Te), 300.0, PHYS,
+                                         D=dev(D), flux_species=fs)
+        assert np.array_equal(host(div), got)
+        ref = oracle.face_flux(g, pbc, sbc[fs], species[fs], n[fs], phi, mu[fs], D[fs], Te, 300.0, PHYS)
+        for d in range(3):
+            e, ep = rel_err(host(faces[d]), ref[d]), rel_err_pointwise(host(faces[d]), ref[d], 1e-6)
+            say("   faces", fs, d, "%.2e %.2e" % (e, ep))
+            assert e <= TOL, (fs, d, e)
 
 
 def test_reaction_source(ctx, oracle):

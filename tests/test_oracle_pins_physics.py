@@ -394,3 +394,69 @@ def test_energy_temperature_clamped_at_gas_temperature(oracle):
                     poisson=oracle.mg_opts(rtol=1e-14, max_cycles=2000))
     assert r["status"] == 0
     assert np.all(r["Te"] == 300.0)
+
+
+# --------------------------------------------------------------------------
+# Face flux Gamma = mu n E - D grad n (Eq. (2)) on every face
+# --------------------------------------------------------------------------
+def test_face_flux_linear_density_closed_form(oracle):
+    """Linear density between Dirichlet values in a uniform field: WENO5 is
+    exact on linear data (its ghosts continue the line), the central
+    difference gives the exact slope, so every x face carries
+    mu E n(x_f) - D s and the y, z faces nothing."""
+    nx, ny, nz, h = 12, 4, 6, 1e-4
+    L = nx * h
+    V, mu, D = 30.0, -0.03, 0.07
+    g0, g1 = 1e17, 5e17
+    X, _, _ = I.cell_centres(nx, ny, nz, h, h, h)
+    s = (g1 - g0) / L
+    u = g0 + s * X
+    phi = V * (1 - X / L)
+    pbc = I.bc([0, 0, 3, 3, 3, 3], (V, 0, 0, 0, 0, 0))
+    ubc = I.bc([0, 0, 3, 3, 1, 1], (g0, g1, 0, 0, 0, 0))
+    sp = {"Z": -1, "mass": PHYS["me"], "mob_kind": 0, "wall_kind": 1, "mu_const": mu}
+    fx, fy, fz = oracle.face_flux((nx, ny, nz, h, h, h), pbc, ubc, sp, u, phi, np.full(u.shape, mu),
+                                  np.full(u.shape, D), np.full(u.shape, 2e4), 300.0)
+    xf = np.arange(nx + 1) * h
+    want = mu * (V / L) * (g0 + s * xf) - D * s
+    scale = np.abs(want).max()
+    assert np.abs(fx - want[None, None, :]).max() <= 1e-12 * scale
+    assert np.abs(fy).max() <= 1e-12 * scale
+    assert np.abs(fz).max() <= 1e-12 * scale
+
+
+def test_face_flux_wall_faces(oracle):
+    """Uniform density, no field: interior faces carry nothing; a WALLFLUX
+    face carries the Maxwellian electron flux outwards (negative along +x
+    at x = 0, positive at x = L) and no diffusion."""
+    nx, ny, nz, h = 8, 4, 4, 1e-4
+    n0, Te = 3e16, 3.0 * I.EV_IN_K
+    u = np.full((nz, ny, nx), n0)
+    ubc = I.bc([2, 2, 3, 3, 3, 3])
+    sp = {"Z": -1, "mass": PHYS["me"], "mob_kind": 0, "wall_kind": 1, "mu_const": -0.03}
+    fx, fy, fz = oracle.face_flux((nx, ny, nz, h, h, h), I.bc([0, 0, 3, 3, 3, 3]), ubc, sp, u, np.zeros(u.shape),
+                                  np.full(u.shape, -0.03), np.full(u.shape, 0.1), np.full(u.shape, Te), 300.0)
+    fl = n0 / 4 * np.sqrt(8 * PHYS["kB"] * Te / (np.pi * PHYS["me"]))
+    np.testing.assert_allclose(fx[:, :, 0], -fl, rtol=1e-14)
+    np.testing.assert_allclose(fx[:, :, -1], fl, rtol=1e-14)
+    assert np.all(fx[:, :, 1:-1] == 0) and np.all(fy == 0) and np.all(fz == 0)
+
+
+def test_step_check_mode_reproduces_the_solver_residuals(oracle):
+    """The check mode (potential given, species iterates given) recomputes
+    the relative residuals the solves stopped on: a converged oracle step
+    checks below its tolerance, a perturbed density does not."""
+    cfg = I.cfg1(n=16)
+    sp = oracle.species_ar3()
+    opts = oracle.mg_opts(rtol=1e-10)
+    r = oracle.step(cfg, sp, poisson=opts, species_mg=opts)
+    assert r["status"] == 0
+    c = oracle.step(cfg, sp, phi=r["phi"], phi_fixed=True, check_n=r["n"], poisson=opts, species_mg=opts)
+    assert c["status"] == 0
+    assert abs(c["info"]["poisson_rel"] - r["info"]["poisson_rel"]) <= 1e-3 * r["info"]["poisson_rel"]
+    assert np.all(c["check_res"][:3] <= 1e-10 * 1.001)
+    np.testing.assert_array_equal(c["n"], r["n"])
+    bad = r["n"].copy()
+    bad[1, 8, 8, 8] *= 1.0 + 1e-6
+    c2 = oracle.step(cfg, sp, phi=r["phi"], phi_fixed=True, check_n=bad, poisson=opts, species_mg=opts)
+    assert c2["check_res"][1] > 1e-9 and c2["check_res"][0] <= 1.001e-10
