@@ -168,6 +168,29 @@ vd_status vd_poisson_solve(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc
                            const double *beta_cell, double beta_c, const double *rho, double *phi,
                            const vd_mg_opts *opts, vd_solve_info *info /* host, nullable */);
 
+/* vd_poisson_solve without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, arithmetic and results
+ * as vd_poisson_solve, bit for bit.  Every multigrid array, plan and
+ * descriptor table of the solve is carved from one static device array of
+ * 64 MiB per GPU, which the library holds from the first context created on
+ * that GPU until the process ends; the call makes no hipMalloc, hipFree or
+ * hipHostMalloc and no allocating library call.  The hierarchy is rebuilt
+ * on every call (nothing is cached between calls), so the call costs
+ * set-up time that vd_poisson_solve spends only once per shape.  Fits, for
+ * example, a 160^3 uniform-permittivity solve in FP64 or in FP32
+ * refinement; a problem whose hierarchy needs more than 64 MiB returns
+ * VD_EINVAL with the caller's arrays untouched.  opts.flags must not ask for
+ * VD_MG_GRAPH or VD_MG_AUTOTUNE (they allocate) and opts.guess must be
+ * VD_GUESS_GIVEN or VD_GUESS_ZERO; otherwise VD_EINVAL.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (other
+ * streams, other contexts, other host threads) race and give undefined
+ * results; calls ordered on one stream are safe.  The current device must
+ * be the one the context's stream runs on. */
+vd_status vd_poisson_solve_noalloc(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const uint8_t *mask,
+                                   const double *beta_cell, double beta_c, const double *rho, double *phi,
+                                   const vd_mg_opts *opts, vd_solve_info *info /* host, nullable */);
+
 /* nprob independent Helmholtz problems of possibly different sizes solved
  * together (Sec. 7: several components per multigrid solve): one launch per
  * smoother colour covers every problem's level, coarse levels of all

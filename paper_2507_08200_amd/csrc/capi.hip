@@ -1,5 +1,7 @@
 // extern "C" entry points of libvd: argument checks, error capture and
 // dispatch to the internal engines.  No exception crosses this boundary.
+#include <mutex>
+
 #include "physics.hpp"
 
 namespace vd {
@@ -75,6 +77,34 @@ vd_status mg_solve_batch_guess(vd_ctx *ctx, int nprob, const vd_problem *probs, 
                                const char *cache_tag);
 }  // namespace vd
 
+// ---------------------------------------------- allocation-free solves
+// Device scratch of vd_poisson_solve_noalloc: a static array that every GPU
+// the library runs on holds until the process ends.  In host code the
+// array's name only identifies the symbol; kernels get the device address
+// that hipGetSymbolAddress returns for the current device, resolved once
+// per device (at context creation, or on the first such call on a device).
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+vd_status resolve_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VD_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return VD_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VD_OK;
+}
+}  // namespace
+
 namespace vd {
 template <typename F>
 static vd_status guarded(vd_ctx *ctx, F &&fn) {
@@ -103,6 +133,8 @@ vd_status vd_ctx_create(vd_ctx **out, void *stream) {
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return VD_EHIP;
+    void *scratch_ptr = nullptr;
+    if (resolve_scratch(&scratch_ptr) != VD_OK) return VD_EHIP;
     vd_ctx *c = new (std::nothrow) vd_ctx();
     if (!c) return VD_ENOMEM;
     c->stream = (hipStream_t)stream;
@@ -144,6 +176,25 @@ vd_status vd_poisson_solve(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc
             return vd::mg_solve_batch_guess(ctx, 1, &p, opts, info, "poisson:");
         }
         return vd::mg_solve_batch(ctx, 1, &p, opts, info, "poisson:");
+    });
+}
+
+vd_status vd_poisson_solve_noalloc(vd_ctx *ctx, const vd_grid *grid, const vd_bc *phi_bc, const uint8_t *mask,
+                                   const double *beta_cell, double beta_c, const double *rho, double *phi,
+                                   const vd_mg_opts *opts, vd_solve_info *info) {
+    return guarded(ctx, [&] {
+        VD_CHECK(grid && phi_bc && rho && phi && opts, "null argument");
+        VD_CHECK(beta_cell || beta_c > 0.0, "permittivity must be positive");
+        void *ptr = nullptr;
+        if (resolve_scratch(&ptr) != VD_OK) throw vd::Error{VD_EHIP, "no device address for the scratch array"};
+        vd_problem p;
+        memset(&p, 0, sizeof(p));
+        p.grid = *grid; p.bc = *phi_bc; p.mask = mask; p.beta = beta_cell; p.beta_c = beta_c;
+        p.rhs = rho; p.x = phi;
+        vd::Arena arena;
+        arena.base = (char *)ptr;
+        arena.cap = kScratchBytes;
+        return vd::mg_solve_noalloc(ctx, &arena, 1, &p, opts, info);
     });
 }
 

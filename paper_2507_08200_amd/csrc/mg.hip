@@ -1998,9 +1998,10 @@ struct Solver {
     std::vector<HProblem> probs;
     DevBuf<LevDesc> d64, d32;
     std::vector<LevDesc> h64, h32;
-    LevDesc *pin64 = nullptr, *pin32 = nullptr;   // pinned staging of the descriptors
+    LevDesc *pin64 = nullptr, *pin32 = nullptr;   // host staging of the descriptors
     DevBuf<ProbState> st;
     ProbState *pin_st = nullptr;
+    bool pinned = true;           // staging in pinned memory (ordinary host memory without allocation)
     DevBuf<double> partials, partials_b;
     DevBuf<FusedDesc> fused;
     int nfused = 0;
@@ -2031,9 +2032,9 @@ struct Solver {
     int cur_it = 0, cur_phase = 2;     // phase 0: residual check of iteration it, 1: its cycle(s), 2: set-up
     bool aligned = true;                         // finest-level unknowns 16-byte aligned (row-pair loads)
     ~Solver() {
-        if (pin64) (void)hipHostFree(pin64);
-        if (pin32) (void)hipHostFree(pin32);
-        if (pin_st) (void)hipHostFree(pin_st);
+        stage_free(pin64, pinned);
+        stage_free(pin32, pinned);
+        stage_free(pin_st, pinned);
         if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
@@ -2320,10 +2321,10 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
     S->h32.assign((size_t)nprob * Lmax, LevDesc{});
     S->d64.alloc(S->h64.size());
     if (ir) S->d32.alloc(S->h32.size());
-    VD_HIP(hipHostMalloc((void **)&S->pin64, sizeof(LevDesc) * S->h64.size(), hipHostMallocDefault));
-    if (ir) VD_HIP(hipHostMalloc((void **)&S->pin32, sizeof(LevDesc) * S->h32.size(), hipHostMallocDefault));
+    S->pin64 = (LevDesc *)stage_alloc(sizeof(LevDesc) * S->h64.size(), &S->pinned);
+    if (ir) S->pin32 = (LevDesc *)stage_alloc(sizeof(LevDesc) * S->h32.size(), &S->pinned);
     S->st.alloc(nprob);
-    VD_HIP(hipHostMalloc((void **)&S->pin_st, sizeof(ProbState) * nprob, hipHostMallocDefault));
+    S->pin_st = (ProbState *)stage_alloc(sizeof(ProbState) * nprob, &S->pinned);
     // plans
     S->pre.resize(Lmax);
     S->restr.resize(Lmax);
@@ -2428,6 +2429,7 @@ static std::shared_ptr<Solver> build_solver(vd_ctx *ctx, int nprob, const vd_pro
                 pr->gbase.alloc(gb.size());
                 VD_HIP(hipMemcpyAsync(pr->gbase.p, gb.data(), sizeof(int) * gb.size(), hipMemcpyHostToDevice, ctx->stream));
             }
+            VD_HIP(hipStreamSynchronize(ctx->stream));   // gu, gg are read by the copies
         }
     }
     upload_plan(S->all0, ctx->stream);
@@ -3016,7 +3018,7 @@ static void autotune(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *probs,
 // Full solve of a batch (the engine behind vd_poisson_solve,
 // vd_helmholtz_solve_batched and the implicit solves of vd_step).
 static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
-                               const char *cache_tag, bool check_guess);
+                               const char *cache_tag, bool check_guess, bool noalloc = false);
 
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
                          const char *cache_tag) {
@@ -3033,16 +3035,42 @@ vd_status mg_solve_batch_guess(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     return mg_solve_impl(ctx, nprob, probs, &og, infos, cache_tag, true);
 }
 
+// The same solve without allocating: the hierarchy, plans, descriptor
+// tables and convergence words are carved from the arena's device region on
+// every call (nothing carries over between calls, so nothing there needs to
+// start at zero: each array is written by the call before it is read), the
+// host staging is ordinary memory, and the options that allocate (graph
+// capture, autotuning) are refused.
+vd_status mg_solve_noalloc(vd_ctx *ctx, Arena *arena, int nprob, const vd_problem *probs, const vd_mg_opts *o,
+                           vd_solve_info *infos) {
+    VD_CHECK(o, "null options");
+    VD_CHECK(!(o->flags & (VD_MG_GRAPH | VD_MG_AUTOTUNE)), "graph replay and autotuning allocate: not available without allocation");
+    VD_CHECK(o->guess == VD_GUESS_GIVEN || o->guess == VD_GUESS_ZERO, "only given or zero initial guesses without allocation");
+    struct Bind {
+        explicit Bind(Arena *a) { a->used = 0; tl_arena = a; }
+        ~Bind() { tl_arena = nullptr; }
+    } bind(arena);
+    return mg_solve_impl(ctx, nprob, probs, o, infos, nullptr, false, true);
+}
+
 static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
-                               const char *cache_tag, bool check_guess) {
+                               const char *cache_tag, bool check_guess, bool noalloc) {
     validate(nprob, probs, o);
-    std::string key = std::string(cache_tag ? cache_tag : "") + shape_key(nprob, probs, o);
     std::shared_ptr<Solver> S;
-    auto it = ctx->cache.find(key);
-    if (it != ctx->cache.end()) S = std::static_pointer_cast<Solver>(it->second);
-    else {
+    if (noalloc) {
+        // built afresh in the arena; kept until the next such call so that
+        // its host staging outlives the copies enqueued from it (building
+        // the next one synchronises the stream before this one is dropped)
         S = build_solver(ctx, nprob, probs, o);
-        ctx->cache[key] = S;
+        ctx->cache["noalloc:solver"] = S;
+    } else {
+        std::string key = std::string(cache_tag ? cache_tag : "") + shape_key(nprob, probs, o);
+        auto it = ctx->cache.find(key);
+        if (it != ctx->cache.end()) S = std::static_pointer_cast<Solver>(it->second);
+        else {
+            S = build_solver(ctx, nprob, probs, o);
+            ctx->cache[key] = S;
+        }
     }
     refresh_descs(ctx, *S, nprob, probs, o);
     setup_coefficients(ctx, *S, probs);

@@ -114,6 +114,8 @@ void launch_extrap_species(vd_ctx *ctx, const ExtrapSet &e, int count, int order
 
 vd_status mg_solve_batch(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
                          const char *cache_tag);
+vd_status mg_solve_noalloc(vd_ctx *ctx, Arena *arena, int nprob, const vd_problem *probs, const vd_mg_opts *o,
+                           vd_solve_info *infos);
 vd_status mg_cell_flags(vd_ctx *ctx, const vd_problem *prob, int n_levels, int level, uint8_t *out);
 vd_status mg_smooth(vd_ctx *ctx, const vd_problem *prob, int ncolour);
 

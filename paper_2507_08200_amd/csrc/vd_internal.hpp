@@ -34,36 +34,84 @@ struct Error {
     } while (0)
 
 // ------------------------------------------------------- device buffers
+// A fixed device region handed out front to back (256-byte aligned) while
+// an allocation-free call runs on this host thread: buffers created then
+// take their memory from it instead of hipMalloc and never free it.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    void *carve(size_t bytes) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off > cap || bytes > cap - off)
+            throw Error{VD_EINVAL, "the problem needs more than the " + std::to_string(cap >> 20) +
+                                       " MiB of device scratch memory of the allocation-free entry point"};
+        used = off + bytes;
+        return base + off;
+    }
+};
+inline thread_local Arena *tl_arena = nullptr;
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    bool owned = false;     // hipMalloc'd (freed on release) rather than carved from an arena
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), owned(o.owned) { o.p = nullptr; o.n = 0; o.owned = false; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; owned = o.owned;
+            o.p = nullptr; o.n = 0; o.owned = false;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        owned = false;
     }
     void alloc(size_t count) {
         if (count <= n && p) return;
         release();
         if (count == 0) return;
+        if (tl_arena) {
+            p = (T *)tl_arena->carve(count * sizeof(T));
+            n = count;
+            return;
+        }
         hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
         if (e != hipSuccess) {
             p = nullptr;
             throw Error{VD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
         }
         n = count;
+        owned = true;
     }
 };
+
+// Host staging buffers of the solvers: pinned, or ordinary host memory
+// while an allocation-free call runs (no hipHostMalloc then).
+inline void *stage_alloc(size_t bytes, bool *pinned) {
+    void *p = nullptr;
+    *pinned = tl_arena == nullptr;
+    if (*pinned) {
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess)
+            throw Error{VD_ENOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed"};
+    } else {
+        p = ::operator new(bytes);
+    }
+    return p;
+}
+inline void stage_free(void *p, bool pinned) {
+    if (!p) return;
+    if (pinned) (void)hipHostFree(p);
+    else ::operator delete(p);
+}
 
 // ---------------------------------------------------- level descriptor
 // One multigrid level of one problem, as the kernels see it.  Coefficient

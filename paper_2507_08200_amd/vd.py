@@ -29,7 +29,8 @@ MOB_CONST, MOB_ELECTRON_FIT, MOB_ION_N0, MOB_NEUTRAL_N0 = 0, 1, 2, 3
 WALL_NONE, WALL_ELECTRON, WALL_ION, WALL_NEUTRAL = 0, 1, 2, 3
 
 EXPORTS = ["vd_ctx_create", "vd_ctx_destroy", "vd_ctx_set_stream", "vd_last_error", "vd_version",
-           "vd_poisson_solve", "vd_helmholtz_solve_batched", "vd_species_flux", "vd_reaction_source",
+           "vd_poisson_solve", "vd_poisson_solve_noalloc", "vd_helmholtz_solve_batched", "vd_species_flux",
+           "vd_reaction_source",
            "vd_step", "vd_cell_flags", "vd_smooth", "vd_timing_select", "vd_timing_read",
            "vd_nn_param_count", "vd_nn_create", "vd_nn_get", "vd_nn_set", "vd_nn_forward", "vd_nn_train_step",
            "vd_nn_features", "vd_nn_save", "vd_nn_load", "vd_nn_conv3d", "vd_check_tiles25", "vd_step_reset"]
@@ -129,6 +130,7 @@ def load():
         "vd_last_error": ([P], C.c_char_p),
         "vd_version": ([], C.c_char_p),
         "vd_poisson_solve": ([P, P, P, P, P, d, P, P, P, P], i32),
+        "vd_poisson_solve_noalloc": ([P, P, P, P, P, d, P, P, P, P], i32),
         "vd_helmholtz_solve_batched": ([P, i32, P, P, P], i32),
         "vd_species_flux": ([P, P, P, P, i32, P, P, P, P, P, P, d, P, P, i32, P], i32),
         "vd_reaction_source": ([P, i32, C.c_int64, i32, P, P, P, d, P, P], i32),
@@ -241,15 +243,27 @@ class Context:
 
     # ---------------------------------------------------------- solvers
     def vd_poisson_solve(self, g, phi_bc, rho, phi, *, mask=None, beta=None, beta_c=8.8541878128e-12,
-                         opts=None, allow_fail=False):
+                         opts=None, allow_fail=False, want_info=True):
+        return self._poisson(self.lib.vd_poisson_solve, g, phi_bc, rho, phi, mask, beta, beta_c, opts, allow_fail,
+                             want_info)
+
+    def vd_poisson_solve_noalloc(self, g, phi_bc, rho, phi, *, mask=None, beta=None, beta_c=8.8541878128e-12,
+                                 opts=None, allow_fail=False, want_info=True):
+        """vd_poisson_solve with every work array in the library's static
+        device scratch (no device allocation)."""
+        return self._poisson(self.lib.vd_poisson_solve_noalloc, g, phi_bc, rho, phi, mask, beta, beta_c, opts,
+                             allow_fail, want_info)
+
+    def _poisson(self, fn, g, phi_bc, rho, phi, mask, beta, beta_c, opts, allow_fail, want_info):
         nx, ny, nz = g[:3]
         shp = (nz, ny, nx)
         info = SolveInfo()
-        st = self.lib.vd_poisson_solve(self.h, C.byref(grid(g)), C.byref(bc(phi_bc)),
-                                       _dptr(mask, shp, torch.uint8, "mask"), _dptr(beta, shp, name="beta"),
-                                       float(beta_c), _dptr(rho, shp, name="rho"), _dptr(phi, shp, name="phi"),
-                                       C.byref(opts or mg_opts()), C.byref(info))
+        st = fn(self.h, C.byref(grid(g)), C.byref(bc(phi_bc)), _dptr(mask, shp, torch.uint8, "mask"),
+                _dptr(beta, shp, name="beta"), float(beta_c), _dptr(rho, shp, name="rho"), _dptr(phi, shp, name="phi"),
+                C.byref(opts or mg_opts()), C.byref(info) if want_info else None)
         self._check(st, (VD_ENOCONV,) if allow_fail else ())
+        if not want_info:
+            return {"return": st}
         d = _info(info)
         d["return"] = st
         return d
