@@ -10,8 +10,10 @@ species solve, all in libvd's HIP kernels.
 
 Prints one JSON line: cell-steps/s, the roofline of the dominant kernel
 (algorithmic bytes / HIP-event-timed duration over the timed region), the
-Poisson time-to-1e-10 comparison and the FP64 CPU oracle timed on a bounded
-sample on the host cores.
+Poisson time-to-1e-10 comparison, the 64-problem batched Helmholtz solve
+with its roofline, the per-field error of GPU trajectories against FP64
+oracle trajectories, and the FP64 CPU oracle timed on a warm step on all
+host cores and on one.
 """
 import argparse
 import json
@@ -58,10 +60,12 @@ def parse():
     ap.add_argument("--ir-inner", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default smoother tiling")
     ap.add_argument("--poisson-reps", type=int, default=5)
-    ap.add_argument("--cpu-n", type=int, default=0,
-                    help="grid edge of the oracle's timed sample (0: the workload's own grid, which also gives the "
-                         "per-field error of the GPU step against the oracle)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle leg")
+    ap.add_argument("--traj-n", type=int, default=64, help="grid edge of the long accuracy trajectory")
+    ap.add_argument("--traj-steps", type=int, default=100)
+    ap.add_argument("--traj160-steps", type=int, default=5,
+                    help="steps of the accuracy trajectory on the workload's own grid (its last oracle step is the "
+                         "CPU baseline)")
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (auto = dominant)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched Helmholtz timing")
     ap.add_argument("--nn-file", default=os.path.join(ROOT, "paper_2507_08200_amd", "warmstart_arh2_160.bin"),
@@ -120,7 +124,11 @@ def learned_guess(ctx, V, I, cfg, rho, args):
     return out
 
 
-def batch_bench(ctx, V, I, dev, reps):
+MG_FAMILIES = ["gsrb", "gsrb_fine", "gsrb_uniform", "sweep", "resid_restrict", "prolong", "copy", "coarse", "norm",
+               "finalize", "prep", "ir_update", "setup"]
+
+
+def batch_bench(ctx, V, I, dev, reps, oracle_sample=True):
     """The 64-problem batch (edges 32..160 in steps of 16, unit cube, alpha 1,
     a 1e-3..1 sheath jump, random Dirichlet/Neumann faces, N(0,1) rhs) solved
     to 1e-10 from zero: one call per problem, one batched call, and the
@@ -130,6 +138,9 @@ def batch_bench(ctx, V, I, dev, reps):
     probs = I.cfg4()
     cells = sum(p["grid"][0] ** 3 for p in probs)
     log("[bench] batch: %d problems, %d cells" % (len(probs), cells))
+    # the oracle's sample: the two smallest problems, kept on the host
+    order = sorted(range(len(probs)), key=lambda q: probs[q]["grid"][0] ** 3)
+    sample = [dict(probs[q], beta=probs[q]["beta"].copy(), rhs=probs[q]["rhs"].copy()) for q in order[:2]]
     gs = []
     for p in probs:
         gs.append({"grid": p["grid"], "bc": p["bc"], "mask": None, "alpha": None, "alpha_c": p["alpha_c"],
@@ -167,14 +178,168 @@ def batch_bench(ctx, V, I, dev, reps):
         # batching changes no arithmetic: same iterate as the sequential solves
         dmax = max(float((g["x"] - x).abs().max() / x.abs().max()) for g, x in zip(gs, x_seq))
         res[name.replace("_ms", "_max_rel_diff_vs_sequential")] = dmax
-    res["cell_cycles_per_s_batched_graph"] = round(sum(i["cycles"] * p["grid"][0] ** 3 for i, p in zip(infos, probs))
-                                                   / (res["batched_graph_ms"] * 1e-3), 1)
+    cell_cycles = sum(i["cycles"] * p["grid"][0] ** 3 for i, p in zip(infos, probs))
+    res["cell_cycles_per_s_batched_graph"] = round(cell_cycles / (res["batched_graph_ms"] * 1e-3), 1)
+    # roofline of the batched solve: the algorithmic bytes of all its
+    # multigrid launches (read from the library's per-family accounting in
+    # one event-timed call) over the untimed batched call's duration
+    ctx.vd_timing_select(",".join(MG_FAMILIES))
+    bat()()
+    torch.cuda.synchronize()
+    alg = kms = 0.0
+    for f in MG_FAMILIES:
+        cnt, ms_f, by = ctx.vd_timing_read(f)
+        alg += by
+        kms += ms_f
+    ctx.vd_timing_select(None)
+    ach = alg / (res["batched_ms"] * 1e-3) / 1e9
+    res["roofline"] = {"bound": "hbm", "alg_bytes_per_solve": round(alg), "achieved": round(ach, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                       "event_timed_kernel_ms": round(kms, 3),
+                       "note": "algorithmic bytes of every multigrid launch of one batched solve / batched_ms"}
+    if oracle_sample:
+        res["oracle"] = batch_oracle(sample, infos, probs, order, cell_cycles)
     log("[bench] batch: %s" % res)
     return res
 
 
+def batch_oracle(sample, infos, probs, order, cell_cycles):
+    """The FP64 oracle solving the batch's two smallest problems one after
+    the other from zero to 1e-10, single-threaded and on all host cores; the
+    whole 64-problem sequential time is extrapolated from the measured cell
+    cycles per second and the cycle counts of the GPU's solves."""
+    import numpy as np
+    from oracle import oracle as O
+    out = {"sample": "problems %s (edges %s), solved one after the other" % (
+        [int(q) for q in order[:len(sample)]], [p["grid"][0] for p in sample])}
+    for tag, par in (("single_core", False), ("all_cores", True)):
+        t = time.perf_counter()
+        cc = 0
+        for p in sample:
+            x, info, st = O.mg_solve(p, p["rhs"], np.zeros(p["rhs"].shape), parallel=par, rtol=1e-10)
+            assert st == 0
+            cc += info["cycles"] * p["grid"][0] ** 3
+        el = time.perf_counter() - t
+        rate = cc / el
+        out[tag] = {"ms": round(el * 1e3, 1), "cell_cycles_per_s": round(rate, 1),
+                    "cores": 1 if not par else int(os.environ.get("OMP_NUM_THREADS", "1")),
+                    "batch_ms_extrapolated": round(cell_cycles / rate * 1e3, 1)}
+    return out
+
+
+def field_errors(names, got, want):
+    """Per field: max |gpu - oracle| / max |oracle| and the pointwise
+    max |gpu - oracle| / max(|oracle|, 1e-6 max |oracle|)."""
+    import numpy as np
+    out = {}
+    for name, g, w in zip(names, got, want):
+        sc = np.abs(w).max()
+        if sc == 0:
+            out[name] = [float("%.3g" % np.abs(g).max())] * 2
+            continue
+        d = np.abs(g - w)
+        out[name] = [float("%.3g" % (d.max() / sc)), float("%.3g" % (d / np.maximum(np.abs(w), 1e-6 * sc)).max())]
+    out["max"] = [max(v[0] for v in out.values()), max(v[1] for v in out.values())]
+    return out
+
+
+def oracle_legs(args, ctx, V, I, M, P, P64, state0, cfg, n, dev):
+    """GPU trajectories of the timed configuration (FP32-refined and all
+    FP64) against FP64 oracle trajectories with the same solver schedule,
+    tolerance and extrapolated guesses (formed from the oracle's own
+    results): args.traj_steps steps at args.traj_n^3 and args.traj160_steps
+    steps at the workload's grid.  The oracle's last step of the latter,
+    a warm step like the timed ones, is the CPU baseline on all host cores;
+    one more step from that state on one core is the single-core figure."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    O.build()
+    O.build(parallel=True)
+    threads = int(os.environ["OMP_NUM_THREADS"])
+    names = ["phi", "Te"] + ["n_" + sp for sp in M.ARH2_NAMES]
+    po, so = P.poisson, P.species_mg
+    oP = O.mg_opts(rtol=po.rtol, nu_pre=po.nu_pre, nu_post=po.nu_post, n_levels=po.n_levels)
+    oS = O.mg_opts(rtol=so.rtol, nu_pre=so.nu_pre, nu_post=so.nu_post, n_levels=so.n_levels)
+    sp = O.species_arh2_15()
+
+    def gpu_traj(PP, c, steps):
+        st = {k: torch.tensor(c[k], device=dev) for k in ("n", "phi", "Te")}
+        ctx.vd_step_reset()
+        for t in range(steps):
+            inf = ctx.vd_step(PP, st)
+            assert inf["status"] == 0
+        out = [st["phi"].cpu().numpy(), st["Te"].cpu().numpy()] + list(st["n"].cpu().numpy())
+        del st
+        return out
+
+    errors = {"oracle": "FP64 oracle trajectory, Poisson V(%d,%d) and species %d-level V(%d,%d) to %.0e, "
+                        "starting iterates extrapolated from its own results; [max-scaled, pointwise with a 1e-6 "
+                        "floor] per field" % (po.nu_pre, po.nu_post, so.n_levels, so.nu_pre, so.nu_post, po.rtol)}
+    legs = [(args.traj_n, args.traj_steps)]
+    if args.traj160_steps > 0:
+        legs.append((n, args.traj160_steps))
+    warm = None
+    for gn, steps in legs:
+        c = cfg if gn == n else I.cfg3(n=gn)
+        log("[bench] oracle trajectory: %d steps at %d^3 on %d threads" % (steps, gn, threads))
+        t = time.perf_counter()
+        ref = O.trajectory(c, sp, steps, poisson=oP, species_mg=oS, parallel=True)
+        log("[bench]   %.1f s (last step %.2f s)" % (time.perf_counter() - t, ref["times"][-1]))
+        want = [ref["phi"], ref["Te"]] + list(ref["n"])
+        tight = None
+        if gn != n:
+            # the oracle's own tolerance error: the same trajectory with
+            # every solve taken to 1e-13
+            oPt = O.mg_opts(rtol=1e-13, nu_pre=po.nu_pre, nu_post=po.nu_post, n_levels=po.n_levels, max_cycles=200)
+            oSt = O.mg_opts(rtol=1e-13, nu_pre=so.nu_pre, nu_post=so.nu_post, n_levels=so.n_levels, max_cycles=200)
+            rt = O.trajectory(c, sp, steps, poisson=oPt, species_mg=oSt, parallel=True)
+            tight = field_errors(names, want, [rt["phi"], rt["Te"]] + list(rt["n"]))
+            del rt
+        PPc = V.step_params(c, M.arh2_15(), lfa=lfa_dev(c, dev), poisson=P.poisson, species_mg=P.species_mg)
+        PP64 = V.step_params(c, M.arh2_15(), lfa=lfa_dev(c, dev), poisson=P64.poisson, species_mg=P64.species_mg)
+        key = "trajectory_%d^3_%d_steps" % (gn, steps)
+        errors[key] = {"fp32_ir": field_errors(names, gpu_traj(PPc, c, steps), want),
+                       "fp64": field_errors(names, gpu_traj(PP64, c, steps), want),
+                       "oracle_cycles_last_step": {k: ref["infos"][-1][k] for k in ("poisson_cycles", "species_cycles")}}
+        if tight is not None:
+            errors[key]["oracle_1e-10_vs_oracle_1e-13"] = tight
+        log("[bench]   error %s: fp32_ir max %s, fp64 max %s" % (key, errors[key]["fp32_ir"]["max"],
+                                                                 errors[key]["fp64"]["max"]))
+        if gn == n:
+            warm = ref
+    cpu = None
+    if warm is not None:
+        t_all = warm["times"][-1]
+        # the trajectory's last step again, from the same inputs and guesses,
+        # on a single core
+        t = time.perf_counter()
+        r1 = O.step(cfg, sp, poisson=oP, species_mg=oS, **warm["last_step_inputs"])
+        t_one = time.perf_counter() - t
+        assert r1["status"] == 0 and r1["info"] == warm["infos"][-1]
+        cpu = {"value": round(n ** 3 / t_all, 1), "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+               "sample": "step %d of the FP64 oracle trajectory of the same %d^3 workload (warm: starting iterates "
+                         "extrapolated from its earlier steps, %d Poisson cycles), OpenMP on %d threads, %.2f s" %
+                         (len(warm["times"]), n, warm["infos"][-1]["poisson_cycles"], threads, t_all),
+               "single_core": {"value": round(n ** 3 / t_one, 1), "cores": 1,
+                               "sample": "the same step from the same inputs and guesses, single-threaded, %.2f s" %
+                                         t_one},
+               "host_cpus_available": len(os.sched_getaffinity(0))}
+        log("[bench] oracle warm step: %.4g cell-steps/s on %d threads, %.4g on one core" %
+            (cpu["value"], threads, cpu["single_core"]["value"]))
+    return errors, cpu
+
+
+def lfa_dev(c, dev):
+    import torch
+    lfa = dict(c["lfa"])
+    lfa["te_K"] = torch.tensor(c["lfa"]["te_K"], device=dev)
+    return lfa
+
+
 def main():
     args = parse()
+    os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
@@ -342,46 +507,15 @@ def main():
     log("[bench] poisson time-to-1e-10: %s" % poisson)
 
     # ---- 64 uneven sheath-jump Helmholtz problems: sequential vs batched
-    batch = None if args.no_batch else batch_bench(ctx, V, I, dev, args.batch_reps)
+    batch = None if args.no_batch else batch_bench(ctx, V, I, dev, args.batch_reps,
+                                                    oracle_sample=not args.no_cpu_baseline)
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample (one step of the
-    # workload from its initial state), and the per-field error of the GPU
-    # step from the same state against it
+    # ---- accuracy against the FP64 oracle over trajectories of the timed
+    # configuration, and the oracle timed on the same kind of warm step
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        O.build()
-        cn = args.cpu_n if args.cpu_n > 0 else n
-        ccfg = cfg if cn == n else I.cfg3(n=cn)
-        log("[bench] oracle: one step at %d^3 on one host core" % cn)
-        t = time.perf_counter()
-        r = O.step(ccfg, O.species_arh2_15(), poisson=O.mg_opts(rtol=1e-10), species_mg=O.mg_opts(rtol=1e-10))
-        dt_cpu = time.perf_counter() - t
-        assert r["status"] == 0
-        cpu = {"value": round(cn ** 3 / dt_cpu, 1), "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-               "sample": "one FP64 oracle step of the same Ar-H2 streamer workload at %d^3 (%d cells) from its initial "
-                         "state (cold Poisson start, %d Poisson cycles), single-threaded, %.1f s; scaled per cell" %
-                         (cn, cn ** 3, r["info"]["poisson_cycles"], dt_cpu),
-               "host_cpus_available": len(os.sched_getaffinity(0))}
-        log("[bench] oracle %.2f s -> %.4g cell-steps/s" % (dt_cpu, cpu["value"]))
-        if cn == n:
-            errors = {}
-            for tag, PP in (("fp32_ir_step", P), ("fp64_step", P64)):
-                st = {k: v.clone() for k, v in state0.items()}
-                inf = ctx.vd_step(PP, st)
-                assert inf["status"] == 0
-
-                def rel(a, b):
-                    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-                e = {"phi": rel(st["phi"].cpu().numpy(), r["phi"]), "Te": rel(st["Te"].cpu().numpy(), r["Te"])}
-                nn = st["n"].cpu().numpy()
-                for k2, sp in enumerate(M.ARH2_NAMES):
-                    e["n_" + sp] = rel(nn[k2], r["n"][k2])
-                errors[tag] = {f: float("%.3g" % v) for f, v in e.items()}
-                errors[tag]["max"] = max(errors[tag].values())
-                del st, nn
-            log("[bench] error vs the FP64 oracle (max |gpu - oracle| / max |oracle| per field): %s" % errors)
+        errors, cpu = oracle_legs(args, ctx, V, I, M, P, P64, state0, cfg, n, dev)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -399,6 +533,8 @@ def main():
                        args.species_precision, args.species_levels, list(args.species_nu),
                        "extrapolated from the last three steps" if args.species_guess == "extrap"
                        else "the current densities"),
+                   "background_gas": "Ar and H2 transported like the other 13 species (the paper holds the "
+                                     "background constant)",
                    "mg_inner_dtype": "f32" if "fp32" in args.poisson_precision + args.species_precision else "f64",
                    "poisson_cycles_last_step": cyc_p, "species_cycles_last_step": cyc_s},
         "roofline": roofline,

@@ -16,20 +16,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# timing build for the all-cores CPU baseline: the same source with OpenMP
+# on its independent per-cell loops (sums stay sequential: same results)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, EINVAL, ENOMEM, ENOCONV, ESINGULAR = 0, -1, -2, -4, -5
 MOB_CONST, MOB_ELECTRON_FIT, MOB_ION_N0, MOB_NEUTRAL_N0 = 0, 1, 2, 3
 WALL_NONE, WALL_ELECTRON, WALL_ION, WALL_NEUTRAL = 0, 1, 2, 3
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, FP64, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, parallel: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no FMA contraction);
+    parallel=True builds the OpenMP timing variant."""
+    out = _LIB_OMP if parallel else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"] +
+                              (["-fopenmp"] if parallel else []) + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class Grid(C.Structure):
@@ -91,13 +96,16 @@ class StepInfo(C.Structure):
                 ("poisson_rel", C.c_double), ("dt_used", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
+def lib(parallel: bool = False):
+    """The oracle library (parallel: the OpenMP timing build, whose threads
+    follow OMP_NUM_THREADS)."""
+    _lib = _libs.get(parallel)
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(build(parallel=parallel))
+        _libs[parallel] = _lib
         d = C.c_double
         P = C.c_void_p
         _lib.or_mu_electron.restype = d
@@ -164,7 +172,7 @@ def _problem(prob, keep):
                    float(prob.get("alpha_c", 0.0)), _ptr(beta), float(prob.get("beta_c", 0.0)))
 
 
-def mg_solve(prob, rhs, x0, **opts):
+def mg_solve(prob, rhs, x0, parallel=False, **opts):
     """(alpha - div beta grad) x = rhs; returns (x, info dict, status)."""
     keep = []
     P = _problem(prob, keep)
@@ -172,7 +180,7 @@ def mg_solve(prob, rhs, x0, **opts):
     r = _f64(rhs)
     o = mg_opts(**opts)
     info = MGInfo()
-    st = lib().or_mg_solve(C.byref(P), _ptr(r), _ptr(x), C.byref(o), C.byref(info))
+    st = lib(parallel).or_mg_solve(C.byref(P), _ptr(r), _ptr(x), C.byref(o), C.byref(info))
     d = {k: getattr(info, k) for k, _ in MGInfo._fields_}
     return x, d, st
 
@@ -327,7 +335,7 @@ def face_flux(g, phi_bc, sp_bc, sp, u, phi, mu, D, Te, Tg, consts=PHYS):
 
 def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poisson=None, species_mg=None,
          energy_mg=None, extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0,
-         k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None):
+         k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None, parallel=False):
     """One step of the semi-implicit scheme on a workload dict (see inputs).
     species_guess ([S][cells], optional): starting iterate of the first
     corrector's species solves in place of n^n.
@@ -388,9 +396,48 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
     P.species_mg = species_mg or mg_opts()
     P.energy_mg = energy_mg or mg_opts()
     info = StepInfo()
-    st = lib().or_step(C.byref(P), _ptr(n), _ptr(phi), _ptr(Te), _ptr(Ee), C.byref(info))
+    st = lib(parallel).or_step(C.byref(P), _ptr(n), _ptr(phi), _ptr(Te), _ptr(Ee), C.byref(info))
     d = {k: getattr(info, k) for k, _ in StepInfo._fields_}
     return {"n": n, "phi": phi, "Te": Te, "Ee": Ee, "info": d, "status": st, "check_res": res}
+
+
+def trajectory(cfg, species, steps, *, poisson=None, species_mg=None, extrapolate=True, parallel=False, **kw):
+    """`steps` oracle steps from the workload's initial state.  With
+    extrapolate, each step's Poisson and species solves start from the
+    polynomial extrapolation in time of the oracle's own earlier results
+    (2u - h1 after one kept result, 3u - 3h1 + h2 after two; the initial
+    state's potential, a guess rather than a result, is not kept), else from
+    the previous values.  Harness code: the guesses are starting iterates
+    and the solves still stop on their residual tests.  Returns the final
+    state, the wall time of every step, the cycle counts and the inputs of
+    the last step (to time that same step again)."""
+    import time
+    n, phi, Te = (_f64(cfg[k]).copy() for k in ("n", "phi", "Te"))
+    hphi, hn = [], []          # kept results, newest last
+    times, infos = [], []
+    for t in range(steps):
+        pg, sg = phi, None
+        if extrapolate and len(hphi) == 1:
+            pg = 2.0 * phi - hphi[-1]
+        elif extrapolate and len(hphi) >= 2:
+            pg = 3.0 * phi - 3.0 * hphi[-1] + hphi[-2]
+        if extrapolate and len(hn) == 1:
+            sg = 2.0 * n - hn[-1]
+        elif extrapolate and len(hn) >= 2:
+            sg = 3.0 * n - 3.0 * hn[-1] + hn[-2]
+        last = {"n": n, "phi": pg, "Te": Te, "species_guess": sg}
+        t0 = time.perf_counter()
+        r = step(cfg, species, n=n, phi=pg, Te=Te, poisson=poisson, species_mg=species_mg, species_guess=sg,
+                 parallel=parallel, **kw)
+        times.append(time.perf_counter() - t0)
+        if r["status"] != OK:
+            raise RuntimeError("oracle step %d failed with status %d" % (t, r["status"]))
+        if t > 0:
+            hphi = (hphi + [phi])[-2:]
+            hn = (hn + [n])[-2:]
+        n, phi, Te = r["n"], r["phi"], r["Te"]
+        infos.append(r["info"])
+    return {"n": n, "phi": phi, "Te": Te, "times": times, "infos": infos, "last_step_inputs": last}
 
 
 # ---------------------------------------------------------------------------

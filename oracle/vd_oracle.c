@@ -127,6 +127,18 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 #define IDX(i, j, k, nx, ny) ((size_t)(i) + (size_t)(nx) * ((size_t)(j) + (size_t)(ny) * (size_t)(k)))
 
+/* Timing build only (compiled with -fopenmp for the all-cores CPU
+ * baseline): the outer loop of a per-cell pass whose cells are independent
+ * is shared among threads.  Sums (norms, dot products) stay sequential, so
+ * both builds give the same bits; the default build ignores these. */
+#ifdef _OPENMP
+#define OR_PAR_FOR _Pragma("omp parallel for schedule(static)")
+#define OR_PAR_FOR_IF_OK _Pragma("omp parallel for schedule(static) if(par_ok)")
+#else
+#define OR_PAR_FOR
+#define OR_PAR_FOR_IF_OK
+#endif
+
 static double harmonic(double a, double b)
 {
     /* face coefficient across a jump: harmonic mean, 0 if both are 0 */
@@ -376,6 +388,13 @@ static void row_terms(const or_level *L, int i, int j, int k, const double *x, d
  * then every valid black cell. */
 static void gsrb_colour(or_level *L, int colour)
 {
+    /* cells of one colour couple only to the other colour, unless a
+     * periodic direction has an odd count (then the loop order matters and
+     * the timing build keeps it sequential) */
+    int par_ok = !((L->kind[0] == OR_PER && L->nx % 2) || (L->kind[2] == OR_PER && L->ny % 2) ||
+                   (L->kind[4] == OR_PER && L->nz % 2));
+    (void)par_ok;
+    OR_PAR_FOR_IF_OK
     for (int k = 0; k < L->nz; k++)
         for (int j = 0; j < L->ny; j++)
             for (int i = 0; i < L->nx; i++) {
@@ -397,6 +416,7 @@ static void gsrb_sweep(or_level *L)
 /* r = b - A x on valid cells (0 on covered cells) */
 static void residual(const or_level *L, const double *x, const double *b, double *r)
 {
+    OR_PAR_FOR
     for (int k = 0; k < L->nz; k++)
         for (int j = 0; j < L->ny; j++)
             for (int i = 0; i < L->nx; i++) {
@@ -425,6 +445,7 @@ static double dot(const double *a, const double *b, size_t n)
 /* Restriction: coarse rhs = mean of the 8 children's residuals. */
 static void restrict_mean(const or_level *F, const double *r, or_level *C)
 {
+    OR_PAR_FOR
     for (int k = 0; k < C->nz; k++)
         for (int j = 0; j < C->ny; j++)
             for (int i = 0; i < C->nx; i++) {
@@ -441,6 +462,7 @@ static void restrict_mean(const or_level *F, const double *r, or_level *C)
 /* Prolongation: piecewise constant, x_fine += e_coarse on valid fine cells. */
 static void prolong_add(const or_level *C, or_level *F)
 {
+    OR_PAR_FOR
     for (int k = 0; k < F->nz; k++)
         for (int j = 0; j < F->ny; j++)
             for (int i = 0; i < F->nx; i++) {
@@ -974,6 +996,7 @@ static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const doubl
 {
     const or_grid *g = X->g;
     int nx = g->nx, ny = g->ny, nz = g->nz;
+    OR_PAR_FOR
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i < nx; i++) {
@@ -1286,10 +1309,8 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     double *beta = (double *)malloc(sizeof(double) * nc);
     double *mue = (double *)malloc(sizeof(double) * nc);
     double *divE = (double *)malloc(sizeof(double) * nc);
-    double *ncol = (double *)malloc(sizeof(double) * S);
-    double *Gcol = (double *)malloc(sizeof(double) * S);
     int status = OR_OK;
-    if (!n0 || !ns || !mu || !Dk || !div || !G || !rhs || !rho || !Sinel || !en || !Ee0 || !Ees || !beta || !mue || !divE || !ncol || !Gcol) {
+    if (!n0 || !ns || !mu || !Dk || !div || !G || !rhs || !rho || !Sinel || !en || !Ee0 || !Ees || !beta || !mue || !divE) {
         status = OR_ENOMEM;
         goto out;
     }
@@ -1319,6 +1340,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
         }
         if (st != OR_OK) { status = st; goto out; }
         /* E/N and Te at u* */
+        OR_PAR_FOR
         for (int k = 0; k < g->nz; k++)
             for (int j = 0; j < g->ny; j++)
                 for (int i = 0; i < g->nx; i++) {
@@ -1334,19 +1356,22 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                     }
                 }
         /* transport at u* */
-        for (int k = 0; k < S; k++)
+        for (int k = 0; k < S; k++) {
+            OR_PAR_FOR
             for (size_t c = 0; c < nc; c++)
                 transport(&P->species[k], cs, en[c], Te[c], P->Tg, P->N_gas, &mu[k * nc + c], &Dk[k * nc + c]);
+        }
         /* explicit drift divergence and chemistry at u* */
         or_flux_ctx X = { g, &P->phi_bc, phi, Te, P->Tg, cs };
         for (int k = 0; k < S; k++)
             drift_divergence(&X, &P->species_bc[k], ns + k * nc, mu + k * nc, P->species[k].wall_kind,
                              P->species[k].mass, NULL, div + k * nc);
+        OR_PAR_FOR
         for (size_t c = 0; c < nc; c++) {
-            for (int k = 0; k < S; k++) ncol[k] = ns[k * nc + c];
-            double loss;
-            cell_rates(P->mech, ncol, Te[c], P->bg, P->k_decay, S, cs->qe, Gcol, &loss);
-            for (int k = 0; k < S; k++) G[k * nc + c] = Gcol[k];
+            double nloc[32], Gloc[32], loss;
+            for (int k = 0; k < S; k++) nloc[k] = ns[k * nc + c];
+            cell_rates(P->mech, nloc, Te[c], P->bg, P->k_decay, S, cs->qe, Gloc, &loss);
+            for (int k = 0; k < S; k++) G[k * nc + c] = Gloc[k];
             Sinel[c] = loss;
         }
         /* electron energy (Eqs. (5)-(8)) */
@@ -1463,7 +1488,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     }
 out:
     free(n0); free(ns); free(mu); free(Dk); free(div); free(G); free(rhs); free(rho); free(Sinel);
-    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE); free(ncol); free(Gcol);
+    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE);
     info->status = status;
     return status;
 }

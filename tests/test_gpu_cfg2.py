@@ -48,6 +48,7 @@ def test_cfg2_step_parity_128(V, oracle):
         errs["n%d" % k] = (rel_err(n[k], ref["n"][k]), rel_err_pointwise(n[k], ref["n"][k]))
     say("   errors max-scaled/pointwise", {k: "%.1e/%.1e" % v for k, v in errs.items()}, info)
     assert max(e[0] for e in errs.values()) <= 1e-12
+    assert max(e[1] for e in errs.values()) <= 1e-10     # pointwise, floor 1e-6 of the field's largest
 
 
 def _steady(V, n, max_steps=600):

@@ -230,6 +230,7 @@ def test_species_flux(ctx, oracle, kinds, shape):
             e, ep = rel_err(host(faces[d]), ref[d]), rel_err_pointwise(host(faces[d]), ref[d], 1e-6)
             say("   faces", fs, d, "%.2e %.2e" % (e, ep))
             assert e <= TOL, (fs, d, e)
+            assert ep <= 1e-10, (fs, d, ep)      # pointwise, floor 1e-6 of the largest face flux
 
 
 def test_reaction_source(ctx, oracle):
