@@ -405,12 +405,15 @@ vd_status vd_smooth(vd_ctx *ctx, const vd_problem *prob, int32_t ncolour);
  * ahead planes, halo elements, FP64 unknown pairs of the fused last colour
  * pass, FP32 residual stores in both row layouts, LDS slots) or in the
  * parity-split FP32 colour pass (kernel 1, both colours: other-colour
- * pairs, halo, b, the four FP64 cells of the fused last pass, stores), with
- * the kernels' own index functions, and counts the accesses (accesses) and
- * those outside the level's arrays or the LDS tile, or misaligned for a
- * vector access (violations; also 1 if the workgroup-to-tile mapping does
- * not take every tile once).  VD_EINVAL for nx odd (kernel 0) or not a
- * multiple of 4 (kernel 1), kz < 1, or null outputs. */
+ * pairs, halo, b, the four FP64 cells of the fused last pass, stores) or in
+ * the direct residual check of levels with coefficient arrays (kernel 2: x
+ * window and x-y neighbours, b, the three face arrays, the cell
+ * coefficient, FP32 residual stores in both row layouts), with the kernels'
+ * own index functions, and counts the accesses (accesses) and those outside
+ * the level's arrays or the LDS tile, or misaligned for a vector access
+ * (violations; also 1 if the workgroup-to-tile mapping does not take every
+ * tile once).  VD_EINVAL for nx odd (kernels 0 and 2) or not a multiple of
+ * 4 (kernel 1), another kernel number, kz < 1, or null outputs. */
 vd_status vd_check_tiles25(int32_t nx, int32_t ny, int32_t nz, int32_t periodic, int32_t kz, int32_t kernel,
                            int64_t *accesses, int64_t *violations);
 

@@ -560,6 +560,341 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     }
 }
 
+// --------------------------------- FP64 residual check, uniform levels (LDS)
+// The residual checks of k_st25 (modes 1 and 2) for levels with uniform
+// coefficients and no mask, with the plane loop unrolled by four: one named
+// register set per plane of the z window (k-1 .. k+2), so no register is
+// copied while its load is in flight, and positions that are not cells read
+// from g_zero4 (address select) instead of being masked after the load.
+// The x-y part of each cell's diagonal and Dirichlet lifting is summed once
+// per thread (the same additions in the same order as row_terms_uni /
+// lift_term_uni, completed per plane by the z faces), and neighbours outside
+// a non-periodic face, which read as zero, enter the off-diagonal sum with
+// their weight (a zero term leaves the sum's bits unchanged).  Residuals,
+// partial sums and the stored FP32 residual are bit-identical to k_st25's.
+// MODE 1: partial sums of r^2 (and of b^2 when partials_b is given); MODE 2:
+// also r rounded to FP32 into the FP32 hierarchy's finest right-hand side
+// (either row layout) and, unless keep_e, its unknown cleared.
+__device__ double g_zero4[4];
+
+struct Pr {
+    double a, b;
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_res25u(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32,
+                                                   Plan pl, int kz, int keep_e, double *__restrict__ partials,
+                                                   const ProbState *__restrict__ st, int check_active,
+                                                   double *__restrict__ partials_b) {
+    __shared__ double xs[2][(kT25Y + 2) * kT25W];
+    __shared__ double red[kBlock / 64];
+    const int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    const int d = plan_find(pl, t);
+    const int id = pl.ids[d];
+    const LevDesc L = descs[id];
+    if (check_active && !gld(&st[L.prob].active, 0)) return;
+    const int lt = t - pl.prefix[d];
+    const int slot = pl.gbase ? pl.gbase[d] + lt : t;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, nxy = L.nxy;
+    const Tile25 T25 = tile25(lt, nx, ny, nz, kz);
+    const int k0 = T25.k0, k1 = T25.k1;
+    const int tid = threadIdx.x;
+    const int tp = tid & 15, r = tid >> 4;
+    const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
+    const Thr25 H = thr25(T25, tid, nx, nx, ny, px, py, 0, 0);
+    const int ia = H.ua, j = H.j;
+    const bool own = H.own, halo_thread = H.halo, okxy = H.okp, okh = H.okh;
+    const int pair_off = (int)H.pair_off, b_off = (int)H.b_off, h_off = (int)H.h_off;
+    const int hslot = halo_slot(tid);
+    const double *__restrict__ X = (const double *)L.x;
+    const double *__restrict__ B = (const double *)L.b;
+    const double *zero = g_zero4;
+    const double bc = L.beta_c;
+    const double cfx = bc * L.idx2, cfy = bc * L.idy2, cfz = bc * L.idz2;
+    // x-y prefixes of the diagonal and of the lifting, per cell of the pair
+    double dgxy[2], lfxy[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int i = ia + q;
+        const bool in[4] = {i > 0, i < nx - 1, j > 0, j < ny - 1};
+        double dg = L.alpha_c, lf = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            const double cf = f < 2 ? cfx : cfy;
+            const int kd = L.kind[f];
+            if (in[f] || kd == VD_BC_PERIODIC) dg += cf;
+            else if (kd == VD_BC_DIRICHLET) dg += 2.0 * cf;
+        }
+        if (i == 0 && L.kind[0] == VD_BC_DIRICHLET) lf += 2.0 * bc * L.gval[0] * L.idx2;
+        if (i == nx - 1 && L.kind[1] == VD_BC_DIRICHLET) lf += 2.0 * bc * L.gval[1] * L.idx2;
+        if (j == 0 && L.kind[2] == VD_BC_DIRICHLET) lf += 2.0 * bc * L.gval[2] * L.idy2;
+        if (j == ny - 1 && L.kind[3] == VD_BC_DIRICHLET) lf += 2.0 * bc * L.gval[3] * L.idy2;
+        dgxy[q] = dg;
+        lfxy[q] = lf;
+    }
+    const bool lift = L.lift;
+    const double lz0 = 2.0 * bc * L.gval[4] * L.idz2, lz1 = 2.0 * bc * L.gval[5] * L.idz2;
+    const bool dz0 = L.kind[4] == VD_BC_DIRICHLET, dz1 = L.kind[5] == VD_BC_DIRICHLET;
+    float *__restrict__ Eb = MODE == 2 ? (float *)d32[id].b : nullptr;
+    float *__restrict__ Ex = MODE == 2 ? (float *)d32[id].x : nullptr;
+    const bool rbE = MODE == 2 && d32[id].rb;
+    const int nh = nx >> 1;
+    auto ld_pair = [&](int kk) -> Pr {
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const double *p = (okxy && okz) ? X + (pair_off + nxy * kw) : zero;
+        const PairD v = *(const VD_GAS PairD *)p;
+        return Pr{v.x, v.y};
+    };
+    auto ld_h = [&](int kk) -> double {
+        bool okz;
+        const int kw = wrap_idx(kk, nz, pz, okz);
+        const double *p = (okh && okz) ? X + (h_off + nxy * kw) : zero;
+        return *(const VD_GAS double *)p;
+    };
+    auto ld_b = [&](int kk) -> Pr {
+        const double *p = (own && kk < k1) ? B + (b_off + nxy * kk) : zero;
+        const PairD v = *(const VD_GAS PairD *)p;
+        return Pr{v.x, v.y};
+    };
+    double v = 0.0, vb = 0.0;
+    const int lc = (r + 1) * kT25W + 2 * tp + 1;
+    // plane k: xm, xc, xp the pairs of planes k-1, k, k+1 (loaded), xq
+    // receives plane k+2; hc / bcur plane k's halo element and right-hand
+    // side, hn / bn receive plane k+1's
+    auto plane = [&](int k, const Pr &xm, const Pr &xc, const Pr &xp, Pr &xq, const double &hc, double &hn,
+                     const Pr &bcur, Pr &bn) {
+        double *buf = xs[k & 1];
+        buf[lc] = xc.a;
+        buf[lc + 1] = xc.b;
+        if (halo_thread) buf[hslot] = hc;
+        xq = ld_pair(k + 2);
+        hn = ld_h(k + 1);
+        bn = ld_b(k + 1);
+        __syncthreads();
+        if (!own) return;
+        // z faces of this plane: diagonal and lifting terms
+        const double az0 = (k > 0 || pz) ? cfz : (dz0 ? 2.0 * cfz : 0.0);
+        const double az1 = (k < nz - 1 || pz) ? cfz : (dz1 ? 2.0 * cfz : 0.0);
+        const double lzk0 = (k == 0 && dz0) ? lz0 : 0.0, lzk1 = (k == nz - 1 && dz1) ? lz1 : 0.0;
+        const double wl = buf[lc - 1], wr = buf[lc + 2];
+        double rv[2];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const double xv = q == 0 ? xc.a : xc.b;
+            double of = 0.0;
+            of += cfx * (q == 0 ? wl : xc.a);
+            of += cfx * (q == 0 ? xc.b : wr);
+            of += cfy * buf[lc + q - kT25W];
+            of += cfy * buf[lc + q + kT25W];
+            of += cfz * (q == 0 ? xm.a : xm.b);
+            of += cfz * (q == 0 ? xp.a : xp.b);
+            double dg = dgxy[q];
+            dg += az0;
+            dg += az1;
+            double b = q == 0 ? bcur.a : bcur.b;
+            if (lift) {
+                double lf = lfxy[q];
+                lf += lzk0;
+                lf += lzk1;
+                b = b + lf;
+            }
+            rv[q] = b - (dg * xv - of);
+            v += rv[q] * rv[q];
+            if (partials_b) vb += b * b;
+        }
+        if (MODE == 2) {
+            const int row = nx * j + nxy * k;
+            if (rbE) {
+                // cell ia is red ((i+j+k) even) when j + k is even; the
+                // pair's cells sit at position ia/2 of the two halves
+                const int h0 = ((j + k) & 1) ? nh : 0;
+                gst(Eb, row + h0 + (ia >> 1), (float)rv[0]);
+                gst(Eb, row + (nh - h0) + (ia >> 1), (float)rv[1]);
+                if (!keep_e) {
+                    gst(Ex, row + h0 + (ia >> 1), 0.0f);
+                    gst(Ex, row + (nh - h0) + (ia >> 1), 0.0f);
+                }
+            } else {
+                PairF rp;
+                rp.x = (float)rv[0];
+                rp.y = (float)rv[1];
+                *(VD_GAS PairF *)(Eb + row + ia) = rp;
+                if (!keep_e) *(VD_GAS PairF *)(Ex + row + ia) = PairF{0.0f, 0.0f};
+            }
+        }
+    };
+    Pr P0 = ld_pair(k0 - 1), P1 = ld_pair(k0), P2 = ld_pair(k0 + 1), P3;
+    double H0 = ld_h(k0), H1;
+    Pr B0 = ld_b(k0), B1;
+    for (int k = k0; k < k1; k += 4) {
+        plane(k, P0, P1, P2, P3, H0, H1, B0, B1);
+        if (k + 1 >= k1) break;
+        plane(k + 1, P1, P2, P3, P0, H1, H0, B1, B0);
+        if (k + 2 >= k1) break;
+        plane(k + 2, P2, P3, P0, P1, H0, H1, B0, B1);
+        if (k + 3 >= k1) break;
+        plane(k + 3, P3, P0, P1, P2, H1, H0, B1, B0);
+    }
+    const double sum = block_sum(v, red);
+    if (tid == 0) gst(partials, slot, sum);
+    if (partials_b) {
+        const double sb = block_sum(vb, red);
+        if (tid == 0) gst(partials_b, slot, sb);
+    }
+}
+
+// ---------------------------------------- FP64 residual checks, direct form
+// The residual checks of k_st25 (modes 1 and 2) for levels with face and/or
+// cell coefficient arrays and no mask (the electrons' variable diffusion, a
+// variable permittivity), with no LDS and no barrier: a thread owns the row
+// pair (i, i+1) of row j
+// in a 32 x 16 tile and marches the tile's KZ planes (fully unrolled, so no
+// register is copied while its load is in flight); the pair's x-y
+// neighbours are loaded straight from memory (the cache serves the re-reads
+// of the neighbouring threads and tiles) and its z neighbours are carried in
+// registers.  With no barrier each wavefront runs ahead on its own loads,
+// which keeps far more bytes in flight than the LDS-staged march.  Tiles and
+// partial slots are those of the 2.5D plans.
+//
+// Each row is row_terms_fc's from the loaded faces (the arithmetic of
+// k_st25's face-coefficient march), so residuals, partial sums and the
+// stored FP32 residual are bit-identical to k_st25's.  This form carries 88
+// VGPRs against the march's 113 (five wavefronts per SIMD instead of four).  MODE 1: partial sums of
+// r^2 (and of b^2 when partials_b is given); MODE 2: also r rounded to FP32
+// into the FP32 hierarchy's finest right-hand side (either row layout) and,
+// unless keep_e, its unknown cleared.
+template <int MODE, int KZ>
+__global__ void __launch_bounds__(kBlock) k_resd(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32,
+                                                 Plan pl, int keep_e, double *__restrict__ partials,
+                                                 const ProbState *__restrict__ st, int check_active,
+                                                 double *__restrict__ partials_b) {
+    __shared__ double red[kBlock / 64];
+    const int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    const int d = plan_find(pl, t);
+    const int id = pl.ids[d];
+    const LevDesc L = descs[id];
+    if (check_active && !gld(&st[L.prob].active, 0)) return;
+    const int lt = t - pl.prefix[d];
+    const int slot = pl.gbase ? pl.gbase[d] + lt : t;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, nxy = L.nxy;
+    const Tile25 T25 = tile25(lt, nx, ny, nz, KZ);
+    const int k0 = T25.k0, k1 = T25.k1;
+    const int tid = threadIdx.x;
+    const int ia = T25.u0 + 2 * (tid & 15), j = T25.j0 + (tid >> 4);
+    double v = 0.0, vb = 0.0;
+    if (ia < nx && j < ny) {
+        const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
+        bool okl, okr, oks, okn;
+        const int il = wrap_idx(ia - 1, nx, px, okl), ir = wrap_idx(ia + 2, nx, px, okr);
+        const int js = wrap_idx(j - 1, ny, py, oks), jn = wrap_idx(j + 1, ny, py, okn);
+        const int oc = ia + nx * j, ol = il + nx * j, orr = ir + nx * j, os = ia + nx * js, on = ia + nx * jn;
+        const double *__restrict__ X = (const double *)L.x;
+        const double *__restrict__ B = (const double *)L.b;
+        auto ldp = [&](int off) -> PairD { return *(const VD_GAS PairD *)(X + off); };
+        // pair of plane kk (zero where the plane is not one of cells)
+        auto zpair = [&](int kk) -> PairD {
+            bool okz;
+            const int kw = wrap_idx(kk, nz, pz, okz);
+            const PairD q = ldp(oc + nxy * kw);
+            return okz ? q : PairD{0.0, 0.0};
+        };
+        const double bc = L.beta_c;
+        const bool lift = L.lift;
+        // coefficient arrays: faces of the pair and its cell
+        // coefficient, read from x's own addresses when absent
+        const double *__restrict__ BX = L.var_beta ? L.bx : X;
+        const double *__restrict__ BY = L.var_beta ? L.by : X;
+        const double *__restrict__ BZ = L.var_beta ? L.bz : X;
+        const double *__restrict__ AL = L.var_alpha ? L.alpha : X;
+        float *__restrict__ Eb = MODE == 2 ? (float *)d32[id].b : nullptr;
+        float *__restrict__ Ex = MODE == 2 ? (float *)d32[id].x : nullptr;
+        const bool rbE = MODE == 2 && d32[id].rb;
+        const int nh = nx >> 1;
+        PairD xm = zpair(k0 - 1), xc = zpair(k0);
+#pragma unroll
+        for (int q = 0; q < KZ; q++) {
+            const int k = k0 + q;
+            if (k >= k1) break;
+            const PairD xp = zpair(k + 1);
+            const int pk = nxy * k;
+            const double wl0 = gld(X, ol + pk), wr0 = gld(X, orr + pk);
+            const PairD ys0 = ldp(os + pk), yn0 = ldp(on + pk);
+            const PairD bv = __builtin_nontemporal_load((const VD_GAS PairD *)(B + oc + pk));
+            const double wl = okl ? wl0 : 0.0, wr = okr ? wr0 : 0.0;
+            const PairD ys = oks ? ys0 : PairD{0.0, 0.0}, yn = okn ? yn0 : PairD{0.0, 0.0};
+            double rv[2];
+            {
+                const bool fb = L.var_beta;
+                const int fxrow = (nx + 1) * (j + ny * k), fyrow = nx * (j + (ny + 1) * k);
+                const double fx0 = gld(BX, fb ? fxrow + ia : oc), fx1 = gld(BX, fb ? fxrow + ia + 1 : oc),
+                             fx2 = gld(BX, fb ? fxrow + ia + 2 : oc);
+                const PairD fyl = *(const VD_GAS PairD *)(BY + (fb ? fyrow + ia : oc));
+                const PairD fyh = *(const VD_GAS PairD *)(BY + (fb ? fyrow + nx + ia : oc));
+                const PairD fzl = *(const VD_GAS PairD *)(BZ + (fb ? oc + pk : oc));
+                const PairD fzh = *(const VD_GAS PairD *)(BZ + (fb ? oc + pk + nxy : oc));
+                const PairD alp = *(const VD_GAS PairD *)(AL + (L.var_alpha ? oc + pk : oc));
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const int i = ia + c;
+                    double nbv[6], fc[6];
+                    nbv[0] = c == 0 ? wl : xc.x;
+                    nbv[1] = c == 0 ? xc.y : wr;
+                    nbv[2] = c == 0 ? ys.x : ys.y;
+                    nbv[3] = c == 0 ? yn.x : yn.y;
+                    nbv[4] = c == 0 ? xm.x : xm.y;
+                    nbv[5] = c == 0 ? xp.x : xp.y;
+                    fc[0] = c == 0 ? fx0 : fx1;
+                    fc[1] = c == 0 ? fx1 : fx2;
+                    fc[2] = c == 0 ? fyl.x : fyl.y;
+                    fc[3] = c == 0 ? fyh.x : fyh.y;
+                    fc[4] = c == 0 ? fzl.x : fzl.y;
+                    fc[5] = c == 0 ? fzh.x : fzh.y;
+                    if (!fb) for (int f = 0; f < 6; f++) fc[f] = bc;
+                    const double al = L.var_alpha ? (c == 0 ? alp.x : alp.y) : L.alpha_c;
+                    double dg, of, lf;
+                    row_terms_fc<double>(L, i, j, k, nbv, fc, al, dg, of, lf);
+                    double b = c == 0 ? bv.x : bv.y;
+                    if (lift) b = b + lf;
+                    rv[c] = b - (dg * (c == 0 ? xc.x : xc.y) - of);
+                    v += rv[c] * rv[c];
+                    if (partials_b) vb += b * b;
+                }
+            }
+            if (MODE == 2) {
+                const int row = nx * j + pk;
+                if (rbE) {
+                    // cell ia is red ((i+j+k) even) when j + k is even; the
+                    // pair's cells sit at position ia/2 of the two halves
+                    const int h0 = ((j + k) & 1) ? nh : 0;
+                    __builtin_nontemporal_store((float)rv[0], (VD_GAS float *)(Eb + row + h0 + (ia >> 1)));
+                    __builtin_nontemporal_store((float)rv[1], (VD_GAS float *)(Eb + row + (nh - h0) + (ia >> 1)));
+                    if (!keep_e) {
+                        __builtin_nontemporal_store(0.0f, (VD_GAS float *)(Ex + row + h0 + (ia >> 1)));
+                        __builtin_nontemporal_store(0.0f, (VD_GAS float *)(Ex + row + (nh - h0) + (ia >> 1)));
+                    }
+                } else {
+                    PairF rp;
+                    rp.x = (float)rv[0];
+                    rp.y = (float)rv[1];
+                    __builtin_nontemporal_store(rp, (VD_GAS PairF *)(Eb + row + ia));
+                    if (!keep_e) __builtin_nontemporal_store(PairF{0.0f, 0.0f}, (VD_GAS PairF *)(Ex + row + ia));
+                }
+            }
+            xm = xc;
+            xc = xp;
+        }
+    }
+    const double sum = block_sum(v, red);
+    if (tid == 0) gst(partials, slot, sum);
+    if (partials_b) {
+        const double sb = block_sum(vb, red);
+        if (tid == 0) gst(partials_b, slot, sb);
+    }
+}
+
 // ------------------------- parity-split colour pass (refinement corrections)
 // The FP32 corrections of the finest level of uniform-coefficient problems
 // are held parity-split by row (cell_pos): a colour pass then reads only
@@ -577,6 +912,13 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
 // colour is read); 0: a colour pass; 5: the last (black) pass, which adds
 // the final correction of the thread's four consecutive cells to the FP64
 // unknown (d64) instead of storing it.  Needs nx % 4 == 0.
+struct Pf {
+    float a, b;
+};
+struct Q4 {
+    PairD lo, hi;
+};
+
 template <int PM>
 __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d64, Plan pl,
                                                  int kz, int colour, const ProbState *__restrict__ st) {
@@ -588,7 +930,7 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     const LevDesc L = descs[id];
     if (!gld(&st[L.prob].active, 0)) return;
     const int lt = t - pl.prefix[d];
-    const int nx = L.nx, ny = L.ny, nz = L.nz, nh = nx >> 1;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, nh = nx >> 1, nxy = L.nxy;
     const Tile25 T25 = tile25(lt, nh, ny, nz, kz);
     const int k0 = T25.k0, k1 = T25.k1;
     const int tid = threadIdx.x;
@@ -596,7 +938,7 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     const int hslot = halo_slot(tid);
     float *__restrict__ X = (float *)L.x;
     const float *__restrict__ B = (const float *)L.b;
-    const long nxy = L.nxy;
+    const float *zero = (const float *)g_zero4;
     const int oofs = (1 - colour) * nh, uofs = colour * nh;   // half-row offsets: other / updated colour
     const bool px = L.kind[0] == VD_BC_PERIODIC, py = L.kind[2] == VD_BC_PERIODIC, pz = L.kind[4] == VD_BC_PERIODIC;
     // the thread's pair of the other colour: wrapped (a partial tile's
@@ -608,96 +950,100 @@ __global__ void __launch_bounds__(kBlock) k_rb32(const LevDesc *__restrict__ des
     const bool own = H.own;      // nh is even, so the pair (ma, ma + 1) is whole
     const bool halo_thread = H.halo;
     const bool okp = H.okp, okh = H.okh;
-    const long pair_off = H.pair_off, b_off = H.b_off, h_off = H.h_off;
-    auto ld_pair = [&](int kk, float &a, float &b2) {
-        if constexpr (PM == 4) {
-            a = b2 = 0.0f;
-            return;
-        }
+    const int pair_off = (int)H.pair_off, b_off = (int)H.b_off, h_off = (int)H.h_off;
+    // loads from the address of a cell, or of zeros where the position is
+    // not one (no masking after the load)
+    auto ld_pair = [&](int kk) -> Pf {
+        if constexpr (PM == 4) return Pf{0.0f, 0.0f};
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
-        const PairF v = *(const VD_GAS PairF *)(X + pair_off + nxy * kw);
-        const bool ok = okp && okz;
-        a = ok ? v.x : 0.0f;
-        b2 = ok ? v.y : 0.0f;
+        const float *p = (okp && okz) ? X + (pair_off + nxy * kw) : zero;
+        const PairF v = *(const VD_GAS PairF *)p;
+        return Pf{v.x, v.y};
     };
     auto ld_h = [&](int kk) -> float {
         if constexpr (PM == 4) return 0.0f;
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
-        const float v = gld(X, h_off + nxy * kw);
-        return (okh && okz) ? v : 0.0f;
+        const float *p = (okh && okz) ? X + (h_off + nxy * kw) : zero;
+        return *(const VD_GAS float *)p;
     };
-    auto ld_b = [&](int kk, float &a, float &b2) {
-        const PairF v = *(const VD_GAS PairF *)(B + b_off + nxy * min(kk, nz - 1));
-        const bool ok = own && kk < k1;
-        a = ok ? v.x : 0.0f;
-        b2 = ok ? v.y : 0.0f;
+    auto ld_b = [&](int kk) -> Pf {
+        const float *p = (own && kk < k1) ? B + (b_off + nxy * kk) : zero;
+        const PairF v = *(const VD_GAS PairF *)p;
+        return Pf{v.x, v.y};
     };
-    float xm0, xm1, xc0, xc1, xp0, xp1;
-    ld_pair(k0 - 1, xm0, xm1);
-    ld_pair(k0, xc0, xc1);
-    ld_pair(k0 + 1, xp0, xp1);
-    float hcur = ld_h(k0);
-    float bc0, bc1;
-    ld_b(k0, bc0, bc1);
-    const long q_off = quad_off25(ma, j, nh, nx, ny);   // first of the four cells (FP64)
-    for (int k = k0; k < k1; k++) {
+    const int q_off = (int)quad_off25(ma, j, nh, nx, ny);   // first of the four cells (FP64)
+    double *__restrict__ X64 = PM == 5 ? (double *)d64[id].x : nullptr;
+    auto ld_q = [&](int kk) -> Q4 {
+        if constexpr (PM != 5) return Q4{};
+        const double *p = (own && kk < k1) ? X64 + (q_off + nxy * kk) : g_zero4;
+        return Q4{*(const VD_GAS PairD *)p, *(const VD_GAS PairD *)(p + 2)};
+    };
+    const int lc0 = (r + 1) * kT25W + 2 * tp + 1;    // LDS slot of position ma
+    // plane k: xm, xc, xp the other colour's pairs of planes k-1, k, k+1,
+    // xq receives plane k+2; hc / bcur / qc plane k's halo element,
+    // right-hand side pair and (PM 5) FP64 quad, hn / bn / qn receive plane
+    // k+1's
+    auto plane = [&](int k, const Pf &xm, const Pf &xc, const Pf &xp, Pf &xq, const float &hc, float &hn,
+                     const Pf &bcur, Pf &bn, const Q4 &qc, Q4 &qn) {
         float *buf = xs[k & 1];
-        buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
-        buf[(r + 1) * kT25W + 2 * tp + 2] = xc1;
-        if (halo_thread) buf[hslot] = hcur;
-        float xq0, xq1, bn0, bn1;
-        ld_pair(k + 2, xq0, xq1);
-        const float hnext = ld_h(k + 1);
-        ld_b(k + 1, bn0, bn1);
-        PairD xa{}, xb{};
-        if constexpr (PM == 5) {
-            const double *x64 = (const double *)d64[id].x + q_off + nxy * k;
-            xa = *(const VD_GAS PairD *)x64;
-            xb = *(const VD_GAS PairD *)(x64 + 2);
-        }
+        buf[lc0] = xc.a;
+        buf[lc0 + 1] = xc.b;
+        if (halo_thread) buf[hslot] = hc;
+        xq = ld_pair(k + 2);
+        hn = ld_h(k + 1);
+        bn = ld_b(k + 1);
+        qn = ld_q(k + 1);
         __syncthreads();
-        if (own) {
-            const int s = (j + k + colour) & 1;      // updated cells at i = 2m + s
-            float out[2];
+        if (!own) return;
+        const int s = (j + k + colour) & 1;      // updated cells at i = 2m + s
+        float out[2];
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const int i = 2 * (ma + q) + s;
-                float nbv[6];
-                const int lc = (r + 1) * kT25W + 2 * tp + 1 + q;    // LDS slot of position ma + q
-                nbv[0] = s ? buf[lc] : buf[lc - 1];
-                nbv[1] = s ? buf[lc + 1] : buf[lc];
-                nbv[2] = buf[lc - kT25W];
-                nbv[3] = buf[lc + kT25W];
-                nbv[4] = q == 0 ? xm0 : xm1;
-                nbv[5] = q == 0 ? xp0 : xp1;
-                float dg, of;
-                row_terms_uni<float>(L, i, j, k, nbv, dg, of);
-                out[q] = ((q == 0 ? bc0 : bc1) + of) / dg;
-            }
-            if constexpr (PM == 5) {
-                // cells 2ma .. 2ma+3: updated at offsets s and s+2, the other
-                // colour (this plane's values xc) at 1-s and 3-s
-                xa.x = xa.x + (double)(s ? xc0 : out[0]);
-                xa.y = xa.y + (double)(s ? out[0] : xc0);
-                xb.x = xb.x + (double)(s ? xc1 : out[1]);
-                xb.y = xb.y + (double)(s ? out[1] : xc1);
-                double *x64 = (double *)d64[id].x + q_off + nxy * k;
-                *(VD_GAS PairD *)x64 = xa;
-                *(VD_GAS PairD *)(x64 + 2) = xb;
-            } else {
-                PairF pv;
-                pv.x = out[0];
-                pv.y = out[1];
-                *(VD_GAS PairF *)(X + uofs + ma + (long)nx * j + nxy * k) = pv;
-            }
+        for (int q = 0; q < 2; q++) {
+            const int i = 2 * (ma + q) + s;
+            float nbv[6];
+            const int lc = lc0 + q;               // LDS slot of position ma + q
+            nbv[0] = s ? buf[lc] : buf[lc - 1];
+            nbv[1] = s ? buf[lc + 1] : buf[lc];
+            nbv[2] = buf[lc - kT25W];
+            nbv[3] = buf[lc + kT25W];
+            nbv[4] = q == 0 ? xm.a : xm.b;
+            nbv[5] = q == 0 ? xp.a : xp.b;
+            float dg, of;
+            row_terms_uni<float>(L, i, j, k, nbv, dg, of);
+            out[q] = ((q == 0 ? bcur.a : bcur.b) + of) / dg;
         }
-        xm0 = xc0; xm1 = xc1;
-        xc0 = xp0; xc1 = xp1;
-        xp0 = xq0; xp1 = xq1;
-        hcur = hnext;
-        bc0 = bn0; bc1 = bn1;
+        if constexpr (PM == 5) {
+            // cells 2ma .. 2ma+3: updated at offsets s and s+2, the other
+            // colour (this plane's values xc) at 1-s and 3-s
+            PairD xa = qc.lo, xb = qc.hi;
+            xa.x = xa.x + (double)(s ? xc.a : out[0]);
+            xa.y = xa.y + (double)(s ? out[0] : xc.a);
+            xb.x = xb.x + (double)(s ? xc.b : out[1]);
+            xb.y = xb.y + (double)(s ? out[1] : xc.b);
+            double *x64 = X64 + (q_off + nxy * k);
+            *(VD_GAS PairD *)x64 = xa;
+            *(VD_GAS PairD *)(x64 + 2) = xb;
+        } else {
+            PairF pv;
+            pv.x = out[0];
+            pv.y = out[1];
+            *(VD_GAS PairF *)(X + uofs + ma + nx * j + nxy * k) = pv;
+        }
+    };
+    Pf P0 = ld_pair(k0 - 1), P1 = ld_pair(k0), P2 = ld_pair(k0 + 1), P3;
+    float H0 = ld_h(k0), H1;
+    Pf B0 = ld_b(k0), B1;
+    Q4 Q0 = ld_q(k0), Q1;
+    for (int k = k0; k < k1; k += 4) {
+        plane(k, P0, P1, P2, P3, H0, H1, B0, B1, Q0, Q1);
+        if (k + 1 >= k1) break;
+        plane(k + 1, P1, P2, P3, P0, H1, H0, B1, B0, Q1, Q0);
+        if (k + 2 >= k1) break;
+        plane(k + 2, P2, P3, P0, P1, H0, H1, B0, B1, Q0, Q1);
+        if (k + 3 >= k1) break;
+        plane(k + 3, P3, P0, P1, P2, H1, H0, B1, B0, Q1, Q0);
     }
 }
 
@@ -2188,16 +2534,18 @@ static LevDesc make_desc(const HProblem &H, const vd_problem &P, int l, int prob
 // 2.5D tiled plan over (descriptor id, level) items: usable when every
 // level has an even nx.  kz = planes per workgroup; 0 picks the deepest
 // tile that still gives a launch >= 2048 workgroups.
-static void build_plan25(vd_ctx *ctx, HPlan &out, const std::vector<std::pair<int, const HLevel *>> &items, int force_kz) {
+static void build_plan25(vd_ctx *ctx, HPlan &out, const std::vector<std::pair<int, const HLevel *>> &items, int force_kz,
+                         int max_kz = 8) {
     out = HPlan{};
     if (items.empty()) return;
     for (auto &it : items) if (it.second->nx % 2) return;
     int kz = force_kz;
     if (kz <= 0) {
-        // the deepest of 8, 4, 2 planes that still gives 2048 tiles (16
-        // planes measured slower for the FP64 residual checks)
+        // the deepest of 8, 4, 2 planes (at most max_kz) that still gives
+        // 2048 tiles (16 planes measured slower for the FP64 residual checks)
         kz = 2;
         for (int cand : {8, 4, 2}) {
+            if (cand > max_kz) continue;
             long tot = 0;
             for (auto &it : items)
                 tot += (long)ceil_div(it.second->nx, kT25X) * ceil_div(it.second->ny, kT25Y) * ceil_div(it.second->nz, cand);
@@ -2746,16 +3094,41 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
     const int kind = (mode == 2 && keep_e) ? 10 : 3 + mode;
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
+    // the direct (barrier-free) residual kernels for tiles of 2, 4 or 8 planes
+    auto direct = [&](const HPlan &q, auto mode_tag) -> bool {
+        constexpr int M = decltype(mode_tag)::value;
+        const dim3 g = xcd_grid(q.ntiles);
+        const Plan P = q.dev();
+        if (q.kz == 8)
+            k_resd<M, 8><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+        else if (q.kz == 4)
+            k_resd<M, 4><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+        else if (q.kz == 2)
+            k_resd<M, 2><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+        else
+            return false;
+        return true;
+    };
     auto launch25 = [&](const HPlan &q, bool uni) {
+        // uniform levels: the LDS march; levels with coefficient arrays and
+        // no mask: the direct kernel; masked levels: the general march
+        bool masked = false;
+        for (int id : q.h_ids) masked = masked || S.probs[id / S.Lmax].has_mask;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        if (!masked && !uni) {
+            if (mode == 1 && direct(q, I1{})) return;
+            if (mode == 2 && direct(q, I2{})) return;
+        }
         if (mode == 1 && uni)
-            k_st25<double, 1, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p,
-                                                                          S.st.p, check_active, pb);
+            k_res25u<1><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
+                                                              check_active, pb);
         else if (mode == 1)
             k_st25<double, 1><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
                                                                     check_active, pb);
         else if (uni)
-            k_st25<double, 2, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, ksel, S.partials.p,
-                                                                          S.st.p, check_active, pb);
+            k_res25u<2><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, ksel, S.partials.p, S.st.p,
+                                                              check_active, pb);
         else
             k_st25<double, 2><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, ksel, S.partials.p, S.st.p,
                                                                     check_active, pb);
@@ -2768,21 +3141,7 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
         return;
     }
     if (mode != 0 && S.all0_25.nd && S.aligned) {
-        const HPlan &p25 = S.all0_25;
-        timed_mg(ctx, S, "norm", pl, false, kind, 1.0, [&] {
-            if (mode == 1 && p25.uni)
-                k_st25<double, 1, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
-                                                                                S.partials.p, S.st.p, check_active, pb);
-            else if (mode == 1)
-                k_st25<double, 1><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, 0,
-                                                                          S.partials.p, S.st.p, check_active, pb);
-            else if (p25.uni)
-                k_st25<double, 2, true><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, ksel,
-                                                                                S.partials.p, S.st.p, check_active, pb);
-            else
-                k_st25<double, 2><<<xcd_grid(p25.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, p25.dev(), p25.kz, ksel,
-                                                                          S.partials.p, S.st.p, check_active, pb);
-        });
+        timed_mg(ctx, S, "norm", pl, false, kind, 1.0, [&] { launch25(S.all0_25, S.all0_25.uni); });
         return;
     }
     timed_mg(ctx, S, "norm", pl, false, 3 + mode, 1.0, [&] {

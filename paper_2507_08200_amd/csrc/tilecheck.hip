@@ -1,7 +1,9 @@
 // Host-side walk over every memory access of the 2.5D tiled passes
-// (k_st25 in all its modes, k_rb32 in all its modes) for one level shape
-// and tile depth, using the kernels' own geometry functions (tile25.hpp).
-// Nothing here touches the GPU.
+// (k_st25 in all its modes, which also covers the residual checks of
+// k_res25u, k_rb32 in all its modes, and the direct residual checks k_resd
+// with their coefficient arrays) for one level shape and tile depth, using
+// the kernels' own geometry functions (tile25.hpp).  Nothing here touches
+// the GPU.
 #include "vd_internal.hpp"
 #include "tile25.hpp"
 
@@ -145,6 +147,58 @@ void walk_rb32(Walk &W, int nx, int ny, int nz, bool px, bool py, bool pz, int k
     }
 }
 
+// k_resd: a thread owns the pair (ia, ia + 1) of row j and reads its x-y
+// neighbours, its z window, the right-hand side, the face arrays and the
+// cell coefficient directly; it stores the FP32 residual in either layout
+void walk_resd(Walk &W, int nx, int ny, int nz, bool px, bool py, bool pz, int kz) {
+    const long n = (long)nx * ny * nz, nxy = (long)nx * ny;
+    const long nbx = (long)(nx + 1) * ny * nz, nby = (long)nx * (ny + 1) * nz, nbz = nxy * (nz + 1);
+    const int nt = tiles25(nx, ny, nz, kz);
+    for (int lt = 0; lt < nt; lt++) {
+        const Tile25 T = tile25(lt, nx, ny, nz, kz);
+        for (int tid = 0; tid < kBlock; tid++) {
+            const int ia = T.u0 + 2 * (tid & 15), j = T.j0 + (tid >> 4);
+            if (!(ia < nx && j < ny)) continue;
+            bool okl, okr, oks, okn;
+            const long il = wrap_idx(ia - 1, nx, px, okl), ir = wrap_idx(ia + 2, nx, px, okr);
+            const long js = wrap_idx(j - 1, ny, py, oks), jn = wrap_idx(j + 1, ny, py, okn);
+            const long oc = ia + (long)nx * j;
+            auto zpair = [&](int kk) {
+                bool ok;
+                W.vec(oc + nxy * wrap_idx(kk, nz, pz, ok), 2, n);
+            };
+            zpair(T.k0 - 1);
+            zpair(T.k0);
+            for (int k = T.k0; k < T.k1; k++) {
+                const long pk = nxy * k;
+                zpair(k + 1);
+                W.elem(il + (long)nx * j + pk, n);
+                W.elem(ir + (long)nx * j + pk, n);
+                W.vec(ia + (long)nx * js + pk, 2, n);
+                W.vec(ia + (long)nx * jn + pk, 2, n);
+                W.vec(oc + pk, 2, n);                                        // b
+                const long fxrow = (long)(nx + 1) * (j + (long)ny * k), fyrow = (long)nx * (j + (long)(ny + 1) * k);
+                for (int q = 0; q < 3; q++) W.elem(fxrow + ia + q, nbx);      // x faces
+                W.vec(fyrow + ia, 2, nby);                                   // y faces
+                W.vec(fyrow + nx + ia, 2, nby);
+                W.vec(oc + pk, 2, nbz);                                      // z faces
+                W.vec(oc + pk + nxy, 2, nbz);
+                W.vec(oc + pk, 2, n);                                        // cell coefficient
+                LevDesc D;
+                memset(&D, 0, sizeof D);
+                D.nx = nx; D.ny = ny; D.nz = nz; D.nxy = (int)nxy;
+                for (int q = 0; q < 2; q++)
+                    for (int rb = 0; rb < 2; rb++) {
+                        if (rb && nx % 4) continue;
+                        D.rb = rb;
+                        W.elem(cell_pos(D, ia + q, j, k), n);                // FP32 residual / unknown
+                    }
+                W.vec(oc + pk, 2, n);                                        // lexicographic pair store
+            }
+        }
+    }
+}
+
 }  // namespace
 }  // namespace vd
 
@@ -154,12 +208,14 @@ extern "C" vd_status vd_check_tiles25(int32_t nx, int32_t ny, int32_t nz, int32_
     if (nx < 2 || ny < 1 || nz < 1 || kz < 1 || !accesses || !violations) return VD_EINVAL;
     if (kernel == 0 && nx % 2) return VD_EINVAL;
     if (kernel == 1 && nx % 4) return VD_EINVAL;
-    if (kernel != 0 && kernel != 1) return VD_EINVAL;
+    if (kernel == 2 && nx % 2) return VD_EINVAL;
+    if (kernel < 0 || kernel > 2) return VD_EINVAL;
     const bool px = periodic & 1, py = periodic & 2, pz = periodic & 4;
     Walk W;
     if (kernel == 0) walk_st25(W, nx, ny, nz, px, py, pz, kz);
-    else walk_rb32(W, nx, ny, nz, px, py, pz, kz);
-    const int nt = kernel == 0 ? tiles25(nx, ny, nz, kz) : tiles25(nx >> 1, ny, nz, kz);
+    else if (kernel == 1) walk_rb32(W, nx, ny, nz, px, py, pz, kz);
+    else walk_resd(W, nx, ny, nz, px, py, pz, kz);
+    const int nt = kernel == 1 ? tiles25(nx >> 1, ny, nz, kz) : tiles25(nx, ny, nz, kz);
     W.accesses++;
     if (!xcd_mapping_ok(nt)) W.violations++;
     *accesses = W.accesses;

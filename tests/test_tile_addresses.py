@@ -1,8 +1,10 @@
 """Host-side bounds check of the 2.5D tiled multigrid passes.
 
 The lexicographic colour/residual pass (all modes, including the fused
-first and last colour passes of the FP32 refinement corrections) and the
-parity-split FP32 colour pass load from wrapped or clamped addresses with
+first and last colour passes of the FP32 refinement corrections, and the
+residual checks of uniform levels, which share its tile geometry), the
+parity-split FP32 colour pass and the direct residual check of levels with
+coefficient arrays (kernel 2) load from wrapped or clamped addresses with
 no branches and store whole pairs, so an index mistake would fault the GPU
 before it showed as a wrong value.  vd_check_tiles25 walks every access of
 every thread of every tile with the kernels' own index functions, on the
@@ -25,7 +27,7 @@ def _check(shape, periodic, kz, kernel):
     assert bad == 0, (shape, periodic, kz, kernel, bad)
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("kz", [2, 4, 8, 16, 32])
 def test_160_refinement_levels(kernel, kz):
     for shape in LEVELS_160:
@@ -33,7 +35,7 @@ def test_160_refinement_levels(kernel, kz):
             _check(shape, periodic, kz, kernel)
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("shape", RAGGED, ids=[str(s) for s in RAGGED])
 def test_partial_tiles(kernel, shape):
     for periodic, kz in itertools.product(range(8), (1, 2, 3, 8)):
@@ -45,3 +47,7 @@ def test_rejects_unsupported_shapes():
         V.check_tiles25(6, 4, 4, 0, 8, 1)      # parity split needs nx % 4 == 0
     with pytest.raises(V.VDError):
         V.check_tiles25(5, 4, 4, 0, 8, 0)      # row pairs need an even nx
+    with pytest.raises(V.VDError):
+        V.check_tiles25(5, 4, 4, 0, 8, 2)
+    with pytest.raises(V.VDError):
+        V.check_tiles25(8, 4, 4, 0, 8, 3)      # no such kernel
