@@ -388,10 +388,15 @@ def main():
         del src, dst
         log("[bench] copy calibration: 3 copies of %d MiB" % args.calibrate_copy_mib)
 
-    # ---- warmup, with every kernel family timed to find the dominant one
-    ctx.vd_timing_select(",".join(FAMILIES))
+    # ---- warmup; every kernel family is timed over the later warmup steps
+    # (the first steps start the extrapolation histories and take more
+    # cycles than the steady state) to find the dominant one
     infos = []
+    n_prof = max(1, args.warmup // 2)
     for w in range(args.warmup):
+        if w == args.warmup - n_prof:
+            torch.cuda.synchronize()
+            ctx.vd_timing_select(",".join(FAMILIES))
         infos.append(ctx.vd_step(P, state))
         log("[bench] warmup step %d: %s" % (w, {k: infos[-1][k] for k in ("poisson_cycles", "species_cycles", "ms_total")}))
     torch.cuda.synchronize()
@@ -399,12 +404,12 @@ def main():
     for f in FAMILIES:
         cnt, ms, by = ctx.vd_timing_read(f)
         if cnt:
-            prof[f] = {"launches_per_step": cnt / max(1, args.warmup), "ms_per_step": ms / max(1, args.warmup),
+            prof[f] = {"launches_per_step": cnt / n_prof, "ms_per_step": ms / n_prof,
                        "gb_per_s": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
     kernel = args.kernel
     if kernel == "auto":
         kernel = max(prof, key=lambda f: prof[f]["ms_per_step"]) if prof else "gsrb"
-    log("[bench] per-family ms/step (warmup): %s" % {f: round(v["ms_per_step"], 3) for f, v in prof.items()})
+    log("[bench] per-family ms/step (last %d warmup steps): %s" % (n_prof, {f: round(v["ms_per_step"], 3) for f, v in prof.items()}))
 
     # ---- timed region: K steps; the dominant family is event-timed live
     ctx.vd_timing_select(kernel)
