@@ -87,7 +87,13 @@ class StepParams(C.Structure):
                 ("extra_source", C.c_void_p), ("extra_energy", C.c_void_p), ("eps_cell", C.c_void_p),
                 ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts),
                 ("species_guess", C.c_void_p), ("phi_fixed", C.c_int32), ("pad2", C.c_int32),
-                ("check_n", C.c_void_p), ("check_Ee", C.c_void_p), ("check_res", C.c_void_p)]
+                ("check_n", C.c_void_p), ("check_Ee", C.c_void_p), ("check_res", C.c_void_p),
+                ("photo_n", C.c_int32), ("photo_e", C.c_int32), ("photo_ion", C.c_int32), ("pad3", C.c_int32),
+                ("photo_A", C.c_double * 3), ("photo_lambda", C.c_double * 3),
+                ("photo_pO2", C.c_double), ("photo_pg", C.c_double), ("photo_xi", C.c_double),
+                ("photo_pq", C.c_double), ("photo_p", C.c_double), ("photo_nu_ratio", C.c_double),
+                ("photo_bc", BC), ("photo_mg", MGOpts), ("photo_out", C.c_void_p),
+                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p)]
 
 
 class StepInfo(C.Structure):
@@ -335,10 +341,21 @@ def face_flux(g, phi_bc, sp_bc, sp, u, phi, mu, D, Te, Tg, consts=PHYS):
 
 def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poisson=None, species_mg=None,
          energy_mg=None, extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0,
-         k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None, parallel=False):
+         k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None, parallel=False,
+         photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None):
     """One step of the semi-implicit scheme on a workload dict (see inputs).
     species_guess ([S][cells], optional): starting iterate of the first
     corrector's species solves in place of n^n.
+    photo (optional dict): photoionization terms -- "A", "lam" (lists of up
+    to 3), "pO2", "pg", "xi", "pq", "p", "nu_ratio" (default 1), "e", "ion"
+    (species indices), "bc" (boundary dict, default homogeneous Dirichlet),
+    "mg" (solver options); the S_j of the last corrector come back as
+    "photo_S" ([3][cells]).  adaptive_dt (optional dict "c_adv", "c_diff",
+    "c_diel"): time step of Eq. (20) with cfg["dt"] as its largest value
+    (the electron species index is `electron`).  diel (six flags) with
+    sigma (packed surface charge of the marked faces, see the C header):
+    dielectric faces, sigma advanced and returned as "sigma".  see_gamma:
+    secondary emission coefficient; stick ([S]): sticking coefficients.
     Checking a step computed elsewhere (n_t = 1): phi_fixed takes phi as the
     Poisson result (its relative residual in info["poisson_rel"]); check_n /
     check_Ee replace the species / energy solves by the relative residuals
@@ -395,10 +412,42 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
     P.poisson = poisson or mg_opts()
     P.species_mg = species_mg or mg_opts()
     P.energy_mg = energy_mg or mg_opts()
+    nc = int(np.prod(n.shape[1:]))
+    photo_S = None
+    if photo is not None:
+        A, lam = list(photo["A"]), list(photo["lam"])
+        if not 1 <= len(A) <= 3 or len(lam) != len(A):
+            raise ValueError("photoionization takes one to three terms")
+        P.photo_n = len(A)
+        for q in range(len(A)):
+            P.photo_A[q], P.photo_lambda[q] = float(A[q]), float(lam[q])
+        P.photo_pO2, P.photo_pg = float(photo["pO2"]), float(photo["pg"])
+        P.photo_xi, P.photo_pq, P.photo_p = float(photo["xi"]), float(photo["pq"]), float(photo["p"])
+        P.photo_nu_ratio = float(photo.get("nu_ratio", 1.0))
+        P.photo_e, P.photo_ion = int(photo["e"]), int(photo["ion"])
+        P.photo_bc = bc(photo.get("bc", {"kind": [0] * 6, "value": [0.0] * 6}))
+        P.photo_mg = photo.get("mg") or mg_opts()
+        photo_S = np.zeros((3,) + tuple(n.shape[1:]))
+        P.photo_out = _ptr(photo_S)
+    if adaptive_dt is not None:
+        P.dt_mode = 1
+        P.c_adv, P.c_diff, P.c_diel = (float(adaptive_dt[k]) for k in ("c_adv", "c_diff", "c_diel"))
+    sig = None
+    if diel is not None:
+        for f in range(6):
+            P.diel[f] = int(bool(diel[f]))
+        sig = _f64(sigma).copy()
+        P.sigma = _ptr(sig)
+    P.see_gamma = float(see_gamma)
+    if stick is not None:
+        a = _f64(stick)
+        keep.append(a)
+        P.stick = _ptr(a)
     info = StepInfo()
     st = lib(parallel).or_step(C.byref(P), _ptr(n), _ptr(phi), _ptr(Te), _ptr(Ee), C.byref(info))
     d = {k: getattr(info, k) for k, _ in StepInfo._fields_}
-    return {"n": n, "phi": phi, "Te": Te, "Ee": Ee, "info": d, "status": st, "check_res": res}
+    return {"n": n, "phi": phi, "Te": Te, "Ee": Ee, "info": d, "status": st, "check_res": res, "photo_S": photo_S,
+            "sigma": sig}
 
 
 def trajectory(cfg, species, steps, *, poisson=None, species_mg=None, extrapolate=True, parallel=False, **kw):

@@ -20,7 +20,14 @@
  *   - Electron energy equation, its flux and source: Sec. 2.1, Eqs. (5)-(8).
  *   - Wall fluxes: Sec. 2.2, the electron, electron-energy and ion wall
  *     fluxes (Eqs. (14)-(16)) and the neutral variant stated after them.
+ *   - Photoionization: Sec. 2.1, the three-term Helmholtz model
+ *     (Eqs. (9)-(10)) with the emission functions of Eqs. (11)-(12).
+ *   - Surface charge on dielectric walls: Sec. 2.1, Eq. (13), applied to
+ *     the Poisson source of the adjacent cells.
+ *   - Secondary electron emission and sticking at walls: Sec. 2.2 (the
+ *     variations of the wall fluxes named after them).
  *   - Mid-point corrector iteration: Sec. 3, Eqs. (18)-(19).
+ *   - Adaptive time step: Sec. 3, Eq. (20).
  *   - Helmholtz-form multigrid per equation: Sec. 4.
  *   - Cell masking: Sec. 3 (masking paragraph).
  *   - Mechanism and transport: Appendix A, Tables A.1-A.4.
@@ -115,6 +122,30 @@ typedef struct {
     const double *check_n;
     const double *check_Ee;
     double *check_res;              /* [S + 1] */
+    /* Photoionization (Sec. 2.1): photo_n Helmholtz terms (0 = off), each
+     * (lambda_j p_O2)^2 S_j - lap S_j = A_j p_g^2 I, S_ph = sum_j S_j added
+     * to the sources of species photo_e (electrons) and photo_ion; I =
+     * p_q / (p + p_q) xi nu_ratio S_i with S_i the rate of R2 (direct
+     * ionization of the background Ar), nu_ratio = 1 for Eq. (11) and the
+     * ratio nu_u / nu_i for Eq. (12).  Each solve starts from zero; the
+     * S_j of the last corrector go to photo_out ([3][cells]) when given. */
+    int32_t photo_n, photo_e, photo_ion, pad3;
+    double photo_A[3], photo_lambda[3];
+    double photo_pO2, photo_pg, photo_xi, photo_pq, photo_p, photo_nu_ratio;
+    or_bc photo_bc;
+    or_mg_opts photo_mg;
+    double *photo_out;
+    /* Dielectric walls (Sec. 2.1, Eq. (13)): diel[f] marks domain face f (x-, x+,
+     * y-, y+, z-, z+) as dielectric.  sigma holds the surface charge of the
+     * marked faces back to back in face order (x faces ny*nz values,
+     * index j + ny k; y faces nx*nz, i + nx k; z faces nx*ny, i + nx j); it
+     * is read and advanced in place.  see_gamma: secondary electron
+     * emission coefficient of every wall face; stick ([S] or NULL = 1):
+     * sticking coefficients of the neutral wall fluxes (Sec. 2.2). */
+    int32_t diel[6];
+    double *sigma;
+    double see_gamma;
+    const double *stick;
 } or_step_params;
 
 typedef struct {
@@ -916,6 +947,16 @@ typedef struct {
     const double *Te;     /* K, per cell */
     double Tg;
     const or_consts *cs;
+    /* wall variants (Sec. 2.2): secondary emission coefficient gamma (the
+     * electron wall flux less gamma times the ion wall fluxes of the same
+     * face, ions being the species with the ion wall model; their densities
+     * and signed mobilities n_all, mu_all [S_all][cells]) and the sticking
+     * coefficient of the species whose flux is taken (neutral wall model) */
+    double see_gamma;
+    int S_all;
+    const or_species *sp_all;
+    const double *n_all, *mu_all;
+    double stick;
 } or_flux_ctx;
 
 /* Outward wall flux (Sec. 2.2) of a species with value uc in the boundary
@@ -928,6 +969,25 @@ static double wall_flux(int wk, double uc, double mu, double e_n, double Te, dou
     case OR_WALL_NEUTRAL: return uc * 0.25 * sqrt(8.0 * cs->kB * Tg / (M_PI * mass));
     default: return 0.0;
     }
+}
+
+/* Outward wall flux of model wk at boundary cell cb with the wall
+ * variants of X: sticking scales the neutral flux, secondary emission
+ * returns gamma times the ions' wall fluxes at the face to the gas. */
+static double wall_flux_x(const or_flux_ctx *X, int wk, size_t cb, double uc, double mu, double e_n, double mass)
+{
+    double fl = wall_flux(wk, uc, mu, e_n, X->Te[cb], X->Tg, mass, X->cs);
+    if (wk == OR_WALL_NEUTRAL) fl = X->stick * fl;
+    if (wk == OR_WALL_ELECTRON && X->see_gamma != 0.0) {
+        size_t nc = (size_t)X->g->nx * X->g->ny * X->g->nz;
+        double ions = 0.0;
+        for (int s = 0; s < X->S_all; s++)
+            if (X->sp_all[s].wall_kind == OR_WALL_ION)
+                ions += wall_flux(OR_WALL_ION, X->n_all[s * nc + cb], X->mu_all[s * nc + cb], e_n, X->Te[cb], X->Tg,
+                                  X->sp_all[s].mass, X->cs);
+        fl = fl - X->see_gamma * ions;
+    }
+    return fl;
 }
 
 /* Drift flux along +d (species continuity, Eq. (2), drift part) through
@@ -961,7 +1021,7 @@ static double drift_face_flux(const or_flux_ctx *X, const or_bc *ubc, const doub
         if (ne_wall) /* energy: 2 kB Te times the electron wall flux */
             fl = 2.0 * X->cs->kB * X->Te[cb] * wall_flux(OR_WALL_ELECTRON, ne_wall[cb], 0.0, e_n, X->Te[cb], X->Tg, X->cs->me, X->cs);
         else
-            fl = wall_flux(wk, u[cb], mu[cb], e_n, X->Te[cb], X->Tg, mass, X->cs);
+            fl = wall_flux_x(X, wk, cb, u[cb], mu[cb], e_n, mass);
         return fidx == 0 ? -fl : fl;   /* flux in +d direction */
     }
     /* cells left and right of the face along d */
@@ -1046,7 +1106,7 @@ int or_species_flux(const or_grid *g, const or_bc *phi_bc, const or_bc *sp_bc, i
                     const or_consts *cs, double *div)
 {
     size_t nc = (size_t)g->nx * g->ny * g->nz;
-    or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs };
+    or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs, 0.0, 0, NULL, NULL, NULL, 1.0 };
     for (int s = 0; s < S; s++)
         drift_divergence(&X, &sp_bc[s], n + s * nc, mu + s * nc, sp[s].wall_kind, sp[s].mass, NULL, div + s * nc);
     return OR_OK;
@@ -1062,7 +1122,7 @@ int or_face_flux(const or_grid *g, const or_bc *phi_bc, const or_bc *ubc, const 
                  const or_consts *cs, double *fx, double *fy, double *fz)
 {
     int nx = g->nx, ny = g->ny, nz = g->nz;
-    or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs };
+    or_flux_ctx X = { g, phi_bc, phi, Te, Tg, cs, 0.0, 0, NULL, NULL, NULL, 1.0 };
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i <= nx; i++)
@@ -1202,10 +1262,10 @@ static const int OR_AR3_RXNS[7] = { 0, 1, 2, 3, 4, 11, 12 };
  * cell.  Rate of progress r_i = k_i prod(n_reactant).  Loss = sum dE_i e r_i
  * over the rows that print an energy. */
 static void cell_rates(int mech, const double *nc, double Te, const double *bg, double k_decay, int S,
-                       double qe, double *G, double *Sinel)
+                       double qe, double *G, double *Sinel, double *ion_rate)
 {
     for (int s = 0; s < S; s++) G[s] = 0.0;
-    double loss = 0.0;
+    double loss = 0.0, r_ion = 0.0;
     if (mech == OR_MECH_DECAY) {
         for (int s = 0; s < S; s++) G[s] = -k_decay * nc[s];
     } else if (mech == OR_MECH_ARH2_15 || mech == OR_MECH_AR3) {
@@ -1230,9 +1290,11 @@ static void cell_rates(int mech, const double *nc, double Te, const double *bg, 
             for (int m = 0; m < R->nr; m++) if (map[R->r[m]] >= 0) G[map[R->r[m]]] -= r;
             for (int m = 0; m < R->np; m++) if (map[R->p[m]] >= 0) G[map[R->p[m]]] += r;
             loss += R->dE * qe * r;
+            if (id == 1) r_ion = r;        /* R2: e + Ar -> Ar+ + 2e */
         }
     }
     if (Sinel) *Sinel = loss;
+    if (ion_rate) *ion_rate = r_ion;
 }
 
 int or_reaction_source(int mech, size_t ncells, int S, const double *n, const double *Te, const double *bg,
@@ -1245,7 +1307,7 @@ int or_reaction_source(int mech, size_t ncells, int S, const double *n, const do
     for (size_t c = 0; c < ncells; c++) {
         for (int s = 0; s < S; s++) nc[s] = n[s * ncells + c];
         double loss;
-        cell_rates(mech, nc, Te[c], bg, k_decay, S, qe, Gc, &loss);
+        cell_rates(mech, nc, Te[c], bg, k_decay, S, qe, Gc, &loss, NULL);
         for (int s = 0; s < S; s++) G[s * ncells + c] = Gc[s];
         if (Sinel) Sinel[c] = loss;
     }
@@ -1283,6 +1345,63 @@ static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v >
 
 #define OR_TE_MAX 1e6
 
+/* Dielectric faces: the number of values of face f's surface-charge array
+ * and its offset in the packed sigma array (marked faces back to back). */
+static size_t diel_size(const or_grid *g, int f)
+{
+    return f < 2 ? (size_t)g->ny * g->nz : (f < 4 ? (size_t)g->nx * g->nz : (size_t)g->nx * g->ny);
+}
+
+static size_t diel_offset(const or_step_params *P, int f)
+{
+    size_t o = 0;
+    for (int q = 0; q < f; q++)
+        if (P->diel[q]) o += diel_size(&P->grid, q);
+    return o;
+}
+
+/* Boundary cell of face f at face position (a, b): (j, k) for x faces,
+ * (i, k) for y faces, (i, j) for z faces; face-array index a + n_a b. */
+static void diel_cell(const or_grid *g, int f, int a, int b, int *i, int *j, int *k)
+{
+    int d = f / 2, hi = f & 1;
+    if (d == 0) { *i = hi ? g->nx - 1 : 0; *j = a; *k = b; }
+    else if (d == 1) { *i = a; *j = hi ? g->ny - 1 : 0; *k = b; }
+    else { *i = a; *j = b; *k = hi ? g->nz - 1 : 0; }
+}
+
+/* Adaptive time step (Sec. 3, Eq. (20)): the least of the advection,
+ * diffusion and dielectric-relaxation limits of the electrons over all
+ * cells, with the field and Te of the state passed in, N_dim = 3 and
+ * dx_min the smallest spacing; the caller's dt is the largest step taken
+ * (a limit whose denominator vanishes is not a limit). */
+static double adaptive_dt(const or_step_params *P, const double *n, const double *phi, const double *Te)
+{
+    const or_grid *g = &P->grid;
+    const or_consts *cs = &P->c;
+    size_t nc = (size_t)g->nx * g->ny * g->nz;
+    double dxmin = g->dx;
+    if (g->dy < dxmin) dxmin = g->dy;
+    if (g->dz < dxmin) dxmin = g->dz;
+    double dt = P->dt;
+    const or_species *se = &P->species[P->electron];
+    for (int k = 0; k < g->nz; k++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++) {
+                size_t c = IDX(i, j, k, g->nx, g->ny);
+                double E[3], mu, D;
+                e_cell(g, &P->phi_bc, phi, i, j, k, E);
+                double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+                transport(se, cs, Em / P->N_gas / OR_TD, Te[c], P->Tg, P->N_gas, &mu, &D);
+                double am = fabs(mu) * Em;
+                if (am > 0.0) { double t = P->c_adv * dxmin / am; if (t < dt) dt = t; }
+                if (D > 0.0) { double t = P->c_diff / 3.0 * (dxmin * dxmin) / (2.0 * D); if (t < dt) dt = t; }
+                double bm = cs->qe * fabs(mu) * n[P->electron * nc + c];
+                if (bm > 0.0) { double t = P->c_diel * cs->eps0 / bm; if (t < dt) dt = t; }
+            }
+    return dt;
+}
+
 int or_step(const or_step_params *P, double *n, double *phi, double *Te, double *Ee, or_step_info *info)
 {
     memset(info, 0, sizeof(*info));
@@ -1293,6 +1412,13 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     if (P->te_mode == OR_TE_ENERGY && (!Ee || P->electron < 0)) return info->status = OR_EINVAL;
     if ((P->phi_fixed || P->check_n || P->check_Ee) && P->n_t != 1) return info->status = OR_EINVAL;
     if ((P->check_n || P->check_Ee) && !P->check_res) return info->status = OR_EINVAL;
+    if (P->photo_n < 0 || P->photo_n > 3) return info->status = OR_EINVAL;
+    if (P->photo_n > 0 && (P->photo_e < 0 || P->photo_e >= S || P->photo_ion < 0 || P->photo_ion >= S))
+        return info->status = OR_EINVAL;
+    if (P->dt_mode != 0 && (P->dt_mode != 1 || P->electron < 0 || P->electron >= S)) return info->status = OR_EINVAL;
+    int any_diel = 0;
+    for (int f = 0; f < 6; f++) any_diel = any_diel || P->diel[f];
+    if (any_diel && !P->sigma) return info->status = OR_EINVAL;
     const or_consts *cs = &P->c;
     double *n0 = (double *)malloc(sizeof(double) * nc * S);
     double *ns = (double *)malloc(sizeof(double) * nc * S);
@@ -1309,14 +1435,21 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     double *beta = (double *)malloc(sizeof(double) * nc);
     double *mue = (double *)malloc(sizeof(double) * nc);
     double *divE = (double *)malloc(sizeof(double) * nc);
+    double *Si = (double *)malloc(sizeof(double) * nc);
+    double *Sj = (double *)malloc(sizeof(double) * nc);
+    double *Sph = (double *)malloc(sizeof(double) * nc);
+    size_t nsig = any_diel ? diel_offset(P, 6) : 0;
+    double *sig0 = (double *)malloc(sizeof(double) * (nsig ? nsig : 1));
     int status = OR_OK;
-    if (!n0 || !ns || !mu || !Dk || !div || !G || !rhs || !rho || !Sinel || !en || !Ee0 || !Ees || !beta || !mue || !divE) {
+    if (!n0 || !ns || !mu || !Dk || !div || !G || !rhs || !rho || !Sinel || !en || !Ee0 || !Ees || !beta || !mue || !divE ||
+        !Si || !Sj || !Sph || !sig0) {
         status = OR_ENOMEM;
         goto out;
     }
     memcpy(n0, n, sizeof(double) * nc * S);
     if (Ee) memcpy(Ee0, Ee, sizeof(double) * nc);
-    double dt = P->dt;
+    if (nsig) memcpy(sig0, P->sigma, sizeof(double) * nsig);
+    double dt = P->dt_mode == 1 ? adaptive_dt(P, n, phi, Te) : P->dt;
     info->dt_used = dt;
     for (int m = 0; m < P->n_t; m++) {
         /* u* = (u^n + u^m)/2 */
@@ -1327,6 +1460,23 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             double s = 0.0;
             for (int k = 0; k < S; k++) s += P->species[k].Z * ns[k * nc + c];
             rho[c] = cs->qe * s;
+        }
+        /* surface charge of the dielectric faces (at the mid-point of the
+         * corrector, as the densities) over the adjacent cells' width */
+        for (int f = 0; f < 6; f++) {
+            if (!P->diel[f]) continue;
+            int d = f / 2;
+            int na = d == 0 ? g->ny : g->nx, nb = d == 2 ? g->ny : g->nz;
+            double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
+            size_t off = diel_offset(P, f);
+            for (int b = 0; b < nb; b++)
+                for (int a = 0; a < na; a++) {
+                    int i, j, k;
+                    diel_cell(g, f, a, b, &i, &j, &k);
+                    size_t q = off + (size_t)a + (size_t)na * b;
+                    double sg = m == 0 ? sig0[q] : 0.5 * (sig0[q] + P->sigma[q]);
+                    rho[IDX(i, j, k, g->nx, g->ny)] += sg / h;
+                }
         }
         or_problem PP = { *g, P->phi_bc, NULL, NULL, 0.0, P->eps_cell, cs->eps0 };
         or_mg_info mi;
@@ -1362,17 +1512,42 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                 transport(&P->species[k], cs, en[c], Te[c], P->Tg, P->N_gas, &mu[k * nc + c], &Dk[k * nc + c]);
         }
         /* explicit drift divergence and chemistry at u* */
-        or_flux_ctx X = { g, &P->phi_bc, phi, Te, P->Tg, cs };
-        for (int k = 0; k < S; k++)
-            drift_divergence(&X, &P->species_bc[k], ns + k * nc, mu + k * nc, P->species[k].wall_kind,
+        or_flux_ctx X = { g, &P->phi_bc, phi, Te, P->Tg, cs, P->see_gamma, S, P->species, ns, mu, 1.0 };
+        for (int k = 0; k < S; k++) {
+            or_flux_ctx Xk = X;
+            Xk.stick = P->stick ? P->stick[k] : 1.0;
+            drift_divergence(&Xk, &P->species_bc[k], ns + k * nc, mu + k * nc, P->species[k].wall_kind,
                              P->species[k].mass, NULL, div + k * nc);
+        }
         OR_PAR_FOR
         for (size_t c = 0; c < nc; c++) {
             double nloc[32], Gloc[32], loss;
             for (int k = 0; k < S; k++) nloc[k] = ns[k * nc + c];
-            cell_rates(P->mech, nloc, Te[c], P->bg, P->k_decay, S, cs->qe, Gloc, &loss);
+            cell_rates(P->mech, nloc, Te[c], P->bg, P->k_decay, S, cs->qe, Gloc, &loss, &Si[c]);
             for (int k = 0; k < S; k++) G[k * nc + c] = Gloc[k];
             Sinel[c] = loss;
+        }
+        /* photoionization (Sec. 2.1, Eqs. (9)-(12)): I = p_q/(p+p_q) xi
+         * nu_ratio S_i; per term (lambda_j p_O2)^2 S_j - lap S_j =
+         * A_j p_g^2 I from zero; S_ph = sum_j S_j into electrons and ions */
+        if (P->photo_n > 0) {
+            double cem = P->photo_pq / (P->photo_p + P->photo_pq) * P->photo_xi * P->photo_nu_ratio;
+            for (size_t c = 0; c < nc; c++) Sph[c] = 0.0;
+            for (int q = 0; q < P->photo_n; q++) {
+                double coef = P->photo_A[q] * P->photo_pg * P->photo_pg * cem;
+                double kl = P->photo_lambda[q] * P->photo_pO2;
+                or_problem PH = { *g, P->photo_bc, NULL, NULL, kl * kl, NULL, 1.0 };
+                for (size_t c = 0; c < nc; c++) { rhs[c] = coef * Si[c]; Sj[c] = 0.0; }
+                or_mg_info pmi;
+                int pst = or_mg_solve(&PH, rhs, Sj, &P->photo_mg, &pmi);
+                if (pst != OR_OK) { status = pst; goto out; }
+                for (size_t c = 0; c < nc; c++) Sph[c] += Sj[c];
+                if (P->photo_out) memcpy(P->photo_out + (size_t)q * nc, Sj, sizeof(double) * nc);
+            }
+            for (size_t c = 0; c < nc; c++) {
+                G[P->photo_e * nc + c] += Sph[c];
+                G[P->photo_ion * nc + c] += Sph[c];
+            }
         }
         /* electron energy (Eqs. (5)-(8)) */
         if (P->te_mode == OR_TE_ENERGY) {
@@ -1403,7 +1578,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                                     if (boundary && kind == OR_NEU) { Fs[side] = 0.0; continue; }
                                     if (boundary && kind == OR_WALL) {
                                         double e_n = fidx == 0 ? -Ef : Ef;
-                                        double fl = wall_flux(OR_WALL_ELECTRON, ne[c], mu_e[c], e_n, Te[c], P->Tg, cs->me, cs);
+                                        double fl = wall_flux_x(&X, OR_WALL_ELECTRON, c, ne[c], mu_e[c], e_n, cs->me);
                                         Fs[side] = fidx == 0 ? -fl : fl;
                                         continue;
                                     }
@@ -1480,6 +1655,35 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             if (mi.cycles > info->species_cycles) info->species_cycles = mi.cycles;
             if (st2 != OR_OK) { status = st2; goto out; }
         }
+        /* surface charge (Sec. 2.1, Eq. (13)): sigma = sigma^n + dt sum_s
+         * q_s Gamma_s . n_hat, the outward wall fluxes of this corrector's
+         * mid-point state (the ones the species equations used) */
+        for (int f = 0; f < 6; f++) {
+            if (!P->diel[f]) continue;
+            int d = f / 2, hi = f & 1;
+            int na = d == 0 ? g->ny : g->nx, nb = d == 2 ? g->ny : g->nz;
+            int n_d = d == 0 ? g->nx : (d == 1 ? g->ny : g->nz);
+            size_t off = diel_offset(P, f);
+            for (int b = 0; b < nb; b++)
+                for (int a = 0; a < na; a++) {
+                    int i, j, k;
+                    diel_cell(g, f, a, b, &i, &j, &k);
+                    size_t cb = IDX(i, j, k, g->nx, g->ny);
+                    double Ef = e_face(g, &P->phi_bc, phi, d, i, j, k, hi ? n_d : 0);
+                    double e_n = hi ? Ef : -Ef;
+                    double q = 0.0;
+                    for (int sp = 0; sp < S; sp++) {
+                        if (P->species_bc[sp].kind[f] != OR_WALL) continue;
+                        or_flux_ctx Xs = X;
+                        Xs.stick = P->stick ? P->stick[sp] : 1.0;
+                        double fl = wall_flux_x(&Xs, P->species[sp].wall_kind, cb, ns[sp * nc + cb], mu[sp * nc + cb], e_n,
+                                                P->species[sp].mass);
+                        q += P->species[sp].Z * cs->qe * fl;
+                    }
+                    size_t qi = off + (size_t)a + (size_t)na * b;
+                    P->sigma[qi] = sig0[qi] + dt * q;
+                }
+        }
     }
     if (P->te_mode == OR_TE_ENERGY) {
         const double *ne = n + P->electron * nc;
@@ -1488,7 +1692,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     }
 out:
     free(n0); free(ns); free(mu); free(Dk); free(div); free(G); free(rhs); free(rho); free(Sinel);
-    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE);
+    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE); free(Si); free(Sj); free(Sph); free(sig0);
     info->status = status;
     return status;
 }
