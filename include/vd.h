@@ -265,6 +265,47 @@ typedef struct {
     const double *extra_energy;     /* device cells or NULL */
     const double *eps_cell;         /* device cells or NULL (eps0) */
     vd_mg_opts poisson, species_mg, energy_mg;
+    /* Photoionization (Sec. 2.1, Eqs. (9)-(12)): photo_n terms (0 = off,
+     * at most 3), each (lambda_j p_O2)^2 S_j - lap S_j = A_j p_g^2 I under
+     * photo_bc, solved after the chemistry of every corrector; S_ph = sum_j
+     * S_j is added to the sources of species photo_e (electrons) and
+     * photo_ion.  Emission function I = p_q / (p + p_q) * xi * nu_ratio *
+     * S_i with S_i the rate of R2 (e + Ar -> Ar+ + 2e, direct ionization of
+     * the background gas; 0 for mechanisms without it); nu_ratio = 1 gives
+     * Eq. (11), the ratio nu_u / nu_i Eq. (12).  Units are the caller's:
+     * lambda_j p_O2 in 1/m, A_j p_g^2 in 1/m^2.  photo_mg.guess: VD_GUESS_GIVEN
+     * starts each term from its solution of the previous call (zero at
+     * first), VD_GUESS_ZERO from zero.  photo_out: device [3][cells] or NULL,
+     * receives the S_j of the last corrector. */
+    int32_t photo_n, photo_e, photo_ion;
+    int32_t dt_mode;                /* 0: dt; 1: adaptive time step (Sec. 3, Eq. (20)) */
+    double photo_A[3], photo_lambda[3];
+    double photo_pO2, photo_pg, photo_xi, photo_pq, photo_p, photo_nu_ratio;
+    vd_bc photo_bc;
+    vd_mg_opts photo_mg;
+    double *photo_out;
+    /* Adaptive time step (dt_mode 1): the least over cells of c_adv dx_min /
+     * (|mu_e| |E|), c_diff / 3 dx_min^2 / (2 D_e) and c_diel eps0 / (e |mu_e|
+     * n_e) for the electron species `electron`, from the phi, Te and n
+     * passed in; dt is the largest step taken; the step taken is returned in
+     * vd_step_info.dt_used.  Synchronises the stream once per step. */
+    double c_adv, c_diff, c_diel;
+    /* Dielectric walls (Sec. 2.1, Eq. (13)): diel[f] != 0 marks domain face
+     * f (x-, x+, y-, y+, z-, z+) as dielectric.  sigma: device, the surface
+     * charge (C/m^2) of the marked faces back to back in face order (x faces
+     * ny*nz values at j + ny*k, y faces nx*nz at i + nx*k, z faces nx*ny at
+     * i + nx*j), read and advanced in place: sigma / h_d of the corrector's
+     * mid-point is added to the Poisson source of the adjacent cells, and
+     * sigma = sigma^n + dt sum_s q_s Gamma_s . n_hat with the outward wall
+     * fluxes of the corrector's mid-point state.  see_gamma (Sec. 2.2):
+     * secondary electron emission coefficient of every wall face (the
+     * electron wall flux less gamma times the ion wall fluxes of the face;
+     * at most 8 species with the ion wall model).  stick: host [S] sticking
+     * coefficients that multiply the neutral wall fluxes, NULL = 1. */
+    int32_t diel[6];
+    double *sigma;
+    double see_gamma;
+    const double *stick;
 } vd_step_params;
 
 /* State updated in place (device arrays). */

@@ -134,6 +134,24 @@ __device__ __forceinline__ double wall_flux(int wk, double uc, double mu, double
     }
 }
 
+// Outward wall flux of field F at its boundary cell cb with F's wall
+// variants (Sec. 2.2): sticking scales the neutral flux; secondary emission
+// returns gamma times the ions' wall fluxes of the face to the gas
+__device__ __forceinline__ double wall_flux_f(const FieldDesc &F, long cb, double uc, double mu, double e_n, double Te,
+                                              double Tg, double kB, double me) {
+    double fl = wall_flux(F.wall, uc, mu, e_n, Te, Tg, F.mass, kB, me);
+    if (F.wall == VD_WALL_NEUTRAL) fl = F.stick * fl;
+    if (F.wall == VD_WALL_ELECTRON && F.see_gamma != 0.0) {
+        double ions = 0.0;
+        for (int q = 0; q < F.nion; q++) {
+            const double mi = F.ion_mu[q] ? gld(F.ion_mu[q], cb) : F.ion_mu_c[q];
+            ions += wall_flux(VD_WALL_ION, gld(F.ion_n[q], cb), mi, e_n, Te, Tg, 0.0, kB, me);
+        }
+        fl = fl - F.see_gamma * ions;
+    }
+    return fl;
+}
+
 // Drift flux along +d at a non-wall face fidx of the row through c: face
 // velocity mu_f E_f (mu_f the mean of the two cells, the boundary cell's on
 // a domain face) times the upwind WENO5 value.
@@ -203,7 +221,7 @@ __device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const dou
                     fl = 2.0 * kB * gld(Te, c) * wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, c), 0.0, e_n, gld(Te, c), Tg, me, kB, me);
                 } else {
                     const double muc = F.mu ? gld(F.mu, c) : F.mu_c;
-                    fl = wall_flux(F.wall, gld(u, c), muc, e_n, gld(Te, c), Tg, F.mass, kB, me);
+                    fl = wall_flux_f(F, c, gld(u, c), muc, e_n, gld(Te, c), Tg, kB, me);
                 }
                 Fs[side] = fidx == 0 ? -fl : fl;
                 continue;
@@ -233,7 +251,7 @@ __device__ __forceinline__ double face_flux(const GridDev &G, const FieldDesc &F
             const double e_n = fidx == 0 ? -Ef : Ef;
             double fl;
             if (F.ne_wall) fl = 2.0 * kB * gld(Te, cb) * wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, cb), 0.0, e_n, gld(Te, cb), Tg, me, kB, me);
-            else fl = wall_flux(F.wall, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(Te, cb), Tg, F.mass, kB, me);
+            else fl = wall_flux_f(F, cb, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(Te, cb), Tg, kB, me);
             return fidx == 0 ? -fl : fl;
         }
     }
@@ -624,7 +642,7 @@ __global__ void __launch_bounds__(kBlock) k_wall_div(DriftArgs a, int d) {
             fl = 2.0 * a.kB * gld(a.Te, cb) *
                  wall_flux(VD_WALL_ELECTRON, gld(F.ne_wall, cb), 0.0, e_n, gld(a.Te, cb), a.Tg, a.me, a.kB, a.me);
         else
-            fl = wall_flux(F.wall, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(a.Te, cb), a.Tg, F.mass, a.kB, a.me);
+            fl = wall_flux_f(F, cb, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, gld(a.Te, cb), a.Tg, a.kB, a.me);
         // flux along +d through the face, and its share of the cell's divergence
         const double Fs = side == 0 ? -fl : fl;
         const double contrib = (side == 0 ? -Fs : Fs) * G.ihl[d];
@@ -710,7 +728,7 @@ __device__ void rates_arh2(double T, double k[33]) {
 
 // Net production per species for the full mechanism (rates of progress r_i
 // accumulated into the 15 species) and the inelastic electron loss.
-__device__ void source_arh2(const double n[15], double T, double qe, double G[15], double *loss) {
+__device__ void source_arh2(const double n[15], double T, double qe, double G[15], double *loss, double *ion) {
     double k[33];
     rates_arh2(T, k);
     const double e = n[SE];
@@ -767,10 +785,11 @@ __device__ void source_arh2(const double n[15], double T, double qe, double G[15
     G[SH2] = -r[14] - r[16] - r[17] + r[20] - r[22] - r[23] - r[24] - r[25] - r[27] + r[29] + r[30] - r[31] - r[32];
     *loss = qe * (11.6 * r[0] + 15.759 * r[1] + 4.159 * r[2] + 4.2 * r[5] + 14.68 * r[14] + 13.6 * r[15] + 15.4 * r[16] +
                   28.08 * r[17] + 12.68 * r[18]);
+    *ion = r[1];
 }
 
 // Argon subset on (e, Ar+, Ar*) with background Ar: R1-R5, R12, R13.
-__device__ void source_ar3(const double n[3], double T, double nAr, double qe, double G[3], double *loss) {
+__device__ void source_ar3(const double n[3], double T, double nAr, double qe, double G[3], double *loss, double *ion) {
     const double Tev = T / kEvK, eps = 1.5 * Tev, ie = 1.0 / eps, it = 1.0 / T, lT = log(T);
     const double e = n[0], ip = n[1], ms = n[2];
     const double k1 = exp(-37.44 + 1.407 * log(eps) + ie * (50.34 + ie * (-348.6 - 230.5 * ie)));
@@ -784,22 +803,23 @@ __device__ void source_ar3(const double n[3], double T, double nAr, double qe, d
     G[1] = r2 + r3 + r4 - r12 - r13;
     G[2] = r1 - r3 - 2.0 * r4 - r5 + r12 + r13;
     *loss = qe * (11.6 * r1 + 15.759 * r2 + 4.159 * r3);
+    *ion = r2;
 }
 
 __global__ void __launch_bounds__(kBlock) k_react(ReactArgs a) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     const long N = a.ncell;
-    double loss = 0.0;
+    double loss = 0.0, ion = 0.0;
     if (a.mech == VD_MECH_ARH2_15) {
         double n[15], G[15];
         for (int s = 0; s < 15; s++) n[s] = gld(a.n, s * N + c);
-        source_arh2(n, gld(a.Te, c), a.qe, G, &loss);
+        source_arh2(n, gld(a.Te, c), a.qe, G, &loss, &ion);
         for (int s = 0; s < 15; s++) gst(a.G, s * N + c, G[s]);
     } else if (a.mech == VD_MECH_AR3) {
         double n[3], G[3];
         for (int s = 0; s < 3; s++) n[s] = gld(a.n, s * N + c);
-        source_ar3(n, gld(a.Te, c), a.bg0, a.qe, G, &loss);
+        source_ar3(n, gld(a.Te, c), a.bg0, a.qe, G, &loss, &ion);
         for (int s = 0; s < 3; s++) gst(a.G, s * N + c, G[s]);
     } else if (a.mech == VD_MECH_DECAY) {
         for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, -a.bg0 * gld(a.n, s * N + c));
@@ -807,6 +827,7 @@ __global__ void __launch_bounds__(kBlock) k_react(ReactArgs a) {
         for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, 0.0);
     }
     if (a.S_inel) gst(a.S_inel, c, loss);
+    if (a.ion) gst(a.ion, c, ion);
 }
 
 // rho = e sum_k Z_k n_k (optionally at the mid-point (n0 + n)/2)
@@ -816,6 +837,102 @@ __global__ void __launch_bounds__(kBlock) k_rho(RhoArgs a) {
     double s = 0.0;
     for (int k = 0; k < a.S; k++) s += a.Z[k] * gld(a.n, k * a.ncell + c);
     gst(a.rho, c, a.qe * s);
+}
+
+// Photoionization right-hand sides (Sec. 2.1, Eqs. (9)-(12)): term q gets
+// coef_q S_i, coef_q = A_q p_g^2 p_q / (p + p_q) xi nu_ratio (formed on the
+// host)
+__global__ void __launch_bounds__(kBlock) k_photo_rhs(PhotoArgs a) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    const double si = gld(a.ion, c);
+    for (int q = 0; q < a.nterm; q++) gst(a.rhs, q * a.ncell + c, a.coef[q] * si);
+}
+
+// S_ph = sum_q S_q into the electron and ion sources
+__global__ void __launch_bounds__(kBlock) k_photo_add(PhotoArgs a) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    double s = 0.0;
+    for (int q = 0; q < a.nterm; q++) s += gld(a.S, q * a.ncell + c);
+    gst(a.Ge, c, gld(a.Ge, c) + s);
+    gst(a.Gi, c, gld(a.Gi, c) + s);
+}
+
+// One dielectric face (Sec. 2.1, Eq. (13)), one thread per face position
+// (a, b) with boundary cell (i, j, k).  update 0: rho += sigma / h with
+// sigma at the corrector's mid-point (sig0, or (sig0 + sigma) / 2).
+// update 1: sigma = sig0 + dt sum_s q_s Gamma_s . n_hat over the species
+// with a wall face there, outward wall fluxes with the wall variants.
+__global__ void __launch_bounds__(kBlock) k_sigma(SigmaArgs a, int update) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.na * a.nb) return;
+    const GridDev &G = a.g;
+    const int pa = t % a.na, pb = t / a.na;
+    const int d = a.face / 2, hi = a.face & 1;
+    const int n = G.n[d];
+    int i, j, k;
+    if (d == 0) { i = hi ? n - 1 : 0; j = pa; k = pb; }
+    else if (d == 1) { i = pa; j = hi ? n - 1 : 0; k = pb; }
+    else { i = pa; j = pb; k = hi ? n - 1 : 0; }
+    const long cb = i + (long)G.n[0] * j + (long)G.nxy * k;
+    const long q = a.off + t;
+    if (!update) {
+        const double sg = a.mid ? 0.5 * (gld(a.sig0, q) + gld(a.sigma, q)) : gld(a.sig0, q);
+        gst(a.rho, cb, gld(a.rho, cb) + sg / a.h);
+        return;
+    }
+    const int pos = d == 0 ? i : (d == 1 ? j : k);
+    const double Ef = e_face(G, a.phi, d, (int)cb, pos, hi ? n : 0);
+    const double e_n = hi ? Ef : -Ef;
+    const double te = gld(a.Te, cb);
+    double sum = 0.0;
+    for (int s = 0; s < a.S; s++) {
+        const FieldDesc &F = a.f[s];
+        if (F.kind[a.face] != VD_BC_WALLFLUX) continue;
+        const double fl = wall_flux_f(F, cb, gld(F.u, cb), F.mu ? gld(F.mu, cb) : F.mu_c, e_n, te, a.Tg, a.kB, a.me);
+        sum += a.Z[s] * a.qe * fl;
+    }
+    gst(a.sigma, q, gld(a.sig0, q) + a.dt * sum);
+}
+
+// Time-step limits of Eq. (20) per cell, least over each workgroup
+__global__ void __launch_bounds__(kBlock) k_dt_limit(DtArgs a) {
+    __shared__ double red[kBlock / 64];
+    const GridDev &G = a.g;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double dt = a.dt_max;
+    if (c < G.ncell) {
+        int pos[3];
+        pos[2] = c / G.nxy;
+        const int r = c - pos[2] * G.nxy;
+        pos[1] = r / G.n[0];
+        pos[0] = r - pos[1] * G.n[0];
+        double E[3];
+        e_cell(G, a.phi, c, pos, E);
+        const double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+        double mu = a.mu_c, D = a.D_c;
+        if (a.fit) {
+            mu = mu_electron(Em / a.N_gas / kTd, a.N_gas);
+            D = mu * a.kB * gld(a.Te, c) / a.qe;
+        }
+        const double am = fabs(mu) * Em;
+        if (am > 0.0) { const double t = a.c_adv * a.dxmin / am; dt = t < dt ? t : dt; }
+        if (D > 0.0) { const double t = a.c_diff / 3.0 * (a.dxmin * a.dxmin) / (2.0 * D); dt = t < dt ? t : dt; }
+        const double bm = a.qe * fabs(mu) * gld(a.ne, c);
+        if (bm > 0.0) { const double t = a.c_diel * a.eps0 / bm; dt = t < dt ? t : dt; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(dt, o, 64);
+        dt = v < dt ? v : dt;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kBlock / 64; w++) m = red[w] < m ? red[w] : m;
+        gst(a.partial, blockIdx.x, m);
+    }
 }
 
 // u* = (u0 + u)/2 (mid-point of the corrector iteration)
@@ -933,7 +1050,8 @@ __global__ void __launch_bounds__(kBlock) k_energy_rhs(EnergyArgs a) {
             const int kd = Fe.kind[2 * d + side];
             if (boundary && kd == VD_BC_NEUMANN) { Fs[side] = 0.0; continue; }
             if (boundary && kd == VD_BC_WALLFLUX) {
-                const double fl = wall_flux(VD_WALL_ELECTRON, gld(Fe.u, c), 0.0, 0.0, gld(a.Te, c), a.Tg, a.me, a.kB, a.me);
+                const double Ef = e_face(G, a.phi, d, c, pos[d], fidx);
+                const double fl = wall_flux_f(Fe, c, gld(Fe.u, c), 0.0, fidx == 0 ? -Ef : Ef, gld(a.Te, c), a.Tg, a.kB, a.me);
                 Fs[side] = fidx == 0 ? -fl : fl;
                 continue;
             }
@@ -1051,6 +1169,29 @@ void launch_rho(vd_ctx *ctx, const RhoArgs &a) {
 
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a) {
     timed(ctx, "energy", (double)a.g.ncell, [&] { k_energy_rhs<<<ceil_div(a.g.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+}
+
+void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a) {
+    timed(ctx, "photo", (double)a.ncell * 8.0 * (1 + a.nterm), [&] {
+        k_photo_rhs<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
+    });
+}
+
+void launch_photo_add(vd_ctx *ctx, const PhotoArgs &a) {
+    timed(ctx, "photo", (double)a.ncell * 8.0 * (a.nterm + 4), [&] {
+        k_photo_add<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
+    });
+}
+
+void launch_sigma(vd_ctx *ctx, const SigmaArgs &a, int update) {
+    const long n = (long)a.na * a.nb;
+    timed(ctx, "sigma", 0.0, [&] { k_sigma<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(a, update); });
+}
+
+int launch_dt_limit(vd_ctx *ctx, const DtArgs &a) {
+    const int nb = (int)ceil_div(a.g.ncell, kBlock);
+    timed(ctx, "dt", (double)a.g.ncell * 24.0, [&] { k_dt_limit<<<nb, kBlock, 0, ctx->stream>>>(a); });
+    return nb;
 }
 
 void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n) {

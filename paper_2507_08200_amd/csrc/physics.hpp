@@ -14,6 +14,8 @@ struct GridDev {
     double phi_val[6];
 };
 
+constexpr int kMaxSee = 8;   // ion species returning secondary electrons
+
 // One field whose drift divergence is taken: u with signed mobility mu
 // (array, or constant mu_c when mu is null), boundary kinds of the field,
 // wall model; for the electron energy ne_wall is the electron density whose
@@ -32,6 +34,16 @@ struct FieldDesc {
     const double *u0;      // time level n (right-hand side mode)
     const double *src;     // chemical source (right-hand side mode)
     const double *extra;   // extra source (right-hand side mode)
+    // wall variants (Sec. 2.2): the sticking coefficient of a neutral wall
+    // flux; secondary emission: gamma and the ion species whose wall fluxes
+    // at the same face it returns (densities, signed mobilities per cell or
+    // constant)
+    double stick;
+    double see_gamma;
+    int nion;
+    const double *ion_n[kMaxSee];
+    const double *ion_mu[kMaxSee];
+    double ion_mu_c[kMaxSee];
 };
 
 constexpr int kMaxFields = 33;
@@ -68,6 +80,46 @@ struct ReactArgs {
     const double *n, *Te;
     double bg0, qe;
     double *G, *S_inel;
+    double *ion;           // rate of R2 (direct ionization of Ar), or null
+};
+
+// Photoionization terms (Sec. 2.1, Eqs. (9)-(12)): right-hand sides coef_q
+// * S_i of the Helmholtz terms, then S_ph = sum_q S_q added to the sources
+// of the electrons (Ge) and of an ion (Gi)
+struct PhotoArgs {
+    long ncell;
+    int nterm;
+    double coef[3];
+    const double *ion;     // S_i per cell
+    double *rhs;           // [nterm][cells]
+    const double *S;       // [nterm][cells]
+    double *Ge, *Gi;
+};
+
+// Surface charge of one dielectric face (Sec. 2.1, Eq. (13))
+struct SigmaArgs {
+    GridDev g;
+    const double *phi, *Te;
+    const FieldDesc *f;    // device table, every species (u at the mid-point)
+    int S;
+    double Z[32];
+    double Tg, kB, me, qe, dt, h;
+    int face, na, nb, mid;
+    long off;              // offset of the face's values in the packed arrays
+    double *sigma;
+    const double *sig0;
+    double *rho;
+};
+
+// Adaptive time step (Sec. 3, Eq. (20)): per-workgroup minima
+struct DtArgs {
+    GridDev g;
+    const double *phi, *Te, *ne;
+    double N_gas, kB, qe, eps0;
+    int fit;               // electron mobility from the E/N fit (else constant)
+    double mu_c, D_c;
+    double c_adv, c_diff, c_diel, dxmin, dt_max;
+    double *partial;
 };
 
 struct RhoArgs {
@@ -100,6 +152,12 @@ void launch_react(vd_ctx *ctx, const ReactArgs &a);
 void launch_rho(vd_ctx *ctx, const RhoArgs &a);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
+void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a);
+void launch_photo_add(vd_ctx *ctx, const PhotoArgs &a);
+void launch_sigma(vd_ctx *ctx, const SigmaArgs &a, int update);
+// per-workgroup minima of the time-step limits into a.partial; returns the
+// number of workgroups
+int launch_dt_limit(vd_ctx *ctx, const DtArgs &a);
 // Poisson guess extrapolated from earlier steps' potentials (order 0..2)
 void launch_extrap(vd_ctx *ctx, double *phi, const double *h1, double *hdst, int order, long n);
 // species guesses extrapolated in time (order 0..2) from FP32 histories:

@@ -12,6 +12,8 @@ struct StepBuffers {
     long ncell = 0;
     int S = 0;
     DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
+    DevBuf<double> ion, photo, prhs, sig0, dtpart;
+    bool photo_zeroed = false;
 };
 
 // phi arrays passed in by the previous steps with an extrapolated Poisson
@@ -79,6 +81,30 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
         }
     }
     VD_CHECK(nvar <= 4, "at most 4 species with field-dependent mobility");
+    VD_CHECK(P->photo_n >= 0 && P->photo_n <= 3, "photo_n must be in 0..3");
+    if (P->photo_n > 0) {
+        VD_CHECK(P->photo_e >= 0 && P->photo_e < P->S && P->photo_ion >= 0 && P->photo_ion < P->S,
+                 "photoionization species indices out of range");
+        VD_CHECK(P->photo_mg.guess == VD_GUESS_GIVEN || P->photo_mg.guess == VD_GUESS_ZERO,
+                 "the photoionization guess must be GIVEN or ZERO");
+        for (int q = 0; q < P->photo_n; q++)
+            VD_CHECK(P->photo_lambda[q] * P->photo_pO2 != 0.0, "photoionization terms need lambda_j p_O2 != 0");
+    }
+    VD_CHECK(P->dt_mode == 0 || P->dt_mode == 1, "dt_mode must be 0 or 1");
+    if (P->dt_mode == 1) VD_CHECK(P->electron >= 0 && P->electron < P->S, "the adaptive time step needs the electron index");
+    bool any_diel = false;
+    for (int f = 0; f < 6; f++) any_diel = any_diel || P->diel[f];
+    VD_CHECK(!any_diel || P->sigma, "dielectric faces need the sigma array");
+    if (P->see_gamma != 0.0) {
+        int nion = 0;
+        for (int k = 0; k < P->S; k++) nion += P->species[k].wall_kind == VD_WALL_ION;
+        VD_CHECK(nion <= kMaxSee, "secondary emission takes at most 8 species with the ion wall model");
+    }
+}
+
+// number of values of dielectric face f's surface-charge array
+static long diel_size(const vd_grid &g, int f) {
+    return f < 2 ? (long)g.ny * g.nz : (f < 4 ? (long)g.nx * g.nz : (long)g.nx * g.ny);
 }
 
 static inline double sgn(double z) { return z > 0.0 ? 1.0 : (z < 0.0 ? -1.0 : 0.0); }
@@ -152,7 +178,66 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
     GridDev G = make_grid(g, P->phi_bc);
     vd_step_info I;
     memset(&I, 0, sizeof(I));
-    I.dt_used = P->dt;
+    // time step: fixed, or the least of the limits of Eq. (20) over the
+    // state passed in (one host synchronisation)
+    double dt = P->dt;
+    if (P->dt_mode == 1) {
+        DtArgs da;
+        memset(&da, 0, sizeof(da));
+        da.g = G; da.phi = st->phi; da.Te = st->Te; da.ne = st->n + (long)P->electron * N;
+        da.N_gas = P->N_gas > 0 ? P->N_gas : 1.0; da.kB = P->consts.kB; da.qe = P->consts.qe; da.eps0 = P->consts.eps0;
+        da.fit = P->species[P->electron].mob_kind == VD_MOB_ELECTRON_FIT;
+        da.mu_c = mu_c[P->electron]; da.D_c = D_c[P->electron];
+        da.c_adv = P->c_adv; da.c_diff = P->c_diff; da.c_diel = P->c_diel;
+        da.dxmin = std::min(g.dx, std::min(g.dy, g.dz));
+        da.dt_max = P->dt;
+        B->dtpart.alloc(ceil_div(N, kBlock));
+        da.partial = B->dtpart.p;
+        const int nb = launch_dt_limit(ctx, da);
+        std::vector<double> part(nb);
+        VD_HIP(hipMemcpyAsync(part.data(), B->dtpart.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        VD_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < nb; q++) dt = part[q] < dt ? part[q] : dt;
+    }
+    I.dt_used = dt;
+    // surface charge of the dielectric faces at time level n
+    long nsig = 0;
+    long sig_off[6];
+    for (int f = 0; f < 6; f++) {
+        sig_off[f] = nsig;
+        if (P->diel[f]) nsig += diel_size(g, f);
+    }
+    if (nsig) {
+        B->sig0.alloc(nsig);
+        VD_HIP(hipMemcpyAsync(B->sig0.p, P->sigma, sizeof(double) * nsig, hipMemcpyDeviceToDevice, s));
+    }
+    // photoionization: ionization rate, right-hand sides and the terms'
+    // solutions (kept from call to call as the next starting iterates)
+    if (P->photo_n > 0) {
+        B->ion.alloc(N);
+        B->prhs.alloc(N * 3);
+        if (B->photo.n < (size_t)N * 3 || !B->photo.p) B->photo_zeroed = false;
+        B->photo.alloc(N * 3);
+        if (!B->photo_zeroed) {
+            VD_HIP(hipMemsetAsync(B->photo.p, 0, sizeof(double) * N * 3, s));
+            B->photo_zeroed = true;
+        }
+    }
+    // wall variants of a species' field: sticking and secondary emission
+    auto wall_variants = [&](FieldDesc &F, int k, const double *nbase) {
+        F.stick = P->stick ? P->stick[k] : 1.0;
+        F.see_gamma = 0.0;
+        F.nion = 0;
+        if (P->species[k].wall_kind != VD_WALL_ELECTRON || P->see_gamma == 0.0) return;
+        F.see_gamma = P->see_gamma;
+        for (int q = 0; q < S; q++) {
+            if (P->species[q].wall_kind != VD_WALL_ION) continue;
+            F.ion_n[F.nion] = nbase + (long)q * N;
+            F.ion_mu[F.nion] = var_idx[q] >= 0 ? B->mu.p + (long)var_idx[q] * N : nullptr;
+            F.ion_mu_c[F.nion] = mu_c[q];
+            F.nion++;
+        }
+    };
     const bool want_info = info != nullptr;
     hipEvent_t ev[6];
     if (want_info) for (auto &e : ev) VD_HIP(hipEventCreate(&e));
@@ -167,12 +252,12 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         auto ih = ctx->cache.find("phi_history");
         if (ih != ctx->cache.end()) H = std::static_pointer_cast<PhiHistory>(ih->second);
         else { H = std::make_shared<PhiHistory>(); ctx->cache["phi_history"] = H; }
-        if (H->phi != st->phi || H->nx != g.nx || H->ny != g.ny || H->nz != g.nz || H->dt != P->dt) {
+        if (H->phi != st->phi || H->nx != g.nx || H->ny != g.ny || H->nz != g.nz || H->dt != dt) {
             H->count = -1;
             H->newest = 0;
             H->phi = st->phi;
             H->nx = g.nx; H->ny = g.ny; H->nz = g.nz;
-            H->dt = P->dt;
+            H->dt = dt;
         }
         if (H->count < 0) {
             H->count = 0;
@@ -194,13 +279,13 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         else { SH = std::make_shared<SpeciesHistory>(); ctx->cache["species_history"] = SH; }
         uint32_t tmask = 0;
         for (int k = 0; k < S; k++) if (P->species[k].transported) tmask |= 1u << k;
-        if (SH->n != st->n || SH->nx != g.nx || SH->ny != g.ny || SH->nz != g.nz || SH->S != S || SH->dt != P->dt ||
+        if (SH->n != st->n || SH->nx != g.nx || SH->ny != g.ny || SH->nz != g.nz || SH->S != S || SH->dt != dt ||
             SH->transported != tmask) {
             SH->count = -1;
             SH->newest = 0;
             SH->n = st->n;
             SH->nx = g.nx; SH->ny = g.ny; SH->nz = g.nz; SH->S = S;
-            SH->dt = P->dt;
+            SH->dt = dt;
             SH->transported = tmask;
         }
         sopt.guess = VD_GUESS_GIVEN;
@@ -222,6 +307,25 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         ra.ncell = N; ra.S = S; ra.qe = P->consts.qe; ra.n = nst; ra.rho = B->rho.p;
         for (int k = 0; k < S; k++) ra.Z[k] = P->species[k].Z;
         launch_rho(ctx, ra);
+        // surface charge over the adjacent cells' width (mid-point value)
+        auto sigma_args = [&](int f, const double *nbase) {
+            SigmaArgs sa;
+            memset(&sa, 0, sizeof(sa));
+            sa.g = G; sa.phi = st->phi; sa.Te = st->Te; sa.S = S;
+            for (int k = 0; k < S; k++) sa.Z[k] = P->species[k].Z;
+            sa.Tg = P->Tg; sa.kB = P->consts.kB; sa.me = P->consts.me; sa.qe = P->consts.qe; sa.dt = dt;
+            sa.h = f < 2 ? g.dx : (f < 4 ? g.dy : g.dz);
+            sa.face = f;
+            sa.na = f < 2 ? g.ny : g.nx;
+            sa.nb = f < 4 ? g.nz : g.ny;
+            sa.mid = m > 0;
+            sa.off = sig_off[f];
+            sa.sigma = P->sigma; sa.sig0 = B->sig0.p; sa.rho = B->rho.p;
+            (void)nbase;
+            return sa;
+        };
+        for (int f = 0; f < 6; f++)
+            if (P->diel[f]) launch_sigma(ctx, sigma_args(f, nst), 0);
         vd_problem pp;
         memset(&pp, 0, sizeof(pp));
         pp.grid = g; pp.bc = P->phi_bc; pp.beta = P->eps_cell; pp.beta_c = P->consts.eps0;
@@ -253,7 +357,27 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         rc.ncell = N; rc.mech = P->mech; rc.S = S; rc.n = nst; rc.Te = st->Te;
         rc.bg0 = P->mech == VD_MECH_DECAY ? P->k_decay : P->bg[0];
         rc.qe = P->consts.qe; rc.G = B->G.p; rc.S_inel = B->S_inel.p;
+        rc.ion = P->photo_n > 0 ? B->ion.p : nullptr;
         launch_react(ctx, rc);
+        // photoionization (Sec. 2.1, Eqs. (9)-(12)) into the sources
+        if (P->photo_n > 0) {
+            PhotoArgs pa;
+            memset(&pa, 0, sizeof(pa));
+            pa.ncell = N; pa.nterm = P->photo_n; pa.ion = B->ion.p; pa.rhs = B->prhs.p; pa.S = B->photo.p;
+            pa.Ge = B->G.p + (long)P->photo_e * N; pa.Gi = B->G.p + (long)P->photo_ion * N;
+            const double cem = P->photo_pq / (P->photo_p + P->photo_pq) * P->photo_xi * P->photo_nu_ratio;
+            vd_problem pr[3];
+            memset(pr, 0, sizeof(pr));
+            for (int q = 0; q < P->photo_n; q++) {
+                pa.coef[q] = P->photo_A[q] * P->photo_pg * P->photo_pg * cem;
+                const double kl = P->photo_lambda[q] * P->photo_pO2;
+                pr[q].grid = g; pr[q].bc = P->photo_bc; pr[q].alpha_c = kl * kl; pr[q].beta_c = 1.0;
+                pr[q].rhs = B->prhs.p + (long)q * N; pr[q].x = B->photo.p + (long)q * N;
+            }
+            launch_photo_rhs(ctx, pa);
+            mg_solve_batch(ctx, P->photo_n, pr, &P->photo_mg, nullptr, "photo:");
+            launch_photo_add(ctx, pa);
+        }
         if (want_info) VD_HIP(hipEventRecord(ev[2], s));
 
         // ---- electron energy
@@ -262,7 +386,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             EnergyArgs ea;
             memset(&ea, 0, sizeof(ea));
             ea.g = G; ea.phi = st->phi; ea.Te = st->Te; ea.Tg = P->Tg; ea.kB = P->consts.kB; ea.me = P->consts.me;
-            ea.qe = P->consts.qe; ea.m_bg = P->m_bg; ea.inv_dt = 1.0 / P->dt;
+            ea.qe = P->consts.qe; ea.m_bg = P->m_bg; ea.inv_dt = 1.0 / dt;
             FieldDesc fe;
             memset(&fe, 0, sizeof(fe));
             fe.u = nst + (long)e * N;
@@ -271,6 +395,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             fe.mu_scale = 1.0;
             for (int f = 0; f < 6; f++) { fe.kind[f] = P->species_bc[e].kind[f]; fe.gval[f] = P->species_bc[e].value[f]; }
             fe.wall = VD_WALL_ELECTRON; fe.mass = P->consts.me;
+            wall_variants(fe, e, nst);
             FieldDesc fE = fe;
             fE.u = Est;
             fE.mu_scale = 5.0 / 3.0;
@@ -283,7 +408,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             launch_energy(ctx, ea);
             vd_problem ep;
             memset(&ep, 0, sizeof(ep));
-            ep.grid = g; ep.bc = implicit_bc(P->energy_bc); ep.alpha_c = 1.0 / P->dt;
+            ep.grid = g; ep.bc = implicit_bc(P->energy_bc); ep.alpha_c = 1.0 / dt;
             ep.beta = var_idx[e] >= 0 ? B->beta_e.p : nullptr;
             ep.beta_c = 5.0 / 3.0 * D_c[e];
             ep.rhs = B->Erhs.p; ep.x = st->Ee;
@@ -297,7 +422,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         DriftArgs da;
         memset(&da, 0, sizeof(da));
         da.g = G; da.phi = st->phi; da.Te = st->Te; da.Tg = P->Tg; da.kB = P->consts.kB; da.me = P->consts.me;
-        da.inv_dt = 1.0 / P->dt; da.mode = 1;
+        da.inv_dt = 1.0 / dt; da.mode = 1;
         vd_problem sp[32];
         FieldDesc fds[32];
         memset(fds, 0, sizeof(fds));
@@ -317,15 +442,40 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             F.u0 = n_old + (long)k * N;
             F.src = B->G.p + (long)k * N;
             F.extra = P->extra_source ? P->extra_source + (long)k * N : nullptr;
+            wall_variants(F, k, nst);
             vd_problem &q = sp[nf];
             memset(&q, 0, sizeof(q));
-            q.grid = g; q.bc = implicit_bc(P->species_bc[k]); q.alpha_c = 1.0 / P->dt;
+            q.grid = g; q.bc = implicit_bc(P->species_bc[k]); q.alpha_c = 1.0 / dt;
             q.beta = var_idx[k] >= 0 ? B->D.p + (long)var_idx[k] * N : nullptr;
             q.beta_c = D_c[k];
             q.rhs = F.out; q.x = st->n + (long)k * N;
             nf++;
         }
         launch_drift(ctx, da, fds, nf, "step");
+        // surface charge (Sec. 2.1, Eq. (13)) from the wall fluxes of this
+        // mid-point state, before the species arrays are overwritten
+        if (nsig) {
+            FieldDesc all[32];
+            memset(all, 0, sizeof(all));
+            for (int k = 0; k < S; k++) {
+                FieldDesc &F = all[k];
+                F.u = nst + (long)k * N;
+                F.mu = var_idx[k] >= 0 ? B->mu.p + (long)var_idx[k] * N : nullptr;
+                F.mu_c = mu_c[k];
+                F.mu_scale = 1.0;
+                for (int f = 0; f < 6; f++) { F.kind[f] = P->species_bc[k].kind[f]; F.gval[f] = P->species_bc[k].value[f]; }
+                F.wall = P->species[k].wall_kind;
+                F.mass = P->species[k].mass_kg;
+                wall_variants(F, k, nst);
+            }
+            const FieldDesc *dall = (const FieldDesc *)upload_blob(ctx, "fields:sigma", all, sizeof(FieldDesc) * S);
+            for (int f = 0; f < 6; f++) {
+                if (!P->diel[f]) continue;
+                SigmaArgs sa = sigma_args(f, nst);
+                sa.f = dall;
+                launch_sigma(ctx, sa, 1);
+            }
+        }
         // the right-hand sides hold u^n now: the first corrector's species
         // iterates may start from the extrapolated guesses
         if (SH && m == 0) {
@@ -366,6 +516,8 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             VD_HIP(hipEventElapsedTime(&a, ev[3], ev[5])); ms_species += a;
         }
     }
+    if (P->photo_n > 0 && P->photo_out)
+        VD_HIP(hipMemcpyAsync(P->photo_out, B->photo.p, sizeof(double) * N * P->photo_n, hipMemcpyDeviceToDevice, s));
     if (energy) {
         // Te from the new electron energy and density
         TransportArgs ta;
@@ -428,6 +580,7 @@ vd_status species_flux(vd_ctx *ctx, const vd_grid *g, const vd_bc *phi_bc, const
         for (int f = 0; f < 6; f++) { F.kind[f] = sp_bc[k].kind[f]; F.gval[f] = sp_bc[k].value[f]; }
         F.wall = sp[k].wall_kind;
         F.mass = sp[k].mass_kg;
+        F.stick = 1.0;
         F.out = div + (long)k * N;
     }
     launch_drift(ctx, da, fds, S, "flux");

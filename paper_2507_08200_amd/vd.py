@@ -88,7 +88,14 @@ class StepParams(C.Structure):
                 ("species_bc", C.c_void_p), ("species", C.c_void_p), ("lfa_te", C.c_void_p),
                 ("lfa_ln_min", C.c_double), ("lfa_ln_max", C.c_double), ("lfa_n", C.c_int32),
                 ("pad1", C.c_int32), ("extra_source", C.c_void_p), ("extra_energy", C.c_void_p),
-                ("eps_cell", C.c_void_p), ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts)]
+                ("eps_cell", C.c_void_p), ("poisson", MGOpts), ("species_mg", MGOpts), ("energy_mg", MGOpts),
+                ("photo_n", C.c_int32), ("photo_e", C.c_int32), ("photo_ion", C.c_int32), ("dt_mode", C.c_int32),
+                ("photo_A", C.c_double * 3), ("photo_lambda", C.c_double * 3),
+                ("photo_pO2", C.c_double), ("photo_pg", C.c_double), ("photo_xi", C.c_double),
+                ("photo_pq", C.c_double), ("photo_p", C.c_double), ("photo_nu_ratio", C.c_double),
+                ("photo_bc", BC), ("photo_mg", MGOpts), ("photo_out", C.c_void_p),
+                ("c_adv", C.c_double), ("c_diff", C.c_double), ("c_diel", C.c_double),
+                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p)]
 
 
 class NNConfig(C.Structure):
@@ -473,10 +480,16 @@ PHYS = {"qe": 1.602176634e-19, "eps0": 8.8541878128e-12, "kB": 1.380649e-23, "me
 
 
 def step_params(cfg, species, *, consts=PHYS, lfa=None, poisson=None, species_mg=None, energy_mg=None,
-                extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0, k_decay=0.0):
+                extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0, k_decay=0.0,
+                photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None):
     """Pack a workload dict (see inputs) into vd_step_params.  Device arrays
-    (lfa table, sources) must be torch tensors; the returned object keeps
-    references to everything it points at."""
+    (lfa table, sources, sigma, photo["out"]) must be torch tensors; the
+    returned object keeps references to everything it points at.
+    photo: dict with "A", "lam" (one to three terms), "pO2", "pg", "xi",
+    "pq", "p", "nu_ratio" (default 1), "e", "ion", "bc" (default
+    homogeneous Dirichlet), "mg" (mg_opts), "out" (optional [3][cells]).
+    adaptive_dt: dict with "c_adv", "c_diff", "c_diel".  diel: six flags with
+    sigma the packed surface charge (advanced in place).  stick: [S]."""
     P = StepParams()
     P.grid = grid(cfg["grid"])
     P.dt = float(cfg["dt"])
@@ -513,5 +526,34 @@ def step_params(cfg, species, *, consts=PHYS, lfa=None, poisson=None, species_mg
     P.poisson = poisson or mg_opts()
     P.species_mg = species_mg or mg_opts()
     P.energy_mg = energy_mg or mg_opts()
+    if photo is not None:
+        A, lam = list(photo["A"]), list(photo["lam"])
+        if not 1 <= len(A) <= 3 or len(lam) != len(A):
+            raise ValueError("photoionization takes one to three terms")
+        P.photo_n = len(A)
+        for q in range(len(A)):
+            P.photo_A[q], P.photo_lambda[q] = float(A[q]), float(lam[q])
+        P.photo_pO2, P.photo_pg = float(photo["pO2"]), float(photo["pg"])
+        P.photo_xi, P.photo_pq, P.photo_p = float(photo["xi"]), float(photo["pq"]), float(photo["p"])
+        P.photo_nu_ratio = float(photo.get("nu_ratio", 1.0))
+        P.photo_e, P.photo_ion = int(photo["e"]), int(photo["ion"])
+        P.photo_bc = bc(photo.get("bc", {"kind": [0] * 6, "value": [0.0] * 6}))
+        P.photo_mg = photo.get("mg") or mg_opts()
+        if photo.get("out") is not None:
+            P.photo_out = _dptr(photo["out"], name="photo out")
+            keep.append(photo["out"])
+    if adaptive_dt is not None:
+        P.dt_mode = 1
+        P.c_adv, P.c_diff, P.c_diel = (float(adaptive_dt[k]) for k in ("c_adv", "c_diff", "c_diel"))
+    if diel is not None:
+        for f in range(6):
+            P.diel[f] = int(bool(diel[f]))
+        P.sigma = _dptr(sigma, name="sigma")
+        keep.append(sigma)
+    P.see_gamma = float(see_gamma)
+    if stick is not None:
+        st = (C.c_double * P.S)(*[float(v) for v in stick])
+        keep.append(st)
+        P.stick = C.addressof(st)
     P._keep = keep
     return P
