@@ -115,6 +115,64 @@ __device__ __forceinline__ void restrict_cell_uni(const LevDesc &F, const LevDes
     gst((T *)C.x, cc, (T)0);
 }
 
+// residual of a level with face and/or cell coefficient arrays and no mask
+// at (i, j, k): the six neighbours, the six face coefficients, the cell
+// coefficient and b are loaded from valid (wrapped or clamped) addresses
+// without branches, and the row is row_terms_fc's (the arithmetic of
+// residual_at: same faces, order and lifting), so all loads of a coarse
+// cell's eight children can be in flight together
+template <typename T>
+__device__ __forceinline__ T residual_fc(const LevDesc &F, const T *__restrict__ x, int i, int j, int k) {
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const long nxy = F.nxy;
+    auto w = [](int p, int n, bool per) { return p < 0 ? (per ? p + n : 0) : (p >= n ? (per ? p - n : n - 1) : p); };
+    const bool px = F.kind[0] == VD_BC_PERIODIC, py = F.kind[2] == VD_BC_PERIODIC, pz = F.kind[4] == VD_BC_PERIODIC;
+    const long c = i + (long)nx * j + nxy * k;
+    T nb[6], fc[6];
+    nb[0] = gld(x, w(i - 1, nx, px) + (long)nx * j + nxy * k);
+    nb[1] = gld(x, w(i + 1, nx, px) + (long)nx * j + nxy * k);
+    nb[2] = gld(x, i + (long)nx * w(j - 1, ny, py) + nxy * k);
+    nb[3] = gld(x, i + (long)nx * w(j + 1, ny, py) + nxy * k);
+    nb[4] = gld(x, i + (long)nx * j + nxy * w(k - 1, nz, pz));
+    nb[5] = gld(x, i + (long)nx * j + nxy * w(k + 1, nz, pz));
+    const T xc = gld(x, c);
+    T bv = gld((const T *)F.b, c);
+    const bool fb = F.var_beta;
+    const T *__restrict__ BX = fb ? (const T *)Coef<T>::bx(F) : x;
+    const T *__restrict__ BY = fb ? (const T *)Coef<T>::by(F) : x;
+    const T *__restrict__ BZ = fb ? (const T *)Coef<T>::bz(F) : x;
+    const T *__restrict__ AL = F.var_alpha ? (const T *)Coef<T>::al(F) : x;
+    const long fxrow = (long)(nx + 1) * (j + (long)ny * k), fyrow = (long)nx * (j + (long)(ny + 1) * k);
+    fc[0] = gld(BX, fb ? fxrow + i : c);
+    fc[1] = gld(BX, fb ? fxrow + i + 1 : c);
+    fc[2] = gld(BY, fb ? fyrow + i : c);
+    fc[3] = gld(BY, fb ? fyrow + i + nx : c);
+    fc[4] = gld(BZ, fb ? i + (long)nx * j + nxy * k : c);
+    fc[5] = gld(BZ, fb ? i + (long)nx * j + nxy * (k + 1) : c);
+    const T alv = gld(AL, c);
+    if (!fb)
+        for (int f = 0; f < 6; f++) fc[f] = (T)F.beta_c;
+    const T al = F.var_alpha ? alv : (T)F.alpha_c;
+    T dg, of;
+    double lf;
+    row_terms_fc<T>(F, i, j, k, nb, fc, al, dg, of, lf);
+    if (F.lift) bv = (T)((double)bv + lf);
+    return bv - (dg * xc - of);
+}
+
+template <typename T>
+__device__ __forceinline__ void restrict_cell_fc(const LevDesc &F, const LevDesc &C, int cc, int I, int J, int K) {
+    const T *x = (const T *)F.x;
+    T r[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) r[q] = residual_fc<T>(F, x, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2));
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) s += r[q];
+    gst((T *)C.b, cc, (T)0.125 * s);
+    gst((T *)C.x, cc, (T)0);
+}
+
 template <typename T>
 __device__ __forceinline__ void prolong_cell(const LevDesc &F, const LevDesc &C, int c, int i, int j, int k) {
     if (F.has_mask && !gld(F.mask, c)) return;
@@ -175,6 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const LevDesc *__restrict__
             int I, J, K;
             cell_ijk(C, cc, I, J, K);
             if (uni) restrict_cell_uni<T>(F, C, cc, I, J, K);
+            else if (!F.has_mask && !F.rb && !C.has_mask) restrict_cell_fc<T>(F, C, cc, I, J, K);
             else restrict_cell<T>(F, C, cc, I, J, K);
         }
     });
@@ -344,6 +403,11 @@ __device__ __forceinline__ T ld_halo(const LevDesc &L, const T *__restrict__ X, 
 
 
 
+// Zeros read in place of positions that are not cells: a load whose
+// position lies outside a non-periodic face (or past the tile) takes its
+// address here, so the loaded value needs no masking afterwards.
+__device__ double g_zero4[4];
+
 // MODE 0: one Gauss-Seidel colour pass (in place); MODE 1: FP64 residual
 // norm partials; MODE 2: same, also storing the FP32 residual and, unless
 // colour is 1, clearing the FP32 unknown (iterative refinement).  MODE 4:
@@ -352,8 +416,12 @@ __device__ __forceinline__ T ld_halo(const LevDesc &L, const T *__restrict__ X, 
 // last colour pass of a correction solve, which adds the final correction
 // pair to the FP64 unknown (d32 then holds the FP64 descriptors) instead of
 // storing it.  Software-pipelined: while plane k is computed, plane k+2's
-// pair, plane k+1's halo and plane k+1's b are in flight; the LDS tile is
-// double-buffered so one barrier per plane suffices.
+// pair, plane k+1's halo and b (and in MODE 5 its FP64 pair) are in flight;
+// the LDS tile is double-buffered so one barrier per plane suffices.  The
+// plane loop is unrolled by four, one named register set per plane of the
+// z window, so no register is copied while its load is in flight, and
+// positions that are not cells read from g_zero4 (no masking after the
+// load); the face coefficients of a plane are issued before its barrier.
 template <typename T, int MODE, bool UNIONLY = false>
 __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
                                                  int kz, int colour, double *__restrict__ partials,
@@ -392,35 +460,40 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const bool okxy = H.okp, okh = H.okh;
     const long pair_off = H.pair_off, b_off = H.b_off, h_off = H.h_off;
     const long nxy = L.nxy;
-    auto ld_pair = [&](int kk, T &a, T &b2) {
-        if constexpr (MODE == 4) {
-            a = b2 = (T)0;
-            return;
-        }
+    const T *zero = (const T *)g_zero4;
+    using PV = typename Pair<T>::V;
+    struct PT {
+        T a, b;
+    };
+    auto ld_pair = [&](int kk) -> PT {
+        if constexpr (MODE == 4) return PT{(T)0, (T)0};
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
-        const typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(X + pair_off + nxy * kw);
-        const bool ok = okxy && okz;
-        a = ok ? v.x : (T)0;
-        b2 = ok ? v.y : (T)0;
+        const T *p = (okxy && okz) ? X + (pair_off + nxy * kw) : zero;
+        const PV v = *(const VD_GAS PV *)p;
+        return PT{v.x, v.y};
     };
     auto ld_h = [&](int kk) -> T {
         if constexpr (MODE == 4) return (T)0;
         bool okz;
         const int kw = wrap_idx(kk, nz, pz, okz);
-        const T v = gld(X, h_off + nxy * kw);
-        return (okh && okz) ? v : (T)0;
+        const T *p = (okh && okz) ? X + (h_off + nxy * kw) : zero;
+        return *(const VD_GAS T *)p;
     };
-    auto ld_b = [&](int kk, T &a, T &b2) {
-        const typename Pair<T>::V v = *(const VD_GAS typename Pair<T>::V *)(B + b_off + nxy * min(kk, nz - 1));
-        const bool ok = own && kk < k1;
-        a = ok ? v.x : (T)0;
-        b2 = ok ? v.y : (T)0;
+    auto ld_b = [&](int kk) -> PT {
+        const T *p = (own && kk < k1) ? B + (b_off + nxy * kk) : zero;
+        const PV v = *(const VD_GAS PV *)p;
+        return PT{v.x, v.y};
+    };
+    // MODE 5: the FP64 unknown pair of plane kk
+    auto ld_x64 = [&](int kk) -> PairD {
+        if constexpr (MODE != 5) return PairD{};
+        const double *p = (own && kk < k1) ? (const double *)d32[id].x + (b_off + nxy * kk) : g_zero4;
+        return *(const VD_GAS PairD *)p;
     };
     const long rowoff = (long)nx * j;
     double v = 0.0, vb = 0.0;
-    // the plane loop, instantiated twice: for uniform-coefficient levels
-    // (no coefficient or mask loads inside the pipeline) and in general
+    // the plane loop, instantiated per level kind:
     // variant 1: uniform coefficients, no mask (nothing loaded inside the
     // pipeline); 2: coefficient arrays, no mask (faces and alpha of the pair
     // loaded together, from clamped addresses); 0: general
@@ -433,30 +506,15 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
     const T *__restrict__ BY = VAR == 2 && L.var_beta ? (const T *)Coef<T>::by(L) : X;
     const T *__restrict__ BZ = VAR == 2 && L.var_beta ? (const T *)Coef<T>::bz(L) : X;
     const T *__restrict__ AL = VAR == 2 && L.var_alpha ? (const T *)Coef<T>::al(L) : X;
-    T xm0, xm1, xc0, xc1, xp0, xp1;
-    ld_pair(k0 - 1, xm0, xm1);
-    ld_pair(k0, xc0, xc1);
-    ld_pair(k0 + 1, xp0, xp1);
-    T hcur = ld_h(k0);
-    T bc0, bc1;
-    ld_b(k0, bc0, bc1);
-    for (int k = k0; k < k1; k++) {
-        T *buf = xs[k & 1];
-        buf[(r + 1) * kT25W + 2 * tp + 1] = xc0;
-        buf[(r + 1) * kT25W + 2 * tp + 2] = xc1;
-        if (halo_thread) buf[hslot] = hcur;
-        // look-ahead for the next plane
-        T xq0, xq1, bn0, bn1;
-        ld_pair(k + 2, xq0, xq1);
-        const T hnext = ld_h(k + 1);
-        ld_b(k + 1, bn0, bn1);
-        PairD x64v{};
-        if constexpr (MODE == 5) x64v = *(const VD_GAS PairD *)((const double *)d32[id].x + b_off + nxy * k);
-        __syncthreads();
+    // plane k: xm, xc, xp the pairs of planes k-1, k, k+1, xq receives
+    // plane k+2; hc / bcur / qc plane k's halo element, right-hand side and
+    // (MODE 5) FP64 pair, hn / bn / qn receive plane k+1's
+    auto plane = [&](int k, const PT &xm, const PT &xc, const PT &xp, PT &xq, const T &hc, T &hn, const PT &bcur,
+                     PT &bn, const PairD &qc, PairD &qn) {
         // coefficient arrays of this plane for the pair (variant 2): all
-        // issued together from clamped addresses
+        // issued together from clamped addresses, before the barrier
         T fx0 = 0, fx1 = 0, fx2 = 0;
-        typename Pair<T>::V fyl{}, fyh{}, fzl{}, fzh{}, alp{};
+        PV fyl{}, fyh{}, fzl{}, fzh{}, alp{};
         if constexpr (VAR == 2) {
             const long fxrow = (long)(nx + 1) * (jc + (long)ny * k);
             const long fyrow = (long)nx * (jc + (long)(ny + 1) * k);
@@ -465,82 +523,100 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
             fx0 = gld(BX, fb ? fxrow + ic : pair_off);
             fx1 = gld(BX, fb ? fxrow + ic + 1 : pair_off);
             fx2 = gld(BX, fb ? fxrow + ic + 2 : pair_off);
-            fyl = *(const VD_GAS typename Pair<T>::V *)(BY + (fb ? fyrow + ic : pair_off));
-            fyh = *(const VD_GAS typename Pair<T>::V *)(BY + (fb ? fyrow + nx + ic : pair_off));
-            fzl = *(const VD_GAS typename Pair<T>::V *)(BZ + (fb ? fz + nxy * k : pair_off));
-            fzh = *(const VD_GAS typename Pair<T>::V *)(BZ + (fb ? fz + nxy * (k + 1) : pair_off));
-            alp = *(const VD_GAS typename Pair<T>::V *)(AL + (L.var_alpha ? ic + (long)nx * jc + nxy * k : pair_off));
+            fyl = *(const VD_GAS PV *)(BY + (fb ? fyrow + ic : pair_off));
+            fyh = *(const VD_GAS PV *)(BY + (fb ? fyrow + nx + ic : pair_off));
+            fzl = *(const VD_GAS PV *)(BZ + (fb ? fz + nxy * k : pair_off));
+            fzh = *(const VD_GAS PV *)(BZ + (fb ? fz + nxy * (k + 1) : pair_off));
+            alp = *(const VD_GAS PV *)(AL + (L.var_alpha ? ic + (long)nx * jc + nxy * k : pair_off));
         }
-        if (own) {
-            // colour pass: the pair is stored whole (the other cell with its
-            // unchanged value, which no other thread writes in this pass), so
-            // every cache line is written in full
-            T out0 = xc0, out1 = xc1;
+        T *buf = xs[k & 1];
+        buf[(r + 1) * kT25W + 2 * tp + 1] = xc.a;
+        buf[(r + 1) * kT25W + 2 * tp + 2] = xc.b;
+        if (halo_thread) buf[hslot] = hc;
+        // look-ahead for the next planes
+        xq = ld_pair(k + 2);
+        hn = ld_h(k + 1);
+        bn = ld_b(k + 1);
+        qn = ld_x64(k + 1);
+        __syncthreads();
+        if (!own) return;
+        // colour pass: the pair is stored whole (the other cell with its
+        // unchanged value, which no other thread writes in this pass), so
+        // every cache line is written in full
+        T out0 = xc.a, out1 = xc.b;
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const int i = ia + q;
-                if (PASS && ((i + j + k) & 1) != colour) continue;
-                const int c = i + nx * j + L.nxy * k;
-                const bool valid = VAR != 0 || !(L.has_mask && !gld(L.mask, c));
-                if (PASS && !valid) continue;
-                T nbv[6];
-                nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc0;
-                nbv[1] = q == 0 ? xc1 : buf[(r + 1) * kT25W + 2 * tp + 3];
-                nbv[2] = buf[r * kT25W + 2 * tp + 1 + q];
-                nbv[3] = buf[(r + 2) * kT25W + 2 * tp + 1 + q];
-                nbv[4] = q == 0 ? xm0 : xm1;
-                nbv[5] = q == 0 ? xp0 : xp1;
-                T dg, of;
-                T b = q == 0 ? bc0 : bc1;
-                if constexpr (VAR == 2) {
-                    T fc[6];
-                    fc[0] = q == 0 ? fx0 : fx1;
-                    fc[1] = q == 0 ? fx1 : fx2;
-                    fc[2] = q == 0 ? fyl.x : fyl.y;
-                    fc[3] = q == 0 ? fyh.x : fyh.y;
-                    fc[4] = q == 0 ? fzl.x : fzl.y;
-                    fc[5] = q == 0 ? fzh.x : fzh.y;
-                    if (!L.var_beta) for (int f = 0; f < 6; f++) fc[f] = (T)L.beta_c;
-                    const T al = L.var_alpha ? (q == 0 ? alp.x : alp.y) : (T)L.alpha_c;
-                    double lf;
-                    row_terms_fc<T>(L, i, j, k, nbv, fc, al, dg, of, lf);
-                    if (L.lift) b = (T)((double)b + lf);
-                } else {
-                    if constexpr (UNI) row_terms_uni<T>(L, i, j, k, nbv, dg, of);
-                    else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
-                    if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
-                }
-                if (PASS) {
-                    if (q == 0) out0 = (b + of) / dg;
-                    else out1 = (b + of) / dg;
-                } else {
-                    const T xv = q == 0 ? xc0 : xc1;
-                    const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
-                    v += rv * rv;
-                    if (partials_b && valid) vb += (double)b * (double)b;
-                    if (MODE == 2) {
-                        const long ce = rbE ? cell_pos(d32[id], i, j, k) : (long)c;
-                        gst(Eb, ce, (float)rv);
-                        if (colour != 1) gst(Ex, ce, 0.0f);
-                    }
-                }
+        for (int q = 0; q < 2; q++) {
+            const int i = ia + q;
+            if (PASS && ((i + j + k) & 1) != colour) continue;
+            const int c = i + nx * j + L.nxy * k;
+            const bool valid = VAR != 0 || !(L.has_mask && !gld(L.mask, c));
+            if (PASS && !valid) continue;
+            T nbv[6];
+            nbv[0] = q == 0 ? buf[(r + 1) * kT25W + 2 * tp] : xc.a;
+            nbv[1] = q == 0 ? xc.b : buf[(r + 1) * kT25W + 2 * tp + 3];
+            nbv[2] = buf[r * kT25W + 2 * tp + 1 + q];
+            nbv[3] = buf[(r + 2) * kT25W + 2 * tp + 1 + q];
+            nbv[4] = q == 0 ? xm.a : xm.b;
+            nbv[5] = q == 0 ? xp.a : xp.b;
+            T dg, of;
+            T b = q == 0 ? bcur.a : bcur.b;
+            if constexpr (VAR == 2) {
+                T fc[6];
+                fc[0] = q == 0 ? fx0 : fx1;
+                fc[1] = q == 0 ? fx1 : fx2;
+                fc[2] = q == 0 ? fyl.x : fyl.y;
+                fc[3] = q == 0 ? fyh.x : fyh.y;
+                fc[4] = q == 0 ? fzl.x : fzl.y;
+                fc[5] = q == 0 ? fzh.x : fzh.y;
+                if (!L.var_beta) for (int f = 0; f < 6; f++) fc[f] = (T)L.beta_c;
+                const T al = L.var_alpha ? (q == 0 ? alp.x : alp.y) : (T)L.alpha_c;
+                double lf;
+                row_terms_fc<T>(L, i, j, k, nbv, fc, al, dg, of, lf);
+                if (L.lift) b = (T)((double)b + lf);
+            } else {
+                if constexpr (UNI) row_terms_uni<T>(L, i, j, k, nbv, dg, of);
+                else row_terms_nb<T>(L, i, j, k, c, nbv, dg, of);
+                if (L.lift) b = (T)((double)b + (UNI ? lift_term_uni(L, i, j, k) : lift_term(L, i, j, k)));
             }
-            if (MODE == 0 || MODE == 4) {
-                typename Pair<T>::V pv;
-                pv.x = out0;
-                pv.y = out1;
-                *(VD_GAS typename Pair<T>::V *)(X + ia + rowoff + (long)L.nxy * k) = pv;
-            } else if (MODE == 5) {
-                x64v.x = x64v.x + (double)out0;
-                x64v.y = x64v.y + (double)out1;
-                *(VD_GAS PairD *)((double *)d32[id].x + ia + rowoff + (long)L.nxy * k) = x64v;
+            if (PASS) {
+                if (q == 0) out0 = (b + of) / dg;
+                else out1 = (b + of) / dg;
+            } else {
+                const T xv = q == 0 ? xc.a : xc.b;
+                const double rv = valid ? (double)(b - (dg * xv - of)) : 0.0;
+                v += rv * rv;
+                if (partials_b && valid) vb += (double)b * (double)b;
+                if (MODE == 2) {
+                    const long ce = rbE ? cell_pos(d32[id], i, j, k) : (long)c;
+                    gst(Eb, ce, (float)rv);
+                    if (colour != 1) gst(Ex, ce, 0.0f);
+                }
             }
         }
-        xm0 = xc0; xm1 = xc1;
-        xc0 = xp0; xc1 = xp1;
-        xp0 = xq0; xp1 = xq1;
-        hcur = hnext;
-        bc0 = bn0; bc1 = bn1;
+        if (MODE == 0 || MODE == 4) {
+            PV pv;
+            pv.x = out0;
+            pv.y = out1;
+            *(VD_GAS PV *)(X + ia + rowoff + (long)L.nxy * k) = pv;
+        } else if (MODE == 5) {
+            PairD x64v = qc;
+            x64v.x = x64v.x + (double)out0;
+            x64v.y = x64v.y + (double)out1;
+            *(VD_GAS PairD *)((double *)d32[id].x + ia + rowoff + (long)L.nxy * k) = x64v;
+        }
+    };
+    PT P0 = ld_pair(k0 - 1), P1 = ld_pair(k0), P2 = ld_pair(k0 + 1), P3;
+    T H0 = ld_h(k0), H1;
+    PT B0 = ld_b(k0), B1;
+    PairD Q0 = ld_x64(k0), Q1;
+    for (int k = k0; k < k1; k += 4) {
+        plane(k, P0, P1, P2, P3, H0, H1, B0, B1, Q0, Q1);
+        if (k + 1 >= k1) break;
+        plane(k + 1, P1, P2, P3, P0, H1, H0, B1, B0, Q1, Q0);
+        if (k + 2 >= k1) break;
+        plane(k + 2, P2, P3, P0, P1, H0, H1, B0, B1, Q0, Q1);
+        if (k + 3 >= k1) break;
+        plane(k + 3, P3, P0, P1, P2, H1, H0, B1, B0, Q1, Q0);
     }
     };
     if constexpr (UNIONLY) {
@@ -575,8 +651,6 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
 // MODE 1: partial sums of r^2 (and of b^2 when partials_b is given); MODE 2:
 // also r rounded to FP32 into the FP32 hierarchy's finest right-hand side
 // (either row layout) and, unless keep_e, its unknown cleared.
-__device__ double g_zero4[4];
-
 struct Pr {
     double a, b;
 };
