@@ -65,8 +65,19 @@ enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2, VD_GUESS_EXT
  * afterwards; every variant computes the same values).  VD_MG_FUSED_SWEEP:
  * use the out-of-place sweep on every tiled level without timing.  Tuning
  * results and the forced choice stay with the context's cached hierarchy of
- * that problem shape. */
-enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2, VD_MG_FUSED_SWEEP = 4 };
+ * that problem shape.  VD_MG_TUNE_NU (tolerance mode only): on the first
+ * solve of a problem shape, time solves (the faster of two) with the
+ * caller's schedule and with each V(nu_pre, nu_post) of (1,1), (2,1), (1,2),
+ * (2,2), (3,3) from the caller's starting iterates (restored after each),
+ * and keep the fastest to reach the tolerance, another than the caller's
+ * only if more than 3 % faster, for this and later solves of the shape
+ * (reported in
+ * vd_solve_info.nu_pre / nu_post; the iterates change, the stopping test
+ * does not).  When the environment variable VD_TUNE_CACHE names a file,
+ * the choice is looked up there first (key: a hash of the problem shapes,
+ * precision, levels, rtol and the solve's role) and appended after tuning,
+ * so later processes skip it.  Not with vd_poisson_solve_noalloc. */
+enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2, VD_MG_FUSED_SWEEP = 4, VD_MG_TUNE_NU = 8 };
 enum { VD_TE_FIXED = 0, VD_TE_LFA = 1, VD_TE_ENERGY = 2 };          /* electron temperature */
 enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3 };
 /* mobility models (Table A.4 with the Einstein relation):
@@ -113,10 +124,11 @@ typedef struct {
  * residual evaluations in IR mode; rel_res0 / rel_res: relative residual
  * before the first and after the last cycle; bnorm = ||b||_2; status as the
  * return code for this problem; fallback = 1 if a learned guess was
- * rejected. */
+ * rejected; nu_pre / nu_post: the smoothing schedule the solve used. */
 typedef struct {
     int32_t cycles, outer_iters, fallback, levels, status, pad;
     double rel_res, rel_res0, bnorm;
+    int32_t nu_pre, nu_post;
 } vd_solve_info;
 
 /* One Helmholtz problem (alpha - div(beta grad)) x = rhs (Sec. 3, the

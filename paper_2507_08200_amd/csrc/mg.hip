@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 
 namespace vd {
 
@@ -2443,6 +2444,7 @@ struct Solver {
     hipGraphExec_t gexec = nullptr;              // one captured cycle (VD_MG_GRAPH)
     std::string gkey;                            // options the graph was captured with
     bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
+    int nu_pre = -1, nu_post = -1;               // smoothing schedule chosen by VD_MG_TUNE_NU (-1: not tuned)
     int last_iters = 2;                          // cycles (refinement steps) the previous solve needed
     std::vector<int> use_fused;                  // per level: fused out-of-place sweeps instead of colour passes
     // timed launches of the current solve, credited with the algorithmic
@@ -3448,6 +3450,106 @@ static void autotune(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *probs,
     S.tuned = true;
 }
 
+// FNV-1a hash of a string, as the key of a persisted tuning result
+static uint64_t fnv1a(const std::string &k) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : k) { h ^= c; h *= 1099511628211ull; }
+    return h;
+}
+
+static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
+                               const char *cache_tag, bool check_guess, bool noalloc);
+
+// VD_MG_TUNE_NU: the smoothing schedule that reaches the tolerance fastest
+// from the caller's starting iterates (which are restored), looked up in
+// and appended to the file named by VD_TUNE_CACHE when it is set.
+static void tune_nu(vd_ctx *ctx, Solver &S, int nprob, const vd_problem *probs, const vd_mg_opts *o, const char *tag) {
+    char kbuf[96];
+    snprintf(kbuf, sizeof kbuf, ":%s:%.6e:%d", tag ? tag : "", o->rtol, o->ir_inner);
+    const std::string key = shape_key(nprob, probs, o) + kbuf;
+    char hkey[24];
+    snprintf(hkey, sizeof hkey, "%016llx", (unsigned long long)fnv1a(key));
+    const char *path = getenv("VD_TUNE_CACHE");
+    if (path && *path) {
+        if (FILE *f = fopen(path, "r")) {
+            char line[128], h[32];
+            int a, b;
+            while (fgets(line, sizeof line, f))
+                if (sscanf(line, "vdnu %31s %d %d", h, &a, &b) == 3 && !strcmp(h, hkey) && a >= 0 && b >= 0 && a + b > 0) {
+                    S.nu_pre = a;
+                    S.nu_post = b;
+                }
+            fclose(f);
+            if (S.nu_pre >= 0) return;
+        }
+    }
+    hipStream_t s = ctx->stream;
+    long total = 0;
+    for (int p = 0; p < nprob; p++) total += (long)probs[p].grid.nx * probs[p].grid.ny * probs[p].grid.nz;
+    DevBuf<double> save;
+    save.alloc(total);
+    auto copy_x = [&](bool to_save) {
+        long off = 0;
+        for (int p = 0; p < nprob; p++) {
+            const long n = (long)probs[p].grid.nx * probs[p].grid.ny * probs[p].grid.nz;
+            if (to_save) VD_HIP(hipMemcpyAsync(save.p + off, probs[p].x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            else VD_HIP(hipMemcpyAsync(probs[p].x, save.p + off, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            off += n;
+        }
+    };
+    copy_x(true);
+    hipEvent_t e0, e1;
+    VD_HIP(hipEventCreate(&e0));
+    VD_HIP(hipEventCreate(&e1));
+    // the faster of two solves with schedule (a, b) from the saved start;
+    // a negative time if it does not reach the tolerance within max_cycles
+    auto time_schedule = [&](int a, int b) -> float {
+        vd_mg_opts oc = *o;
+        oc.nu_pre = a;
+        oc.nu_post = b;
+        oc.flags &= ~VD_MG_TUNE_NU;
+        float best_ms = -1.0f;
+        for (int rep = 0; rep < 2; rep++) {
+            copy_x(false);
+            VD_HIP(hipEventRecord(e0, s));
+            try {
+                mg_solve_impl(ctx, nprob, probs, &oc, nullptr, tag, false, false);
+            } catch (const Error &) {
+                return -1.0f;
+            }
+            VD_HIP(hipEventRecord(e1, s));
+            VD_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            VD_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (best_ms < 0.0f || ms < best_ms) best_ms = ms;
+        }
+        return best_ms;
+    };
+    // the caller's schedule is the baseline; another replaces it only when
+    // it is more than 3 % faster
+    int bp = o->nu_pre, bq = o->nu_post;
+    const float base = time_schedule(bp, bq);
+    float best = base;
+    static const int cand[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 3}};
+    for (const auto &c : cand) {
+        if (c[0] == o->nu_pre && c[1] == o->nu_post) continue;
+        const float ms = time_schedule(c[0], c[1]);
+        if (ms < 0.0f) continue;
+        if (best < 0.0f || (ms < best && (base < 0.0f || ms < 0.97f * base))) { best = ms; bp = c[0]; bq = c[1]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    copy_x(false);
+    VD_HIP(hipStreamSynchronize(s));
+    S.nu_pre = bp;
+    S.nu_post = bq;
+    if (path && *path)
+        if (FILE *f = fopen(path, "a")) {
+            fprintf(f, "vdnu %s %d %d\n", hkey, bp, bq);
+            fclose(f);
+        }
+}
+
 // Full solve of a batch (the engine behind vd_poisson_solve,
 // vd_helmholtz_solve_batched and the implicit solves of vd_step).
 static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, const vd_mg_opts *o, vd_solve_info *infos,
@@ -3510,6 +3612,16 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
     // tuning runs smoother passes on the caller's iterate (restored after),
     // before the convergence state of this solve is initialised
     if ((o->flags & VD_MG_AUTOTUNE) && !S->tuned) autotune(ctx, *S, nprob, probs, o);
+    // the tuned smoothing schedule replaces the caller's for this shape
+    vd_mg_opts onu;
+    if ((o->flags & VD_MG_TUNE_NU) && o->fixed_cycles == 0 && !noalloc) {
+        if (S->nu_pre < 0) tune_nu(ctx, *S, nprob, probs, o, cache_tag);
+        onu = *o;
+        onu.nu_pre = S->nu_pre;
+        onu.nu_post = S->nu_post;
+        onu.flags &= ~VD_MG_TUNE_NU;
+        o = &onu;
+    }
     if ((o->flags & VD_MG_FUSED_SWEEP) && !S->tuned) {
         bool any = false;
         for (int l = 0; l < S->Lmax; l++)
@@ -3649,6 +3761,8 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
             I.rel_res0 = q.rel0;
             I.bnorm = q.bnorm;
             I.fallback = fell_back[p];
+            I.nu_pre = o->nu_pre;
+            I.nu_post = o->nu_post;
             if (q.status != VD_OK) worst = (vd_status)q.status;
         }
     } else if (!async_fixed) {
