@@ -76,8 +76,11 @@ enum { VD_GUESS_GIVEN = 0, VD_GUESS_ZERO = 1, VD_GUESS_LEARNED = 2, VD_GUESS_EXT
  * does not).  When the environment variable VD_TUNE_CACHE names a file,
  * the choice is looked up there first (key: a hash of the problem shapes,
  * precision, levels, rtol and the solve's role) and appended after tuning,
- * so later processes skip it.  Not with vd_poisson_solve_noalloc. */
-enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2, VD_MG_FUSED_SWEEP = 4, VD_MG_TUNE_NU = 8 };
+ * so later processes skip it.  Not with vd_poisson_solve_noalloc.
+ * VD_MG_PERSISTENT: the tiled colour passes run as persistent launches (a
+ * fixed grid of resident workgroups walking the level's (problem, tile)
+ * items) instead of one workgroup per tile; same values. */
+enum { VD_MG_GRAPH = 1, VD_MG_AUTOTUNE = 2, VD_MG_FUSED_SWEEP = 4, VD_MG_TUNE_NU = 8, VD_MG_PERSISTENT = 16 };
 enum { VD_TE_FIXED = 0, VD_TE_LFA = 1, VD_TE_ENERGY = 2 };          /* electron temperature */
 enum { VD_MECH_NONE = 0, VD_MECH_DECAY = 1, VD_MECH_AR3 = 2, VD_MECH_ARH2_15 = 3 };
 /* mobility models (Table A.4 with the Einstein relation):

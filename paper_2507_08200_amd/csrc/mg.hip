@@ -423,15 +423,12 @@ __device__ double g_zero4[4];
 // z window, so no register is copied while its load is in flight, and
 // positions that are not cells read from g_zero4 (no masking after the
 // load); the face coefficients of a plane are issued before its barrier.
-template <typename T, int MODE, bool UNIONLY = false>
-__global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
-                                                 int kz, int colour, double *__restrict__ partials,
-                                                 const ProbState *__restrict__ st, int check_active,
-                                                 double *__restrict__ partials_b) {
-    __shared__ T xs[2][(kT25Y + 2) * kT25W];
-    __shared__ double red[kBlock / 64];
-    const int t = xcd_tile(pl.ntiles);
-    if (t >= pl.ntiles) return;
+// one tile t of the pass (the body of k_st25 and of its persistent form)
+template <typename T, int MODE, bool UNIONLY>
+__device__ __forceinline__ void st25_tile(int t, T (*xs)[(kT25Y + 2) * kT25W], double *red, const LevDesc *__restrict__ descs,
+                                          const LevDesc *__restrict__ d32, const Plan &pl, int kz, int colour,
+                                          double *__restrict__ partials, const ProbState *__restrict__ st,
+                                          int check_active, double *__restrict__ partials_b) {
     const int d = plan_find(pl, t);
     const int id = pl.ids[d];
     const LevDesc L = descs[id];
@@ -634,6 +631,37 @@ __global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ des
             const double sb = block_sum(vb, red);
             if (tid == 0) gst(partials_b, slot, sb);
         }
+    }
+}
+
+template <typename T, int MODE, bool UNIONLY = false>
+__global__ void __launch_bounds__(kBlock) k_st25(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32, Plan pl,
+                                                 int kz, int colour, double *__restrict__ partials,
+                                                 const ProbState *__restrict__ st, int check_active,
+                                                 double *__restrict__ partials_b) {
+    __shared__ T xs[2][(kT25Y + 2) * kT25W];
+    __shared__ double red[kBlock / 64];
+    const int t = xcd_tile(pl.ntiles);
+    if (t >= pl.ntiles) return;
+    st25_tile<T, MODE, UNIONLY>(t, xs, red, descs, d32, pl, kz, colour, partials, st, check_active, partials_b);
+}
+
+// Persistent colour pass (VD_MG_PERSISTENT): a grid of resident workgroups
+// (a multiple of 8) walks the plan's (problem, tile) items; workgroup b
+// works in XCD b % 8's contiguous eighth of the tiles, striding by the
+// workgroups of its XCD; a barrier separates consecutive tiles (they reuse
+// the LDS buffers).  Every workgroup exits after its last item.
+template <typename T, bool UNIONLY>
+__global__ void __launch_bounds__(kBlock) k_st25p(const LevDesc *__restrict__ descs, Plan pl, int kz, int colour,
+                                                  const ProbState *__restrict__ st) {
+    __shared__ T xs[2][(kT25Y + 2) * kT25W];
+    __shared__ double red[kBlock / 64];
+    const int chunk = (pl.ntiles + 7) >> 3;
+    const int x = blockIdx.x & 7, per_xcd = gridDim.x >> 3;
+    const int end = min(pl.ntiles, (x + 1) * chunk);
+    for (int t = x * chunk + (int)(blockIdx.x >> 3); t < end; t += per_xcd) {
+        __syncthreads();
+        st25_tile<T, 0, UNIONLY>(t, xs, red, descs, nullptr, pl, kz, colour, nullptr, st, 1, nullptr);
     }
 }
 
@@ -2445,6 +2473,7 @@ struct Solver {
     std::string gkey;                            // options the graph was captured with
     bool tuned = false;                          // smoother tiles autotuned (VD_MG_AUTOTUNE)
     int nu_pre = -1, nu_post = -1;               // smoothing schedule chosen by VD_MG_TUNE_NU (-1: not tuned)
+    bool persistent = false;                     // colour passes in persistent launches (VD_MG_PERSISTENT)
     int last_iters = 2;                          // cycles (refinement steps) the previous solve needed
     std::vector<int> use_fused;                  // per level: fused out-of-place sweeps instead of colour passes
     // timed launches of the current solve, credited with the algorithmic
@@ -3024,6 +3053,12 @@ static void gs_pass(vd_ctx *ctx, Solver &S, int l, const LevDesc *dT, int col, i
     const LevDesc *alt = pmode == 5 ? S.d64.p : nullptr;
     const int kind = pmode == 4 ? 8 : (pmode == 5 ? 9 : 0);
     auto st25 = [&](const HPlan &q, bool uni) {
+        if (pmode == 0 && S.persistent) {
+            const int g = std::min(xcd_grid(q.ntiles), kMaxGrid);
+            if (uni) k_st25p<T, true><<<g, kBlock, 0, s>>>(dT, q.dev(), q.kz, col, S.st.p);
+            else k_st25p<T, false><<<g, kBlock, 0, s>>>(dT, q.dev(), q.kz, col, S.st.p);
+            return;
+        }
         if (uni) {
             if (pmode == 4)
                 k_st25<T, 4, true><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(dT, alt, q.dev(), q.kz, col, nullptr, S.st.p, 1, nullptr);
@@ -3308,8 +3343,8 @@ static void one_cycle(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
 // graph stays valid until the options, the tiling or the alignment change.
 static hipGraphExec_t cycle_graph(vd_ctx *ctx, Solver &S, const vd_mg_opts *o) {
     char kb[160];
-    snprintf(kb, sizeof(kb), "%d,%d,%d,%d,%.17g,%d,%d,%d", o->nu_pre, o->nu_post, o->ir_inner, o->max_cycles, o->rtol,
-             o->fixed_cycles, (int)S.aligned, (int)S.tuned);
+    snprintf(kb, sizeof(kb), "%d,%d,%d,%d,%.17g,%d,%d,%d,%d", o->nu_pre, o->nu_post, o->ir_inner, o->max_cycles, o->rtol,
+             o->fixed_cycles, (int)S.aligned, (int)S.tuned, (int)S.persistent);
     std::string gk = kb;
     for (int l = 0; l < S.Lmax; l++) gk += "," + std::to_string(S.pre25[l].kz) + (S.use_fused[l] ? "f" : "c");
     if (S.gexec && S.gkey == gk) return S.gexec;
@@ -3629,6 +3664,7 @@ static vd_status mg_solve_impl(vd_ctx *ctx, int nprob, const vd_problem *probs, 
         if (any) refresh_descs(ctx, *S, nprob, probs, o);
     }
     if (S->prec == VD_FP32_IR) set_rb(ctx, *S, o);
+    S->persistent = (o->flags & VD_MG_PERSISTENT) != 0;
     hipStream_t s = ctx->stream;
     S->recs.clear();
     S->cur_it = 0;

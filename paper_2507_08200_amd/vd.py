@@ -22,7 +22,7 @@ VD_OK, VD_EINVAL, VD_ENOMEM, VD_EHIP, VD_ENOCONV, VD_ESINGULAR = 0, -1, -2, -3, 
 BC_DIRICHLET, BC_NEUMANN, BC_WALLFLUX, BC_PERIODIC = 0, 1, 2, 3
 FP64, FP32_IR = 0, 1
 GUESS_GIVEN, GUESS_ZERO, GUESS_LEARNED, GUESS_EXTRAP = 0, 1, 2, 3
-MG_GRAPH, MG_AUTOTUNE, MG_FUSED_SWEEP, MG_TUNE_NU = 1, 2, 4, 8
+MG_GRAPH, MG_AUTOTUNE, MG_FUSED_SWEEP, MG_TUNE_NU, MG_PERSISTENT = 1, 2, 4, 8, 16
 TE_FIXED, TE_LFA, TE_ENERGY = 0, 1, 2
 MECH_NONE, MECH_DECAY, MECH_AR3, MECH_ARH2_15 = 0, 1, 2, 3
 MOB_CONST, MOB_ELECTRON_FIT, MOB_ION_N0, MOB_NEUTRAL_N0 = 0, 1, 2, 3
@@ -207,11 +207,13 @@ def bc(b):
 
 
 def mg_opts(rtol=1e-10, max_cycles=100, fixed_cycles=0, nu_pre=2, nu_post=2, n_levels=0, precision=FP64,
-            guess=GUESS_GIVEN, ir_inner=4, graph=False, autotune=False, fused_sweep=False, tune_nu=False):
+            guess=GUESS_GIVEN, ir_inner=4, graph=False, autotune=False, fused_sweep=False, tune_nu=False,
+            persistent=False):
     return MGOpts(float(rtol), int(max_cycles), int(fixed_cycles), int(nu_pre), int(nu_post), int(n_levels),
                   int(precision), int(guess), int(ir_inner),
                   (MG_GRAPH if graph else 0) | (MG_AUTOTUNE if autotune else 0) |
-                  (MG_FUSED_SWEEP if fused_sweep else 0) | (MG_TUNE_NU if tune_nu else 0))
+                  (MG_FUSED_SWEEP if fused_sweep else 0) | (MG_TUNE_NU if tune_nu else 0) |
+                  (MG_PERSISTENT if persistent else 0))
 
 
 def _info(si):

@@ -387,6 +387,35 @@ def test_graph_replay_and_autotune(ctx, V, oracle, precision):
             _pinned_compare(oracle, probs[p], host(ref[p]["x"]), i_ref[p], 1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_persistent_colour_passes_bit_identical(V, precision):
+    """Persistent colour passes (a fixed grid of workgroups walking the
+    (problem, tile) items) compute every tile as the one-workgroup-per-tile
+    launch does, and a colour pass reads only the other colour: the iterate
+    is bit-identical, with the same cycle counts, for a batch that mixes
+    uniform, variable-coefficient and masked problems, kernel by kernel and
+    under graph replay."""
+    prec = V.FP64 if precision == "fp64" else V.FP32_IR
+    probs = [I.random_helmholtz(940, (64, 48, 32), alpha_kind="const", beta_kind="const"),
+             I.random_helmholtz(941, (48, 40, 36), beta_jump=True),
+             I.random_helmholtz(942, (32, 32, 32), mask_holes=2),
+             I.random_helmholtz(943, (96, 64, 48), alpha_kind="zero", kinds=[I.BC_PERIODIC] * 4 + [I.BC_DIRICHLET] * 2)]
+    ref = [gpu_problem(p) for p in probs]
+    i_ref, st = V.Context().vd_helmholtz_solve_batched(ref, V.mg_opts(rtol=1e-10, precision=prec))
+    assert st == 0
+    for opts in (dict(persistent=True), dict(persistent=True, graph=True)):
+        ctx2 = V.Context()
+        for rep in range(3):
+            gs = [gpu_problem(p) for p in probs]
+            infos, st = ctx2.vd_helmholtz_solve_batched(gs, V.mg_opts(rtol=1e-10, precision=prec, **opts))
+            assert st == 0
+            torch.cuda.synchronize()
+            say("   persistent", precision, opts, rep, [i["cycles"] for i in infos])
+            for p in range(len(probs)):
+                assert infos[p]["cycles"] == i_ref[p]["cycles"], (opts, rep, p)
+                assert torch.equal(gs[p]["x"], ref[p]["x"]), (opts, rep, p)
+
+
 def test_ir_fused_corrections_match_cleared(ctx, V, oracle):
     """FP32 corrections that start from zero without being cleared and add
     themselves to the FP64 unknown inside their last colour pass give the
