@@ -7,12 +7,14 @@
 // stride padded to a power of two >= 8, stored as bfloat16; gradients are
 // FP32 in the same layout.  A 3x3x3 convolution is an implicit GEMM
 // (M = cells, N = output channels, K = 27 taps x input channels) on
-// v_mfma_f32_16x16x32_bf16: each wavefront owns 32 cells x up to 64 output
-// channels, K advances 32 at a time (a lane's 8 K values are 8 consecutive
-// channels of one tap: one 16-byte load), FP32 accumulation, bias and ReLU
-// fused into the store.  The input gradient is the same kernel on the FP32
-// output gradient with flipped, transposed weights; weight gradients are an
-// FP32 reduction over cells in fixed-order chunks (deterministic).
+// v_mfma_f32_16x16x32_bf16: a workgroup owns a 16 x 8 x 2 block of cells x
+// up to 64 output channels and stages the block's input halo in LDS, 16
+// channels at a time; K advances 32 at a time (a lane's 8 K values are 8
+// consecutive channels of one tap: one 16-byte LDS read), FP32
+// accumulation, bias and ReLU fused into the store.  The input gradient is
+// the same kernel on the FP32 output gradient with flipped, transposed
+// weights; weight gradients are an FP32 reduction over cells in
+// fixed-order chunks (deterministic).
 #include "vd_internal.hpp"
 
 namespace vd {
@@ -31,124 +33,359 @@ __host__ __device__ __forceinline__ u16 f2bf(float f) {
     return (u16)u;
 }
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+// the same rounding (to nearest even) by the conversion instruction
+__device__ __forceinline__ u16 f2bf_hw(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2_hw(float lo, float hi) {
+    return (uint32_t)f2bf_hw(lo) | ((uint32_t)f2bf_hw(hi) << 16);
+}
 
 constexpr int kConvWaves = 4;             // wavefronts per workgroup, 32 cells each
-constexpr int kChunk = 8192;              // cells per weight-gradient partial
-constexpr int kWgBlock = 64;              // cells staged in LDS per step of the weight gradient
 
 struct ConvArgs {
     const void *in;       // [cell][cin_s], bf16 or FP32
-    int in_f32, cin_s, lg_cin;
+    int cin_s;
     int nx, ny, nz;
-    long ncell;
-    const u16 *w;         // packed [cop][kp] bf16
-    int kp;
+    const u16 *w;         // packed [cop][nch][28][16] bf16
     const float *bias;    // [co] or null
     void *out;            // [cell][out_s], bf16 or FP32
     int out_f32, out_s, co, relu;
 };
 
-__device__ __forceinline__ bf16x8 load8(const ConvArgs &a, long cell, int c0) {
-    if (!a.in_f32) {
-        u32x4 v = gld((const u32x4 *)((const u16 *)a.in + cell * a.cin_s + c0), 0);
-        return __builtin_bit_cast(bf16x8, v);
-    }
-    const f32x4 *p = (const f32x4 *)((const float *)a.in + cell * a.cin_s + c0);
-    f32x4 lo = gld(p, 0), hi = gld(p, 1);
-    u32x4 v;
-    v[0] = (uint32_t)f2bf(lo[0]) | ((uint32_t)f2bf(lo[1]) << 16);
-    v[1] = (uint32_t)f2bf(lo[2]) | ((uint32_t)f2bf(lo[3]) << 16);
-    v[2] = (uint32_t)f2bf(hi[0]) | ((uint32_t)f2bf(hi[1]) << 16);
-    v[3] = (uint32_t)f2bf(hi[2]) | ((uint32_t)f2bf(hi[3]) << 16);
-    return __builtin_bit_cast(bf16x8, v);
-}
+// Tile of the convolution: 16 x 8 x 2 output cells (16 MFMA row blocks of
+// 16 cells along x, four per wavefront), its input halo 18 x 10 x 4 cells
+// staged in LDS 16 channels at a time (32 bytes per cell).  A K step of 32
+// covers two taps x 16 channels; 27 taps are padded to 28 (the padded tap's
+// weights are zero and its operand is read from a valid slot).
+constexpr int kTX = 16, kTY = 8, kTZ = 2;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
 
-template <int NB>
+// LDS slot (in 16-byte units) of half h (channels 8h..8h+7) of halo cell
+// c: the two halves in separate planes, so that the 16-byte reads of
+// consecutive cells are consecutive slots
+__device__ __forceinline__ int lds_slot(int c, int h) { return h * kHalo + c; }
+// halo offset of tap t (dz, dy, dx = t / 9, t / 3 % 3, t % 3)
+__host__ __device__ constexpr int tap_off(int t) { return t % 3 + kHX * ((t / 3) % 3 + kHY * (t / 9)); }
+
+// Weights of a chunk sit in LDS as [column][28 taps x 2 halves] 16-byte
+// slots with one slot of padding per column, so that the 16 columns read
+// by one K step fall in different banks.
+constexpr int kWRow = 57;
+
+template <int NB, bool IN_F32>
 __global__ void __launch_bounds__(64 * kConvWaves) k_conv(ConvArgs a) {
+    __shared__ u32x4 xs[2 * kHalo];
+    __shared__ u32x4 wl[NB * 16 * kWRow];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long vbase = ((long)blockIdx.x * kConvWaves + wave) * 32;
     const int r = lane & 15, kq = lane >> 4;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long nxy = (long)nx * ny;
-    int vi[2], vj[2], vk[2];
-    bool vok[2];
+    const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY;
+    const int bt = blockIdx.x;
+    const int x0 = (bt % ntx) * kTX, y0 = ((bt / ntx) % nty) * kTY, z0 = (bt / (ntx * nty)) * kTZ;
+    const int col0 = blockIdx.y * NB * 16;          // first output column of this workgroup
+    f32x4 acc[4][NB];
 #pragma unroll
-    for (int rb = 0; rb < 2; rb++) {
-        const long v = vbase + rb * 16 + r;
-        vok[rb] = v < a.ncell;
-        const long vv = vok[rb] ? v : 0;
-        vk[rb] = (int)(vv / nxy);
-        const long rem = vv - (long)vk[rb] * nxy;
-        vj[rb] = (int)(rem / nx);
-        vi[rb] = (int)(rem - (long)vj[rb] * nx);
-    }
-    f32x4 acc[2][NB];
+    for (int q = 0; q < 4; q++)
 #pragma unroll
-    for (int rb = 0; rb < 2; rb++)
+        for (int nb = 0; nb < NB; nb++) acc[q][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the wavefront's rows: y = 4 (wave & 1) + q, z = wave >> 1
+    const int ry = 4 * (wave & 1), rz = wave >> 1;
+    const int nch = (a.cin_s + 15) >> 4;
+    constexpr int kNT = 64 * kConvWaves;
+    constexpr int kHalf = (2 * kHalo + kNT - 1) / kNT;          // halo items per thread
+    constexpr int kWIt = (NB * 16 * 56 + kNT - 1) / kNT;        // weight items per thread
+    for (int ch = 0; ch < nch; ch++) {
+        // every load of the chunk is issued before the first LDS store
+        u32x4 hv[kHalf], wv[kWIt];
+        {
+            // item it = threadIdx + u kNT is half h = it & 1 (fixed per
+            // thread) of halo cell it >> 1, which advances by kNT / 2 cells
+            // per u: the halo coordinates are stepped, not divided
+            const int h = threadIdx.x & 1, c0 = ch * 16 + h * 8;
+            int c = threadIdx.x >> 1;
+            int hx = c % kHX, hy = (c / kHX) % kHY, hz = c / (kHX * kHY);
+            constexpr int kStep = kNT / 2, kSx = kStep % kHX, kSy = (kStep / kHX) % kHY;
+            static_assert(kStep < kHX * kHY, "halo step");
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++) acc[rb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
-    for (int k0 = kq * 8; k0 < a.kp; k0 += 32) {
-        const int tap = k0 >> a.lg_cin;
-        const int c0 = k0 & (a.cin_s - 1);
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-        bf16x8 A[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; rb++) {
-            const int ii = vi[rb] + dx - 1, jj = vj[rb] + dy - 1, kk = vk[rb] + dz - 1;
-            const bool ok = tap < 27 && vok[rb] && ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz;
-            A[rb] = ok ? load8(a, ii + nx * (jj + (long)ny * kk), c0) : zero;
-        }
-        bf16x8 B[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; nb++)
-            B[nb] = __builtin_bit_cast(bf16x8, gld((const u32x4 *)(a.w + (long)(nb * 16 + r) * a.kp + k0), 0));
-#pragma unroll
-        for (int rb = 0; rb < 2; rb++)
-#pragma unroll
-            for (int nb = 0; nb < NB; nb++)
-                acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[rb], B[nb], acc[rb][nb], 0, 0, 0);
-    }
-    // lane holds rows 4*kq .. 4*kq+3 (cells) of column r (output channel)
-#pragma unroll
-    for (int rb = 0; rb < 2; rb++)
-#pragma unroll
-        for (int nb = 0; nb < NB; nb++) {
-            const int col = nb * 16 + r;
-            if (col >= a.out_s) continue;
-            const float bv = (a.bias && col < a.co) ? gld(a.bias, col) : 0.0f;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const long v = vbase + rb * 16 + kq * 4 + e;
-                if (v >= a.ncell) continue;
-                float val = 0.0f;
-                if (col < a.co) {
-                    val = acc[rb][nb][e] + bv;
-                    if (a.relu) val = fmaxf(val, 0.0f);
+            for (int u = 0; u < kHalf; u++) {
+                const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+                hv[u] = u32x4{0u, 0u, 0u, 0u};
+                if (c < kHalo && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny && (unsigned)gz < (unsigned)nz &&
+                    c0 < a.cin_s) {
+                    const unsigned off = ((unsigned)(gz * ny + gy) * (unsigned)nx + (unsigned)gx) * (unsigned)a.cin_s + c0;
+                    if (!IN_F32) {
+                        hv[u] = gld((const u32x4 *)((const u16 *)a.in + off), 0);
+                    } else {
+                        const f32x4 *pp = (const f32x4 *)((const float *)a.in + off);
+                        const f32x4 lo = gld(pp, 0), hi = gld(pp, 1);
+                        hv[u] = u32x4{f2bf2_hw(lo[0], lo[1]), f2bf2_hw(lo[2], lo[3]), f2bf2_hw(hi[0], hi[1]),
+                                      f2bf2_hw(hi[2], hi[3])};
+                    }
                 }
-                if (a.out_f32) gst((float *)a.out, v * a.out_s + col, val);
-                else gst((u16 *)a.out, v * a.out_s + col, f2bf(val));
+                c += kStep;
+                hx += kSx;
+                hy += kSy;
+                if (hx >= kHX) { hx -= kHX; hy += 1; }
+                if (hy >= kHY) { hy -= kHY; hz += 1; }
             }
         }
+        const u32x4 *wg = (const u32x4 *)a.w;
+#pragma unroll
+        for (int u = 0; u < kWIt; u++) {
+            const int it = threadIdx.x + u * kNT;
+            const int n = it / 56, j = it - n * 56;
+            if (it < NB * 16 * 56) wv[u] = gld(wg, ((long)(col0 + n) * nch + ch) * 56 + j);
+        }
+        if (ch) __syncthreads();     // the previous chunk's reads are done
+#pragma unroll
+        for (int u = 0; u < kHalf; u++) {
+            const int it = threadIdx.x + u * kNT;
+            if (it < 2 * kHalo) xs[lds_slot(it >> 1, it & 1)] = hv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kWIt; u++) {
+            const int it = threadIdx.x + u * kNT;
+            const int n = it / 56, j = it - n * 56;
+            if (it < NB * 16 * 56) wl[n * kWRow + j] = wv[u];
+        }
+        __syncthreads();
+        // K step st: lanes kq < 2 take tap 2 st, kq >= 2 tap 2 st + 1 (tap
+        // 27 reads tap 26's slot, its weights are zero); fragments of step
+        // st + 1 are read while step st multiplies
+        const int hsel = kq >> 1;
+        const int lb = lds_slot(r + kHX * (ry + kHY * rz), kq & 1);
+        int wb[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) wb[nb] = (nb * 16 + r) * kWRow + (kq & 1) + 2 * hsel;
+        bf16x8 A[2][4], B[2][NB];
+        auto load = [&](int st, int buf) {
+            const int t0 = 2 * st, t1 = 2 * st + 1 < 27 ? 2 * st + 1 : 26;
+            const int base = lb + (hsel ? tap_off(t1) : tap_off(t0));
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) B[buf][nb] = __builtin_bit_cast(bf16x8, wl[wb[nb] + 4 * st]);
+#pragma unroll
+            for (int q = 0; q < 4; q++) A[buf][q] = __builtin_bit_cast(bf16x8, xs[base + q * kHX]);
+        };
+        load(0, 0);
+#pragma unroll
+        for (int st = 0; st < 14; st++) {
+            if (st + 1 < 14) load(st + 1, (st + 1) & 1);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++)
+                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[st & 1][q], B[st & 1][nb], acc[q][nb], 0, 0, 0);
+        }
+    }
+    // lane holds rows 4 kq .. 4 kq + 3 (cells along x) of column r (output channel)
+    const bool fullx = x0 + kTX <= nx;
+    float bv[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+        const int col = col0 + nb * 16 + r;
+        bv[nb] = (a.bias && col < a.co) ? gld(a.bias, col) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int gy = y0 + ry + q, gz = z0 + rz;
+        if (gy >= ny || gz >= nz) continue;
+        const unsigned rowc = (unsigned)(gz * ny + gy) * (unsigned)nx + (unsigned)(x0 + 4 * kq);
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) {
+            const int col = col0 + nb * 16 + r;
+            if (col >= a.out_s) continue;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (!fullx && x0 + 4 * kq + e >= nx) continue;
+                const unsigned o = (rowc + e) * (unsigned)a.out_s + col;
+                float val = 0.0f;
+                if (col < a.co) {
+                    val = acc[q][nb][e] + bv[nb];
+                    if (a.relu) val = fmaxf(val, 0.0f);
+                }
+                if (a.out_f32) gst((float *)a.out, o, val);
+                else gst((u16 *)a.out, o, f2bf_hw(val));
+            }
+        }
+    }
 }
 
-// packed bf16 weights of one convolution: forward [cop][kp] with
-// k = tap * cin_s + ci; transposed (for the input gradient) [cip16][kpT]
-// with k = tap' * cout_s + co and tap' = 26 - tap
-__global__ void k_pack(const float *__restrict__ w, int ci, int co, int cin_s, int kp, int cop, u16 *__restrict__ wf,
-                       int cout_s, int kpT, int cipT, u16 *__restrict__ wt) {
-    const long n1 = (long)cop * kp, n2 = (long)cipT * kpT;
+// The same convolution for inputs of at most 16 channels (one chunk), with
+// the workgroup marching along z: it owns a 16 x 8 column of kZS slabs of
+// two output planes, keeps four input halo planes in an LDS ring (plane k
+// of the march, z = z0 - 1 + k, in slot k % 4), stages the weights once,
+// and loads the next slab's two new planes into registers while the
+// current slab multiplies.
+constexpr int kZS = 4;
+constexpr int kPlane = kHX * kHY;                 // halo cells per plane
+
+template <int NB, bool IN_F32>
+__global__ void __launch_bounds__(64 * kConvWaves) k_conv_z(ConvArgs a) {
+    __shared__ u32x4 xs[2 * 4 * kPlane];          // [half][slot][halo cell of the plane]
+    __shared__ u32x4 wl[NB * 16 * kWRow];
+    constexpr int kNT = 64 * kConvWaves;
+    constexpr int kPIt = (2 * 2 * kPlane + kNT - 1) / kNT;   // items of two planes per thread
+    constexpr int kWIt = (NB * 16 * 56 + kNT - 1) / kNT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY;
+    const int bt = blockIdx.x;
+    const int x0 = (bt % ntx) * kTX, y0 = ((bt / ntx) % nty) * kTY, z0 = (bt / (ntx * nty)) * (2 * kZS);
+    const int col0 = blockIdx.y * NB * 16;
+    // this thread's items of a pair of planes: item it = threadIdx + u kNT,
+    // half h = it & 1, cell it >> 1 of the pair (plane it >> 1 >= kPlane)
+    const int h = threadIdx.x & 1, c0 = h * 8;
+    auto load_pair = [&](int k0, u32x4 *v) {          // planes k0, k0 + 1 of the march
+#pragma unroll
+        for (int u = 0; u < kPIt; u++) {
+            const int c = (threadIdx.x + u * kNT) >> 1;
+            const int pl = c >= kPlane ? 1 : 0, cc = c - pl * kPlane;
+            const int hx = cc % kHX, hy = cc / kHX;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 - 1 + k0 + pl;
+            v[u] = u32x4{0u, 0u, 0u, 0u};
+            if (c < 2 * kPlane && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny && (unsigned)gz < (unsigned)nz &&
+                c0 < a.cin_s) {
+                const unsigned off = ((unsigned)(gz * ny + gy) * (unsigned)nx + (unsigned)gx) * (unsigned)a.cin_s + c0;
+                if (!IN_F32) {
+                    v[u] = gld((const u32x4 *)((const u16 *)a.in + off), 0);
+                } else {
+                    const f32x4 *pp = (const f32x4 *)((const float *)a.in + off);
+                    const f32x4 lo = gld(pp, 0), hi = gld(pp, 1);
+                    v[u] = u32x4{f2bf2_hw(lo[0], lo[1]), f2bf2_hw(lo[2], lo[3]), f2bf2_hw(hi[0], hi[1]), f2bf2_hw(hi[2], hi[3])};
+                }
+            }
+        }
+    };
+    auto store_pair = [&](int k0, const u32x4 *v) {
+#pragma unroll
+        for (int u = 0; u < kPIt; u++) {
+            const int c = (threadIdx.x + u * kNT) >> 1;
+            if (c < 2 * kPlane) {
+                const int pl = c >= kPlane ? 1 : 0, cc = c - pl * kPlane;
+                xs[(h * 4 + ((k0 + pl) & 3)) * kPlane + cc] = v[u];
+            }
+        }
+    };
+    {
+        u32x4 p0[kPIt], p1[kPIt], wv[kWIt];
+        load_pair(0, p0);
+        load_pair(2, p1);
+        const u32x4 *wg = (const u32x4 *)a.w;
+#pragma unroll
+        for (int u = 0; u < kWIt; u++) {
+            const int it = threadIdx.x + u * kNT;
+            const int n = it / 56, j = it - n * 56;
+            if (it < NB * 16 * 56) wv[u] = gld(wg, (long)(col0 + n) * 56 + j);
+        }
+        store_pair(0, p0);
+        store_pair(2, p1);
+#pragma unroll
+        for (int u = 0; u < kWIt; u++) {
+            const int it = threadIdx.x + u * kNT;
+            const int n = it / 56, j = it - n * 56;
+            if (it < NB * 16 * 56) wl[n * kWRow + j] = wv[u];
+        }
+        __syncthreads();
+    }
+    const int ry = 4 * (wave & 1), rz = wave >> 1;
+    const int hsel = kq >> 1;
+    const int lxy = r + kHX * ry;                 // the lane's cell within a plane (row q adds q kHX)
+    int wb[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) wb[nb] = (nb * 16 + r) * kWRow + (kq & 1) + 2 * hsel;
+    float bv[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+        const int col = col0 + nb * 16 + r;
+        bv[nb] = (a.bias && col < a.co) ? gld(a.bias, col) : 0.0f;
+    }
+    const bool fullx = x0 + kTX <= nx;
+    for (int sl = 0; sl < kZS; sl++) {
+        const int zs = z0 + 2 * sl;                  // first output plane of the slab
+        if (zs >= nz) break;
+        u32x4 nxt[kPIt];
+        const bool more = sl + 1 < kZS && zs + 2 < nz;
+        if (more) load_pair(2 * sl + 4, nxt);
+        f32x4 acc[4][NB];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) acc[q][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // input plane of row rz, tap dz: march plane 2 sl + rz + dz, slot (2 sl + rz + dz) & 3
+        bf16x8 A[2][4], B[2][NB];
+        auto load = [&](int st, int buf) {
+            const int t0 = 2 * st, t1 = 2 * st + 1 < 27 ? 2 * st + 1 : 26;
+            const int t = hsel ? t1 : t0;
+            const int dz = hsel ? t1 / 9 : t0 / 9;
+            const int xy = hsel ? (t1 % 3 + kHX * ((t1 / 3) % 3)) : (t0 % 3 + kHX * ((t0 / 3) % 3));
+            const int base = ((kq & 1) * 4 + ((2 * sl + rz + dz) & 3)) * kPlane + lxy + xy;
+            (void)t;
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) B[buf][nb] = __builtin_bit_cast(bf16x8, wl[wb[nb] + 4 * st]);
+#pragma unroll
+            for (int q = 0; q < 4; q++) A[buf][q] = __builtin_bit_cast(bf16x8, xs[base + q * kHX]);
+        };
+        load(0, 0);
+#pragma unroll
+        for (int st = 0; st < 14; st++) {
+            if (st + 1 < 14) load(st + 1, (st + 1) & 1);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++)
+                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[st & 1][q], B[st & 1][nb], acc[q][nb], 0, 0, 0);
+        }
+        const int gz = zs + rz;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int gy = y0 + ry + q;
+            if (gy >= ny || gz >= nz) continue;
+            const unsigned rowc = (unsigned)(gz * ny + gy) * (unsigned)nx + (unsigned)(x0 + 4 * kq);
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) {
+                const int col = col0 + nb * 16 + r;
+                if (col >= a.out_s) continue;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (!fullx && x0 + 4 * kq + e >= nx) continue;
+                    const unsigned o = (rowc + e) * (unsigned)a.out_s + col;
+                    float val = 0.0f;
+                    if (col < a.co) {
+                        val = acc[q][nb][e] + bv[nb];
+                        if (a.relu) val = fmaxf(val, 0.0f);
+                    }
+                    if (a.out_f32) gst((float *)a.out, o, val);
+                    else gst((u16 *)a.out, o, f2bf_hw(val));
+                }
+            }
+        }
+        if (more) {
+            __syncthreads();                        // slots of planes 2 sl, 2 sl + 1 are free
+            store_pair(2 * sl + 4, nxt);
+            __syncthreads();
+        }
+    }
+}
+
+// packed bf16 weights of one convolution, in 16-channel chunks of the
+// input: forward [cop][nch][28][16] with element (n, q, tap, c) =
+// w[n][tap][16 q + c]; transposed (for the input gradient)
+// [cipT][nchT][28][16] with element (n, q, tap', c) = w[16 q + c][26 - tap'][n]
+__global__ void k_pack(const float *__restrict__ w, int ci, int co, int nch, int cop, u16 *__restrict__ wf, int nchT, int cipT,
+                       u16 *__restrict__ wt) {
+    const long n1 = (long)cop * nch * 448, n2 = (long)cipT * nchT * 448;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n1 + n2; q += (long)gridDim.x * blockDim.x) {
         if (q < n1) {
-            const int n = (int)(q / kp), k = (int)(q % kp);
-            const int tap = k / cin_s, c = k % cin_s;
+            const int n = (int)(q / (nch * 448)), rem = (int)(q % (nch * 448));
+            const int tap = (rem % 448) / 16, c = (rem / 448) * 16 + rem % 16;
             float v = 0.0f;
             if (n < co && c < ci && tap < 27) v = gld(w, ((long)n * 27 + tap) * ci + c);
             gst(wf, q, f2bf(v));
         } else {
             const long q2 = q - n1;
-            const int n = (int)(q2 / kpT), k = (int)(q2 % kpT);
-            const int tp = k / cout_s, c = k % cout_s;
+            const int n = (int)(q2 / (nchT * 448)), rem = (int)(q2 % (nchT * 448));
+            const int tp = (rem % 448) / 16, c = (rem / 448) * 16 + rem % 16;
             float v = 0.0f;
             if (n < ci && c < co && tp < 27) v = gld(w, ((long)c * 27 + (26 - tp)) * ci + n);
             gst(wt, q2, f2bf(v));
@@ -156,146 +393,227 @@ __global__ void k_pack(const float *__restrict__ w, int ci, int co, int cin_s, i
     }
 }
 
-// Weight and bias gradient partials: workgroup (chunk, tap) sums
-// x[cell + offset(tap)][ci] * dy[cell][co] over its chunk of cells in a fixed
-// order; the bias partial (sum of dy) comes from the tap-0 workgroups.
+// Weight and bias gradient partials on v_mfma_f32_16x16x4_f32: workgroup
+// (chunk, block pair) owns a 16 output-channel x 16 input-channel block of
+// all 27 taps (K = cells, 4 per step; a lane's operand is one value, so the
+// channels-last layouts need no transposition).  Its chunk is a run of the
+// convolution's 16 x 8 x 2 cell blocks: the output gradient of a block
+// (FP32) and the input halo (bf16) are staged in LDS, wavefront w
+// accumulates taps w, w + 4, ...; the sums run in a fixed order
+// (deterministic).  Block-pair 0 (first block of each) also sums the
+// output gradient per channel for the bias.
 struct WgArgs {
-    const u16 *x;
+    const u16 *x;         // [cell][xs] bf16, channels >= ci ignored
     int xs, ci;
-    const float *dy;
+    const float *dy;      // [cell][dys] FP32, channels >= co ignored
     int dys, co;
     int nx, ny, nz;
-    long ncell;
+    int tiles_per_chunk;
     float *part, *partb;
 };
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256) k_wgrad(WgArgs a) {
-    extern __shared__ float wlds[];
-    const int tap = blockIdx.y;
-    const long c_begin = (long)blockIdx.x * kChunk;
-    const long c_end = min(c_begin + (long)kChunk, a.ncell);
-    const int ci = a.ci, co = a.co, nout = ci * co;
-    float *xsb = wlds;                       // [kWgBlock][ci]
-    float *dyb = wlds + kWgBlock * ci;       // [kWgBlock][co]
-    float *red = dyb + kWgBlock * co;        // [256]
-    const int groups = nout >= 256 ? 1 : 256 / nout;
-    const int nq = (nout + 255) / 256;
-    const int t = threadIdx.x;
-    const int g = nout >= 256 ? 0 : t / nout;
-    const int dz = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dxo = tap % 3 - 1;
-    const long nxy = (long)a.nx * a.ny;
-    float acc[16] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.0f;
-    for (long b0 = c_begin; b0 < c_end; b0 += kWgBlock) {
-        for (int q = t; q < kWgBlock * ci; q += 256) {
-            const int vv = q / ci, c = q % ci;
-            const long v = b0 + vv;
-            float val = 0.0f;
-            if (v < c_end) {
-                const int k = (int)(v / nxy);
-                const long rem = v - (long)k * nxy;
-                const int j = (int)(rem / a.nx), i = (int)(rem - (long)j * a.nx);
-                const int ii = i + dxo, jj = j + dyo, kk = k + dz;
-                if (ii >= 0 && ii < a.nx && jj >= 0 && jj < a.ny && kk >= 0 && kk < a.nz)
-                    val = bf2f(gld(a.x, (ii + a.nx * (jj + (long)a.ny * kk)) * a.xs + c));
+    __shared__ __align__(16) float dyl[kTX * kTY * kTZ * 16];
+    __shared__ __align__(16) u16 xl[kHalo * 16];
+    __shared__ float bred[256 * 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
+    const int ntiles = ntx * nty * ntz;
+    const int ncb = (a.co + 15) / 16;
+    const int cb = blockIdx.y % ncb, ib = blockIdx.y / ncb;
+    const int t_begin = blockIdx.x * a.tiles_per_chunk;
+    const int t_end = min(t_begin + a.tiles_per_chunk, ntiles);
+    f32x4v acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) acc[i] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    float bsum[4] = {0.f, 0.f, 0.f, 0.f};     // channels cb 16 + 4 (threadIdx & 3) + m
+    for (int t = t_begin; t < t_end; t++) {
+        const int x0 = (t % ntx) * kTX, y0 = ((t / ntx) % nty) * kTY, z0 = (t / (ntx * nty)) * kTZ;
+        // every load of the block is issued before the first LDS store:
+        // the output gradient as 4-channel quads ([cell][4 quads] FP32), the
+        // input halo as 8-channel halves ([halo cell][2 halves] bf16);
+        // channels past co (ci) read as zero
+        constexpr int kDq = kTX * kTY * kTZ * 4 / 256, kXh = (2 * kHalo + 255) / 256;
+        f32x4 dq[kDq];
+        u32x4 xh[kXh];
+#pragma unroll
+        for (int u = 0; u < kDq; u++) {
+            const int e = threadIdx.x + 256 * u;
+            const int c = e >> 2, k = 4 * (e & 3);
+            const int gx = x0 + (c % kTX), gy = y0 + (c / kTX) % kTY, gz = z0 + c / (kTX * kTY);
+            dq[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (gx < nx && gy < ny && gz < nz && cb * 16 + k + 4 <= a.dys)
+                dq[u] = gld((const f32x4 *)(a.dy + (gx + nx * (gy + (long)ny * gz)) * a.dys + cb * 16 + k), 0);
+#pragma unroll
+            for (int m = 0; m < 4; m++)
+                if (cb * 16 + k + m >= a.co) dq[u][m] = 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kXh; u++) {
+            const int e = threadIdx.x + 256 * u;
+            const int c = e >> 1, k = 8 * (e & 1);
+            const int gx = x0 + (c % kHX) - 1, gy = y0 + (c / kHX) % kHY - 1, gz = z0 + c / (kHX * kHY) - 1;
+            xh[u] = u32x4{0u, 0u, 0u, 0u};
+            if (e < 2 * kHalo && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz && ib * 16 + k + 8 <= a.xs)
+                xh[u] = gld((const u32x4 *)(a.x + (gx + nx * (gy + (long)ny * gz)) * a.xs + ib * 16 + k), 0);
+#pragma unroll
+            for (int m = 0; m < 8; m++)
+                if (ib * 16 + k + m >= a.ci) xh[u][m >> 1] &= (m & 1) ? 0x0000FFFFu : 0xFFFF0000u;
+        }
+        if (t > t_begin) __syncthreads();     // the previous block's reads are done
+#pragma unroll
+        for (int u = 0; u < kDq; u++) {
+            const int e = threadIdx.x + 256 * u;
+            *(f32x4 *)&dyl[4 * e] = dq[u];
+#pragma unroll
+            for (int m = 0; m < 4; m++) bsum[m] += dq[u][m];
+        }
+#pragma unroll
+        for (int u = 0; u < kXh; u++) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < 2 * kHalo) *(u32x4 *)&xl[8 * e] = xh[u];
+        }
+        __syncthreads();
+        // K step st: the lane's cell is c = 4 st + kg, at halo position
+        // kg + (4 (st % 4) + kHX ((st / 4) % 8 + kHY (st / 32))) + tap offset
+#pragma unroll 4
+        for (int st = 0; st < kTX * kTY * kTZ / 4; st++) {
+            const float Av = dyl[(4 * st + kg) * 16 + col];
+            const int hb = kg + 4 * (st % 4) + kHX * ((st / 4) % kTY + kHY * (st / (4 * kTY)));
+            float Bv[7];
+#pragma unroll
+            for (int i = 0; i < 7; i++) {
+                const int tap = wave + 4 * i < 27 ? wave + 4 * i : 26;
+                Bv[i] = bf2f(xl[(hb + tap_off(tap)) * 16 + col]);
             }
-            lst(xsb, q, val);
-        }
-        for (int q = t; q < kWgBlock * co; q += 256) {
-            const int vv = q / co, c = q % co;
-            const long v = b0 + vv;
-            lst(dyb, q, v < c_end ? gld(a.dy, v * a.dys + c) : 0.0f);
-        }
-        __syncthreads();
-        if (nout >= 256) {
-            for (int qq = 0; qq < nq; qq++) {
-                const int o = t + 256 * qq;
-                if (o >= nout) break;
-                const int oc = o / ci, ic = o % ci;
-                float s = acc[qq];
-                for (int vv = 0; vv < kWgBlock; vv++) s += lld(xsb, vv * ci + ic) * lld(dyb, vv * co + oc);
-                acc[qq] = s;
-            }
-        } else if (t < groups * nout) {
-            const int o = t % nout, oc = o / ci, ic = o % ci;
-            float s = acc[0];
-            for (int vv = g; vv < kWgBlock; vv += groups) s += lld(xsb, vv * ci + ic) * lld(dyb, vv * co + oc);
-            acc[0] = s;
-        }
-        if (tap == 0 && t < co) {
-            float s = bacc;
-            for (int vv = 0; vv < kWgBlock; vv++) s += lld(dyb, vv * co + t);
-            bacc = s;
-        }
-        __syncthreads();
-    }
-    float *out = a.part + ((long)blockIdx.x * 27 + tap) * nout;
-    if (nout >= 256) {
-        for (int qq = 0; qq < nq; qq++) {
-            const int o = t + 256 * qq;
-            if (o < nout) gst(out, o, acc[qq]);
-        }
-    } else {
-        // fixed-order sum over the groups
-        lst(red, t, t < groups * nout ? acc[0] : 0.0f);
-        __syncthreads();
-        if (t < nout) {
-            float s = 0.0f;
-            for (int q = 0; q < groups; q++) s += lld(red, q * nout + t);
-            gst(out, t, s);
+#pragma unroll
+            for (int i = 0; i < 7; i++)
+                if (wave + 4 * i < 27) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Av, Bv[i], acc[i], 0, 0, 0);
         }
     }
-    if (tap == 0 && t < co) gst(a.partb, (long)blockIdx.x * co + t, bacc);
+    // lane holds rows 4 kg .. 4 kg + 3 (output channels) of column col (input channel)
+    const int nout = a.ci * a.co;
+    const int ic = ib * 16 + col;
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+        const int tap = wave + 4 * i;
+        if (tap >= 27 || ic >= a.ci) continue;
+        float *out = a.part + ((long)blockIdx.x * 27 + tap) * nout;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int oc = cb * 16 + 4 * kg + e;
+            if (oc < a.co) gst(out, oc * a.ci + ic, acc[i][e]);
+        }
+    }
+    if (ib == 0) {
+        // fixed-order sum over the 64 threads of each channel quad
+#pragma unroll
+        for (int m = 0; m < 4; m++) bred[threadIdx.x * 4 + m] = bsum[m];
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < 16 && cb * 16 + k < a.co) {
+            float sacc = 0.0f;
+            for (int q = 0; q < 64; q++) sacc += bred[(4 * q + (k >> 2)) * 4 + (k & 3)];
+            gst(a.partb, (long)blockIdx.x * a.co + cb * 16 + k, sacc);
+        }
+    }
 }
 
 // dW[co][tap][ci] (the flat parameter layout) and db[co] from the partials,
-// summed over chunks in order
-__global__ void k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ partb, int nchunk, int ci, int co,
-                               float *__restrict__ dw, float *__restrict__ db) {
-    const int nout = ci * co;
+// summed over chunks in a fixed order: first per group of consecutive
+// chunks (one thread per output and group), then over the groups in order
+constexpr int kRedGroups = 64;
+
+__global__ void k_wgrad_reduce1(const float *__restrict__ part, const float *__restrict__ partb, int nch, int ngrp, int ci,
+                                int co, float *__restrict__ red) {
+    const int nout = ci * co, tot = 27 * nout + co;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+    if (q >= tot) return;
+    const int c0 = (int)((long)nch * g / ngrp), c1 = (int)((long)nch * (g + 1) / ngrp);
+    float s = 0.0f;
+    if (q < 27 * nout) {
+        for (int c = c0; c < c1; c++) s += gld(part, (long)c * 27 * nout + q);
+    } else {
+        for (int c = c0; c < c1; c++) s += gld(partb, (long)c * co + (q - 27 * nout));
+    }
+    gst(red, (long)g * tot + q, s);
+}
+
+__global__ void k_wgrad_reduce2(const float *__restrict__ red, int ngrp, int ci, int co, float *__restrict__ dw,
+                                float *__restrict__ db) {
+    const int nout = ci * co, tot = 27 * nout + co;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= tot) return;
+    float s = 0.0f;
+    for (int g = 0; g < ngrp; g++) s += gld(red, (long)g * tot + q);
     if (q < 27 * nout) {
         const int tap = q / nout, o = q % nout, oc = o / ci, ic = o % ci;
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; c++) s += gld(part, ((long)c * 27 + tap) * nout + o);
         gst(dw, ((long)oc * 27 + tap) * ci + ic, s);
-    } else if (q < 27 * nout + co) {
-        const int oc = q - 27 * nout;
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; c++) s += gld(partb, (long)c * co + oc);
-        gst(db, oc, s);
+    } else {
+        gst(db, q - 27 * nout, s);
     }
 }
 
 // ---------------------------------------------------------- elementwise
-// mean of the 2x2x2 children, rounded to bf16
+// 8 bf16 <-> 8 floats
+__device__ __forceinline__ void unpack8(const u32x4 v, float *f) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        f[2 * i] = __uint_as_float(v[i] << 16);
+        f[2 * i + 1] = __uint_as_float(v[i] & 0xFFFF0000u);
+    }
+}
+__device__ __forceinline__ u32x4 pack8(const float *f) {
+    return u32x4{f2bf2_hw(f[0], f[1]), f2bf2_hw(f[2], f[3]), f2bf2_hw(f[4], f[5]), f2bf2_hw(f[6], f[7])};
+}
+
+// mean of the 2x2x2 children, rounded to bf16; one thread per coarse cell
+// and group of 8 channels
 __global__ void k_pool(const u16 *__restrict__ in, u16 *__restrict__ out, int nx, int ny, int nz, int cs) {
-    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-    const long n = (long)cx * cy * cz * cs;
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2, ng = cs >> 3;
+    const long n = (long)cx * cy * cz * ng;
+    const u32x4 *src = (const u32x4 *)in;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % cs);
-        const long v = q / cs;
+        const int gq = (int)(q % ng);
+        const long v = q / ng;
         const int I = (int)(v % cx), J = (int)((v / cx) % cy), K = (int)(v / ((long)cx * cy));
-        float s = 0.0f;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int kk = 0; kk < 2; kk++)
             for (int jj = 0; jj < 2; jj++)
-                for (int ii = 0; ii < 2; ii++)
-                    s += bf2f(gld(in, ((2 * I + ii) + nx * ((2 * J + jj) + (long)ny * (2 * K + kk))) * cs + c));
-        gst(out, q, f2bf(s * 0.125f));
+                for (int ii = 0; ii < 2; ii++) {
+                    float f[8];
+                    unpack8(gld(src, ((2 * I + ii) + nx * ((2 * J + jj) + (long)ny * (2 * K + kk))) * ng + gq), f);
+#pragma unroll
+                    for (int c = 0; c < 8; c++) s[c] += f[c];
+                }
+#pragma unroll
+        for (int c = 0; c < 8; c++) s[c] *= 0.125f;
+        gst((u32x4 *)out, q, pack8(s));
     }
 }
 
-// s = upsample(t) + e (nearest), rounded to bf16
+// s = upsample(t) + e (nearest), rounded to bf16; one thread per cell and
+// group of 8 channels
 __global__ void k_upadd(const u16 *__restrict__ t, const u16 *__restrict__ e, u16 *__restrict__ s, int nx, int ny, int nz,
                         int cs) {
-    const long n = (long)nx * ny * nz * cs;
+    const int ng = cs >> 3;
+    const long n = (long)nx * ny * nz * ng;
     const int cx = nx / 2, cy = ny / 2;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % cs);
-        const long v = q / cs;
+        const int gq = (int)(q % ng);
+        const long v = q / ng;
         const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((long)nx * ny));
         const long pv = (i / 2) + cx * ((j / 2) + (long)cy * (k / 2));
-        gst(s, q, f2bf(bf2f(gld(t, pv * cs + c)) + bf2f(gld(e, q))));
+        float a[8], b[8];
+        unpack8(gld((const u32x4 *)t, pv * ng + gq), a);
+        unpack8(gld((const u32x4 *)e, q), b);
+#pragma unroll
+        for (int c = 0; c < 8; c++) a[c] += b[c];
+        gst((u32x4 *)s, q, pack8(a));
     }
 }
 
@@ -336,12 +654,22 @@ __global__ void k_pool_bwd_add(const float *__restrict__ gp, const float *__rest
     }
 }
 
-// [cell][cin] bf16 -> [cell][cs] bf16 with zero channels
+// [cell][cin] bf16 -> [cell][cs] bf16 with zero channels; one thread per
+// cell and group of 8 channels
 __global__ void k_in_pad(const u16 *__restrict__ in, int cin, u16 *__restrict__ out, int cs, long ncell) {
-    const long n = ncell * cs;
+    const int ng = cs >> 3;
+    const long n = ncell * ng;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % cs);
-        gst(out, q, c < cin ? gld(in, (q / cs) * cin + c) : (u16)0);
+        const int gq = (int)(q % ng);
+        const long v = q / ng;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const int cc = gq * 8 + c;
+            const uint32_t h = cc < cin ? (uint32_t)gld(in, v * cin + cc) : 0u;
+            w[c >> 1] |= h << (16 * (c & 1));
+        }
+        gst((u32x4 *)out, q, u32x4{w[0], w[1], w[2], w[3]});
     }
 }
 
@@ -402,10 +730,42 @@ static int lg2(int p) {
 }
 static int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 8192); }
 
+// cell blocks per weight-gradient chunk: enough workgroups to fill the
+// chip (>= 2048 with the block pairs), at most 16 blocks per chunk
+static int wgrad_tpc(int ntiles, int pairs) {
+    int tpc = 16;
+    while (tpc > 1 && (long)((ntiles + tpc - 1) / tpc) * pairs < 2048) tpc /= 2;
+    return tpc;
+}
+static int conv_tiles(int nx, int ny, int nz) {
+    return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kTZ - 1) / kTZ);
+}
+// weight-gradient chunks of a ci -> co convolution on an nx x ny x nz grid
+static int wgrad_chunks(int ci, int co, int nx, int ny, int nz) {
+    const int nt = conv_tiles(nx, ny, nz), pairs = ((co + 15) / 16) * ((ci + 15) / 16);
+    const int tpc = wgrad_tpc(nt, pairs);
+    return (nt + tpc - 1) / tpc;
+}
+
+
 struct Conv {
-    int ci, co, cis, cos, kp, cop, kpT, cipT;
+    int ci, co, cis, cos, nch, cop, nchT, cipT;
     long woff, boff;
     DevBuf<u16> wf, wt;
+    void init(int ci_, int co_) {
+        ci = ci_; co = co_;
+        cis = pow2pad(ci); cos = pow2pad(co);
+        nch = (cis + 15) / 16;
+        cop = std::max((co + 15) / 16 * 16, cos);
+        nchT = (cos + 15) / 16;
+        cipT = std::max((ci + 15) / 16 * 16, cis);
+        wf.alloc((size_t)cop * nch * 448);
+        wt.alloc((size_t)cipT * nchT * 448);
+    }
+    void pack(const float *w, hipStream_t s) {
+        k_pack<<<grid_for((long)cop * nch * 448 + (long)cipT * nchT * 448), 256, 0, s>>>(w, ci, co, nch, cop, wf.p, nchT, cipT,
+                                                                                         wt.p);
+    }
 };
 
 struct Level {
@@ -427,7 +787,7 @@ struct Net {
     int gx = 0, gy = 0, gz = 0;          // grid the activations are sized for
     std::vector<Level> lv;
     DevBuf<float> out, gout;
-    DevBuf<float> part, partb;
+    DevBuf<float> part, partb, red;
     DevBuf<double> mse_part;
     double *pin_loss = nullptr;
     DevBuf<u16> feat;
@@ -496,23 +856,30 @@ static void size_for_grid(vd_ctx *ctx, Net &N, int nx, int ny, int nz) {
     N.out.alloc(n0);
     N.gout.alloc((size_t)n0 * 8);
     N.feat.alloc((size_t)n0 * 2);
+    // gradient partials: the largest need over the convolutions, each at
+    // the level it runs on (the up-convolution of level l on level l + 1)
     long pmax = 0, pbmax = 0;
-    for (auto &c : N.convs) {
-        // the weight gradient of a convolution runs at the resolution of its input
-        pmax = std::max(pmax, (long)c.ci * c.co * 27);
-        pbmax = std::max(pbmax, (long)c.co);
-    }
-    const long nch = (n0 + kChunk - 1) / kChunk;
-    N.part.alloc((size_t)nch * pmax);
-    N.partb.alloc((size_t)nch * pbmax);
+    auto need = [&](int idx, int l) {
+        const Conv &c = N.convs[idx];
+        const Level &V = N.lv[l];
+        const long nc = wgrad_chunks(c.ci, c.co, V.nx, V.ny, V.nz);
+        pmax = std::max(pmax, nc * 27 * c.ci * c.co);
+        pbmax = std::max(pbmax, nc * c.co);
+    };
+    for (int l = 0; l < L; l++) { need(N.enc_a[l], l); need(N.enc_b[l], l); }
+    for (int l = L - 2; l >= 0; l--) { need(N.up[l], l + 1); need(N.dec[l], l); }
+    need(N.out_conv, 0);
+    N.part.alloc((size_t)pmax);
+    N.partb.alloc((size_t)pbmax);
+    long rmax = 0;
+    for (auto &c : N.convs) rmax = std::max(rmax, (long)kRedGroups * (27L * c.ci * c.co + c.co));
+    N.red.alloc((size_t)rmax);
     N.mse_part.alloc(grid_for(n0));
     N.gx = nx; N.gy = ny; N.gz = nz;
 }
 
 static void pack_all(vd_ctx *ctx, Net &N) {
-    for (auto &c : N.convs)
-        k_pack<<<grid_for((long)c.cop * c.kp + (long)c.cipT * c.kpT), 256, 0, ctx->stream>>>(
-            N.params.p + c.woff, c.ci, c.co, c.cis, c.kp, c.cop, c.wf.p, c.cos, c.kpT, c.cipT, c.wt.p);
+    for (auto &c : N.convs) c.pack(N.params.p + c.woff, ctx->stream);
     VD_HIP(hipGetLastError());
     N.packed = true;
 }
@@ -522,28 +889,41 @@ static void pack_all(vd_ctx *ctx, Net &N) {
 static void run_conv(vd_ctx *ctx, Net &N, const Conv &c, const Level &V, const void *in, bool in_f32, void *out, bool out_f32,
                      int out_s, bool relu, bool transposed) {
     ConvArgs a;
-    a.in = in; a.in_f32 = in_f32 ? 1 : 0;
+    a.in = in;
     a.cin_s = transposed ? c.cos : c.cis;
-    a.lg_cin = lg2(a.cin_s);
-    a.nx = V.nx; a.ny = V.ny; a.nz = V.nz; a.ncell = V.n;
+    a.nx = V.nx; a.ny = V.ny; a.nz = V.nz;
     a.w = transposed ? c.wt.p : c.wf.p;
-    a.kp = transposed ? c.kpT : c.kp;
     a.bias = transposed ? nullptr : N.params.p + c.boff;
     a.out = out; a.out_f32 = out_f32 ? 1 : 0; a.out_s = out_s;
     a.co = transposed ? c.ci : c.co;
     a.relu = relu ? 1 : 0;
     const int cop = transposed ? c.cipT : c.cop;
-    const int nb = cop / 16;
-    const long nblk = (V.n + 32 * kConvWaves - 1) / (32 * kConvWaves);
-    VD_CHECK(nb >= 1 && nb <= 4, "internal: conv width");
+    const int ncb = cop / 16;                      // 16-column blocks
+    const long nblk = (long)((V.nx + kTX - 1) / kTX) * ((V.ny + kTY - 1) / kTY) * ((V.nz + kTZ - 1) / kTZ);
+    VD_CHECK(ncb >= 1 && ncb <= 4 && cop % 16 == 0, "internal: conv width");
     VD_CHECK(out_s <= cop, "internal: conv output stride");
+    VD_CHECK(nblk <= 0x7fffffffL, "internal: conv grid");
+    VD_CHECK(V.n * std::max(a.cin_s, out_s) < (1L << 31), "grid too large for the convolution kernels");
+    // two column blocks per workgroup where that still leaves >= 4096
+    // workgroups, else one (coarse levels: more workgroups, each restaging
+    // the same input block)
+    const int nb = (ncb % 2 == 0 && nblk * (ncb / 2) >= 4096) ? 2 : 1;
+    // inputs of one 16-channel chunk march along z (kZS slabs per workgroup)
+    const long nblk_z = (long)((V.nx + kTX - 1) / kTX) * ((V.ny + kTY - 1) / kTY) * ((V.nz + 2 * kZS - 1) / (2 * kZS));
+    const bool march = a.cin_s <= 16 && nblk_z * (ncb / nb) >= 1024;
+    const dim3 grid((unsigned)(march ? nblk_z : nblk), (unsigned)(ncb / nb));
     timed(ctx, "nn_conv", 0.0, [&] {
-        switch (nb) {
-        case 1: k_conv<1><<<nblk, 64 * kConvWaves, 0, ctx->stream>>>(a); break;
-        case 2: k_conv<2><<<nblk, 64 * kConvWaves, 0, ctx->stream>>>(a); break;
-        case 3: k_conv<3><<<nblk, 64 * kConvWaves, 0, ctx->stream>>>(a); break;
-        default: k_conv<4><<<nblk, 64 * kConvWaves, 0, ctx->stream>>>(a); break;
+#define VD_CONV(K_, NB_)                                                                  \
+    if (in_f32) K_<NB_, true><<<grid, 64 * kConvWaves, 0, ctx->stream>>>(a);            \
+    else K_<NB_, false><<<grid, 64 * kConvWaves, 0, ctx->stream>>>(a);
+        if (march) {
+            if (nb == 2) { VD_CONV(k_conv_z, 2) }
+            else { VD_CONV(k_conv_z, 1) }
+        } else {
+            if (nb == 2) { VD_CONV(k_conv, 2) }
+            else { VD_CONV(k_conv, 1) }
         }
+#undef VD_CONV
     });
 }
 
@@ -551,15 +931,23 @@ static void run_wgrad(vd_ctx *ctx, Net &N, const Conv &c, const Level &V, const 
     WgArgs a;
     a.x = x; a.xs = c.cis; a.ci = c.ci;
     a.dy = dy; a.dys = c.cos; a.co = c.co;
-    a.nx = V.nx; a.ny = V.ny; a.nz = V.nz; a.ncell = V.n;
+    a.nx = V.nx; a.ny = V.ny; a.nz = V.nz;
+    const int ntiles = conv_tiles(V.nx, V.ny, V.nz);
+    const int pairs = ((c.co + 15) / 16) * ((c.ci + 15) / 16);
+    a.tiles_per_chunk = wgrad_tpc(ntiles, pairs);
+    const int nch = (ntiles + a.tiles_per_chunk - 1) / a.tiles_per_chunk;
+    VD_CHECK(nch == wgrad_chunks(c.ci, c.co, V.nx, V.ny, V.nz), "internal: gradient chunks");
+    VD_CHECK((size_t)nch * 27 * c.ci * c.co <= N.part.n && (size_t)nch * c.co <= N.partb.n, "internal: gradient partials");
     a.part = N.part.p; a.partb = N.partb.p;
-    const int nch = (int)((V.n + kChunk - 1) / kChunk);
-    const size_t lds = sizeof(float) * ((size_t)kWgBlock * (c.ci + c.co) + 256);
+    const int tot = 27 * c.ci * c.co + c.co;
+    const int ngrp = std::min(kRedGroups, nch);
+    VD_CHECK((size_t)ngrp * tot <= N.red.n, "internal: gradient reduction buffer");
     timed(ctx, "nn_wgrad", 0.0, [&] {
-        k_wgrad<<<dim3(nch, 27), 256, lds, ctx->stream>>>(a);
-        const int tot = 27 * c.ci * c.co + c.co;
-        k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, ctx->stream>>>(N.part.p, N.partb.p, nch, c.ci, c.co, N.grads.p + c.woff,
-                                                                  N.grads.p + c.boff);
+        k_wgrad<<<dim3(nch, pairs), 256, 0, ctx->stream>>>(a);
+        k_wgrad_reduce1<<<dim3((tot + 255) / 256, ngrp), 256, 0, ctx->stream>>>(N.part.p, N.partb.p, nch, ngrp, c.ci, c.co,
+                                                                                N.red.p);
+        k_wgrad_reduce2<<<(tot + 255) / 256, 256, 0, ctx->stream>>>(N.red.p, ngrp, c.ci, c.co, N.grads.p + c.woff,
+                                                                   N.grads.p + c.boff);
     });
 }
 
@@ -569,13 +957,13 @@ static void forward(vd_ctx *ctx, Net &N, const u16 *in_cin) {
     hipStream_t s = ctx->stream;
     Level &V0 = N.lv[0];
     const int cin_s = pow2pad(N.cfg.cin);
-    k_in_pad<<<grid_for(V0.n * cin_s), 256, 0, s>>>(in_cin, N.cfg.cin, V0.in.p, cin_s, V0.n);
+    k_in_pad<<<grid_for(V0.n * cin_s / 8), 256, 0, s>>>(in_cin, N.cfg.cin, V0.in.p, cin_s, V0.n);
     for (int l = 0; l < L; l++) {
         Level &V = N.lv[l];
         const Conv &ca = N.convs[N.enc_a[l]], &cb = N.convs[N.enc_b[l]];
         if (l > 0) {
             const Level &P = N.lv[l - 1];
-            k_pool<<<grid_for(V.n * ca.cis), 256, 0, s>>>(P.e.p, V.in.p, P.nx, P.ny, P.nz, ca.cis);
+            k_pool<<<grid_for(V.n * ca.cis / 8), 256, 0, s>>>(P.e.p, V.in.p, P.nx, P.ny, P.nz, ca.cis);
         }
         run_conv(ctx, N, ca, V, V.in.p, false, V.a.p, false, ca.cos, true, false);
         run_conv(ctx, N, cb, V, V.a.p, false, V.e.p, false, cb.cos, true, false);
@@ -585,7 +973,7 @@ static void forward(vd_ctx *ctx, Net &N, const u16 *in_cin) {
         Level &V = N.lv[l], &C = N.lv[l + 1];
         const Conv &cu = N.convs[N.up[l]], &cd = N.convs[N.dec[l]];
         run_conv(ctx, N, cu, C, d, false, C.t.p, false, cu.cos, true, false);
-        k_upadd<<<grid_for(V.n * cu.cos), 256, 0, s>>>(C.t.p, V.e.p, V.s.p, V.nx, V.ny, V.nz, cu.cos);
+        k_upadd<<<grid_for(V.n * cu.cos / 8), 256, 0, s>>>(C.t.p, V.e.p, V.s.p, V.nx, V.ny, V.nz, cu.cos);
         run_conv(ctx, N, cd, V, V.s.p, false, V.d.p, false, cd.cos, true, false);
         d = V.d.p;
     }
@@ -646,18 +1034,11 @@ vd_status nn_create(vd_ctx *ctx, const vd_nn_config *cfg, const float *params) {
     long off = 0;
     for (auto &sh : shapes) {
         Conv c;
-        c.ci = sh.first; c.co = sh.second;
-        c.cis = pow2pad(c.ci); c.cos = pow2pad(c.co);
-        c.kp = (27 * c.cis + 31) / 32 * 32;
-        c.cop = std::max((c.co + 15) / 16 * 16, c.cos);
-        c.kpT = (27 * c.cos + 31) / 32 * 32;
-        c.cipT = std::max((c.ci + 15) / 16 * 16, c.cis);
+        c.init(sh.first, sh.second);
         c.woff = off;
         off += (long)c.co * 27 * c.ci;
         c.boff = off;
         off += c.co;
-        c.wf.alloc((size_t)c.cop * c.kp);
-        c.wt.alloc((size_t)c.cipT * c.kpT);
         N->convs.push_back(std::move(c));
     }
     int q = 0;
@@ -842,29 +1223,21 @@ vd_status nn_conv3d(vd_ctx *ctx, const vd_grid *g, const uint16_t *x, int ci, co
     N.cfg.levels = 1;
     N.nparam = (long)co * 27 * ci + co;
     Conv c;
-    c.ci = ci; c.co = co;
-    c.cis = pow2pad(ci); c.cos = pow2pad(co);
-    c.kp = (27 * c.cis + 31) / 32 * 32;
-    c.cop = std::max((co + 15) / 16 * 16, c.cos);
-    c.kpT = (27 * c.cos + 31) / 32 * 32;
-    c.cipT = std::max((ci + 15) / 16 * 16, c.cis);
+    c.init(ci, co);
     c.woff = 0;
     c.boff = (long)co * 27 * ci;
-    c.wf.alloc((size_t)c.cop * c.kp);
-    c.wt.alloc((size_t)c.cipT * c.kpT);
     N.params.alloc(N.nparam);
     N.grads.alloc(N.nparam);
     hipStream_t s = ctx->stream;
     VD_HIP(hipMemcpyAsync(N.params.p, w, sizeof(float) * c.boff, hipMemcpyDeviceToDevice, s));
     if (b) VD_HIP(hipMemcpyAsync(N.params.p + c.boff, b, sizeof(float) * co, hipMemcpyDeviceToDevice, s));
     else VD_HIP(hipMemsetAsync(N.params.p + c.boff, 0, sizeof(float) * co, s));
-    k_pack<<<grid_for((long)c.cop * c.kp + (long)c.cipT * c.kpT), 256, 0, s>>>(N.params.p, ci, co, c.cis, c.kp, c.cop, c.wf.p,
-                                                                               c.cos, c.kpT, c.cipT, c.wt.p);
+    c.pack(N.params.p, s);
     Level V;
     V.nx = g->nx; V.ny = g->ny; V.nz = g->nz; V.n = n;
     DevBuf<u16> xin;
     xin.alloc((size_t)n * c.cis);
-    k_in_pad<<<grid_for(n * c.cis), 256, 0, s>>>(x, ci, xin.p, c.cis, n);
+    k_in_pad<<<grid_for(n * c.cis / 8), 256, 0, s>>>(x, ci, xin.p, c.cis, n);
     DevBuf<float> tmp;
     tmp.alloc((size_t)n * std::max(c.cos, c.cis));
     if (y) {
@@ -879,9 +1252,10 @@ vd_status nn_conv3d(vd_ctx *ctx, const vd_grid *g, const uint16_t *x, int ci, co
         VD_HIP(hipMemsetAsync(dyp.p, 0, sizeof(float) * n * c.cos, s));
         VD_HIP(hipMemcpy2DAsync(dyp.p, sizeof(float) * c.cos, dy, sizeof(float) * co, sizeof(float) * co, n,
                                 hipMemcpyDeviceToDevice, s));
-        const long nch = (n + kChunk - 1) / kChunk;
+        const long nch = wgrad_chunks(ci, co, g->nx, g->ny, g->nz);
         N.part.alloc((size_t)nch * 27 * ci * co);
         N.partb.alloc((size_t)nch * co);
+        N.red.alloc((size_t)kRedGroups * (27L * ci * co + co));
         run_wgrad(ctx, N, c, V, xin.p, dyp.p);
         run_conv(ctx, N, c, V, dyp.p, true, tmp.p, true, c.cis, false, true);
         VD_HIP(hipMemcpy2DAsync(dx, sizeof(float) * ci, tmp.p, sizeof(float) * c.cis, sizeof(float) * ci, n,
