@@ -329,7 +329,7 @@ def cfg4(seed: int = 4, count: int = 64, sizes=tuple(range(32, 161, 16))) -> lis
 
 
 # ------------------------------------------------ warm-start network inputs
-NN_CFG = {"levels": 3, "ch": [8, 16, 32], "cin": 2}
+NN_CFG = {"levels": 4, "ch": [16, 32, 64, 64], "cin": 2}
 
 
 def nn_init(seed: int, cfg: dict = NN_CFG) -> np.ndarray:

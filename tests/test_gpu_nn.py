@@ -1,6 +1,8 @@
 """Warm-start network on the GPU (bfloat16 MFMA convolutions, backward,
 Adam, learned Poisson guess) against the numpy oracle on the same seeded,
 bfloat16-rounded inputs."""
+import os
+
 import numpy as np
 import pytest
 
@@ -187,3 +189,36 @@ def test_save_load_roundtrip(ctx, tmp_path):
     ctx.vd_nn_create(CFG, None)
     assert ctx.vd_nn_load(path) == len(p)
     assert np.array_equal(ctx.vd_nn_get(0), p)
+
+
+def test_trained_network_saves_cycles_on_held_out_state(V, oracle):
+    """The stored network (4 levels, 16-64 channels, trained on solver
+    snapshots of seeded streamer runs) on a held-out run (another noise
+    seed, voltage and seed position, 20 steps in): the Poisson solve from
+    its guess reaches 1e-10 (residual recomputed by the oracle) in fewer
+    cycles than from zero, in FP64 and in FP32 refinement."""
+    from paper_2507_08200_amd import warmstart as WS
+    assert os.path.exists(WS.NET_FILE)
+    ctx = V.Context()
+    run = I.warmstart_runs(7, 1)[0]
+    d = WS.snapshots(ctx, [run], 160, 20, 20, keep_solver_inputs=True)[-1]
+    ctx.vd_nn_load(WS.NET_FILE)
+    gr, pbc, rho = d["grid"], d["bc"], d["rho"]
+    say("held-out run", run)
+    for prec in (V.FP64, V.FP32_IR):
+        phi0 = torch.zeros_like(rho)
+        i0 = ctx.vd_poisson_solve(gr, pbc, rho, phi0, beta_c=8.8541878128e-12,
+                                  opts=V.mg_opts(rtol=1e-10, precision=prec, guess=V.GUESS_ZERO))
+        phi1 = torch.zeros_like(rho)
+        i1 = ctx.vd_poisson_solve(gr, pbc, rho, phi1, beta_c=8.8541878128e-12,
+                                  opts=V.mg_opts(rtol=1e-10, precision=prec, guess=V.GUESS_LEARNED))
+        say("   precision", prec, "cycles zero", i0["cycles"], "learned", i1["cycles"], "rel0", i1["rel_res0"])
+        assert i0["status"] == 0 and i1["status"] == 0 and i1["fallback"] == 0
+        assert i1["cycles"] < i0["cycles"]
+        rh = rho.cpu().numpy()
+        prob = {"grid": gr, "bc": pbc, "alpha": None, "alpha_c": 0.0, "beta": None, "beta_c": 8.8541878128e-12,
+                "mask": None, "rhs": rh, "x0": np.zeros_like(rh)}
+        x = phi1.cpu().numpy()
+        r = oracle.residual(prob, rh, x)
+        b = oracle.residual(prob, rh, np.zeros_like(x))
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10 * (1 + 1e-6)
