@@ -3007,7 +3007,10 @@ static double plan_bytes(const Solver &S, const HPlan &pl, bool fp32, int kind, 
         // residual, the default also clears the FP32 correction
         case 4: total += 2.0 * N * 8.0 + coef; break;
         case 8: total += 1.0 * N * sT + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
-        case 9: total += 1.5 * N * sT + 16.0 * N + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
+        // last pass of a refinement step: the other colour and the updated
+        // colour's b read, the FP64 unknown read and written (the FP32
+        // correction of the updated colour is not stored)
+        case 9: total += 1.0 * N * sT + 16.0 * N + (D.var_beta ? 3.0 * N * sT : 0.0) + (D.var_alpha ? 0.5 * N * sT : 0.0) + (D.has_mask ? N : 0.0); break;
         case 10: total += 2.0 * N * 8.0 + coef + N * 4.0; break;
         default: total += 2.0 * N * 8.0 + coef + 2.0 * N * 4.0; break;
         }
