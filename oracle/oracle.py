@@ -93,7 +93,8 @@ class StepParams(C.Structure):
                 ("photo_pO2", C.c_double), ("photo_pg", C.c_double), ("photo_xi", C.c_double),
                 ("photo_pq", C.c_double), ("photo_p", C.c_double), ("photo_nu_ratio", C.c_double),
                 ("photo_bc", BC), ("photo_mg", MGOpts), ("photo_out", C.c_void_p),
-                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p)]
+                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p),
+                ("mask", C.c_void_p)]
 
 
 class StepInfo(C.Structure):
@@ -342,7 +343,7 @@ def face_flux(g, phi_bc, sp_bc, sp, u, phi, mu, D, Te, Tg, consts=PHYS):
 def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poisson=None, species_mg=None,
          energy_mg=None, extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0,
          k_decay=0.0, species_guess=None, phi_fixed=False, check_n=None, check_Ee=None, parallel=False,
-         photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None):
+         photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None, mask=None):
     """One step of the semi-implicit scheme on a workload dict (see inputs).
     species_guess ([S][cells], optional): starting iterate of the first
     corrector's species solves in place of n^n.
@@ -356,6 +357,9 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
     sigma (packed surface charge of the marked faces, see the C header):
     dielectric faces, sigma advanced and returned as "sigma".  see_gamma:
     secondary emission coefficient; stick ([S]): sticking coefficients.
+    mask ([cells] uint8, 1 valid / 0 covered): a masked step (the covered
+    cells' potentials are Dirichlet values of the Poisson solve, see the C
+    header).
     Checking a step computed elsewhere (n_t = 1): phi_fixed takes phi as the
     Poisson result (its relative residual in info["poisson_rel"]); check_n /
     check_Ee replace the species / energy solves by the relative residuals
@@ -443,6 +447,12 @@ def step(cfg, species, *, n=None, phi=None, Te=None, Ee=None, consts=PHYS, poiss
         a = _f64(stick)
         keep.append(a)
         P.stick = _ptr(a)
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mk.size != nc:
+            raise ValueError("mask has %d cells, the grid %d" % (mk.size, nc))
+        keep.append(mk)
+        P.mask = mk.ctypes.data
     info = StepInfo()
     st = lib(parallel).or_step(C.byref(P), _ptr(n), _ptr(phi), _ptr(Te), _ptr(Ee), C.byref(info))
     d = {k: getattr(info, k) for k, _ in StepInfo._fields_}

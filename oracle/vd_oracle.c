@@ -146,6 +146,17 @@ typedef struct {
     double *sigma;
     double see_gamma;
     const double *stick;
+    /* Cell mask (Sec. 3 masking paragraph; NULL = every cell valid): 1
+     * valid, 0 covered.  Every solve of the step is masked (covered cells
+     * take no part and act as Dirichlet faces for their valid
+     * neighbours); the potential stored in a covered cell is the Dirichlet
+     * value of its faces with valid cells (lifted into the Poisson
+     * right-hand side, kept through the step), the densities take the
+     * homogeneous Dirichlet value there (covered cells hold 0 after the
+     * step); the drift fluxes close the valid runs like Dirichlet domain
+     * faces (stencil5, e_face_m).  Not with periodic faces, the energy
+     * equation, photoionization, dielectric faces or the adaptive step. */
+    const uint8_t *mask;
 } or_step_params;
 
 typedef struct {
@@ -783,13 +794,28 @@ int or_cell_flags(const or_problem *P, int n_levels, int level, uint8_t *out)
 /* E along direction d at face index fidx (0..n_d) of the row through
  * (i,j,k).  Interior: -(phi_R - phi_L)/h.  Dirichlet face with value g:
  * one-sided over half a cell.  Neumann/wall: 0.  Periodic: wrapped. */
-static double e_face(const or_grid *g, const or_bc *pbc, const double *phi, int d, int i, int j, int k, int fidx)
+/* Field along d at face fidx of the row through (i,j,k).  With a cell
+ * mask (Sec. 3 masking paragraph; reading): the potential stored in a
+ * covered cell is the Dirichlet value on its faces with valid cells, so a
+ * covered-valid face takes the one-sided difference over half a cell (as a
+ * Dirichlet domain face does); a face between two covered cells carries no
+ * field. */
+static double e_face_m(const or_grid *g, const or_bc *pbc, const double *phi, const uint8_t *mask, int d, int i, int j,
+                       int k, int fidx)
 {
     int nx = g->nx, ny = g->ny;
     int n_d = d == 0 ? g->nx : (d == 1 ? g->ny : g->nz);
     double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
 #define PHI_AT(p) phi[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
-    if (fidx > 0 && fidx < n_d) return -(PHI_AT(fidx) - PHI_AT(fidx - 1)) / h;
+#define MASK_AT(p) mask[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
+    if (fidx > 0 && fidx < n_d) {
+        if (mask) {
+            int vl = MASK_AT(fidx - 1) != 0, vr = MASK_AT(fidx) != 0;
+            if (!vl && !vr) return 0.0;
+            if (vl != vr) return -(PHI_AT(fidx) - PHI_AT(fidx - 1)) / (0.5 * h);
+        }
+        return -(PHI_AT(fidx) - PHI_AT(fidx - 1)) / h;
+    }
     int f = 2 * d + (fidx == 0 ? 0 : 1);
     int kind = pbc->kind[f];
     if (kind == OR_PER) return -(PHI_AT(0) - PHI_AT(n_d - 1)) / h;
@@ -800,14 +826,26 @@ static double e_face(const or_grid *g, const or_bc *pbc, const double *phi, int 
     }
     return 0.0;
 #undef PHI_AT
+#undef MASK_AT
+}
+
+static double e_face(const or_grid *g, const or_bc *pbc, const double *phi, int d, int i, int j, int k, int fidx)
+{
+    return e_face_m(g, pbc, phi, NULL, d, i, j, k, fidx);
 }
 
 /* cell-centred field: mean of the two faces per direction */
+static void e_cell_m(const or_grid *g, const or_bc *pbc, const double *phi, const uint8_t *mask, int i, int j, int k,
+                     double E[3])
+{
+    E[0] = 0.5 * (e_face_m(g, pbc, phi, mask, 0, i, j, k, i) + e_face_m(g, pbc, phi, mask, 0, i, j, k, i + 1));
+    E[1] = 0.5 * (e_face_m(g, pbc, phi, mask, 1, i, j, k, j) + e_face_m(g, pbc, phi, mask, 1, i, j, k, j + 1));
+    E[2] = 0.5 * (e_face_m(g, pbc, phi, mask, 2, i, j, k, k) + e_face_m(g, pbc, phi, mask, 2, i, j, k, k + 1));
+}
+
 static void e_cell(const or_grid *g, const or_bc *pbc, const double *phi, int i, int j, int k, double E[3])
 {
-    E[0] = 0.5 * (e_face(g, pbc, phi, 0, i, j, k, i) + e_face(g, pbc, phi, 0, i, j, k, i + 1));
-    E[1] = 0.5 * (e_face(g, pbc, phi, 1, i, j, k, j) + e_face(g, pbc, phi, 1, i, j, k, j + 1));
-    E[2] = 0.5 * (e_face(g, pbc, phi, 2, i, j, k, k) + e_face(g, pbc, phi, 2, i, j, k, k + 1));
+    e_cell_m(g, pbc, phi, NULL, i, j, k, E);
 }
 
 int or_efield(const or_grid *g, const or_bc *pbc, const double *phi, double *ex, double *ey, double *ez, double *ecell)
@@ -957,6 +995,7 @@ typedef struct {
     const or_species *sp_all;
     const double *n_all, *mu_all;
     double stick;
+    const uint8_t *mask;  /* cell mask of a masked step, or NULL */
 } or_flux_ctx;
 
 /* Outward wall flux (Sec. 2.2) of a species with value uc in the boundary
@@ -990,6 +1029,40 @@ static double wall_flux_x(const or_flux_ctx *X, int wk, size_t cb, double uc, do
     return fl;
 }
 
+/* The five upwind values of the WENO5 stencil of face fidx (v > 0: row
+ * positions fidx-3 .. fidx+1; v < 0: fidx+2 down to fidx-2).  Without a
+ * mask: u_at.  With one (reading of the one-sided schemes at covered-valid
+ * faces, Sec. 3 masking paragraph): the nearest covered cell on each side
+ * of the face, within the stencil's reach, closes the valid run like a
+ * domain face with a homogeneous Dirichlet value: a position beyond it
+ * takes minus the value mirrored across that face, or 0 when the mirrored
+ * position is not in the run (runs narrower than three cells). */
+static void stencil5(const or_grid *g, const or_bc *ubc, const uint8_t *mask, const double *u, int d, int i, int j, int k,
+                     int fidx, int up, double s[5])
+{
+    int nx = g->nx, ny = g->ny;
+    int n_d = d == 0 ? g->nx : (d == 1 ? g->ny : g->nz);
+#define MASK_AT(p) mask[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
+#define U_AT(p) u[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
+    int lo = -1, hi = -1;   /* interior closing faces of the valid run, -1 = none within reach */
+    if (mask) {
+        for (int p = fidx - 1; p >= fidx - 3 && p >= 0; p--)
+            if (!MASK_AT(p)) { lo = p + 1; break; }
+        for (int p = fidx; p <= fidx + 2 && p < n_d; p++)
+            if (!MASK_AT(p)) { hi = p; break; }
+    }
+    for (int m = 0; m < 5; m++) {
+        int p = up ? fidx - 3 + m : fidx + 2 - m;
+        int fb = (lo >= 0 && p < lo) ? lo : ((hi >= 0 && p >= hi) ? hi : -1);
+        if (fb < 0) { s[m] = u_at(g, ubc, u, d, i, j, k, p); continue; }
+        int q = 2 * fb - 1 - p;
+        int inrun = q >= 0 && q < n_d && (lo < 0 || q >= lo) && (hi < 0 || q < hi) && MASK_AT(q);
+        s[m] = inrun ? -U_AT(q) : 0.0;
+    }
+#undef MASK_AT
+#undef U_AT
+}
+
 /* Drift flux along +d (species continuity, Eq. (2), drift part) through
  * face fidx (0..n_d) of the row through (i,j,k), for field u with signed
  * cell mobility mu[]: face velocity v = mu_f E_f with mu_f the arithmetic
@@ -1010,7 +1083,16 @@ static double drift_face_flux(const or_flux_ctx *X, const or_bc *ubc, const doub
     int boundary = (fidx == 0 || fidx == n_d);
     int kind = ubc->kind[boundary ? (fidx == 0 ? 2 * d : 2 * d + 1) : 2 * d + (fidx - pos)];
     if (boundary && kind == OR_NEU) return 0.0;
-    double Ef = e_face(g, X->phi_bc, X->phi, d, i, j, k, fidx);
+    /* masked step: validity of the face's two cells (a domain face has one) */
+    int vl = 1, vr = 1;
+    if (X->mask) {
+#define MASK_AT(p) X->mask[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
+        vl = fidx > 0 ? MASK_AT(fidx - 1) != 0 : 0;
+        vr = fidx < n_d ? MASK_AT(fidx) != 0 : 0;
+#undef MASK_AT
+        if (!vl && !vr) return 0.0;
+    }
+    double Ef = e_face_m(g, X->phi_bc, X->phi, X->mask, d, i, j, k, fidx);
     if (boundary && kind == OR_WALL) {
         /* the boundary cell of this face */
         size_t cb = d == 0 ? IDX(fidx == 0 ? 0 : nx - 1, j, k, nx, ny)
@@ -1037,15 +1119,12 @@ static double drift_face_flux(const or_flux_ctx *X, const or_bc *ubc, const doub
     }
     double muf;
     if (boundary && kind != OR_PER) muf = fidx == 0 ? mur : mul;
+    else if (vl != vr) muf = vl ? mul : mur;      /* covered-valid face: the valid cell's mobility */
     else muf = 0.5 * (mul + mur);
     double v = muf * Ef;
     if (v == 0.0) return 0.0;
     double s[5];
-    if (v > 0.0) {
-        for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pl - 2 + m);
-    } else {
-        for (int m = 0; m < 5; m++) s[m] = u_at(g, ubc, u, d, i, j, k, pr + 2 - m);
-    }
+    stencil5(g, ubc, X->mask, u, d, i, j, k, fidx, v > 0.0, s);
     return v * or_weno5(s);
 }
 
@@ -1062,6 +1141,7 @@ static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const doubl
             for (int i = 0; i < nx; i++) {
                 size_t c = IDX(i, j, k, nx, ny);
                 double total = 0.0;
+                if (X->mask && !X->mask[c]) { div[c] = 0.0; continue; }   /* covered: no balance */
                 for (int d = 0; d < 3; d++) {
                     int pos = d == 0 ? i : (d == 1 ? j : k);
                     double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
@@ -1419,6 +1499,14 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     int any_diel = 0;
     for (int f = 0; f < 6; f++) any_diel = any_diel || P->diel[f];
     if (any_diel && !P->sigma) return info->status = OR_EINVAL;
+    if (P->mask) {
+        if (P->te_mode == OR_TE_ENERGY || P->photo_n > 0 || any_diel || P->dt_mode != 0 || P->phi_fixed)
+            return info->status = OR_EINVAL;
+        for (int f = 0; f < 6; f++) {
+            if (P->phi_bc.kind[f] == OR_PER) return info->status = OR_EINVAL;
+            for (int k = 0; k < S; k++) if (P->species_bc[k].kind[f] == OR_PER) return info->status = OR_EINVAL;
+        }
+    }
     const or_consts *cs = &P->c;
     double *n0 = (double *)malloc(sizeof(double) * nc * S);
     double *ns = (double *)malloc(sizeof(double) * nc * S);
@@ -1440,12 +1528,14 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     double *Sph = (double *)malloc(sizeof(double) * nc);
     size_t nsig = any_diel ? diel_offset(P, 6) : 0;
     double *sig0 = (double *)malloc(sizeof(double) * (nsig ? nsig : 1));
+    double *phic = (double *)malloc(sizeof(double) * (P->mask ? nc : 1));   /* the covered cells' potentials */
     int status = OR_OK;
     if (!n0 || !ns || !mu || !Dk || !div || !G || !rhs || !rho || !Sinel || !en || !Ee0 || !Ees || !beta || !mue || !divE ||
-        !Si || !Sj || !Sph || !sig0) {
+        !Si || !Sj || !Sph || !sig0 || !phic) {
         status = OR_ENOMEM;
         goto out;
     }
+    if (P->mask) memcpy(phic, phi, sizeof(double) * nc);
     memcpy(n0, n, sizeof(double) * nc * S);
     if (Ee) memcpy(Ee0, Ee, sizeof(double) * nc);
     if (nsig) memcpy(sig0, P->sigma, sizeof(double) * nsig);
@@ -1478,7 +1568,31 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                     rho[IDX(i, j, k, g->nx, g->ny)] += sg / h;
                 }
         }
-        or_problem PP = { *g, P->phi_bc, NULL, NULL, 0.0, P->eps_cell, cs->eps0 };
+        /* masked step: each covered neighbour of a valid cell is a
+         * Dirichlet face with the covered cell's potential g; its lifting
+         * 2 beta_f g / h^2 (beta_f the operator's face coefficient: the
+         * harmonic mean of the two cells' permittivities, or eps0) */
+        if (P->mask) {
+            for (int k = 0; k < g->nz; k++)
+                for (int j = 0; j < g->ny; j++)
+                    for (int i = 0; i < g->nx; i++) {
+                        size_t c = IDX(i, j, k, g->nx, g->ny);
+                        if (!P->mask[c]) continue;
+                        double lift = 0.0;
+                        for (int f = 0; f < 6; f++) {
+                            int d = f / 2, sd = f % 2 ? 1 : -1;
+                            int ii = i + (d == 0 ? sd : 0), jj = j + (d == 1 ? sd : 0), kk = k + (d == 2 ? sd : 0);
+                            if (ii < 0 || ii >= g->nx || jj < 0 || jj >= g->ny || kk < 0 || kk >= g->nz) continue;
+                            size_t nb = IDX(ii, jj, kk, g->nx, g->ny);
+                            if (P->mask[nb]) continue;
+                            double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
+                            double bf = P->eps_cell ? harmonic(P->eps_cell[c], P->eps_cell[nb]) : cs->eps0;
+                            lift += 2.0 * bf * phic[nb] / (h * h);
+                        }
+                        rho[c] += lift;
+                    }
+        }
+        or_problem PP = { *g, P->phi_bc, P->mask, NULL, 0.0, P->eps_cell, cs->eps0 };
         or_mg_info mi;
         int st = OR_OK;
         if (P->phi_fixed) {
@@ -1489,6 +1603,8 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             info->poisson_rel = mi.rel_res;
         }
         if (st != OR_OK) { status = st; goto out; }
+        if (P->mask)
+            for (size_t c = 0; c < nc; c++) if (!P->mask[c]) phi[c] = phic[c];
         /* E/N and Te at u* */
         OR_PAR_FOR
         for (int k = 0; k < g->nz; k++)
@@ -1496,7 +1612,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                 for (int i = 0; i < g->nx; i++) {
                     size_t c = IDX(i, j, k, g->nx, g->ny);
                     double E[3];
-                    e_cell(g, &P->phi_bc, phi, i, j, k, E);
+                    e_cell_m(g, &P->phi_bc, phi, P->mask, i, j, k, E);
                     en[c] = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]) / P->N_gas / OR_TD;
                     if (P->te_mode == OR_TE_LFA) {
                         Te[c] = or_te_lfa(P->lfa_te, P->lfa_n, P->lfa_ln_min, P->lfa_ln_max, en[c]);
@@ -1512,7 +1628,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                 transport(&P->species[k], cs, en[c], Te[c], P->Tg, P->N_gas, &mu[k * nc + c], &Dk[k * nc + c]);
         }
         /* explicit drift divergence and chemistry at u* */
-        or_flux_ctx X = { g, &P->phi_bc, phi, Te, P->Tg, cs, P->see_gamma, S, P->species, ns, mu, 1.0 };
+        or_flux_ctx X = { g, &P->phi_bc, phi, Te, P->Tg, cs, P->see_gamma, S, P->species, ns, mu, 1.0, P->mask };
         for (int k = 0; k < S; k++) {
             or_flux_ctx Xk = X;
             Xk.stick = P->stick ? P->stick[k] : 1.0;
@@ -1642,7 +1758,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
             /* a diffusion coefficient that does not vary between cells is
              * used as a uniform face coefficient */
             int varD = P->species[k].mob_kind == OR_MOB_ELECTRON_FIT;
-            or_problem SP = { *g, P->species_bc[k], NULL, NULL, 1.0 / dt, varD ? Dk + k * nc : NULL, Dk[k * nc] };
+            or_problem SP = { *g, P->species_bc[k], P->mask, NULL, 1.0 / dt, varD ? Dk + k * nc : NULL, Dk[k * nc] };
             for (int f = 0; f < 6; f++) if (SP.bc.kind[f] == OR_WALL) SP.bc.kind[f] = OR_NEU;
             if (P->check_n) {
                 for (size_t c = 0; c < nc; c++) n[k * nc + c] = P->check_n[k * nc + c];
@@ -1692,7 +1808,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     }
 out:
     free(n0); free(ns); free(mu); free(Dk); free(div); free(G); free(rhs); free(rho); free(Sinel);
-    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE); free(Si); free(Sj); free(Sph); free(sig0);
+    free(en); free(Ee0); free(Ees); free(beta); free(mue); free(divE); free(Si); free(Sj); free(Sph); free(sig0); free(phic);
     info->status = status;
     return status;
 }

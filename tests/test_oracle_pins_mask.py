@@ -1,0 +1,113 @@
+"""Pins of the oracle's masked step (covered regions inside the domain).
+
+Expected results come from other code paths of the oracle, not from the
+masked formulas themselves: an all-valid mask is the unmasked step; covered
+planes at the x+ end hold the potential g and must reproduce, cell for cell,
+the unmasked step on the smaller grid whose x+ face is a Dirichlet face
+(potential g, densities 0) -- the half-cell field, the lifting, the WENO5
+ghosts mirrored across the face, the mobility at the face and the
+homogeneous Dirichlet rows of the implicit solves all have their domain-face
+counterparts there; and a covered box centred in y and z with data that are
+mirror-symmetric in y and z gives a mirror-symmetric step.  A wrong sign or
+factor in the lifting or the face field, a mirror index off by one, a
+stencil that reads a covered cell or a missing restore of the covered
+potentials fails one of these.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_08200_amd import inputs as I
+
+D, N, W, P = I.BC_DIRICHLET, I.BC_NEUMANN, I.BC_WALLFLUX, I.BC_PERIODIC
+TOL_MG = dict(rtol=1e-13, max_cycles=400)
+
+
+def _fields(r):
+    return {"n": r["n"], "phi": r["phi"], "Te": r["Te"]}
+
+
+def test_all_valid_mask_is_the_unmasked_step(oracle):
+    cfg = I.cfg1(n=16)
+    sp = oracle.species_ar3()
+    kw = dict(poisson=oracle.mg_opts(fixed_cycles=6), species_mg=oracle.mg_opts(fixed_cycles=2))
+    a = oracle.step(cfg, sp, **kw)
+    b = oracle.step(cfg, sp, mask=np.ones(16 ** 3, np.uint8), **kw)
+    assert a["status"] == 0 and b["status"] == 0
+    for k in ("n", "phi", "Te"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("ncov", [2, 4])
+def test_covered_x_planes_equal_a_dirichlet_face(oracle, ncov):
+    """16 valid x-planes plus ncov covered ones holding phi = g equal the
+    16-plane step with a Dirichlet x+ face (phi = g, densities 0), to the
+    solver tolerance (the two grids have different multigrid hierarchies)."""
+    small = I.cfg1(n=16)
+    g = 250.0
+    nx, h = 16, small["grid"][3]
+    small["phi_bc"] = I.bc([D, D, N, N, N, N], [1000.0, g, 0, 0, 0, 0])
+    small["species_bc"] = [I.bc([W, D, N, N, N, N], [0, 0, 0, 0, 0, 0])] * 3
+    big = dict(small)
+    nb = nx + ncov
+    big["grid"] = (nb, 16, 16, h, h, h)
+    rng = np.random.default_rng(5)
+    nbig = rng.uniform(1e14, 1e16, (3, 16, 16, nb))     # covered values must not matter
+    nbig[:, :, :, :nx] = small["n"]
+    pbig = np.zeros((16, 16, nb))
+    pbig[:, :, nx:] = g
+    big["n"], big["phi"] = nbig, pbig
+    big["Te"] = np.full((16, 16, nb), small["Te"][0, 0, 0])
+    big["phi_bc"] = I.bc([D, N, N, N, N, N], [1000.0, 0, 0, 0, 0, 0])   # beyond the covered planes: unused
+    big["species_bc"] = [I.bc([W, W, N, N, N, N])] * 3
+    mask = np.ones((16, 16, nb), np.uint8)
+    mask[:, :, nx:] = 0
+    sp = oracle.species_ar3()
+    kw = dict(poisson=oracle.mg_opts(**TOL_MG), species_mg=oracle.mg_opts(**TOL_MG))
+    rs = oracle.step(small, sp, **kw)
+    rb = oracle.step(big, sp, mask=mask, **kw)
+    assert rs["status"] == 0 and rb["status"] == 0
+    for k in range(3):
+        a, b = rb["n"][k][:, :, :nx], rs["n"][k]
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), k
+        assert np.all(rb["n"][k][:, :, nx:] == 0.0)
+    assert np.abs(rb["phi"][:, :, :nx] - rs["phi"]).max() <= 1e-10 * np.abs(rs["phi"]).max()
+    assert np.all(rb["phi"][:, :, nx:] == g)
+
+
+def test_mirror_symmetric_electrode(oracle):
+    """A covered box centred in y and z (an electrode at 400 V inside the
+    gas) with y- and z-symmetric data: the step is y- and z-symmetric."""
+    n = 16
+    cfg = I.cfg1(n=n)
+    dens = cfg["n"]
+    dens = 0.25 * (dens + dens[:, :, ::-1, :] + dens[:, ::-1, :, :] + dens[:, ::-1, ::-1, :])
+    cfg["n"] = dens
+    cfg["species_bc"] = [I.bc([W, W, W, W, W, W])] * 3
+    mask = np.ones((n, n, n), np.uint8)
+    mask[6:10, 6:10, 9:12] = 0
+    phi = np.zeros((n, n, n))
+    phi[mask == 0] = 400.0
+    cfg["phi"] = phi
+    sp = oracle.species_ar3()
+    r = oracle.step(cfg, sp, mask=mask.ravel(), poisson=oracle.mg_opts(**TOL_MG), species_mg=oracle.mg_opts(**TOL_MG))
+    assert r["status"] == 0
+    assert np.all(r["phi"][mask == 0] == 400.0)
+    assert np.all(r["n"][:, mask == 0] == 0.0)
+    for f in (r["phi"], r["n"][0], r["n"][1]):
+        s = np.abs(f).max()
+        assert np.abs(f - f[::-1, :, :]).max() <= 1e-9 * s
+        assert np.abs(f - f[:, ::-1, :]).max() <= 1e-9 * s
+    # next to the electrode the potential moves toward its 400 V
+    u = oracle.step(cfg, sp, poisson=oracle.mg_opts(**TOL_MG), species_mg=oracle.mg_opts(**TOL_MG))
+    for c in ((8, 8, 8), (8, 8, 12)):
+        assert abs(r["phi"][c] - 400.0) < abs(u["phi"][c] - 400.0), c
+
+
+def test_mask_rejects_unsupported_combinations(oracle):
+    cfg = I.cfg1(n=8)
+    sp = oracle.species_ar3()
+    m = np.ones(8 ** 3, np.uint8)
+    m[0] = 0
+    c2 = dict(cfg, phi_bc=I.bc([D, D, P, P, N, N], [1000.0, 0, 0, 0, 0, 0]))
+    assert oracle.step(c2, sp, mask=m)["status"] != 0
+    assert oracle.step(cfg, sp, mask=m, adaptive_dt={"c_adv": 0.3, "c_diff": 10.0, "c_diel": 0.5})["status"] != 0
