@@ -321,6 +321,22 @@ typedef struct {
     double *sigma;
     double see_gamma;
     const double *stick;
+    /* Cell mask (Sec. 3, masking paragraph): device uint8 [cells], 1 valid,
+     * 0 covered, NULL = every cell valid.  Every solve of the step is
+     * masked (covered cells take no part and are Dirichlet faces for their
+     * valid neighbours).  The potential stored in a covered cell is the
+     * Dirichlet value of its faces with valid cells: it is lifted into the
+     * Poisson right-hand side (2 beta_f g / h^2, beta_f the operator's face
+     * coefficient) and kept; the field at such a face is the one-sided
+     * difference over half a cell.  The densities take the homogeneous
+     * Dirichlet value there (covered cells hold 0 after the step), and the
+     * WENO5 drift stencils close the valid runs like Dirichlet domain faces
+     * (positions past the closing face take minus the value mirrored
+     * across it, 0 when the mirror leaves the run); the drift at a
+     * covered-valid face uses the valid cell's mobility.  Not with periodic
+     * faces, the energy equation, photoionization, dielectric faces or the
+     * adaptive step (VD_EINVAL). */
+    const uint8_t *mask;
 } vd_step_params;
 
 /* State updated in place (device arrays). */

@@ -16,7 +16,17 @@ __device__ __forceinline__ double e_face(const GridDev &G, const double *__restr
     const long st = G.stride[d];
     const double ih = G.ih[d];
     const long c0 = c - (long)pos * st;     // index of row position 0
-    if (fidx > 0 && fidx < n) return -(gld(phi, c0 + fidx * st) - gld(phi, c0 + (fidx - 1) * st)) * ih;
+    if (fidx > 0 && fidx < n) {
+        // masked step: a covered cell's potential is the Dirichlet value of
+        // its faces with valid cells (one-sided over half a cell); no field
+        // between two covered cells
+        if (G.mask) {
+            const bool vl = gld(G.mask, c0 + (fidx - 1) * st) != 0, vr = gld(G.mask, c0 + fidx * st) != 0;
+            if (!vl && !vr) return 0.0;
+            if (vl != vr) return -(gld(phi, c0 + fidx * st) - gld(phi, c0 + (fidx - 1) * st)) * (2.0 * ih);
+        }
+        return -(gld(phi, c0 + fidx * st) - gld(phi, c0 + (fidx - 1) * st)) * ih;
+    }
     const int f = 2 * d + (fidx == 0 ? 0 : 1);
     const int kind = G.phi_kind[f];
     if (kind == VD_BC_PERIODIC) return -(gld(phi, c0) - gld(phi, c0 + (n - 1) * st)) * ih;
@@ -124,6 +134,31 @@ __device__ __forceinline__ double u_at(const GridDev &G, const int *kind, const 
     return kd == VD_BC_DIRICHLET ? 2.0 * g - v : v;
 }
 
+// Masked step: the five upwind values of face fidx's WENO5 stencil (up:
+// positions fidx-3 .. fidx+1, else fidx+2 down to fidx-2).  The nearest
+// covered cell on each side, within reach, closes the valid run like a
+// homogeneous Dirichlet domain face: a position past it takes minus the
+// value mirrored across that face, 0 when the mirror leaves the run.
+__device__ __forceinline__ void stencil5_masked(const GridDev &G, const FieldDesc &F, int d, long c0, int fidx, bool up,
+                                                double s[5]) {
+    const int n = G.n[d];
+    const long st = G.stride[d];
+    int lo = -1, hi = -1;
+    for (int p = fidx - 1; p >= fidx - 3 && p >= 0; p--)
+        if (!gld(G.mask, c0 + p * st)) { lo = p + 1; break; }
+    for (int p = fidx; p <= fidx + 2 && p < n; p++)
+        if (!gld(G.mask, c0 + p * st)) { hi = p; break; }
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        const int p = up ? fidx - 3 + m : fidx + 2 - m;
+        const int fb = (lo >= 0 && p < lo) ? lo : ((hi >= 0 && p >= hi) ? hi : -1);
+        if (fb < 0) { s[m] = u_at(G, F.kind, F.gval, F.u, d, c0, p); continue; }
+        const int q = 2 * fb - 1 - p;
+        const bool inrun = q >= 0 && q < n && (lo < 0 || q >= lo) && (hi < 0 || q < hi) && gld(G.mask, c0 + q * st) != 0;
+        s[m] = inrun ? -gld(F.u, c0 + q * st) : 0.0;
+    }
+}
+
 __device__ __forceinline__ double wall_flux(int wk, double uc, double mu, double e_n, double Te, double Tg, double mass,
                                             double kB, double me) {
     switch (wk) {
@@ -165,11 +200,19 @@ __device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &
                              : (d == 0 ? F.kind[1] : d == 1 ? F.kind[3] : F.kind[5]);
     const double *__restrict__ u = F.u;
     if (!F.mu && F.mu_c == 0.0) return 0.0;
+    // masked step: validity of the face's two cells (a domain face has one)
+    bool vl = true, vr = true;
+    if (G.mask) {
+        vl = fidx > 0 && gld(G.mask, c0 + (fidx - 1) * st) != 0;
+        vr = fidx < n && gld(G.mask, c0 + fidx * st) != 0;
+        if (!vl && !vr) return 0.0;
+    }
     const double Ef = e_face(G, phi, d, c, pos, fidx);
     double muf;
     if (F.mu) {
         const int pl = fidx - 1, pr = fidx;
         if (boundary && kd != VD_BC_PERIODIC) muf = fidx == 0 ? gld(F.mu, c0) : gld(F.mu, c0 + (n - 1) * st);
+        else if (vl != vr) muf = vl ? gld(F.mu, c0 + pl * st) : gld(F.mu, c0 + pr * st);   // the valid cell's
         else {
             const int ql = pl < 0 ? pl + n : pl, qr = pr >= n ? pr - n : pr;
             muf = 0.5 * (gld(F.mu, c0 + ql * st) + gld(F.mu, c0 + qr * st));
@@ -179,6 +222,11 @@ __device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &
     }
     const double v = muf * F.mu_scale * Ef;
     if (v == 0.0) return 0.0;
+    if (G.mask) {
+        double sm[5];
+        stencil5_masked(G, F, d, c0, fidx, v > 0.0, sm);
+        return v * weno5(sm[0], sm[1], sm[2], sm[3], sm[4]);
+    }
     double s0, s1, s2, s3, s4;
     if (v > 0.0) {
         const int b = fidx - 3;
@@ -202,6 +250,7 @@ __device__ __forceinline__ double face_drift(const GridDev &G, const FieldDesc &
 __device__ double drift_div_cell(const GridDev &G, const FieldDesc &F, const double *__restrict__ phi,
                                  const double *__restrict__ Te, double Tg, double kB, double me, int c, const int pos[3]) {
     double total = 0.0;
+    if (G.mask && !gld(G.mask, (long)c)) return 0.0;     // covered: no balance
     const double *__restrict__ u = F.u;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -1137,7 +1186,10 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
         kz = cand;
         if ((long)(nx / kDX) * (ny / kDY) * (nz / cand) * nfields >= 2048) break;
     }
-    if (nx % kDX == 0 && ny % kDY == 0 && kz > 0 && nx >= 3 && ny >= 3 && nz >= 3) {
+    if (a.g.mask) {
+        // masked step: the per-cell kernel (its face fluxes close the valid runs)
+        timed(ctx, "weno", bytes, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
+    } else if (nx % kDX == 0 && ny % kDY == 0 && kz > 0 && nx >= 3 && ny >= 3 && nz >= 3) {
         dim3 tg((nx / kDX) * (ny / kDY) * (nz / kz), nfields);
         timed(ctx, "weno", bytes, [&] {
             k_drift25<<<tg, kBlock, 0, ctx->stream>>>(a, kz);
@@ -1157,6 +1209,52 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
     } else {
         timed(ctx, "weno", bytes, [&] { k_drift<<<grid, kBlock, 0, ctx->stream>>>(a); });
     }
+}
+
+// masked step, Poisson: each covered neighbour of a valid cell is a
+// Dirichlet face with the covered cell's potential g; rho gains
+// 2 beta_f g / h^2 with beta_f the operator's face coefficient (the harmonic
+// mean of the two cells' permittivities, or eps0), faces in the order x-,
+// x+, y-, y+, z-, z+
+__device__ __forceinline__ double hmean(double a, double b) { return (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b); }
+
+__global__ void __launch_bounds__(kBlock) k_mask_lift(GridDev G, const double *__restrict__ phi_cov,
+                                                      const double *__restrict__ eps, double eps0, double *__restrict__ rho) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell || !gld(G.mask, (long)c)) return;
+    int pos[3];
+    pos[2] = c / G.nxy;
+    const int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    double lift = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        const int d = f >> 1;
+        const int p = pos[d] + ((f & 1) ? 1 : -1);
+        if (p < 0 || p >= G.n[d]) continue;
+        const long nb = c + ((f & 1) ? G.stride[d] : -G.stride[d]);
+        if (gld(G.mask, nb)) continue;
+        const double bf = eps ? hmean(gld(eps, (long)c), gld(eps, nb)) : eps0;
+        lift += 2.0 * bf * gld(phi_cov, nb) * (G.ih[d] * G.ih[d]);
+    }
+    gst(rho, (long)c, gld(rho, (long)c) + lift);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mask_restore(GridDev G, const double *__restrict__ phi_cov, double *__restrict__ phi) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell || gld(G.mask, (long)c)) return;
+    gst(phi, (long)c, gld(phi_cov, (long)c));
+}
+
+void launch_mask_lift(vd_ctx *ctx, const GridDev &G, const double *phi_cov, const double *eps, double eps0, double *rho) {
+    k_mask_lift<<<ceil_div(G.ncell, kBlock), kBlock, 0, ctx->stream>>>(G, phi_cov, eps, eps0, rho);
+    VD_HIP(hipGetLastError());
+}
+
+void launch_mask_restore(vd_ctx *ctx, const GridDev &G, const double *phi_cov, double *phi) {
+    k_mask_restore<<<ceil_div(G.ncell, kBlock), kBlock, 0, ctx->stream>>>(G, phi_cov, phi);
+    VD_HIP(hipGetLastError());
 }
 
 void launch_react(vd_ctx *ctx, const ReactArgs &a) {

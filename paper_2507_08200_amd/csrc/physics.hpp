@@ -12,6 +12,7 @@ struct GridDev {
     double ihl[3];      // 1/h for the divergence
     int phi_kind[6];
     double phi_val[6];
+    const uint8_t *mask;   // cell mask of a masked step (1 valid, 0 covered), or null
 };
 
 constexpr int kMaxSee = 8;   // ion species returning secondary electrons
@@ -150,6 +151,10 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
 void launch_face_flux(vd_ctx *ctx, DriftArgs a, const FieldDesc &field, const double *D, double *out);
 void launch_react(vd_ctx *ctx, const ReactArgs &a);
 void launch_rho(vd_ctx *ctx, const RhoArgs &a);
+// masked step: lifting of the covered cells' potentials into the Poisson
+// right-hand side of their valid neighbours, and their restore after a solve
+void launch_mask_lift(vd_ctx *ctx, const GridDev &G, const double *phi_cov, const double *eps, double eps0, double *rho);
+void launch_mask_restore(vd_ctx *ctx, const GridDev &G, const double *phi_cov, double *phi);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
 void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a);

@@ -12,7 +12,7 @@ struct StepBuffers {
     long ncell = 0;
     int S = 0;
     DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
-    DevBuf<double> ion, photo, prhs, sig0, dtpart;
+    DevBuf<double> ion, photo, prhs, sig0, dtpart, phic;
     bool photo_zeroed = false;
 };
 
@@ -51,6 +51,16 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
     VD_CHECK(P->S >= 1 && P->S <= 32, "S must be in 1..32");
     VD_CHECK(P->dt > 0 && P->n_t >= 1, "dt must be positive and n_t >= 1");
     VD_CHECK(P->species && P->species_bc, "species and species_bc are required");
+    if (P->mask) {
+        bool diel = false;
+        for (int f = 0; f < 6; f++) diel = diel || P->diel[f];
+        VD_CHECK(P->te_mode != VD_TE_ENERGY && P->photo_n == 0 && !diel && P->dt_mode == 0,
+                 "a masked step takes neither the energy equation, photoionization, dielectric faces nor the adaptive step");
+        for (int f = 0; f < 6; f++) {
+            VD_CHECK(P->phi_bc.kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");
+            for (int k = 0; k < P->S; k++) VD_CHECK(P->species_bc[k].kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");
+        }
+    }
     VD_CHECK(st->n && st->phi && st->Te, "state n, phi and Te are required");
     VD_CHECK(P->te_mode >= VD_TE_FIXED && P->te_mode <= VD_TE_ENERGY, "unknown te_mode");
     VD_CHECK(P->poisson.guess == VD_GUESS_GIVEN || P->poisson.guess == VD_GUESS_ZERO || P->poisson.guess == VD_GUESS_EXTRAP,
@@ -176,6 +186,13 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
     for (int k = 0; k < S; k++) const_transport(P->species[k], P, &mu_c[k], &D_c[k]);
 
     GridDev G = make_grid(g, P->phi_bc);
+    G.mask = P->mask;
+    // masked step: the covered cells' potentials (the Dirichlet values of
+    // their faces with valid cells), before anything writes phi
+    if (P->mask) {
+        B->phic.alloc(N);
+        VD_HIP(hipMemcpyAsync(B->phic.p, st->phi, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    }
     vd_step_info I;
     memset(&I, 0, sizeof(I));
     // time step: fixed, or the least of the limits of Eq. (20) over the
@@ -326,12 +343,15 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         };
         for (int f = 0; f < 6; f++)
             if (P->diel[f]) launch_sigma(ctx, sigma_args(f, nst), 0);
+        if (P->mask) launch_mask_lift(ctx, G, B->phic.p, P->eps_cell, P->consts.eps0, B->rho.p);
         vd_problem pp;
         memset(&pp, 0, sizeof(pp));
         pp.grid = g; pp.bc = P->phi_bc; pp.beta = P->eps_cell; pp.beta_c = P->consts.eps0;
+        pp.mask = P->mask;
         pp.rhs = B->rho.p; pp.x = st->phi;
         vd_solve_info pinfo;
         mg_solve_batch(ctx, 1, &pp, &popt, &pinfo, "poisson:");
+        if (P->mask) launch_mask_restore(ctx, G, B->phic.p, st->phi);
         I.poisson_cycles += pinfo.cycles;
         I.poisson_rel = pinfo.rel_res;
         if (want_info) VD_HIP(hipEventRecord(ev[1], s));
@@ -446,6 +466,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             vd_problem &q = sp[nf];
             memset(&q, 0, sizeof(q));
             q.grid = g; q.bc = implicit_bc(P->species_bc[k]); q.alpha_c = 1.0 / dt;
+            q.mask = P->mask;
             q.beta = var_idx[k] >= 0 ? B->D.p + (long)var_idx[k] * N : nullptr;
             q.beta_c = D_c[k];
             q.rhs = F.out; q.x = st->n + (long)k * N;

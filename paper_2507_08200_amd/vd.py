@@ -96,7 +96,8 @@ class StepParams(C.Structure):
                 ("photo_pq", C.c_double), ("photo_p", C.c_double), ("photo_nu_ratio", C.c_double),
                 ("photo_bc", BC), ("photo_mg", MGOpts), ("photo_out", C.c_void_p),
                 ("c_adv", C.c_double), ("c_diff", C.c_double), ("c_diel", C.c_double),
-                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p)]
+                ("diel", C.c_int32 * 6), ("sigma", C.c_void_p), ("see_gamma", C.c_double), ("stick", C.c_void_p),
+                ("mask", C.c_void_p)]
 
 
 class NNConfig(C.Structure):
@@ -484,7 +485,7 @@ PHYS = {"qe": 1.602176634e-19, "eps0": 8.8541878128e-12, "kB": 1.380649e-23, "me
 
 def step_params(cfg, species, *, consts=PHYS, lfa=None, poisson=None, species_mg=None, energy_mg=None,
                 extra_source=None, extra_energy=None, eps_cell=None, electron=0, m_bg=0.0, k_decay=0.0,
-                photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None):
+                photo=None, adaptive_dt=None, diel=None, sigma=None, see_gamma=0.0, stick=None, mask=None):
     """Pack a workload dict (see inputs) into vd_step_params.  Device arrays
     (lfa table, sources, sigma, photo["out"]) must be torch tensors; the
     returned object keeps references to everything it points at.
@@ -492,7 +493,8 @@ def step_params(cfg, species, *, consts=PHYS, lfa=None, poisson=None, species_mg
     "pq", "p", "nu_ratio" (default 1), "e", "ion", "bc" (default
     homogeneous Dirichlet), "mg" (mg_opts), "out" (optional [3][cells]).
     adaptive_dt: dict with "c_adv", "c_diff", "c_diel".  diel: six flags with
-    sigma the packed surface charge (advanced in place).  stick: [S]."""
+    sigma the packed surface charge (advanced in place).  stick: [S].
+    mask: uint8 tensor [cells] (1 valid, 0 covered)."""
     P = StepParams()
     P.grid = grid(cfg["grid"])
     P.dt = float(cfg["dt"])
@@ -558,5 +560,9 @@ def step_params(cfg, species, *, consts=PHYS, lfa=None, poisson=None, species_mg
         st = (C.c_double * P.S)(*[float(v) for v in stick])
         keep.append(st)
         P.stick = C.addressof(st)
+    if mask is not None:
+        nx, ny, nz = cfg["grid"][:3]
+        P.mask = _dptr(mask, (nz, ny, nx), torch.uint8, "mask")
+        keep.append(mask)
     P._keep = keep
     return P
