@@ -154,8 +154,9 @@ typedef struct {
      * right-hand side, kept through the step), the densities take the
      * homogeneous Dirichlet value there (covered cells hold 0 after the
      * step); the drift fluxes close the valid runs like Dirichlet domain
-     * faces (stencil5, e_face_m).  Not with periodic faces, the energy
-     * equation, photoionization, dielectric faces or the adaptive step. */
+     * faces (stencil5, e_face_m); the adaptive step takes its limits over
+     * the valid cells.  Not with periodic faces, the energy equation,
+     * photoionization or dielectric faces. */
     const uint8_t *mask;
 } or_step_params;
 
@@ -1469,8 +1470,9 @@ static double adaptive_dt(const or_step_params *P, const double *n, const double
         for (int j = 0; j < g->ny; j++)
             for (int i = 0; i < g->nx; i++) {
                 size_t c = IDX(i, j, k, g->nx, g->ny);
+                if (P->mask && !P->mask[c]) continue;     /* masked step: valid cells only */
                 double E[3], mu, D;
-                e_cell(g, &P->phi_bc, phi, i, j, k, E);
+                e_cell_m(g, &P->phi_bc, phi, P->mask, i, j, k, E);
                 double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
                 transport(se, cs, Em / P->N_gas / OR_TD, Te[c], P->Tg, P->N_gas, &mu, &D);
                 double am = fabs(mu) * Em;
@@ -1500,7 +1502,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     for (int f = 0; f < 6; f++) any_diel = any_diel || P->diel[f];
     if (any_diel && !P->sigma) return info->status = OR_EINVAL;
     if (P->mask) {
-        if (P->te_mode == OR_TE_ENERGY || P->photo_n > 0 || any_diel || P->dt_mode != 0 || P->phi_fixed)
+        if (P->te_mode == OR_TE_ENERGY || P->photo_n > 0 || any_diel || P->phi_fixed)
             return info->status = OR_EINVAL;
         for (int f = 0; f < 6; f++) {
             if (P->phi_bc.kind[f] == OR_PER) return info->status = OR_EINVAL;

@@ -951,7 +951,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_limit(DtArgs a) {
     const GridDev &G = a.g;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     double dt = a.dt_max;
-    if (c < G.ncell) {
+    if (c < G.ncell && !(G.mask && !gld(G.mask, (long)c))) {     // masked step: valid cells only
         int pos[3];
         pos[2] = c / G.nxy;
         const int r = c - pos[2] * G.nxy;

@@ -54,8 +54,8 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
     if (P->mask) {
         bool diel = false;
         for (int f = 0; f < 6; f++) diel = diel || P->diel[f];
-        VD_CHECK(P->te_mode != VD_TE_ENERGY && P->photo_n == 0 && !diel && P->dt_mode == 0,
-                 "a masked step takes neither the energy equation, photoionization, dielectric faces nor the adaptive step");
+        VD_CHECK(P->te_mode != VD_TE_ENERGY && P->photo_n == 0 && !diel,
+                 "a masked step takes neither the energy equation, photoionization nor dielectric faces");
         for (int f = 0; f < 6; f++) {
             VD_CHECK(P->phi_bc.kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");
             for (int k = 0; k < P->S; k++) VD_CHECK(P->species_bc[k].kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");

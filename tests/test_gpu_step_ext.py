@@ -213,3 +213,26 @@ def test_step_masked_planes_equal_dirichlet_face(ctx, V):
     ep = rel_err(host(s_big["phi"])[:, :, :n], host(s_small["phi"]))
     say("masked planes vs Dirichlet face: n", e, "phi", ep)
     assert e <= 1e-9 and ep <= 1e-9
+
+
+def test_step_masked_adaptive_dt(ctx, V, oracle):
+    """Masked electrode with the time step of Eq. (20) over the valid cells
+    (the covered cells hold a density whose dielectric limit would be the
+    least): the GPU takes the oracle's step and matches its fields."""
+    from paper_2507_08200_amd import mechanisms as M
+    cfg, mask = _electrode_case()
+    cfg["dt"] = 1e-8
+    cfg["n"][:, mask == 0] = 1e18
+    ad = {"c_adv": 0.3, "c_diff": 10.0, "c_diel": 0.5}
+    state = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    P = V.step_params(cfg, M.ar3(), poisson=V.mg_opts(fixed_cycles=12), species_mg=V.mg_opts(fixed_cycles=2),
+                      adaptive_dt=ad, electron=0, mask=torch.tensor(mask, device="cuda"))
+    info = ctx.vd_step(P, state)
+    ref = oracle.step(cfg, oracle.species_ar3(), poisson=oracle.mg_opts(fixed_cycles=12),
+                      species_mg=oracle.mg_opts(fixed_cycles=2), adaptive_dt=ad, electron=0, mask=mask.ravel())
+    assert ref["status"] == 0
+    want = ref["info"]["dt_used"]
+    say("masked adaptive dt", info["dt_used"], want)
+    assert want < cfg["dt"]
+    assert abs(info["dt_used"] - want) <= 1e-13 * want
+    _check("   errors", state, ref)

@@ -110,4 +110,43 @@ def test_mask_rejects_unsupported_combinations(oracle):
     m[0] = 0
     c2 = dict(cfg, phi_bc=I.bc([D, D, P, P, N, N], [1000.0, 0, 0, 0, 0, 0]))
     assert oracle.step(c2, sp, mask=m)["status"] != 0
-    assert oracle.step(cfg, sp, mask=m, adaptive_dt={"c_adv": 0.3, "c_diff": 10.0, "c_diel": 0.5})["status"] != 0
+    c3 = dict(cfg, te_mode=I.TE_ENERGY)
+    assert oracle.step(c3, sp, Ee=np.ones(8 ** 3), mask=m)["status"] != 0
+
+
+def test_masked_adaptive_dt_equals_the_dirichlet_face_grid(oracle):
+    """Eq. (20) over the valid cells: the covered planes' grid takes the same
+    step as the grid with the Dirichlet x+ face (the field next to the face
+    is the half-cell difference on both, and the advection limit there is
+    the least); the covered cells' density of 1e18, whose dielectric limit
+    (~9e-10 s) would be the least, does not enter the minimum."""
+    small = I.cfg1(n=16)
+    g = -2000.0                      # a steep drop at the face: the advection limit sits there
+    nx, h = 16, small["grid"][3]
+    small["dt"] = 1e-8
+    small["phi_bc"] = I.bc([D, D, N, N, N, N], [1000.0, g, 0, 0, 0, 0])
+    small["species_bc"] = [I.bc([W, D, N, N, N, N], [0, 0, 0, 0, 0, 0])] * 3
+    big = dict(small)
+    nb = nx + 2
+    big["grid"] = (nb, 16, 16, h, h, h)
+    nbig = np.full((3, 16, 16, nb), 1e18)
+    nbig[:, :, :, :nx] = small["n"]
+    pbig = np.zeros((16, 16, nb))
+    pbig[:, :, nx:] = g
+    pbig[:, :, nx + 1:] = 5e5            # a huge field between the covered planes: must not count
+    big["n"], big["phi"] = nbig, pbig
+    big["Te"] = np.full((16, 16, nb), small["Te"][0, 0, 0])
+    big["phi_bc"] = I.bc([D, N, N, N, N, N], [1000.0, 0, 0, 0, 0, 0])
+    big["species_bc"] = [I.bc([W, W, N, N, N, N])] * 3
+    mask = np.ones((16, 16, nb), np.uint8)
+    mask[:, :, nx:] = 0
+    sp = oracle.species_ar3()
+    ad = {"c_adv": 0.3, "c_diff": 10.0, "c_diel": 0.5}
+    kw = dict(poisson=oracle.mg_opts(**TOL_MG), species_mg=oracle.mg_opts(**TOL_MG), adaptive_dt=ad, electron=0)
+    small["phi"] = pbig[:, :, :nx].copy()
+    rs = oracle.step(small, sp, **kw)
+    rb = oracle.step(big, sp, mask=mask, **kw)
+    assert rs["status"] == 0 and rb["status"] == 0
+    ds, db = rs["info"]["dt_used"], rb["info"]["dt_used"]
+    assert ds < small["dt"]
+    assert abs(db - ds) <= 1e-14 * ds
