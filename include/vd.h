@@ -333,9 +333,11 @@ typedef struct {
      * WENO5 drift stencils close the valid runs like Dirichlet domain faces
      * (positions past the closing face take minus the value mirrored
      * across it, 0 when the mirror leaves the run); the drift at a
-     * covered-valid face uses the valid cell's mobility; the adaptive step
-     * takes its limits over the valid cells.  Not with periodic faces, the
-     * energy equation, photoionization or dielectric faces (VD_EINVAL). */
+     * covered-valid face uses the valid cell's mobility; the diffusive
+     * electron flux of the Joule term is the homogeneous Dirichlet face
+     * flux there; the adaptive step takes its limits over the valid cells.
+     * Not with periodic faces, photoionization or dielectric faces
+     * (VD_EINVAL). */
     const uint8_t *mask;
 } vd_step_params;
 

@@ -154,9 +154,11 @@ typedef struct {
      * right-hand side, kept through the step), the densities take the
      * homogeneous Dirichlet value there (covered cells hold 0 after the
      * step); the drift fluxes close the valid runs like Dirichlet domain
-     * faces (stencil5, e_face_m); the adaptive step takes its limits over
-     * the valid cells.  Not with periodic faces, the energy equation,
-     * photoionization or dielectric faces. */
+     * faces (stencil5, e_face_m), the diffusive part of the Joule term's
+     * electron flux is a homogeneous Dirichlet face flux there
+     * (diff_face_m); the adaptive step takes its limits over the valid
+     * cells.  Not with periodic faces, photoionization or dielectric
+     * faces. */
     const uint8_t *mask;
 } or_step_params;
 
@@ -1159,15 +1161,24 @@ static void drift_divergence(const or_flux_ctx *X, const or_bc *ubc, const doubl
  * (i,j,k): -beta_f (u_R - u_L)/h with the harmonic-mean face coefficient
  * (Dirichlet face: one-sided over half a cell with the cell's beta; wall
  * and Neumann: 0 here, the wall flux being accounted for separately). */
-static double diff_face(const or_grid *g, const or_bc *ubc, const double *u, const double *beta,
-                        int d, int i, int j, int k, int fidx)
+static double diff_face_m(const or_grid *g, const or_bc *ubc, const double *u, const double *beta, const uint8_t *mask,
+                          int d, int i, int j, int k, int fidx)
 {
     int nx = g->nx, ny = g->ny;
     int n_d = d == 0 ? g->nx : (d == 1 ? g->ny : g->nz);
     double h = d == 0 ? g->dx : (d == 1 ? g->dy : g->dz);
 #define AT(arr, p) arr[d == 0 ? IDX((p), j, k, nx, ny) : (d == 1 ? IDX(i, (p), k, nx, ny) : IDX(i, j, (p), nx, ny))]
-    if (fidx > 0 && fidx < n_d)
+    if (fidx > 0 && fidx < n_d) {
+        if (mask) {
+            /* masked step: a covered-valid face is a homogeneous Dirichlet
+             * face of the valid cell (one-sided over half a cell) */
+            int vl = AT(mask, fidx - 1) != 0, vr = AT(mask, fidx) != 0;
+            if (!vl && !vr) return 0.0;
+            if (!vr) return -AT(beta, fidx - 1) * (0.0 - AT(u, fidx - 1)) / (0.5 * h);
+            if (!vl) return -AT(beta, fidx) * (AT(u, fidx) - 0.0) / (0.5 * h);
+        }
         return -harmonic(AT(beta, fidx - 1), AT(beta, fidx)) * (AT(u, fidx) - AT(u, fidx - 1)) / h;
+    }
     int f = 2 * d + (fidx == 0 ? 0 : 1);
     int kind = ubc->kind[f];
     if (kind == OR_PER)
@@ -1179,6 +1190,12 @@ static double diff_face(const or_grid *g, const or_bc *ubc, const double *u, con
     }
     return 0.0;
 #undef AT
+}
+
+static double diff_face(const or_grid *g, const or_bc *ubc, const double *u, const double *beta,
+                        int d, int i, int j, int k, int fidx)
+{
+    return diff_face_m(g, ubc, u, beta, NULL, d, i, j, k, fidx);
 }
 
 /* Public drift-divergence entry for the tests: all species. */
@@ -1502,10 +1519,10 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
     for (int f = 0; f < 6; f++) any_diel = any_diel || P->diel[f];
     if (any_diel && !P->sigma) return info->status = OR_EINVAL;
     if (P->mask) {
-        if (P->te_mode == OR_TE_ENERGY || P->photo_n > 0 || any_diel || P->phi_fixed)
+        if (P->photo_n > 0 || any_diel || P->phi_fixed)
             return info->status = OR_EINVAL;
         for (int f = 0; f < 6; f++) {
-            if (P->phi_bc.kind[f] == OR_PER) return info->status = OR_EINVAL;
+            if (P->phi_bc.kind[f] == OR_PER || P->energy_bc.kind[f] == OR_PER) return info->status = OR_EINVAL;
             for (int k = 0; k < S; k++) if (P->species_bc[k].kind[f] == OR_PER) return info->status = OR_EINVAL;
         }
     }
@@ -1692,30 +1709,13 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                                     int fidx = pos + side;
                                     int boundary = (fidx == 0 || fidx == n_d);
                                     int kind = ebc->kind[2 * d + side];
-                                    double Ef = e_face(g, &P->phi_bc, phi, d, i, j, k, fidx);
-                                    if (boundary && kind == OR_NEU) { Fs[side] = 0.0; continue; }
-                                    if (boundary && kind == OR_WALL) {
-                                        double e_n = fidx == 0 ? -Ef : Ef;
-                                        double fl = wall_flux_x(&X, OR_WALL_ELECTRON, c, ne[c], mu_e[c], e_n, cs->me);
-                                        Fs[side] = fidx == 0 ? -fl : fl;
-                                        continue;
-                                    }
-                                    /* drift part: same face velocity and upwind WENO as
-                                     * in the continuity equation */
-                                    int pl = fidx - 1, pr = fidx;
-                                    int ql = pl < 0 ? (kind == OR_PER ? n_d - 1 : 0) : pl;
-                                    int qr = pr >= n_d ? (kind == OR_PER ? 0 : n_d - 1) : pr;
-                                    size_t cl = d == 0 ? IDX(ql, j, k, g->nx, g->ny) : (d == 1 ? IDX(i, ql, k, g->nx, g->ny) : IDX(i, j, ql, g->nx, g->ny));
-                                    size_t cr = d == 0 ? IDX(qr, j, k, g->nx, g->ny) : (d == 1 ? IDX(i, qr, k, g->nx, g->ny) : IDX(i, j, qr, g->nx, g->ny));
-                                    double muf = (boundary && kind != OR_PER) ? (fidx == 0 ? mu_e[cr] : mu_e[cl]) : 0.5 * (mu_e[cl] + mu_e[cr]);
-                                    double v = muf * Ef, drift = 0.0;
-                                    if (v != 0.0) {
-                                        double s5[5];
-                                        if (v > 0.0) for (int q = 0; q < 5; q++) s5[q] = u_at(g, ebc, ne, d, i, j, k, pl - 2 + q);
-                                        else for (int q = 0; q < 5; q++) s5[q] = u_at(g, ebc, ne, d, i, j, k, pr + 2 - q);
-                                        drift = v * or_weno5(s5);
-                                    }
-                                    Fs[side] = drift + diff_face(g, ebc, ne, D_e, d, i, j, k, fidx);
+                                    /* drift part (the wall flux at a wall face): the same
+                                     * face velocity and upwind WENO5 as in the continuity
+                                     * equation; central diffusion on the other faces */
+                                    Fs[side] = drift_face_flux(&X, ebc, ne, mu_e, OR_WALL_ELECTRON, cs->me, NULL, d, i, j, k,
+                                                               fidx);
+                                    if (!(boundary && (kind == OR_NEU || kind == OR_WALL)))
+                                        Fs[side] += diff_face_m(g, ebc, ne, D_e, P->mask, d, i, j, k, fidx);
                                 }
                                 Gam[3 * c + d] = 0.5 * (Fs[0] + Fs[1]);
                             }
@@ -1726,7 +1726,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                     for (int i = 0; i < g->nx; i++) {
                         size_t c = IDX(i, j, k, g->nx, g->ny);
                         double E[3];
-                        e_cell(g, &P->phi_bc, phi, i, j, k, E);
+                        e_cell_m(g, &P->phi_bc, phi, P->mask, i, j, k, E);
                         double joule = -cs->qe * (Gam[3 * c] * E[0] + Gam[3 * c + 1] * E[1] + Gam[3 * c + 2] * E[2]);
                         double nu = cs->qe / (cs->me * fabs(mu_e[c]));
                         double elastic = 1.5 * ne[c] * cs->kB * (Te[c] - P->Tg) * (2.0 * cs->me / P->m_bg) * nu;
@@ -1735,7 +1735,7 @@ int or_step(const or_step_params *P, double *n, double *phi, double *Te, double 
                         rhs[c] = Ee0[c] / dt - divE[c] + src;
                     }
             free(Gam);
-            or_problem EP = { *g, P->energy_bc, NULL, NULL, 1.0 / dt, beta, 0.0 };
+            or_problem EP = { *g, P->energy_bc, P->mask, NULL, 1.0 / dt, beta, 0.0 };
             for (int f = 0; f < 6; f++) if (EP.bc.kind[f] == OR_WALL) EP.bc.kind[f] = OR_NEU;
             if (P->check_Ee) {
                 for (size_t c = 0; c < nc; c++) Ee[c] = P->check_Ee[c];

@@ -1053,6 +1053,14 @@ __device__ __forceinline__ double diff_face(const GridDev &G, const int *kind, c
     const long c0 = c - (long)pos * st;
 #define DV(q) (D ? gld(D, c0 + (long)(q) * st) : D_c)
     if (fidx > 0 && fidx < n) {
+        if (G.mask) {
+            // masked step: a covered-valid face is a homogeneous Dirichlet
+            // face of the valid cell (one-sided over half a cell)
+            const bool vl = gld(G.mask, c0 + (fidx - 1) * st) != 0, vr = gld(G.mask, c0 + fidx * st) != 0;
+            if (!vl && !vr) return 0.0;
+            if (!vr) return -DV(fidx - 1) * (0.0 - gld(u, c0 + (fidx - 1) * st)) * (2.0 * ih);
+            if (!vl) return -DV(fidx) * (gld(u, c0 + fidx * st) - 0.0) * (2.0 * ih);
+        }
         const double a = DV(fidx - 1), b = DV(fidx);
         const double hm = (a + b == 0.0) ? 0.0 : 2.0 * a * b / (a + b);
         return -hm * (gld(u, c0 + fidx * st) - gld(u, c0 + (fidx - 1) * st)) * ih;

@@ -54,10 +54,10 @@ static void validate_step(const vd_step_params *P, const vd_state *st) {
     if (P->mask) {
         bool diel = false;
         for (int f = 0; f < 6; f++) diel = diel || P->diel[f];
-        VD_CHECK(P->te_mode != VD_TE_ENERGY && P->photo_n == 0 && !diel,
-                 "a masked step takes neither the energy equation, photoionization nor dielectric faces");
+        VD_CHECK(P->photo_n == 0 && !diel, "a masked step takes neither photoionization nor dielectric faces");
         for (int f = 0; f < 6; f++) {
-            VD_CHECK(P->phi_bc.kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");
+            VD_CHECK(P->phi_bc.kind[f] != VD_BC_PERIODIC && P->energy_bc.kind[f] != VD_BC_PERIODIC,
+                     "a masked step takes no periodic face");
             for (int k = 0; k < P->S; k++) VD_CHECK(P->species_bc[k].kind[f] != VD_BC_PERIODIC, "a masked step takes no periodic face");
         }
     }
@@ -429,6 +429,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             vd_problem ep;
             memset(&ep, 0, sizeof(ep));
             ep.grid = g; ep.bc = implicit_bc(P->energy_bc); ep.alpha_c = 1.0 / dt;
+            ep.mask = P->mask;
             ep.beta = var_idx[e] >= 0 ? B->beta_e.p : nullptr;
             ep.beta_c = 5.0 / 3.0 * D_c[e];
             ep.rhs = B->Erhs.p; ep.x = st->Ee;

@@ -110,8 +110,9 @@ def test_mask_rejects_unsupported_combinations(oracle):
     m[0] = 0
     c2 = dict(cfg, phi_bc=I.bc([D, D, P, P, N, N], [1000.0, 0, 0, 0, 0, 0]))
     assert oracle.step(c2, sp, mask=m)["status"] != 0
-    c3 = dict(cfg, te_mode=I.TE_ENERGY)
-    assert oracle.step(c3, sp, Ee=np.ones(8 ** 3), mask=m)["status"] != 0
+    ph = {"A": [1e3], "lam": [20.0], "pO2": 150.0, "pg": 760.0, "xi": 0.06, "pq": 30.0, "p": 760.0, "e": 0, "ion": 1}
+    assert oracle.step(cfg, sp, mask=m, photo=ph)["status"] != 0
+    assert oracle.step(cfg, sp, mask=m, diel=[1, 0, 0, 0, 0, 0], sigma=np.zeros(64))["status"] != 0
 
 
 def test_masked_adaptive_dt_equals_the_dirichlet_face_grid(oracle):
@@ -150,3 +151,45 @@ def test_masked_adaptive_dt_equals_the_dirichlet_face_grid(oracle):
     ds, db = rs["info"]["dt_used"], rb["info"]["dt_used"]
     assert ds < small["dt"]
     assert abs(db - ds) <= 1e-14 * ds
+
+
+def test_masked_energy_equation_equals_the_dirichlet_face_grid(oracle):
+    """Electron energy (Eqs. (5)-(8)) in a masked step: the covered planes'
+    grid equals the grid with a Dirichlet x+ face (potential g, densities
+    and energy 0), Joule heating with the drift and diffusive electron face
+    fluxes included, to the solver tolerance."""
+    small = I.cfg1(n=16)
+    g = 250.0
+    nx, h = 16, small["grid"][3]
+    small["te_mode"] = I.TE_ENERGY
+    small["phi_bc"] = I.bc([D, D, N, N, N, N], [1000.0, g, 0, 0, 0, 0])
+    small["species_bc"] = [I.bc([W, D, N, N, N, N], [0, 0, 0, 0, 0, 0])] * 3
+    small["energy_bc"] = I.bc([W, D, N, N, N, N], [0, 0, 0, 0, 0, 0])
+    kB = 1.380649e-23
+    Ee_s = 1.5 * small["n"][0] * kB * small["Te"]
+    big = dict(small)
+    nb = nx + 2
+    big["grid"] = (nb, 16, 16, h, h, h)
+    nbig = np.full((3, 16, 16, nb), 2e15)
+    nbig[:, :, :, :nx] = small["n"]
+    pbig = np.zeros((16, 16, nb))
+    pbig[:, :, nx:] = g
+    big["n"], big["phi"] = nbig, pbig
+    big["Te"] = np.full((16, 16, nb), small["Te"][0, 0, 0])
+    big["phi_bc"] = I.bc([D, N, N, N, N, N], [1000.0, 0, 0, 0, 0, 0])
+    big["species_bc"] = [I.bc([W, W, N, N, N, N])] * 3
+    big["energy_bc"] = I.bc([W, W, N, N, N, N])
+    Ee_b = np.full((16, 16, nb), 7e-3)
+    Ee_b[:, :, :nx] = Ee_s
+    mask = np.ones((16, 16, nb), np.uint8)
+    mask[:, :, nx:] = 0
+    sp = oracle.species_ar3()
+    kw = dict(poisson=oracle.mg_opts(**TOL_MG), species_mg=oracle.mg_opts(**TOL_MG), energy_mg=oracle.mg_opts(**TOL_MG),
+              electron=0, m_bg=39.948 * 1.66053906660e-27)
+    rs = oracle.step(small, sp, Ee=Ee_s, **kw)
+    rb = oracle.step(big, sp, Ee=Ee_b, mask=mask, **kw)
+    assert rs["status"] == 0 and rb["status"] == 0
+    for a, b in ((rb["Ee"][:, :, :nx], rs["Ee"]), (rb["Te"][:, :, :nx], rs["Te"]), (rb["n"][0][:, :, :nx], rs["n"][0])):
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
+    assert np.all(rb["Ee"][:, :, nx:] == 0.0)
+    assert np.abs(rs["Ee"] - Ee_s).max() > 1e-6 * np.abs(Ee_s).max()     # the energy really moved
