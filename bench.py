@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--species-guess", choices=["extrap", "previous"], default="extrap",
                     help="species initial guesses: extrapolated from the last three steps, or the current "
                          "densities")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the timings of the step with photoionization, surface charge / emission / adaptive "
+                         "step, and an interior masked electrode")
     ap.add_argument("--no-guess-variant", action="store_true",
                     help="skip the comparison run with the previous step's values as the guesses")
     ap.add_argument("--species-levels", type=int, default=1)
@@ -121,6 +124,78 @@ def learned_guess(ctx, V, I, cfg, rho, args):
     out = {"learned_fp64": WS.time_to_tol(ctx, d, V.GUESS_LEARNED, V.FP64, reps=args.poisson_reps),
            "learned_fp32_ir": WS.time_to_tol(ctx, d, V.GUESS_LEARNED, V.FP32_IR, reps=args.poisson_reps)}
     out["learned_network"] = how
+    return out
+
+
+def widened_variants(ctx, V, I, cfg, species, lfa, popts, sopts, state0, args, dev):
+    """The same workload and solver options with each widened row switched
+    on, from the same initial state: warmup steps, then timed steps
+    (ms/step, cell-steps/s, cycles of the last step).  Photoionization:
+    three Helmholtz terms with synthetic coefficients (A_j, lambda_j of the
+    three-exponential form, p_O2 = 150 Torr, p = p_g = 760 Torr, p_q = 30
+    Torr, xi = 0.06) into the electrons and Ar+, solved in FP64.  Surface charge: the y- face
+    dielectric (sigma from 0), secondary emission gamma = 0.1, Eq. (20)
+    limits with c_adv 0.3, c_diff 10, c_diel 0.5 and dt as their cap.
+    Masked: a grounded post (covered box of n/8 x n/8 x n/8 cells at 0 V)
+    three quarters of the way to the x+ plate."""
+    import torch
+    from paper_2507_08200_amd import mechanisms as M
+    n = cfg["grid"][0]
+    ncell = n ** 3
+    steps = min(args.steps, 20)
+    out = {}
+
+    def run(tag, P, note, fam=None, init=None):
+        st = {k: v.clone() for k, v in (init or state0).items()}
+        ctx.vd_step_reset()
+        for w in range(args.warmup):
+            ctx.vd_step(P, st, want_info=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(steps):
+            ctx.vd_step(P, st, want_info=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        if fam:
+            ctx.vd_timing_select(fam)
+        inf = ctx.vd_step(P, st)
+        r = {"ms_per_step": round(el * 1e3 / steps, 4), "value": round(ncell * steps / el, 1), "steps": steps,
+             "poisson_cycles_last_step": inf["poisson_cycles"], "species_cycles_last_step": inf["species_cycles"],
+             "dt_used": inf["dt_used"], "note": note}
+        if fam:
+            r["family_ms_last_step"] = {}
+            for f in fam.split(","):
+                c, ms, by = ctx.vd_timing_read(f)
+                if c:
+                    r["family_ms_last_step"][f] = round(ms, 4)
+            ctx.vd_timing_select(None)
+        out[tag] = r
+        log("[bench] widened %s: %s" % (tag, r))
+        del st
+
+    ph = {"A": [1.4e3, 2.6e4, 3.3e5], "lam": [21.0, 70.0, 330.0], "pO2": 150.0, "pg": 760.0, "xi": 0.06,
+          "pq": 30.0, "p": 760.0, "e": 0, "ion": 1, "bc": I.bc([I.BC_DIRICHLET] * 6),
+          "mg": V.mg_opts(rtol=1e-10)}
+    run("photoionization", V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts, photo=ph),
+        "NEXT-1: three photoionization Helmholtz terms (synthetic coefficients), FP64 multigrid to 1e-10 from the "
+        "previous step's terms (their right-hand sides, ~1e38 m^-3 s^-1 here, exceed the FP32 range of the refinement "
+        "corrections)")
+    sig = torch.zeros(n * n, dtype=torch.float64, device=dev)
+    run("surface_charge_emission_adaptive_dt",
+        V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts, diel=[0, 0, 1, 0, 0, 0], sigma=sig,
+                      see_gamma=0.1, adaptive_dt={"c_adv": 0.3, "c_diff": 10.0, "c_diel": 0.5}, electron=0),
+        "NEXT-3 and a12: y- face dielectric, gamma 0.1, Eq. (20) step capped at dt")
+    mask = torch.ones((n, n, n), dtype=torch.uint8, device=dev)
+    a, b = n * 3 // 4, n * 3 // 4 + n // 8
+    c0, c1 = n * 7 // 16, n * 7 // 16 + n // 8
+    mask[c0:c1, c0:c1, a:b] = 0
+    init = {k: v.clone() for k, v in state0.items()}
+    init["phi"][mask == 0] = 0.0
+    run("masked_electrode", V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts, mask=mask),
+        "NEXT-2: %d covered cells (a grounded post); drift: the tiled kernel, then the masked per-cell function on "
+        "the cells within three of a covered cell" % int((mask == 0).sum().item()),
+        fam=",".join(FAMILIES), init=init)
+    del init
     return out
 
 
@@ -483,6 +558,8 @@ def main():
         del stg
         log("[bench] previous-values guess variant: %s" % guess_variant)
 
+    widened = None if args.no_widened else widened_variants(ctx, V, I, cfg, species, lfa, popts, sopts, state0, args, dev)
+
     avg_ms = kms / launches if launches else 0.0
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if launches and avg_ms > 0 else 0.0
     roofline = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -557,6 +634,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_variant": fp64_variant,
         "previous_values_guess_variant": guess_variant,
+        "widened_rows": widened,
         "error_vs_fp64_oracle": errors,
         "poisson_time_to_1e-10": poisson,
         "batched_helmholtz_64": batch,

@@ -722,6 +722,53 @@ __global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
     }
 }
 
+// masked step: the cells flagged by k_mask_near get their divergence again
+// from the mask-aware per-cell functions, after the unmasked kernels have
+// filled every cell (elsewhere the masked formulas are the unmasked ones)
+__global__ void __launch_bounds__(kBlock) k_drift_fix(DriftArgs a) {
+    const GridDev &G = a.g;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell || !gld(a.near, (long)c)) return;
+    const FieldDesc F = a.f[blockIdx.y];
+    int pos[3];
+    pos[2] = c / G.nxy;
+    int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    double div = drift_div_cell(G, F, a.phi, a.Te, a.Tg, a.kB, a.me, c, pos);
+    if (a.mode == 0) {
+        gst(F.out, c, div);
+    } else {
+        double v = gld(F.u0, c) * a.inv_dt - div;
+        if (F.src) v += gld(F.src, c);
+        if (F.extra) v += gld(F.extra, c);
+        gst(F.out, c, v);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_mask_near(GridDev G, uint8_t *__restrict__ near) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.ncell) return;
+    int pos[3];
+    pos[2] = c / G.nxy;
+    const int r = c - pos[2] * G.nxy;
+    pos[1] = r / G.n[0];
+    pos[0] = r - pos[1] * G.n[0];
+    bool f = !gld(G.mask, (long)c);
+    for (int d = 0; d < 3 && !f; d++)
+        for (int o = -3; o <= 3; o++) {
+            const int p = pos[d] + o;
+            if (o == 0 || p < 0 || p >= G.n[d]) continue;
+            if (!gld(G.mask, (long)c + (long)o * G.stride[d])) { f = true; break; }
+        }
+    gst(near, (long)c, (uint8_t)(f ? 1 : 0));
+}
+
+void launch_mask_near(vd_ctx *ctx, const GridDev &G, uint8_t *near) {
+    k_mask_near<<<ceil_div(G.ncell, kBlock), kBlock, 0, ctx->stream>>>(G, near);
+    VD_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------ chemistry
 constexpr double kEvK = 11604.518;
 
@@ -1172,6 +1219,19 @@ void launch_transport(vd_ctx *ctx, const TransportArgs &a) {
 
 void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields, const char *tag) {
     if (nfields == 0) return;
+    if (a.g.mask && a.near) {
+        // masked step: the unmasked kernels over every cell, then the cells
+        // whose stencils reach a covered cell again with the mask
+        DriftArgs au = a;
+        au.g.mask = nullptr;
+        au.near = nullptr;
+        launch_drift(ctx, au, fields, nfields, tag);
+        dim3 grid(ceil_div(a.g.ncell, kBlock), nfields);
+        a.f = (const FieldDesc *)upload_blob(ctx, std::string("fields:") + tag, fields, sizeof(FieldDesc) * nfields);
+        timed(ctx, "weno", 0.0, [&] { k_drift_fix<<<grid, kBlock, 0, ctx->stream>>>(a); });
+        VD_HIP(hipGetLastError());
+        return;
+    }
     VD_CHECK(nfields <= kMaxFields, "too many fields");
     a.f = (const FieldDesc *)upload_blob(ctx, std::string("fields:") + tag, fields, sizeof(FieldDesc) * nfields);
     dim3 grid(ceil_div(a.g.ncell, kBlock), nfields);

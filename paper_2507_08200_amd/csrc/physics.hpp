@@ -56,6 +56,7 @@ struct DriftArgs {
     double Tg, kB, me, inv_dt;
     int mode;
     const FieldDesc *f;    // device table, one entry per field (blockIdx.y)
+    const uint8_t *near;   // masked step: cells whose stencils reach a covered cell (or null)
 };
 
 struct TransportArgs {
@@ -155,6 +156,9 @@ void launch_rho(vd_ctx *ctx, const RhoArgs &a);
 // right-hand side of their valid neighbours, and their restore after a solve
 void launch_mask_lift(vd_ctx *ctx, const GridDev &G, const double *phi_cov, const double *eps, double eps0, double *rho);
 void launch_mask_restore(vd_ctx *ctx, const GridDev &G, const double *phi_cov, double *phi);
+// masked step: flag the cells that are covered or have a covered cell
+// within three cells along x, y or z (their drift stencils reach one)
+void launch_mask_near(vd_ctx *ctx, const GridDev &G, uint8_t *near);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
 void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a);

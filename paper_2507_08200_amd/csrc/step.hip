@@ -13,6 +13,7 @@ struct StepBuffers {
     int S = 0;
     DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
     DevBuf<double> ion, photo, prhs, sig0, dtpart, phic;
+    DevBuf<uint8_t> near;
     bool photo_zeroed = false;
 };
 
@@ -192,6 +193,8 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
     if (P->mask) {
         B->phic.alloc(N);
         VD_HIP(hipMemcpyAsync(B->phic.p, st->phi, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        B->near.alloc(N);
+        launch_mask_near(ctx, G, B->near.p);
     }
     vd_step_info I;
     memset(&I, 0, sizeof(I));
@@ -444,6 +447,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         memset(&da, 0, sizeof(da));
         da.g = G; da.phi = st->phi; da.Te = st->Te; da.Tg = P->Tg; da.kB = P->consts.kB; da.me = P->consts.me;
         da.inv_dt = 1.0 / dt; da.mode = 1;
+        da.near = P->mask ? B->near.p : nullptr;
         vd_problem sp[32];
         FieldDesc fds[32];
         memset(fds, 0, sizeof(fds));
