@@ -868,7 +868,11 @@ __global__ void __launch_bounds__(kBlock) k_res25u(const LevDesc *__restrict__ d
 // r^2 (and of b^2 when partials_b is given); MODE 2: also r rounded to FP32
 // into the FP32 hierarchy's finest right-hand side (either row layout) and,
 // unless keep_e, its unknown cleared.
-template <int MODE, int KZ>
+struct MaskPair {
+    unsigned char x, y;   // validity of the cells of a pair (1 valid, 0 covered)
+};
+
+template <int MODE, int KZ, bool MASK = false>
 __global__ void __launch_bounds__(kBlock) k_resd(const LevDesc *__restrict__ descs, const LevDesc *__restrict__ d32,
                                                  Plan pl, int keep_e, double *__restrict__ partials,
                                                  const ProbState *__restrict__ st, int check_active,
@@ -917,6 +921,18 @@ __global__ void __launch_bounds__(kBlock) k_resd(const LevDesc *__restrict__ des
         const bool rbE = MODE == 2 && d32[id].rb;
         const int nh = nx >> 1;
         PairD xm = zpair(k0 - 1), xc = zpair(k0);
+        // masked levels: validity of the pair's cells and of their six
+        // neighbours (a covered neighbour is a homogeneous Dirichlet face:
+        // its value reads as 0 and the diagonal gains the face coefficient
+        // once more; a covered cell has no residual)
+        // (a plan may mix masked and unmasked problems: only a problem
+        // with a mask has a mask array)
+        const bool mk = MASK && L.has_mask;
+        const uint8_t *__restrict__ MK = mk ? L.mask : nullptr;
+        auto mpair = [&](int off) -> MaskPair {
+            const uint16_t v = *(const VD_GAS uint16_t *)(MK + off);
+            return MaskPair{(unsigned char)(v & 0xFFu), (unsigned char)(v >> 8)};
+        };
 #pragma unroll
         for (int q = 0; q < KZ; q++) {
             const int k = k0 + q;
@@ -926,6 +942,19 @@ __global__ void __launch_bounds__(kBlock) k_resd(const LevDesc *__restrict__ des
             const double wl0 = gld(X, ol + pk), wr0 = gld(X, orr + pk);
             const PairD ys0 = ldp(os + pk), yn0 = ldp(on + pk);
             const PairD bv = __builtin_nontemporal_load((const VD_GAS PairD *)(B + oc + pk));
+            MaskPair mo{1, 1}, ms{1, 1}, mn{1, 1}, mzm{1, 1}, mzp{1, 1};
+            unsigned char ml = 1, mr = 1;
+            bool okzm = true, okzp = true;
+            if (MASK && mk) {
+                mo = mpair(oc + pk);
+                ml = okl ? MK[ol + pk] : (unsigned char)1;
+                mr = okr ? MK[orr + pk] : (unsigned char)1;
+                if (oks) ms = mpair(os + pk);
+                if (okn) mn = mpair(on + pk);
+                const int kwm = wrap_idx(k - 1, nz, pz, okzm), kwp = wrap_idx(k + 1, nz, pz, okzp);
+                if (okzm) mzm = mpair(oc + nxy * kwm);
+                if (okzp) mzp = mpair(oc + nxy * kwp);
+            }
             const double wl = okl ? wl0 : 0.0, wr = okr ? wr0 : 0.0;
             const PairD ys = oks ? ys0 : PairD{0.0, 0.0}, yn = okn ? yn0 : PairD{0.0, 0.0};
             double rv[2];
@@ -957,13 +986,31 @@ __global__ void __launch_bounds__(kBlock) k_resd(const LevDesc *__restrict__ des
                     fc[5] = c == 0 ? fzh.x : fzh.y;
                     if (!fb) for (int f = 0; f < 6; f++) fc[f] = bc;
                     const double al = L.var_alpha ? (c == 0 ? alp.x : alp.y) : L.alpha_c;
+                    bool cov[6] = {false, false, false, false, false, false}, own_valid = true;
+                    if (MASK && mk) {
+                        own_valid = (c == 0 ? mo.x : mo.y) != 0;
+                        cov[0] = (c == 0 ? (okl && !ml) : !mo.x);
+                        cov[1] = (c == 0 ? !mo.y : (okr && !mr));
+                        cov[2] = oks && !(c == 0 ? ms.x : ms.y);
+                        cov[3] = okn && !(c == 0 ? mn.x : mn.y);
+                        cov[4] = okzm && !(c == 0 ? mzm.x : mzm.y);
+                        cov[5] = okzp && !(c == 0 ? mzp.x : mzp.y);
+                        for (int f = 0; f < 6; f++)
+                            if (cov[f]) nbv[f] = 0.0;
+                    }
                     double dg, of, lf;
                     row_terms_fc<double>(L, i, j, k, nbv, fc, al, dg, of, lf);
+                    if (MASK && mk) {
+                        const double ih2[3] = {L.idx2, L.idy2, L.idz2};
+                        for (int f = 0; f < 6; f++)
+                            if (cov[f]) dg += fc[f] * ih2[f >> 1];
+                    }
                     double b = c == 0 ? bv.x : bv.y;
                     if (lift) b = b + lf;
                     rv[c] = b - (dg * (c == 0 ? xc.x : xc.y) - of);
+                    if (MASK && !own_valid) rv[c] = 0.0;
                     v += rv[c] * rv[c];
-                    if (partials_b) vb += b * b;
+                    if (partials_b && own_valid) vb += b * b;
                 }
             }
             if (MODE == 2) {
@@ -3209,30 +3256,39 @@ static void launch_norm(vd_ctx *ctx, Solver &S, int mode, int check_active, bool
     const HPlan &pl = S.all0;
     hipStream_t s = ctx->stream;
     // the direct (barrier-free) residual kernels for tiles of 2, 4 or 8 planes
-    auto direct = [&](const HPlan &q, auto mode_tag) -> bool {
+    auto direct = [&](const HPlan &q, auto mode_tag, auto mask_tag) -> bool {
         constexpr int M = decltype(mode_tag)::value;
+        constexpr bool MK = decltype(mask_tag)::value;
         const dim3 g = xcd_grid(q.ntiles);
         const Plan P = q.dev();
         if (q.kz == 8)
-            k_resd<M, 8><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+            k_resd<M, 8, MK><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
         else if (q.kz == 4)
-            k_resd<M, 4><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+            k_resd<M, 4, MK><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
         else if (q.kz == 2)
-            k_resd<M, 2><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
+            k_resd<M, 2, MK><<<g, kBlock, 0, s>>>(S.d64.p, S.d32.p, P, ksel, S.partials.p, S.st.p, check_active, pb);
         else
             return false;
         return true;
     };
     auto launch25 = [&](const HPlan &q, bool uni) {
-        // uniform levels: the LDS march; levels with coefficient arrays and
-        // no mask: the direct kernel; masked levels: the general march
+        // uniform levels: the LDS march; levels with coefficient arrays or a
+        // mask: the direct kernel (the general march for other tile depths)
         bool masked = false;
         for (int id : q.h_ids) masked = masked || S.probs[id / S.Lmax].has_mask;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
+        using NoMask = std::false_type;
+        using Masked = std::true_type;
         if (!masked && !uni) {
-            if (mode == 1 && direct(q, I1{})) return;
-            if (mode == 2 && direct(q, I2{})) return;
+            if (mode == 1 && direct(q, I1{}, NoMask{})) return;
+            if (mode == 2 && direct(q, I2{}, NoMask{})) return;
+        }
+        // masked levels (uniform coefficients or arrays): the direct kernel
+        // with the mask (covered neighbours as homogeneous Dirichlet faces)
+        if (masked) {
+            if (mode == 1 && direct(q, I1{}, Masked{})) return;
+            if (mode == 2 && direct(q, I2{}, Masked{})) return;
         }
         if (mode == 1 && uni)
             k_res25u<1><<<xcd_grid(q.ntiles), kBlock, 0, s>>>(S.d64.p, S.d32.p, q.dev(), q.kz, 0, S.partials.p, S.st.p,
