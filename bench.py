@@ -175,11 +175,11 @@ def widened_variants(ctx, V, I, cfg, species, lfa, popts, sopts, state0, args, d
 
     ph = {"A": [1.4e3, 2.6e4, 3.3e5], "lam": [21.0, 70.0, 330.0], "pO2": 150.0, "pg": 760.0, "xi": 0.06,
           "pq": 30.0, "p": 760.0, "e": 0, "ion": 1, "bc": I.bc([I.BC_DIRICHLET] * 6),
-          "mg": V.mg_opts(rtol=1e-10)}
+          "mg": V.mg_opts(rtol=1e-10, precision=V.FP32_IR)}
     run("photoionization", V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts, photo=ph),
-        "NEXT-1: three photoionization Helmholtz terms (synthetic coefficients), FP64 multigrid to 1e-10 from the "
-        "previous step's terms (their right-hand sides, ~1e38 m^-3 s^-1 here, exceed the FP32 range of the refinement "
-        "corrections)")
+        "NEXT-1: three photoionization Helmholtz terms (synthetic coefficients), FP32-in-FP64 refinement to 1e-10 "
+        "from the previous step's terms, each term solved in units of a power of two near its largest right-hand "
+        "side (~1e38 m^-3 s^-1 here)")
     sig = torch.zeros(n * n, dtype=torch.float64, device=dev)
     run("surface_charge_emission_adaptive_dt",
         V.step_params(cfg, species, lfa=lfa, poisson=popts, species_mg=sopts, diel=[0, 0, 1, 0, 0, 0], sigma=sig,

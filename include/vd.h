@@ -291,7 +291,10 @@ typedef struct {
      * lambda_j p_O2 in 1/m, A_j p_g^2 in 1/m^2.  photo_mg.guess: VD_GUESS_GIVEN
      * starts each term from its solution of the previous call (zero at
      * first), VD_GUESS_ZERO from zero.  photo_out: device [3][cells] or NULL,
-     * receives the S_j of the last corrector. */
+     * receives the S_j of the last corrector.  Each term is solved for S_j /
+     * 2^e, 2^e the power of two at or above its right-hand side's largest
+     * magnitude (exact in FP64; keeps VD_FP32_IR corrections in range; one
+     * host synchronisation per corrector). */
     int32_t photo_n, photo_e, photo_ion;
     int32_t dt_mode;                /* 0: dt; 1: adaptive time step (Sec. 3, Eq. (20)) */
     double photo_A[3], photo_lambda[3];

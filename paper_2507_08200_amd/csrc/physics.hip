@@ -942,7 +942,10 @@ __global__ void __launch_bounds__(kBlock) k_photo_rhs(PhotoArgs a) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     const double si = gld(a.ion, c);
-    for (int q = 0; q < a.nterm; q++) gst(a.rhs, q * a.ncell + c, a.coef[q] * si);
+    for (int q = 0; q < a.nterm; q++) {
+        gst(a.rhs, q * a.ncell + c, (a.coef[q] * si) * a.inv_scale[q]);
+        if (a.ratio[q] != 1.0) gst(a.S, q * a.ncell + c, gld(a.S, q * a.ncell + c) * a.ratio[q]);
+    }
 }
 
 // S_ph = sum_q S_q into the electron and ion sources
@@ -950,9 +953,32 @@ __global__ void __launch_bounds__(kBlock) k_photo_add(PhotoArgs a) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     double s = 0.0;
-    for (int q = 0; q < a.nterm; q++) s += gld(a.S, q * a.ncell + c);
+    for (int q = 0; q < a.nterm; q++) s += gld(a.S, q * a.ncell + c) * a.scale[q];
     gst(a.Ge, c, gld(a.Ge, c) + s);
     gst(a.Gi, c, gld(a.Gi, c) + s);
+}
+
+__global__ void __launch_bounds__(kBlock) k_photo_max(const double *__restrict__ ion, long n, double *__restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double m = c < n ? fabs(gld(ion, c)) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(m, o, 64);
+        m = v > m ? v : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < kBlock / 64; w++) r = red[w] > r ? red[w] : r;
+        gst(partial, (long)blockIdx.x, r);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_photo_unscale(PhotoArgs a, double *__restrict__ out) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    for (int q = 0; q < a.nterm; q++) gst(out, q * a.ncell + c, gld(a.S, q * a.ncell + c) * a.scale[q]);
 }
 
 // One dielectric face (Sec. 2.1, Eq. (13)), one thread per face position
@@ -1341,6 +1367,18 @@ void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a) {
     timed(ctx, "photo", (double)a.ncell * 8.0 * (1 + a.nterm), [&] {
         k_photo_rhs<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
     });
+}
+
+int launch_photo_max(vd_ctx *ctx, const double *ion, long ncell, double *partial) {
+    const int nb = ceil_div(ncell, kBlock);
+    k_photo_max<<<nb, kBlock, 0, ctx->stream>>>(ion, ncell, partial);
+    VD_HIP(hipGetLastError());
+    return nb;
+}
+
+void launch_photo_unscale(vd_ctx *ctx, const PhotoArgs &a, double *out) {
+    k_photo_unscale<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a, out);
+    VD_HIP(hipGetLastError());
 }
 
 void launch_photo_add(vd_ctx *ctx, const PhotoArgs &a) {

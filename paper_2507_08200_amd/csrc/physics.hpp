@@ -92,9 +92,14 @@ struct PhotoArgs {
     long ncell;
     int nterm;
     double coef[3];
+    // each term is solved for S_q / scale[q] (a power of two near its
+    // right-hand side's largest magnitude): exact in FP64, and the FP32
+    // corrections of a refinement stay in range; ratio[q] = the previous
+    // scale / this one rescales the stored terms, the next starting iterates
+    double scale[3], inv_scale[3], ratio[3];
     const double *ion;     // S_i per cell
     double *rhs;           // [nterm][cells]
-    const double *S;       // [nterm][cells]
+    double *S;             // [nterm][cells], scaled terms
     double *Ge, *Gi;
 };
 
@@ -162,6 +167,10 @@ void launch_mask_near(vd_ctx *ctx, const GridDev &G, uint8_t *near);
 void launch_energy(vd_ctx *ctx, const EnergyArgs &a);
 void launch_mid(vd_ctx *ctx, const double *u0, const double *u, double *out, long n);
 void launch_photo_rhs(vd_ctx *ctx, const PhotoArgs &a);
+// per-workgroup maxima of |S_i| (partial), returns the number of workgroups
+int launch_photo_max(vd_ctx *ctx, const double *ion, long ncell, double *partial);
+// out[q] = S[q] * scale[q] (the terms in physical units)
+void launch_photo_unscale(vd_ctx *ctx, const PhotoArgs &a, double *out);
 void launch_photo_add(vd_ctx *ctx, const PhotoArgs &a);
 void launch_sigma(vd_ctx *ctx, const SigmaArgs &a, int update);
 // per-workgroup minima of the time-step limits into a.partial; returns the

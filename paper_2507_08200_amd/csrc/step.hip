@@ -12,7 +12,8 @@ struct StepBuffers {
     long ncell = 0;
     int S = 0;
     DevBuf<double> rho, G, b, S_inel, mu, D, n0, nstar, Ee0, Eestar, Erhs, beta_e;
-    DevBuf<double> ion, photo, prhs, sig0, dtpart, phic;
+    DevBuf<double> ion, photo, prhs, sig0, dtpart, phic, pmax;
+    double photo_scale[3] = {1.0, 1.0, 1.0};   // scales of the stored photoionization terms
     DevBuf<uint8_t> near;
     bool photo_zeroed = false;
 };
@@ -241,7 +242,9 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         if (!B->photo_zeroed) {
             VD_HIP(hipMemsetAsync(B->photo.p, 0, sizeof(double) * N * 3, s));
             B->photo_zeroed = true;
+            for (int q = 0; q < 3; q++) B->photo_scale[q] = 1.0;
         }
+        B->pmax.alloc(ceil_div(N, kBlock));
     }
     // wall variants of a species' field: sticking and secondary emission
     auto wall_variants = [&](FieldDesc &F, int k, const double *nbase) {
@@ -391,10 +394,27 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             const double cem = P->photo_pq / (P->photo_p + P->photo_pq) * P->photo_xi * P->photo_nu_ratio;
             vd_problem pr[3];
             memset(pr, 0, sizeof(pr));
+            // each term's scale: the power of two at or above its
+            // right-hand side's largest magnitude (one host synchronisation)
+            const int nbm = launch_photo_max(ctx, B->ion.p, N, B->pmax.p);
+            std::vector<double> pm(nbm);
+            VD_HIP(hipMemcpyAsync(pm.data(), B->pmax.p, sizeof(double) * nbm, hipMemcpyDeviceToHost, s));
+            VD_HIP(hipStreamSynchronize(s));
+            double mion = 0.0;
+            for (double v : pm) mion = v > mion ? v : mion;
             for (int q = 0; q < P->photo_n; q++) {
                 pa.coef[q] = P->photo_A[q] * P->photo_pg * P->photo_pg * cem;
+                const double m = std::fabs(pa.coef[q]) * mion;
+                int e = 0;
+                double sc = 1.0;
+                if (m > 0.0 && std::isfinite(m)) { (void)std::frexp(m, &e); sc = std::ldexp(1.0, e); }
+                pa.scale[q] = sc;
+                pa.inv_scale[q] = 1.0 / sc;
+                pa.ratio[q] = B->photo_scale[q] / sc;
+                B->photo_scale[q] = sc;
                 const double kl = P->photo_lambda[q] * P->photo_pO2;
                 pr[q].grid = g; pr[q].bc = P->photo_bc; pr[q].alpha_c = kl * kl; pr[q].beta_c = 1.0;
+                for (int f = 0; f < 6; f++) pr[q].bc.value[f] = P->photo_bc.value[f] * pa.inv_scale[q];
                 pr[q].rhs = B->prhs.p + (long)q * N; pr[q].x = B->photo.p + (long)q * N;
             }
             launch_photo_rhs(ctx, pa);
@@ -542,8 +562,13 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             VD_HIP(hipEventElapsedTime(&a, ev[3], ev[5])); ms_species += a;
         }
     }
-    if (P->photo_n > 0 && P->photo_out)
-        VD_HIP(hipMemcpyAsync(P->photo_out, B->photo.p, sizeof(double) * N * P->photo_n, hipMemcpyDeviceToDevice, s));
+    if (P->photo_n > 0 && P->photo_out) {
+        PhotoArgs pu;
+        memset(&pu, 0, sizeof(pu));
+        pu.ncell = N; pu.nterm = P->photo_n; pu.S = B->photo.p;
+        for (int q = 0; q < P->photo_n; q++) pu.scale[q] = B->photo_scale[q];
+        launch_photo_unscale(ctx, pu, P->photo_out);
+    }
     if (energy) {
         // Te from the new electron energy and density
         TransportArgs ta;

@@ -93,6 +93,32 @@ def test_step_photoionization_guess_from_previous_call(ctx, V):
     assert torch.equal(out1, out2)
 
 
+def test_step_photoionization_fp32_refinement(ctx, V, oracle):
+    """The terms (~1e26 here) and their right-hand sides are beyond the FP32
+    range of the refinement's sums unless each term is solved in units of a
+    power of two near its largest right-hand side: FP32-in-FP64 refinement
+    to 1e-11 then meets the oracle's FP64 solve to the same tolerance."""
+    from paper_2507_08200_amd import mechanisms as M
+    cfg = I.cfg1()
+    cfg["Te"] = np.full_like(cfg["Te"], 5.0 * I.EV_IN_K)
+    state = {k: dev(cfg[k]) for k in ("n", "phi", "Te")}
+    out = torch.zeros((3,) + cfg["phi"].shape, dtype=torch.float64, device="cuda")
+    ph = dict(PHOTO, bc=I.bc([D] * 6))
+    P = V.step_params(cfg, M.ar3(), poisson=V.mg_opts(fixed_cycles=12), species_mg=V.mg_opts(fixed_cycles=2),
+                      photo=dict(ph, mg=V.mg_opts(rtol=1e-11, precision=V.FP32_IR, guess=V.GUESS_ZERO), out=out))
+    say("step cfg1 + photoionization, FP32 refinement to 1e-11")
+    ctx.vd_step(P, state)
+    ref = oracle.step(cfg, oracle.species_ar3(), poisson=oracle.mg_opts(fixed_cycles=12),
+                      species_mg=oracle.mg_opts(fixed_cycles=2), photo=dict(ph, mg=oracle.mg_opts(rtol=1e-11)))
+    assert ref["status"] == 0
+    o = host(out)
+    assert float(np.abs(o).max()) > 1e25
+    errs = [rel_err(o[q], ref["photo_S"][q]) for q in range(3)]
+    errs.append(rel_err(host(state["n"])[0], ref["n"][0]))
+    say("   errors", ["%.1e" % e for e in errs])
+    assert max(errs) <= 1e-9, errs
+
+
 def test_step_adaptive_dt(ctx, V, oracle):
     """Eq. (20) with dt = 1e-9 s as the largest step: the advection limit
     in the cells next to the 1 kV plate is smaller; the step takes it and
