@@ -573,6 +573,7 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
     auto zp = [&](int k) -> double { return gld(phi, col + nxy * wrapc(k, nz, pzp)); };
     auto zm = [&](int k) -> double { return gld(mup, col + nxy * wrapc(k, nz, fzp)); };
     const double ihx = G.ih[0], ihy = G.ih[1], ihz = G.ih[2];
+    const bool inner = bx > 0 && bx < tiles_x - 1 && by > 0 && by < tiles_y - 1;
     // the z face above plane k from the column registers
     // column registers: z1..z6 = field at planes k-2 .. k+3
     double z1, z2, z3, z4, z5, z6;
@@ -624,7 +625,23 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
         // one loop, with the direction chosen by selects: a wavefront
         // holding both kinds evaluates each face once
         constexpr int kNFX = kDY * (kDX + 1), kNFY = (kDY + 1) * kDX;
-        for (int q = tid; q < kNFX + kNFY; q += kBlock) {
+        if (inner) {
+            // a tile away from the x and y domain faces: no boundary rules
+            for (int q = tid; q < kNFX + kNFY; q += kBlock) {
+                const bool xf = q < kNFX;
+                const int qy = q - kNFX;
+                const int r = xf ? q / (kDX + 1) : qy / kDX;
+                const int f = xf ? q - r * (kDX + 1) : qy - r * kDX;
+                const int ub = xf ? (r + 3) * kUX + f : r * kUX + f + 3;
+                const int us = xf ? 1 : kUX;
+                const int pb = xf ? (r + 1) * kPX + f : r * kPX + f + 1;
+                const int ps = xf ? 1 : kPX;
+                const double fl = drift_face(F, lld(U, ub), lld(U, ub + us), lld(U, ub + 2 * us), lld(U, ub + 3 * us),
+                                             lld(U, ub + 4 * us), lld(U, ub + 5 * us), lld(P, pb), lld(P, pb + ps),
+                                             lld(M, pb), lld(M, pb + ps), xf ? ihx : ihy, false, false, 0, 0, 0.0);
+                lst(xf ? fx : fy, xf ? q : qy, fl);
+            }
+        } else for (int q = tid; q < kNFX + kNFY; q += kBlock) {
             const bool xf = q < kNFX;
             const int qy = q - kNFX;
             const int r = xf ? q / (kDX + 1) : qy / kDX;

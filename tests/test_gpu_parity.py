@@ -190,10 +190,12 @@ def test_errors(ctx, V):
 PHYS = {"qe": 1.602176634e-19, "eps0": 8.8541878128e-12, "kB": 1.380649e-23, "me": 9.1093837015e-31}
 
 
-@pytest.mark.parametrize("shape", [(20, 18, 16), (64, 16, 16), (32, 24, 32)])
+@pytest.mark.parametrize("shape", [(20, 18, 16), (64, 16, 16), (32, 24, 32), (128, 32, 16)])
 @pytest.mark.parametrize("kinds", [[2, 2, 3, 3, 1, 1], [0, 0, 1, 1, 3, 3], [3, 3, 2, 2, 0, 1]])
 def test_species_flux(ctx, oracle, kinds, shape):
-    """Per-cell kernel (ragged shapes) and tiled kernel (32 x 8 x 16 tiles)."""
+    """Per-cell kernel (ragged shapes) and tiled kernel (32 x 8 tiles; at
+    128 x 32 the tiles away from the x and y domain faces take the
+    kernel's interior face loop)."""
     rng = np.random.default_rng(601)
     nx, ny, nz = shape
     h = 1e-4
