@@ -207,7 +207,9 @@ def batch_bench(ctx, V, I, dev, reps, oracle_sample=True):
     """The 64-problem batch (edges 32..160 in steps of 16, unit cube, alpha 1,
     a 1e-3..1 sheath jump, random Dirichlet/Neumann faces, N(0,1) rhs) solved
     to 1e-10 from zero: one call per problem, one batched call, and the
-    batched call with graph replay and tile autotuning."""
+    batched call with graph replay and tile autotuning, with the tuned
+    smoothing schedule and with FP32 refinement; then the small problems
+    alone, plain, with graph replay and with persistent colour passes."""
     import numpy as np
     import torch
     probs = I.cfg4()
@@ -263,6 +265,27 @@ def batch_bench(ctx, V, I, dev, reps, oracle_sample=True):
             res["tuned_schedule_max_rel_res"] = max(i["rel_res"] for i in infos)
         else:
             res[name.replace("_ms", "_max_rel_diff_vs_sequential")] = dmax
+    # FP32 multigrid inside FP64 refinement on the same batch (same 1e-10)
+    ms, infos = timed_solve(bat(precision=V.FP32_IR))
+    res["batched_fp32_ir_ms"] = round(ms, 3)
+    res["batched_fp32_ir_max_rel_res"] = max(i["rel_res"] for i in infos)
+    # the batch's small problems (edges 32 and 48) alone: short launches,
+    # where the host's launch rate rather than HBM bounds a cycle
+    small = [g for g in gs if g["grid"][0] <= 48]
+    x_small = None
+    sm = {"problems": len(small), "cells": sum(g["grid"][0] ** 3 for g in small)}
+    for name, kw in (("batched_ms", {}), ("batched_graph_ms", {"graph": True}),
+                     ("batched_persistent_graph_ms", {"graph": True, "persistent": True})):
+        ms, _ = timed_solve(lambda: ctx.vd_helmholtz_solve_batched(
+            small, V.mg_opts(rtol=1e-10, guess=V.GUESS_ZERO, **kw))[0])
+        sm[name] = round(ms, 3)
+        xs = [g["x"].clone() for g in small]
+        if x_small is None:
+            x_small = xs
+        else:
+            sm[name.replace("_ms", "_max_rel_diff_vs_batched")] = max(
+                float((a - b).abs().max() / b.abs().max()) for a, b in zip(xs, x_small))
+    res["small_problems"] = sm
     infos = infos_graph
     cell_cycles = sum(i["cycles"] * p["grid"][0] ** 3 for i, p in zip(infos, probs))
     res["cell_cycles_per_s_batched_graph"] = round(cell_cycles / (res["batched_graph_ms"] * 1e-3), 1)
