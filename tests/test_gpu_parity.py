@@ -461,7 +461,8 @@ def test_ir_fused_corrections_match_cleared(ctx, V, oracle):
 def test_ir_parity_split_rows(ctx, V, shapes, kinds):
     """Parity-split corrections on rows that end inside a workgroup's tile
     and across periodic faces give the same iterate as lexicographic ones,
-    bit for bit up to 1e-13, at a fixed cycle count and in tolerance mode.
+    bit for bit up to 1e-13, at a fixed cycle count and in tolerance mode,
+    and as single-level V(1,0) refinement (the species solves' schedule).
     The lexicographic run is the same batch plus a uniform problem whose nx
     is not a multiple of 4, which keeps the whole batch lexicographic
     (batching changes no arithmetic; its coarse levels, like the others',
@@ -470,7 +471,7 @@ def test_ir_parity_split_rows(ctx, V, shapes, kinds):
     probs = [I.random_helmholtz(920 + q, s, alpha_kind="const", beta_kind="const", kinds=kinds) for q, s in enumerate(shapes)]
     extra = I.random_helmholtz(930, (38, 24, 24), alpha_kind="const", beta_kind="const",
                                kinds=[I.BC_DIRICHLET] * 6)
-    for opts in (dict(fixed_cycles=3), dict(rtol=1e-10)):
+    for opts in (dict(fixed_cycles=3), dict(rtol=1e-10), dict(fixed_cycles=3, n_levels=1, nu_pre=1, nu_post=0)):
         split = [gpu_problem(p) for p in probs]
         i_s, st = ctx.vd_helmholtz_solve_batched(split, V.mg_opts(precision=V.FP32_IR, ir_inner=1, **opts))
         assert st == 0
