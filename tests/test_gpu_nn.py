@@ -100,12 +100,19 @@ def test_network_forward(ctx):
     out = ctx.vd_nn_forward(g, bf16_dev(x)).cpu().numpy()
     ref, _ = N.forward(p.astype(np.float64), x, CFG, rounding=True)
     # identical up to FP32-vs-FP64 accumulation; a stored activation that sits
-    # at a bfloat16 rounding boundary may round the other way
+    # at a bfloat16 rounding boundary may round the other way (one bfloat16
+    # step, 2^-8 of it), which moves the outputs downstream of it: most
+    # outputs agree to the accumulation order (3e-8 of the scale at the 90th
+    # percentile), a few percent carry a flip's footprint (below 1e-3)
     err = np.abs(out - ref[..., 0])
     scale = np.abs(ref).max()
-    say("   forward max rel", err.max() / scale, "mean", err.mean() / scale)
-    assert err.max() <= 1e-2 * scale
-    assert err.mean() <= 1e-4 * scale
+    say("   forward max rel", err.max() / scale, "mean", err.mean() / scale,
+        "quantiles 0.5/0.9/0.99/0.999", [float(np.quantile(err, q) / scale) for q in (0.5, 0.9, 0.99, 0.999)],
+        "fraction above 1e-5", float(np.mean(err > 1e-5 * scale)))
+    assert np.quantile(err, 0.9) <= 1e-6 * scale
+    assert np.mean(err > 1e-5 * scale) <= 0.1
+    assert err.max() <= 4e-3 * scale
+    assert err.mean() <= 2e-5 * scale
 
 
 def test_train_step_gradients_and_adam(ctx):
@@ -120,9 +127,13 @@ def test_train_step_gradients_and_adam(ctx):
     l_ref, dout = N.mse(out[..., 0], t)
     g_ref = N.backward(p, cache, dout[..., None], CFG, grad_rounding=True)
     gl = np.linalg.norm(grads - g_ref) / np.linalg.norm(g_ref)
-    say("   loss", loss, l_ref, "grad rel L2", gl)
-    assert abs(loss - l_ref) <= 1e-4 * l_ref
-    assert gl <= 2e-3
+    gmax = np.abs(grads - g_ref).max() / np.abs(g_ref).max()
+    say("   loss", loss, l_ref, "grad rel L2", gl, "grad max-scaled", gmax)
+    # the device rounds dy to bfloat16 as the oracle's grad_rounding does;
+    # what is left is FP32 accumulation (2.6e-7 relative L2 on this sample)
+    assert abs(loss - l_ref) <= 1e-7 * l_ref
+    assert gl <= 1e-5
+    assert gmax <= 1e-5
     # the update: one Adam step from zero moments with the device gradients
     ctx.vd_nn_train_step(g, bf16_dev(x), f32_dev(t), lr=1e-3, update=True)
     g1 = ctx.vd_nn_get(1).astype(np.float64)
