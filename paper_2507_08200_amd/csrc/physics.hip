@@ -948,7 +948,7 @@ __global__ void __launch_bounds__(kBlock) k_rho(RhoArgs a) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     double s = 0.0;
-    for (int k = 0; k < a.S; k++) s += a.Z[k] * gld(a.n, k * a.ncell + c);
+    for (int m = 0; m < a.S; m++) s += a.Z[m] * gld(a.n, a.idx[m] * a.ncell + c);
     gst(a.rho, c, a.qe * s);
 }
 

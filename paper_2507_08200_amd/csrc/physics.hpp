@@ -131,9 +131,10 @@ struct DtArgs {
 
 struct RhoArgs {
     long ncell;
-    int S;
+    int S;                 // charged species only (neutrals add nothing)
     double qe;
-    double Z[32];
+    double Z[32];          // their charge numbers, in species order
+    int idx[32];           // and their species indices
     const double *n;
     double *rho;
 };

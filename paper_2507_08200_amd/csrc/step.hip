@@ -327,8 +327,10 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         // ---- Poisson at u*: -div(eps grad phi) = e sum Z n*
         RhoArgs ra;
         memset(&ra, 0, sizeof(ra));
-        ra.ncell = N; ra.S = S; ra.qe = P->consts.qe; ra.n = nst; ra.rho = B->rho.p;
-        for (int k = 0; k < S; k++) ra.Z[k] = P->species[k].Z;
+        ra.ncell = N; ra.qe = P->consts.qe; ra.n = nst; ra.rho = B->rho.p;
+        ra.S = 0;
+        for (int k = 0; k < S; k++)
+            if (P->species[k].Z != 0.0) { ra.Z[ra.S] = P->species[k].Z; ra.idx[ra.S] = k; ra.S++; }
         launch_rho(ctx, ra);
         // surface charge over the adjacent cells' width (mid-point value)
         auto sigma_args = [&](int f, const double *nbase) {
