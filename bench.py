@@ -451,7 +451,7 @@ def main():
     os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
+        print("bench.py runs on one GPU only: the step has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
               % (args.gpus, world), flush=True)
         sys.exit(2)
 

@@ -124,7 +124,7 @@ _lib = None
 
 
 def load():
-    """Load libvd.so (built by __graft_entry__.build()); raise if absent."""
+    """Load libvd.so (built in-tree by build.py); raise if absent."""
     global _lib
     if _lib is not None:
         return _lib
