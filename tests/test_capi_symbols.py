@@ -39,3 +39,24 @@ def test_binding_rejects_host_tensors():
     from paper_2507_08200_amd import vd
     with pytest.raises(ValueError):
         vd._dptr(torch.zeros(4, dtype=torch.float64), name="x")
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No CPU fallback: with the shared library absent the binding raises
+    instead of computing anything."""
+    from paper_2507_08200_amd import vd
+    monkeypatch.setattr(vd, "_lib", None)
+    monkeypatch.setattr(vd, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libvd.so"))
+    with pytest.raises(ImportError):
+        vd.load()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with a message and status 2
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
