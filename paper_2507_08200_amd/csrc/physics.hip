@@ -360,6 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_drift_tiled(DriftArgs a, int kz) {
     __shared__ double fy[(kTY + 1) * kTX];
     const GridDev &G = a.g;
     const FieldDesc F = a.f[blockIdx.y];
+    if (F.rhs_done) return;
     const int nx = G.n[0], ny = G.n[1];
     const int tiles_x = nx / kTX, tiles_y = ny / kTY;
     int b = blockIdx.x;
@@ -463,6 +464,7 @@ __global__ void __launch_bounds__(kBlock) k_drift25(DriftArgs a, int kz) {
     __shared__ double fy[(kDY + 1) * kDX];
     const GridDev &G = a.g;
     const FieldDesc F = a.f[blockIdx.y];
+    if (F.rhs_done) return;
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
     const int tiles_x = nx / kDX, tiles_y = ny / kDY;
     int b = blockIdx.x;
@@ -722,7 +724,7 @@ __global__ void __launch_bounds__(kBlock) k_drift(DriftArgs a) {
     const GridDev &G = a.g;
     const FieldDesc F = a.f[blockIdx.y];
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.ncell) return;
+    if (c >= G.ncell || F.rhs_done) return;
     int pos[3];
     pos[2] = c / G.nxy;
     int r = c - pos[2] * G.nxy;
@@ -747,6 +749,7 @@ __global__ void __launch_bounds__(kBlock) k_drift_fix(DriftArgs a) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= G.ncell || !gld(a.near, (long)c)) return;
     const FieldDesc F = a.f[blockIdx.y];
+    if (F.rhs_done) return;
     int pos[3];
     pos[2] = c / G.nxy;
     int r = c - pos[2] * G.nxy;
@@ -924,20 +927,37 @@ __global__ void __launch_bounds__(kBlock) k_react(ReactArgs a) {
     if (c >= a.ncell) return;
     const long N = a.ncell;
     double loss = 0.0, ion = 0.0;
+    // G of species s, or its right-hand side (the drift kernel's expression
+    // for a field without drift: u0/dt - 0, then + G, then + extra).  u0 is
+    // read again even when it is the rate state (a cache hit): holding the
+    // densities in registers until here costs occupancy
+    auto put = [&](int s, double g, double) {
+        if ((a.rhs_mask >> s) & 1u) {
+            double v = gld(a.u0, s * N + c) * a.inv_dt - 0.0;
+            v += g;
+            if (a.extra) v += gld(a.extra, s * N + c);
+            gst(a.rhs, s * N + c, v);
+        } else {
+            gst(a.G, s * N + c, g);
+        }
+    };
     if (a.mech == VD_MECH_ARH2_15) {
         double n[15], G[15];
         for (int s = 0; s < 15; s++) n[s] = gld(a.n, s * N + c);
         source_arh2(n, gld(a.Te, c), a.qe, G, &loss, &ion);
-        for (int s = 0; s < 15; s++) gst(a.G, s * N + c, G[s]);
+        for (int s = 0; s < 15; s++) put(s, G[s], n[s]);
     } else if (a.mech == VD_MECH_AR3) {
         double n[3], G[3];
         for (int s = 0; s < 3; s++) n[s] = gld(a.n, s * N + c);
         source_ar3(n, gld(a.Te, c), a.bg0, a.qe, G, &loss, &ion);
-        for (int s = 0; s < 3; s++) gst(a.G, s * N + c, G[s]);
+        for (int s = 0; s < 3; s++) put(s, G[s], n[s]);
     } else if (a.mech == VD_MECH_DECAY) {
-        for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, -a.bg0 * gld(a.n, s * N + c));
+        for (int s = 0; s < a.S; s++) {
+            const double nv = gld(a.n, s * N + c);
+            put(s, -a.bg0 * nv, nv);
+        }
     } else {
-        for (int s = 0; s < a.S; s++) gst(a.G, s * N + c, 0.0);
+        for (int s = 0; s < a.S; s++) put(s, 0.0, 0.0);
     }
     if (a.S_inel) gst(a.S_inel, c, loss);
     if (a.ion) gst(a.ion, c, ion);
@@ -1260,6 +1280,14 @@ void launch_transport(vd_ctx *ctx, const TransportArgs &a) {
     });
 }
 
+// the grids whose unmasked drift runs in k_drift25, with the wall-face
+// fluxes added by k_wall_div (the other kernels fold them into each cell's
+// divergence)
+bool drift25_path(const GridDev &g) {
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    return !g.mask && nx % kDX == 0 && ny % kDY == 0 && nz % 8 == 0 && nx >= 3 && ny >= 3 && nz >= 3;
+}
+
 void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields, const char *tag) {
     if (nfields == 0) return;
     if (a.g.mask && a.near) {
@@ -1284,6 +1312,7 @@ void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields
     double bytes = 8.0 * a.g.ncell;
     for (int f = 0; f < nfields; f++) {
         const FieldDesc &F = fields[f];
+        if (F.rhs_done) continue;
         double per = 16.0 + (F.mu ? 8.0 : 0.0);
         if (a.mode == 1) per += (F.src ? 8.0 : 0.0) + (F.extra ? 8.0 : 0.0) + (F.u0 != F.u ? 8.0 : 0.0);
         bytes += per * a.g.ncell;
@@ -1369,7 +1398,9 @@ void launch_mask_restore(vd_ctx *ctx, const GridDev &G, const double *phi_cov, d
 }
 
 void launch_react(vd_ctx *ctx, const ReactArgs &a) {
-    timed(ctx, "react", (double)a.ncell * 8.0 * (2.0 * a.S + 1.0 + (a.S_inel ? 1.0 : 0.0)), [&] { k_react<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a); });
+    timed(ctx, "react", (double)a.ncell * 8.0 * (2.0 * a.S + 1.0 + (a.S_inel ? 1.0 : 0.0)), [&] {
+        k_react<<<ceil_div(a.ncell, kBlock), kBlock, 0, ctx->stream>>>(a);
+    });
 }
 
 void launch_rho(vd_ctx *ctx, const RhoArgs &a) {

@@ -35,6 +35,9 @@ struct FieldDesc {
     const double *u0;      // time level n (right-hand side mode)
     const double *src;     // chemical source (right-hand side mode)
     const double *extra;   // extra source (right-hand side mode)
+    // right-hand side already formed by k_react (a field without drift): the
+    // drift kernels leave its output alone, the wall fluxes are still added
+    int rhs_done;
     // wall variants (Sec. 2.2): the sticking coefficient of a neutral wall
     // flux; secondary emission: gamma and the ion species whose wall fluxes
     // at the same face it returns (densities, signed mobilities per cell or
@@ -83,6 +86,13 @@ struct ReactArgs {
     double bg0, qe;
     double *G, *S_inel;
     double *ion;           // rate of R2 (direct ionization of Ar), or null
+    // species (bit k) whose implicit right-hand side u0/dt + G (+ extra) is
+    // written to rhs in place of G: fields without drift, whose right-hand
+    // side needs nothing else; rhs, u0, extra: [S][cells] bases
+    unsigned rhs_mask;
+    double *rhs;
+    const double *u0, *extra;
+    double inv_dt;
 };
 
 // Photoionization terms (Sec. 2.1, Eqs. (9)-(12)): right-hand sides coef_q
@@ -154,6 +164,7 @@ struct EnergyArgs {
 GridDev make_grid(const vd_grid &g, const vd_bc &phi_bc);
 void launch_transport(vd_ctx *ctx, const TransportArgs &a);
 void launch_drift(vd_ctx *ctx, DriftArgs a, const FieldDesc *fields, int nfields, const char *tag);
+bool drift25_path(const GridDev &g);
 // total face flux (drift + central diffusion with cell diffusion D) of one field
 void launch_face_flux(vd_ctx *ctx, DriftArgs a, const FieldDesc &field, const double *D, double *out);
 void launch_react(vd_ctx *ctx, const ReactArgs &a);

@@ -386,6 +386,15 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
         rc.bg0 = P->mech == VD_MECH_DECAY ? P->k_decay : P->bg[0];
         rc.qe = P->consts.qe; rc.G = B->G.p; rc.S_inel = B->S_inel.p;
         rc.ion = P->photo_n > 0 ? B->ion.p : nullptr;
+        // transported fields without drift: their right-hand side is
+        // u^n/dt + G (+ extra), formed here in place of G, where the drift
+        // kernel adds the wall-face fluxes in a pass of their own
+        unsigned nodrift = 0;
+        for (int k = 0; k < S && drift25_path(G); k++) {
+            const bool photo_target = P->photo_n > 0 && (k == P->photo_e || k == P->photo_ion);
+            if (P->species[k].transported && var_idx[k] < 0 && mu_c[k] == 0.0 && !photo_target) nodrift |= 1u << k;
+        }
+        rc.rhs_mask = nodrift; rc.rhs = B->b.p; rc.u0 = n_old; rc.extra = P->extra_source; rc.inv_dt = 1.0 / dt;
         launch_react(ctx, rc);
         // photoionization (Sec. 2.1, Eqs. (9)-(12)) into the sources
         if (P->photo_n > 0) {
@@ -489,6 +498,7 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
             F.u0 = n_old + (long)k * N;
             F.src = B->G.p + (long)k * N;
             F.extra = P->extra_source ? P->extra_source + (long)k * N : nullptr;
+            F.rhs_done = (nodrift >> k) & 1u;
             wall_variants(F, k, nst);
             vd_problem &q = sp[nf];
             memset(&q, 0, sizeof(q));

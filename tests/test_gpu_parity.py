@@ -301,11 +301,17 @@ def test_step_arh2_small(ctx, V, oracle):
     assert max(errs.values()) <= TOL
 
 
-def test_step_corrector_two(ctx, V, oracle):
+@pytest.mark.parametrize("n", [16, 32])
+def test_step_corrector_two(ctx, V, oracle, n):
+    """Two correctors: at 16^3 the per-cell drift kernel (wall fluxes inside
+    each cell's divergence); at 32^3 the tiled one, where the neutral
+    field's right-hand side is formed with the reaction source and its wall
+    flux added by the wall pass, from u^n while the rates are taken at the
+    mid-point."""
     from paper_2507_08200_amd import mechanisms as M
-    cfg = I.cfg1(n=16)
+    cfg = I.cfg1(n=n)
     cfg["n_t"] = 2
-    say("step cfg1 16^3 n_t=2")
+    say("step cfg1 %d^3 n_t=2" % n)
     errs = _step_compare(V, oracle, ctx, cfg, M.ar3(), oracle.species_ar3(), 10, 2)
     assert max(errs.values()) <= TOL
 
