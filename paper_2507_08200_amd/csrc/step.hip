@@ -418,10 +418,16 @@ vd_status step(vd_ctx *ctx, const vd_step_params *P, const vd_state *st, vd_step
                 const double m = std::fabs(pa.coef[q]) * mion;
                 int e = 0;
                 double sc = 1.0;
-                if (m > 0.0 && std::isfinite(m)) { (void)std::frexp(m, &e); sc = std::ldexp(1.0, e); }
+                if (m > 0.0 && std::isfinite(m)) (void)std::frexp(m, &e);
+                // a power of two whose inverse is finite and normal (a
+                // right-hand side below 2^-1000 keeps the scale 1)
+                if (e > -1000 && e < 1000) sc = std::ldexp(1.0, e);
                 pa.scale[q] = sc;
                 pa.inv_scale[q] = 1.0 / sc;
+                // the stored terms, rescaled exactly (both scales are powers
+                // of two); a ratio beyond the normal range restarts from zero
                 pa.ratio[q] = B->photo_scale[q] / sc;
+                if (!std::isnormal(pa.ratio[q])) pa.ratio[q] = 0.0;
                 B->photo_scale[q] = sc;
                 const double kl = P->photo_lambda[q] * P->photo_pO2;
                 pr[q].grid = g; pr[q].bc = P->photo_bc; pr[q].alpha_c = kl * kl; pr[q].beta_c = 1.0;
