@@ -93,6 +93,34 @@ def test_step_photoionization_guess_from_previous_call(ctx, V):
     assert torch.equal(out1, out2)
 
 
+def test_step_photoionization_rescaled_guess(V):
+    """Between two calls the ionization rate grows several-fold, so each
+    term's power-of-two unit changes and the stored terms (the second call's
+    starting iterates) are rescaled: the solve from them meets the solve from
+    zero of the same state to its tolerance."""
+    from paper_2507_08200_amd import mechanisms as M
+    cfg = I.cfg1(n=16)
+    outs = {}
+    for guess in (V.GUESS_GIVEN, V.GUESS_ZERO):
+        ctx = V.Context()
+        out = torch.zeros((3,) + cfg["phi"].shape, dtype=torch.float64, device="cuda")
+        maxima = []
+        for te_ev in (5.0, 6.0):
+            c = dict(cfg)
+            c["Te"] = np.full_like(cfg["Te"], te_ev * I.EV_IN_K)
+            state = {k: dev(c[k]) for k in ("n", "phi", "Te")}
+            P = V.step_params(c, M.ar3(), poisson=V.mg_opts(fixed_cycles=8), species_mg=V.mg_opts(fixed_cycles=2),
+                              photo=dict(PHOTO, bc=I.bc([D] * 6), mg=V.mg_opts(rtol=1e-12, guess=guess), out=out))
+            assert ctx.vd_step(P, state)["status"] == 0
+            maxima.append(float(out.abs().max()))
+        outs[guess] = host(out)
+        say("   photo term maxima at 5 and 6 eV", maxima)
+        assert 2.0 * maxima[0] < maxima[1] < 1e3 * maxima[0]      # a different power of two
+    errs = [rel_err(outs[V.GUESS_GIVEN][q], outs[V.GUESS_ZERO][q]) for q in range(3)]
+    say("   rescaled guess vs zero guess", ["%.1e" % e for e in errs])
+    assert max(errs) <= 1e-10
+
+
 def test_step_photoionization_fp32_refinement(ctx, V, oracle):
     """The terms (~1e26 here) and their right-hand sides are beyond the FP32
     range of the refinement's sums unless each term is solved in units of a
